@@ -1,0 +1,192 @@
+"""Seeded synthetic linear systems (CSR, FP64) used by tests, smoke and bench.
+
+This module only builds input matrices and right-hand sides. It holds none of
+the solver's arithmetic (no scaling, no fixed point, no factorisation), so both
+the CPU oracle and the GPU library can be driven from it.
+
+The paper evaluates on SuiteSparse matrices (Sec. VII-A, Table III), which are
+not available here; these seeded stencil families stand in for them:
+
+* ``poisson2d(nx, ny)``   5-point Laplacian, a_ii = 4, neighbours -1,
+  Dirichlet boundaries eliminated; b = A * ones so the solution is all ones.
+* ``convdiff3d(nx, ny, nz, seed)`` 7-point convection-diffusion, nonsymmetric
+  M-matrix: cell diffusivity 10**U(-1, 1), harmonic-mean face values, cell
+  Peclet U(0.1, 2.0) per axis, central-difference convection with positive
+  velocity; b ~ U[-1, 1].
+* ``random27(nx, ny, nz, seed)`` 27-point pattern, off-diagonals N(0, 1),
+  diagonal 1.1 * sum |off-diagonals|; b ~ U[-1, 1].
+* ``random_dd(n, density, seed)`` small unstructured diagonally dominant
+  systems with ragged row lengths (edge-case coverage).
+
+Every generator is a pure function of its arguments (numpy PCG64 seeds).
+Columns within each CSR row are strictly increasing.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class System:
+    """A linear system A x = b in CSR form (row_ptr int64, col int32, val f64)."""
+
+    name: str
+    n: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    b: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def dense(self) -> np.ndarray:
+        a = np.zeros((self.n, self.n))
+        for i in range(self.n):
+            lo, hi = self.row_ptr[i], self.row_ptr[i + 1]
+            a[i, self.col[lo:hi]] = self.val[lo:hi]
+        return a
+
+    def matvec(self, x: np.ndarray) -> np.ndarray:
+        rows = np.repeat(np.arange(self.n), np.diff(self.row_ptr))
+        return np.bincount(rows, weights=self.val * x[self.col], minlength=self.n)
+
+
+def _stencil_pattern(dims, offsets):
+    """CSR pattern of a stencil on a box grid with natural ordering.
+
+    ``dims`` = (nx, ny, nz); ``offsets`` = list of (dx, dy, dz). Returns
+    (row_ptr, col, slot) where ``slot[e]`` is the offset index of entry e, and
+    entries of each row appear in increasing column order.
+    """
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    lin = [dz * nx * ny + dy * nx + dx for (dx, dy, dz) in offsets]
+    order = np.argsort(lin, kind="stable")
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % nx
+    y = (idx // nx) % ny
+    z = idx // (nx * ny)
+    valid = np.zeros((n, len(offsets)), dtype=bool)
+    cols = np.zeros((n, len(offsets)), dtype=np.int64)
+    for k, o in enumerate(order):
+        dx, dy, dz = offsets[o]
+        ok = (x + dx >= 0) & (x + dx < nx) & (y + dy >= 0) & (y + dy < ny) & (z + dz >= 0) & (z + dz < nz)
+        valid[:, k] = ok
+        cols[:, k] = idx + lin[o]
+    counts = valid.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = cols[valid].astype(np.int32)
+    slot = np.broadcast_to(np.asarray(order), (n, len(offsets)))[valid]
+    return row_ptr, col, slot
+
+
+def poisson2d(nx: int = 64, ny: int | None = None) -> System:
+    ny = nx if ny is None else ny
+    offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0)]
+    row_ptr, col, slot = _stencil_pattern((nx, ny, 1), offs)
+    val = np.where(slot == 0, 4.0, -1.0)
+    sysm = System(f"poisson2d_{nx}x{ny}", nx * ny, row_ptr, col, val, np.zeros(nx * ny))
+    sysm.b = sysm.matvec(np.ones(sysm.n))
+    return sysm
+
+
+def convdiff3d(nx: int = 64, ny: int | None = None, nz: int | None = None, seed: int = 2) -> System:
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    n = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    dcell = 10.0 ** rng.uniform(-1.0, 1.0, size=n)
+    pe = rng.uniform(0.1, 2.0, size=(n, 3))
+    b = rng.uniform(-1.0, 1.0, size=n)
+    dims = (nx, ny, nz)
+    strides = (1, nx, nx * ny)
+    idx = np.arange(n)
+    coord = (idx % nx, (idx // nx) % ny, idx // (nx * ny))
+    offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    row_ptr, col, slot = _stencil_pattern(dims, offs)
+    rows = np.repeat(idx, np.diff(row_ptr))
+    # per (cell, axis): face diffusivities toward +e and -e, convection term
+    dplus = np.empty((n, 3))
+    dminus = np.empty((n, 3))
+    for a in range(3):
+        c = coord[a]
+        nb_p = np.minimum(idx + strides[a], n - 1)
+        nb_m = np.maximum(idx - strides[a], 0)
+        hm_p = 2.0 * dcell * dcell[nb_p] / (dcell + dcell[nb_p])
+        hm_m = 2.0 * dcell * dcell[nb_m] / (dcell + dcell[nb_m])
+        dplus[:, a] = np.where(c < dims[a] - 1, hm_p, dcell)
+        dminus[:, a] = np.where(c > 0, hm_m, dcell)
+    p = pe * np.minimum(dplus, dminus) / 2.0
+    diag = (dplus + dminus).sum(axis=1)
+    # slot k in offs: 1 = -x, 2 = +x, 3 = -y, 4 = +y, 5 = -z, 6 = +z
+    val = np.empty(len(col))
+    for k in range(7):
+        m = slot == k
+        r = rows[m]
+        if k == 0:
+            val[m] = diag[r]
+        else:
+            a = (k - 1) // 2
+            if k % 2 == 0:  # +e neighbour
+                val[m] = -dplus[r, a] + p[r, a]
+            else:  # -e neighbour
+                val[m] = -dminus[r, a] - p[r, a]
+    return System(f"convdiff3d_{nx}x{ny}x{nz}_s{seed}", n, row_ptr, col, val, b)
+
+
+def random27(nx: int = 128, ny: int | None = None, nz: int = 64, seed: int = 3) -> System:
+    ny = nx if ny is None else ny
+    n = nx * ny * nz
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    row_ptr, col, slot = _stencil_pattern((nx, ny, nz), offs)
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    is_diag = col == rows
+    off = rng.standard_normal(int((~is_diag).sum()))
+    b = rng.uniform(-1.0, 1.0, size=n)
+    val = np.empty(len(col))
+    val[~is_diag] = off
+    absum = np.bincount(rows[~is_diag], weights=np.abs(off), minlength=n)
+    val[is_diag] = 1.1 * absum
+    return System(f"random27_{nx}x{ny}x{nz}_s{seed}", n, row_ptr, col, val, b)
+
+
+def random_dd(n: int, density: float = 0.1, seed: int = 0, dominance: float = 1.5,
+              nonneg_diag: bool = True) -> System:
+    """Unstructured sparse, strictly diagonally dominant, ragged row lengths."""
+    rng = np.random.default_rng(seed)
+    mask = rng.random((n, n)) < density
+    np.fill_diagonal(mask, True)
+    vals = rng.standard_normal((n, n)) * mask
+    np.fill_diagonal(vals, 0.0)
+    d = dominance * np.abs(vals).sum(axis=1) + 0.5
+    if not nonneg_diag:
+        d = d * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    np.fill_diagonal(vals, d)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=row_ptr[1:])
+    r, c = np.nonzero(mask)
+    b = rng.uniform(-1.0, 1.0, size=n)
+    return System(f"random_dd_{n}_s{seed}", n, row_ptr, c.astype(np.int32), vals[r, c].astype(np.float64), b)
+
+
+def from_dense(a: np.ndarray, b: np.ndarray, name: str = "dense") -> System:
+    n = a.shape[0]
+    mask = a != 0.0
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=row_ptr[1:])
+    r, c = np.nonzero(mask)
+    return System(name, n, row_ptr, c.astype(np.int32), a[r, c].astype(np.float64), np.asarray(b, dtype=np.float64))
+
+
+# Named workloads: (generator, preset name, restart length m).
+WORKLOADS = {
+    "poisson2d_64": (lambda: poisson2d(64), "paper_noprec", 30),
+    "convdiff3d_64": (lambda: convdiff3d(64, seed=2), "jacobi", 50),
+    "random27_1m": (lambda: random27(128, 128, 64, seed=3), "paper_ilu", 30),
+}
