@@ -106,6 +106,8 @@ def lib():
             "orc_div": (i64, [i64, i64, i32, i32, i32, pi32, pi32]),
             "orc_dot": (i64, [i64, vp, vp, i32, i32, pi32]),
             "orc_norm": (i64, [i64, vp, i32, i32, pi32]),
+            "orc_axpy": (None, [i64, vp, vp, i64, i32, i32, pi32]),
+            "orc_normalize": (None, [i64, vp, i64, i32, i32, i32, vp, pi32]),
             "orc_dnrm": (dbl, [i64, vp]),
             "orc_u128_to_double": (dbl, [C.c_uint64, C.c_uint64]),
             "orc_create": (C.c_int, [i64, vp, vp, vp, vp, C.POINTER(Policy), C.POINTER(vp)]),
@@ -203,6 +205,22 @@ def norm(w, b: int, df: int = 30):
     o = C.c_int32(0)
     r = lib().orc_norm(len(w), _p(w), b, df, C.byref(o))
     return r, bool(o.value)
+
+
+def axpy(w, v, h: int, b: int, df: int = 30):
+    w = _i64(w).copy()
+    v = _i64(v)
+    o = C.c_int32(0)
+    lib().orc_axpy(len(w), _p(w), _p(v), h, b, df, C.byref(o))
+    return w, bool(o.value)
+
+
+def normalize(w, den: int, b1: int, b2: int, df: int = 30):
+    w = _i64(w)
+    v = np.empty_like(w)
+    o = C.c_int32(0)
+    lib().orc_normalize(len(w), _p(w), den, b1, b2, df, _p(v), C.byref(o))
+    return v, bool(o.value)
 
 
 def dnrm(x) -> float:

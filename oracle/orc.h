@@ -93,6 +93,9 @@ int64_t orc_mul(int64_t t1, int64_t t2, int32_t b1, int32_t b2, int32_t df, int3
 int64_t orc_div(int64_t t1, int64_t t2, int32_t b1, int32_t b2, int32_t df, int32_t *ovf, int32_t *zero);
 int64_t orc_dot(int64_t n, const int64_t *w, const int64_t *v, int32_t b, int32_t df, int32_t *ovf);
 int64_t orc_norm(int64_t n, const int64_t *w, int32_t b, int32_t df, int32_t *ovf);
+void orc_axpy(int64_t n, int64_t *w, const int64_t *v, int64_t h, int32_t b, int32_t df, int32_t *ovf);
+void orc_normalize(int64_t n, const int64_t *w, int64_t den, int32_t b1, int32_t b2, int32_t df, int64_t *v,
+                   int32_t *ovf);
 
 /* ---- FP64 helpers (orc_ir.c) --------------------------------------------- */
 double orc_dnrm(int64_t n, const double *x);

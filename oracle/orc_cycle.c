@@ -118,14 +118,8 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
       int64_t h = orc_dot(n, w, vi, p->b_dot, f, &ovf); /* line 7 */
       if (ovf) event(&t->first_ovf, ORC_CODE(j, 3, 2 * (i - 1)));
       HH(i - 1, j - 1) = h;
-      ovf = 0; /* line 8: w -= (asr(h, b) * v_i) >> (df - b) */
-      int64_t hs = orc_asr(h, p->b_axpy);
-      for (int64_t l = 0; l < n; ++l) {
-        int64_t q = orc_asr(pmul(hs, vi[l], &ovf), f - p->b_axpy);
-        i128 d = (i128)w[l] - q;
-        if (!fits64(d)) ovf = 1;
-        w[l] = wrap64(d);
-      }
+      ovf = 0; /* line 8 */
+      orc_axpy(n, w, vi, h, p->b_axpy, f, &ovf);
       if (ovf) event(&t->first_ovf, ORC_CODE(j, 3, 2 * (i - 1) + 1));
     }
     /* line 10 */
@@ -137,12 +131,8 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
     int64_t den = orc_asr(hn, p->b_div_den);
     int lucky = den == 0;
     if (!lucky) {
-      int64_t *vn = t->V + (size_t)j * n;
       ovf = 0;
-      for (int64_t l = 0; l < n; ++l) {
-        int64_t q = orc_tdiv(orc_shl(w[l], p->b_div_num, &ovf), den, &ovf);
-        vn[l] = orc_sc(q, f - p->b_div_num - p->b_div_den, &ovf);
-      }
+      orc_normalize(n, w, den, p->b_div_num, p->b_div_den, f, t->V + (size_t)j * n, &ovf);
       if (ovf) event(&t->first_ovf, ORC_CODE(j, 5, 0));
     }
     /* lines 12-14: apply the previous rotations to column j */

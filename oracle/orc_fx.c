@@ -122,3 +122,25 @@ int64_t orc_norm(int64_t n, const int64_t *w, int32_t b, int32_t df, int32_t *ov
   int64_t sq = finish_sum(s, ovf);
   return orc_shl(orc_isqrt(sq), b, ovf);
 }
+
+/* Line 8 (Table II): w_l -= asr(asr(h, b) * v_l, df - b) for every l, in
+ * place; only h is shifted (Sec. V-D.2). */
+void orc_axpy(int64_t n, int64_t *w, const int64_t *v, int64_t h, int32_t b, int32_t df, int32_t *ovf) {
+  int64_t hs = orc_asr(h, b);
+  for (int64_t l = 0; l < n; ++l) {
+    int64_t q = orc_asr(mul_exact(hs, v[l], ovf), df - b);
+    i128 d = (i128)w[l] - q;
+    if (!fits64(d)) *ovf = 1;
+    w[l] = wrap64(d);
+  }
+}
+
+/* Line 11 (Sec. V-B.3): v_l = sc(tdiv(shl(w_l, b1), den), df - b1 - b2) with
+ * den = asr(h, b2) != 0 (the caller checks for 0). */
+void orc_normalize(int64_t n, const int64_t *w, int64_t den, int32_t b1, int32_t b2, int32_t df, int64_t *v,
+                   int32_t *ovf) {
+  for (int64_t l = 0; l < n; ++l) {
+    int64_t q = orc_tdiv(orc_shl(w[l], b1, ovf), den, ovf);
+    v[l] = orc_sc(q, df - b1 - b2, ovf);
+  }
+}

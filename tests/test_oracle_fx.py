@@ -209,3 +209,16 @@ def test_dnrm_matches_textbook_norm_and_is_order_free(orc):
         assert orc.dnrm(-x) == d
     assert orc.dnrm(np.zeros(5)) == 0.0
     assert orc.dnrm(np.array([3.0, 4.0])) == 5.0
+
+
+def test_dot_shifts_first_operand_only(orc):
+    """Table II line 7: w (first operand) is divided by 2^beta, v is not. With
+    v = 1.0 in Q30 (2^30) the result is sum_l floor(w_l / 2^b) 2^b, i.e. w with
+    its low b bits dropped; shifting v instead would keep them."""
+    rng = np.random.default_rng(30)
+    w = rng.integers(-(1 << 24), 1 << 24, 257)
+    v = np.full(257, 1 << 30, dtype=np.int64)
+    for b in (0, 1, 14, 16, 30):
+        h, ovf = orc.dot(w, v, b)
+        assert not ovf
+        assert h == sum((int(t) >> b) << b for t in w)
