@@ -1,0 +1,236 @@
+/*
+ * igmres.h -- C ABI of the MI355X (gfx950) integer-arithmetic GMRES(m) solver
+ * with FP64 iterative refinement.
+ *
+ * Method: T. Iwashita, K. Suzuki, T. Fukaya, "An Integer Arithmetic-Based
+ * Sparse Linear Solver Using a GMRES Method and Iterative Refinement",
+ * ScalA'20 (arXiv 2009.07495).
+ *
+ * The caller hands in an FP64 system Ahat xhat = bhat in CSR form (Sec. III,
+ * eq. (org)). The library scales it (eqs. (eq1), (eq3)), casts the matrix to
+ * integers (Sec. IV-B), builds the optional integer preconditioner (Sec. VI),
+ * and refines xhat in FP64 (Sec. IV, Fig. 1) until the FP64 relative residual
+ * of the original system drops below the tolerance. Each refinement runs one
+ * int-GMRES(m) call (Fig. 2) whose main loop is integer-only and runs on the
+ * GPU as hand-written HIP kernels.
+ *
+ * Conventions for every call:
+ *  - Plain C types only. No exceptions cross the boundary; every call returns
+ *    an igm_status (negative = error, positive = warning) and never aborts.
+ *  - Host pointers are read during the call only; the caller keeps ownership.
+ *    "Device pointers" are HIP device allocations on the system's device
+ *    (e.g. torch CUDA tensors), also owned by the caller.
+ *  - All device work of a system is ordered on the system's HIP stream (the
+ *    null stream unless igm_set_stream was called). Calls that return host
+ *    results synchronise that stream before returning.
+ *  - One system is not thread-safe; distinct systems may be used from
+ *    distinct threads.
+ *  - Integer words are int64 two's complement fixed-point numbers in
+ *    Q(63 - df).df format (Sec. II, WL = 64).
+ */
+#ifndef IGMRES_H
+#define IGMRES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct igm_system igm_system;
+
+typedef enum {
+  IGM_OK = 0,
+  IGM_NOT_CONVERGED = 1,      /* warning: refinement limit reached; x holds the last iterate */
+  IGM_ERR_ARG = -1,           /* invalid argument, CSR or policy */
+  IGM_ERR_SINGULAR_ROW = -2,  /* a row of Ahat is all zero: eq. (eq3) undefined */
+  IGM_ERR_ZERO_PIVOT = -3,    /* zero ILU(0) pivot, missing diagonal, or a cast diagonal of 0 */
+  IGM_ERR_OVERFLOW = -4,      /* an integer word left int64 in a cycle (stats name where) */
+  IGM_ERR_RANGE = -5,         /* an FP64 -> int64 cast out of range, or a non-finite residual */
+  IGM_ERR_OOM = -6,           /* device or host allocation failed */
+  IGM_ERR_DEVICE = -7,        /* HIP error, or a device-side wait that timed out */
+  IGM_ERR_BREAKDOWN = -8,     /* a cycle produced no usable Krylov column */
+  IGM_ERR_UNSUPPORTED = -9    /* size outside what this build supports */
+} igm_status;
+
+enum { IGM_PRE_NONE = 0, IGM_PRE_JACOBI = 1, IGM_PRE_ILU0 = 2 };
+
+/* Presets: the paper's two settings (Sec. VII-B / Table IV, Sec. VII-C /
+ * Table VI) and a diagonal-only variant of the ILU construction. */
+enum { IGM_PRESET_PAPER_NOPREC = 0, IGM_PRESET_PAPER_ILU = 1, IGM_PRESET_JACOBI = 2 };
+
+/* Overflow event code (igm_stats.first_ovf, igm_cycle_trace.first_ovf):
+ *   (step j << 24) | (stage << 16) | sub
+ * stage 1 = line 5 SpMV, 2 = line 5' preconditioner, 3 = lines 7/8 (sub =
+ * 2(i-1) for the inner product with v_i, 2(i-1)+1 for the update), 4 = line
+ * 10, 5 = line 11, 6 = line 13 (sub = i), 7 = line 15, 8 = line 16, 9 = line
+ * 17. The smallest code of a cycle is reported. IGM_NO_EVENT if none. */
+#define IGM_NO_EVENT INT64_MAX
+
+/* Solver parameters (Table I arguments, Table II operand shifts). */
+typedef struct {
+  int32_t struct_size;  /* sizeof(igm_policy) */
+  int32_t df;           /* fraction bits d_f, 1..62 (paper: 30) */
+  int32_t alpha_a;      /* eq. (eq3) exponent, 0..62 (paper: 16 / 32) */
+  int32_t s_terms;      /* s of eq. (AA): correction matrices used, 0..8 (paper: 0) */
+  int32_t m;            /* int-GMRES iterations per refinement, 1..1024 */
+  int32_t precond;      /* IGM_PRE_* (Sec. VI) */
+  int32_t b_dot;        /* line 7 shift of w */
+  int32_t b_axpy;       /* line 8 shift of h */
+  int32_t b_norm;       /* line 10 shift of both operands */
+  int32_t b_div_num;    /* line 11 numerator * 2^b */
+  int32_t b_div_den;    /* line 11 denominator / 2^b */
+  int32_t b_rot;        /* line 13 shift of the h entries */
+  int32_t b_tmp;        /* line 15 shift of both operands */
+  int32_t b_cs_num;     /* line 16 numerator * 2^b */
+  int32_t b_cs_den;     /* line 16 denominator / 2^b */
+  int32_t max_refine;   /* refinement limit (the paper gives none) */
+  int64_t gtol;         /* end a cycle early when |g_{j+1}| <= gtol (Sec. V-A); < 0 = never */
+  double tol;           /* stop when ||bhat - Ahat x|| / ||bhat|| < tol (Sec. III) */
+  int32_t grid_blocks;  /* launch tuning: workgroups of the cycle kernel; 0 = automatic */
+  int32_t reserved_[7];
+} igm_policy;
+
+/* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,
+ * max_refine = 2000, gtol = -1. IGM_ERR_ARG for an unknown preset. */
+igm_status igm_policy_preset(int32_t preset, igm_policy *out);
+
+/* Build a system from an FP64 CSR matrix (row_ptr[n+1] int64, col[nnz] int32
+ * with strictly increasing columns per row, val[nnz]) and right-hand side
+ * b[n], all host memory, copied during the call. Performs the row scaling of
+ * eq. (eq3)/(eq1), the integer matrices of eq. (A), the integer ILU(0) or
+ * Jacobi factors of eqs. (dl)-(ilu2), and uploads everything to the current
+ * HIP device. Errors: IGM_ERR_ARG (bad CSR, non-finite value, bad policy),
+ * IGM_ERR_SINGULAR_ROW, IGM_ERR_ZERO_PIVOT, IGM_ERR_RANGE, IGM_ERR_OOM,
+ * IGM_ERR_DEVICE. On error *out is NULL. */
+igm_status igm_create_system(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                             const double *b, const igm_policy *pol, igm_system **out);
+
+/* Replace the policy; redoes the policy-dependent setup (scaling, integer
+ * matrices, preconditioner). Same errors as igm_create_system; on error the
+ * system keeps its previous policy. */
+igm_status igm_set_policy(igm_system *s, const igm_policy *pol);
+
+/* Replace the right-hand side bhat (host, n doubles). */
+igm_status igm_set_rhs(igm_system *s, const double *b);
+
+/* Use a caller-created HIP stream (hipStream_t passed as void*, e.g. the
+ * handle of a torch stream) for all later device work; NULL = null stream. */
+igm_status igm_set_stream(igm_system *s, void *hip_stream);
+
+/* Solve (Fig. 1): x[n] (host) holds the starting iterate on entry (zeros =
+ * the paper's setting) and the final iterate on return. IGM_OK,
+ * IGM_NOT_CONVERGED, or an error; on IGM_ERR_OVERFLOW / IGM_ERR_BREAKDOWN x
+ * holds the last iterate before the failed refinement. */
+igm_status igm_solve(igm_system *s, double *x);
+
+/* Same as igm_solve with x a device pointer to n doubles on the system's
+ * device; no host copies of x are made. */
+igm_status igm_solve_device(igm_system *s, double *x_dev);
+
+typedef struct {
+  int32_t struct_size;     /* sizeof(igm_stats) */
+  int32_t status;          /* status of the last solve */
+  int32_t refinements;     /* int-GMRES calls of the last solve */
+  int32_t iterations;      /* Arnoldi steps of the last solve */
+  int64_t first_ovf;       /* overflow event code of the failed cycle, IGM_NO_EVENT if none */
+  double relres_orig;      /* final ||bhat - Ahat x|| / ||bhat|| */
+  double relres_scaled;    /* final ||b - A x|| / ||b|| (scaled system, Fig. 1) */
+  double time_solve_ms;    /* wall time of the last solve */
+  double time_cycle_ms;    /* GPU time in the int-GMRES kernels of the last solve */
+  double time_setup_ms;    /* host + upload time of the last setup */
+  int64_t n, nnz;
+  int32_t nterms;          /* integer matrices built (A_0 .. A_p) */
+  int32_t grid_blocks;     /* workgroups of the cycle kernel */
+  int32_t rows_per_thread; /* rows held in registers by each thread */
+  int32_t block_threads;   /* threads per workgroup */
+  int32_t levels_fwd;      /* ILU forward level sets */
+  int32_t levels_bwd;      /* ILU backward level sets */
+  int64_t device_bytes;    /* device memory held by the system */
+  int32_t last_error_line; /* source line of the last HIP error, 0 if none */
+  int32_t reserved0_;
+  double time_kernel_ms;   /* GPU time of the kernels of the last kernel-level call (igm_spmv ...) */
+  int32_t reserved_[4];
+} igm_stats;
+
+/* Copy the statistics of the system's last setup and solve. */
+igm_status igm_get_stats(const igm_system *s, igm_stats *out);
+
+/* Per-refinement history of the last solve: entry k (0-based) holds the
+ * values at the top of refinement k+1: relres of the original and scaled
+ * system, gamma^(k) (eq. (gammak)), rho = ||r0|| (line 1'), and the number of
+ * columns used (j*). Any pointer may be NULL. Returns the number of entries
+ * written (<= cap) in *count. */
+igm_status igm_get_history(const igm_system *s, int32_t cap, double *relres_orig, double *relres_scaled,
+                           double *gamma, double *rho, int32_t *jstar, int32_t *count);
+
+/* One int-GMRES(m) call, lines 3-20 of Fig. 2, from the integer start vector
+ * v1 (host, n int64 words: the output of line 2), with the system's policy.
+ * Outputs (caller-allocated host arrays; V may be NULL):
+ *   H[(m+1)*m] row-major (H[i*m + j], 0-based) after the rotations,
+ *   c[m], s[m], g[m+1], V[(m+1)*n] (basis vector j at V + j*n).
+ * m is taken from trace->m, which must equal the policy's m. */
+typedef struct {
+  int32_t m;          /* in */
+  int32_t jstar;      /* out: columns usable by lines 21-23 */
+  int32_t breakdown;  /* out: 0 none, 1 line 11 zero denominator, 2 line 16 zero denominator */
+  int32_t steps;      /* out: Arnoldi steps executed */
+  int64_t first_ovf;  /* out: overflow event code or IGM_NO_EVENT */
+  int64_t *H, *c, *s, *g, *V;
+} igm_cycle_trace;
+
+igm_status igm_int_cycle(igm_system *s, const int64_t *v1, igm_cycle_trace *trace);
+
+/* Kernel-level entry points (each runs one GPU kernel family on device
+ * buffers, for checking a single step of the method and for timing it).
+ * All vectors are device pointers of length n unless stated otherwise;
+ * *first_ovf receives the overflow event code with step j = 1. */
+
+/* Line 5 (Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_{l=1..nterms-1}
+ * asr(A_l v, alpha_l) over the system's integer matrices (nterms clamped to
+ * the number built). */
+igm_status igm_spmv(igm_system *s, int32_t nterms, const int64_t *v, int64_t *z, int64_t *first_ovf);
+
+/* Line 5' (Sec. VI-A): w = Mbar^-1 z by integer forward/backward substitution
+ * (truncating division), level-scheduled; w = z without a preconditioner. */
+igm_status igm_precond(igm_system *s, const int64_t *z, int64_t *w, int64_t *first_ovf);
+
+/* Line 7 (Sec. V-C.1, Table II): *h = asr(sum_l asr(w_l, b_dot) v_l, df - b_dot). */
+igm_status igm_dot(igm_system *s, const int64_t *w, const int64_t *v, int64_t *h, int64_t *first_ovf);
+
+/* Line 8: w_l -= asr(asr(h, b_axpy) v_l, df - b_axpy), in place. */
+igm_status igm_axpy(igm_system *s, int64_t h, int64_t *w, const int64_t *v, int64_t *first_ovf);
+
+/* Line 10 (Sec. V-C.2): *h = shl(isqrt(sum_l asr(w_l, b_norm)^2), b_norm). */
+igm_status igm_norm(igm_system *s, const int64_t *w, int64_t *h, int64_t *first_ovf);
+
+/* Line 11 (Sec. V-B.3): v_l = sc(tdiv(shl(w_l, b_div_num), asr(h, b_div_den)),
+ * df - b_div_num - b_div_den). IGM_ERR_BREAKDOWN if the shifted denominator is 0. */
+igm_status igm_normalize(igm_system *s, const int64_t *w, int64_t h, int64_t *v, int64_t *first_ovf);
+
+/* Refinement step (eq. (b)): r = b - A x (scaled system) and rhat = bhat -
+ * Ahat x (original system), FP64, each row summed in CSR order. */
+igm_status igm_residual(igm_system *s, const double *x, double *r, double *rhat);
+
+/* The order-free FP64 2-norm used for every norm of the refinement loop
+ * (mu = max|x_i|, exact integer sum of floor(2^96 (x_i/mu)^2), one rounding). */
+igm_status igm_fp_norm(igm_system *s, const double *x, int64_t len, double *norm);
+
+/* Eqs. (gammak), (scale) and lines 1'-2: gamma = max|r|, bk = r / gamma,
+ * r0 = Mbar^-1 bk (FP64 substitution with the integer factors), rho =
+ * ||r0||, v1 = trunc(2^df r0 / rho). IGM_ERR_RANGE if a cast is out of range.
+ * *gamma = 0 means r = 0 (nothing written to v1). */
+igm_status igm_line1(igm_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
+                     double *rho);
+
+/* Release all device and host memory of the system. NULL is a no-op. */
+void igm_destroy(igm_system *s);
+
+/* Static description of a status code. */
+const char *igm_status_str(igm_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGMRES_H */

@@ -1,0 +1,298 @@
+"""ctypes binding of the igmres C ABI (include/igmres.h).
+
+Argument marshalling only: every step of the solver runs inside
+``libigmres.so`` (HIP kernels for gfx950). The functions keep the C names;
+``System`` is a small convenience wrapper around one ``igm_system``. Device
+buffers are passed as integers or as objects with ``data_ptr()`` (for example
+torch CUDA tensors); PyTorch is never imported here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libigmres.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_SINGULAR_ROW, ERR_ZERO_PIVOT, ERR_OVERFLOW = -1, -2, -3, -4
+ERR_RANGE, ERR_OOM, ERR_DEVICE, ERR_BREAKDOWN, ERR_UNSUPPORTED = -5, -6, -7, -8, -9
+PRE_NONE, PRE_JACOBI, PRE_ILU0 = 0, 1, 2
+PRESET = {"paper_noprec": 0, "paper_ilu": 1, "jacobi": 2}
+NO_EVENT = (1 << 63) - 1
+
+_POLICY_INT_FIELDS = ("df", "alpha_a", "s_terms", "m", "precond", "b_dot", "b_axpy", "b_norm", "b_div_num",
+                      "b_div_den", "b_rot", "b_tmp", "b_cs_num", "b_cs_den", "max_refine")
+
+
+class Policy(C.Structure):
+    _fields_ = ([("struct_size", C.c_int32)] + [(f, C.c_int32) for f in _POLICY_INT_FIELDS]
+                + [("gtol", C.c_int64), ("tol", C.c_double), ("grid_blocks", C.c_int32),
+                   ("reserved_", C.c_int32 * 7)])
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f in _POLICY_INT_FIELDS}
+        d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks)
+        return d
+
+
+class Stats(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("status", C.c_int32), ("refinements", C.c_int32),
+                ("iterations", C.c_int32), ("first_ovf", C.c_int64), ("relres_orig", C.c_double),
+                ("relres_scaled", C.c_double), ("time_solve_ms", C.c_double), ("time_cycle_ms", C.c_double),
+                ("time_setup_ms", C.c_double), ("n", C.c_int64), ("nnz", C.c_int64), ("nterms", C.c_int32),
+                ("grid_blocks", C.c_int32), ("rows_per_thread", C.c_int32), ("block_threads", C.c_int32),
+                ("levels_fwd", C.c_int32), ("levels_bwd", C.c_int32), ("device_bytes", C.c_int64),
+                ("last_error_line", C.c_int32), ("reserved0_", C.c_int32), ("time_kernel_ms", C.c_double),
+                ("reserved_", C.c_int32 * 4)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if not f.endswith("_")}
+
+
+class CycleTrace(C.Structure):
+    _fields_ = [("m", C.c_int32), ("jstar", C.c_int32), ("breakdown", C.c_int32), ("steps", C.c_int32),
+                ("first_ovf", C.c_int64), ("H", C.c_void_p), ("c", C.c_void_p), ("s", C.c_void_p),
+                ("g", C.c_void_p), ("V", C.c_void_p)]
+
+
+class IgmError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+_SIGS = {
+    "igm_policy_preset": [C.c_int32, C.c_void_p],
+    "igm_create_system": [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_set_policy": [C.c_void_p, C.c_void_p],
+    "igm_set_rhs": [C.c_void_p, C.c_void_p],
+    "igm_set_stream": [C.c_void_p, C.c_void_p],
+    "igm_solve": [C.c_void_p, C.c_void_p],
+    "igm_solve_device": [C.c_void_p, C.c_void_p],
+    "igm_get_stats": [C.c_void_p, C.c_void_p],
+    "igm_get_history": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                        C.c_void_p],
+    "igm_int_cycle": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_spmv": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_precond": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_dot": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_axpy": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_norm": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_normalize": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
+    "igm_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_fp_norm": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
+    "igm_line1": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_destroy": [C.c_void_p],
+    "igm_status_str": [C.c_int],
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libigmres.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2009_07495_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.igm_destroy.restype = None
+        L.igm_status_str.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take a device pointer of {type(x)}")
+
+
+def _check(st: int, where: str, ok=(OK,)):
+    if st not in ok:
+        raise IgmError(st, where)
+    return st
+
+
+def status_str(st: int) -> str:
+    return lib().igm_status_str(st).decode()
+
+
+igm_status_str = status_str
+
+
+def igm_policy_preset(preset) -> Policy:
+    p = Policy()
+    code = PRESET[preset] if isinstance(preset, str) else int(preset)
+    _check(lib().igm_policy_preset(code, C.byref(p)), "igm_policy_preset")
+    return p
+
+
+def make_policy(preset: str = "paper_noprec", **overrides) -> Policy:
+    p = igm_policy_preset(preset)
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _policy_struct(pol) -> Policy:
+    if isinstance(pol, Policy):
+        return pol
+    p = igm_policy_preset(0)
+    for k, v in dict(pol).items():
+        if k == "pad_":
+            continue
+        setattr(p, k, v)
+    return p
+
+
+def igm_create_system(n, row_ptr, col, val, b, pol):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    vl = np.ascontiguousarray(val, dtype=np.float64)
+    bb = np.ascontiguousarray(b, dtype=np.float64)
+    h = C.c_void_p()
+    ps = _policy_struct(pol)
+    st = lib().igm_create_system(int(n), rp.ctypes.data, cl.ctypes.data, vl.ctypes.data, bb.ctypes.data,
+                                 C.addressof(ps), C.byref(h))
+    return st, h
+
+
+class System:
+    """One igm_system (owned; destroyed with the object)."""
+
+    def __init__(self, n, row_ptr, col, val, b, pol="paper_noprec", **overrides):
+        if isinstance(pol, str):
+            pol = make_policy(pol, **overrides)
+        st, h = igm_create_system(n, row_ptr, col, val, b, pol)
+        _check(st, "igm_create_system")
+        self.h = h
+        self.n = int(n)
+        self.pol = _policy_struct(pol)
+
+    @classmethod
+    def from_system(cls, sysm, pol="paper_noprec", **overrides):
+        return cls(sysm.n, sysm.row_ptr, sysm.col, sysm.val, sysm.b, pol, **overrides)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().igm_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def set_policy(self, pol):
+        ps = _policy_struct(pol)
+        _check(lib().igm_set_policy(self.h, C.addressof(ps)), "igm_set_policy")
+        self.pol = ps
+
+    def set_rhs(self, b):
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        _check(lib().igm_set_rhs(self.h, bb.ctypes.data), "igm_set_rhs")
+
+    def set_stream(self, stream):
+        handle = getattr(stream, "cuda_stream", stream)
+        _check(lib().igm_set_stream(self.h, C.c_void_p(handle or 0)), "igm_set_stream")
+
+    def solve(self, x0=None):
+        """Host solve: returns (x, status)."""
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        st = lib().igm_solve(self.h, x.ctypes.data)
+        if st == ERR_DEVICE:
+            raise IgmError(st, "igm_solve")
+        return x, st
+
+    def solve_device(self, x_dev) -> int:
+        st = lib().igm_solve_device(self.h, _ptr(x_dev))
+        if st == ERR_DEVICE:
+            raise IgmError(st, "igm_solve_device")
+        return st
+
+    def stats(self) -> dict:
+        s = Stats()
+        s.struct_size = C.sizeof(Stats)
+        _check(lib().igm_get_stats(self.h, C.byref(s)), "igm_get_stats")
+        return s.as_dict()
+
+    def history(self, cap: int = 4096) -> dict:
+        ro, rs, g, rho = (np.zeros(cap) for _ in range(4))
+        js = np.zeros(cap, dtype=np.int32)
+        cnt = C.c_int32(0)
+        _check(lib().igm_get_history(self.h, cap, ro.ctypes.data, rs.ctypes.data, g.ctypes.data, rho.ctypes.data,
+                                     js.ctypes.data, C.byref(cnt)), "igm_get_history")
+        k = cnt.value
+        return dict(relres_orig=ro[:k], relres_scaled=rs[:k], gamma=g[:k], rho=rho[:k], jstar=js[:k])
+
+    def int_cycle(self, v1, with_basis: bool = True) -> dict:
+        m = self.pol.m
+        v1 = np.ascontiguousarray(v1, dtype=np.int64)
+        H = np.zeros((m + 1) * m, dtype=np.int64)
+        c, s = np.zeros(m, dtype=np.int64), np.zeros(m, dtype=np.int64)
+        g = np.zeros(m + 1, dtype=np.int64)
+        V = np.zeros((m + 1) * self.n, dtype=np.int64) if with_basis else None
+        t = CycleTrace(m, 0, 0, 0, 0, H.ctypes.data, c.ctypes.data, s.ctypes.data, g.ctypes.data,
+                       V.ctypes.data if V is not None else None)
+        _check(lib().igm_int_cycle(self.h, v1.ctypes.data, C.byref(t)), "igm_int_cycle")
+        return dict(m=m, jstar=t.jstar, breakdown=t.breakdown, steps=t.steps, first_ovf=t.first_ovf,
+                    H=H.reshape(m + 1, m), c=c, s=s, g=g, V=None if V is None else V.reshape(m + 1, self.n))
+
+    # kernel-level entry points (device buffers)
+    def spmv(self, v, z, nterms=None) -> int:
+        ev = C.c_int64(0)
+        nt = self.pol.s_terms + 1 if nterms is None else nterms
+        _check(lib().igm_spmv(self.h, nt, _ptr(v), _ptr(z), C.byref(ev)), "igm_spmv")
+        return ev.value
+
+    def precond(self, z, w) -> int:
+        ev = C.c_int64(0)
+        _check(lib().igm_precond(self.h, _ptr(z), _ptr(w), C.byref(ev)), "igm_precond")
+        return ev.value
+
+    def dot(self, w, v):
+        h, ev = C.c_int64(0), C.c_int64(0)
+        _check(lib().igm_dot(self.h, _ptr(w), _ptr(v), C.byref(h), C.byref(ev)), "igm_dot")
+        return h.value, ev.value
+
+    def axpy(self, h: int, w, v) -> int:
+        ev = C.c_int64(0)
+        _check(lib().igm_axpy(self.h, int(h), _ptr(w), _ptr(v), C.byref(ev)), "igm_axpy")
+        return ev.value
+
+    def norm(self, w):
+        h, ev = C.c_int64(0), C.c_int64(0)
+        _check(lib().igm_norm(self.h, _ptr(w), C.byref(h), C.byref(ev)), "igm_norm")
+        return h.value, ev.value
+
+    def normalize(self, w, h: int, v) -> int:
+        ev = C.c_int64(0)
+        _check(lib().igm_normalize(self.h, _ptr(w), int(h), _ptr(v), C.byref(ev)), "igm_normalize")
+        return ev.value
+
+    def residual(self, x, r, rhat):
+        _check(lib().igm_residual(self.h, _ptr(x), _ptr(r), _ptr(rhat)), "igm_residual")
+
+    def fp_norm(self, x, length=None) -> float:
+        out = C.c_double(0)
+        ln = self.n if length is None else length
+        _check(lib().igm_fp_norm(self.h, _ptr(x), ln, C.byref(out)), "igm_fp_norm")
+        return out.value
+
+    def line1(self, r, bk, r0, v1):
+        g, rho = C.c_double(0), C.c_double(0)
+        st = lib().igm_line1(self.h, _ptr(r), _ptr(bk), _ptr(r0), _ptr(v1), C.byref(g), C.byref(rho))
+        _check(st, "igm_line1", ok=(OK, ERR_RANGE))
+        return st, g.value, rho.value

@@ -1,0 +1,654 @@
+// C ABI of the igmres library: system setup and upload, the FP64 refinement
+// driver of Fig. 1 around the persistent int-GMRES kernel, statistics, and
+// the kernel-level entry points.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+
+#include "igm_launch.hpp"
+
+using namespace igm;
+
+namespace {
+
+#define IGM_HIP(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) {                            \
+      if (s) s->last_error_line = __LINE__;            \
+      return IGM_ERR_DEVICE;                           \
+    }                                                  \
+  } while (0)
+
+#define IGM_TRY(call)                  \
+  do {                                 \
+    igm_status st_ = (call);           \
+    if (st_ != IGM_OK) return st_;     \
+  } while (0)
+
+template <class T>
+igm_status dalloc(igm_system *s, T *&p, size_t count) {
+  size_t bytes = sizeof(T) * (count ? count : 1);
+  void *q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) return IGM_ERR_OOM;
+  if (hipMemset(q, 0, bytes) != hipSuccess) { (void)hipFree(q); return IGM_ERR_DEVICE; }
+  s->bufs.push_back({q, bytes});
+  s->device_bytes += (int64_t)bytes;
+  p = (T *)q;
+  return IGM_OK;
+}
+
+template <class T>
+igm_status upload(igm_system *s, T *&p, const std::vector<T> &v) {
+  IGM_TRY(dalloc(s, p, v.size()));
+  if (!v.empty()) IGM_HIP(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return IGM_OK;
+}
+
+void free_device(igm_system *s) {
+  for (auto &b : s->bufs) (void)hipFree(b.p);
+  s->bufs.clear();
+  s->device_bytes = 0;
+  if (s->h_pinned) { (void)hipHostFree(s->h_pinned); s->h_pinned = nullptr; }
+}
+
+igm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b) {
+  if (n < 1 || n >= ((int64_t)1 << 31) || !rp || !col || !val || !b) return IGM_ERR_ARG;
+  if (rp[0] != 0) return IGM_ERR_ARG;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return IGM_ERR_ARG;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= n) return IGM_ERR_ARG;
+      if (e > rp[i] && col[e] <= col[e - 1]) return IGM_ERR_ARG;
+      if (!isfinite(val[e])) return IGM_ERR_ARG;
+    }
+    if (!isfinite(b[i])) return IGM_ERR_ARG;
+  }
+  return IGM_OK;
+}
+
+CycleArgs make_args(igm_system *s) {
+  CycleArgs a;
+  memset(&a, 0, sizeof(a));
+  const igm_policy &p = s->pol;
+  a.n = s->n;
+  a.npad = s->npad;
+  a.m = p.m;
+  a.df = p.df;
+  a.nterms = std::min(p.s_terms + 1, s->hs.nterms);
+  a.precond = p.precond;
+  a.b_dot = p.b_dot; a.b_axpy = p.b_axpy; a.b_norm = p.b_norm;
+  a.b_div_num = p.b_div_num; a.b_div_den = p.b_div_den; a.b_rot = p.b_rot; a.b_tmp = p.b_tmp;
+  a.b_cs_num = p.b_cs_num; a.b_cs_den = p.b_cs_den;
+  a.gtol = p.gtol;
+  a.sell_off = s->d_sell_off;
+  a.sell_w = s->d_sell_w;
+  a.sell_col = s->d_sell_col;
+  for (int l = 0; l < kMaxTerms; ++l) {
+    a.sell_val[l] = s->d_sell_val[l];
+    a.alpha[l] = s->hs.alpha[l];
+  }
+  a.ldiag = s->d_ldiag; a.udiag = s->d_udiag;
+  a.lptr = s->d_lptr; a.uptr = s->d_uptr; a.lcol = s->d_lcol; a.ucol = s->d_ucol;
+  a.lval = s->d_lval; a.uval = s->d_uval;
+  a.flev_ptr = s->d_flev_ptr; a.flev_rows = s->d_flev_rows;
+  a.blev_ptr = s->d_blev_ptr; a.blev_rows = s->d_blev_rows;
+  a.nflev = s->hs.flev_ptr.empty() ? 0 : (int32_t)s->hs.flev_ptr.size() - 1;
+  a.nblev = s->hs.blev_ptr.empty() ? 0 : (int32_t)s->hs.blev_ptr.size() - 1;
+  a.flev_host = s->hs.flev_ptr.data();
+  a.blev_host = s->hs.blev_ptr.data();
+  a.V = s->d_V;
+  a.zbuf = s->d_z;
+  a.wbuf = s->d_w;
+  a.H = s->d_H; a.c = s->d_c; a.s = s->d_s; a.g = s->d_g;
+  a.state = s->d_state;
+  a.sync = s->d_sync;
+  a.sync_cap = s->sync_cap;
+  a.update = 0;
+  a.x = nullptr;
+  a.scal = s->d_scal;
+  return a;
+}
+
+// Choose rows per thread R and the number of workgroups G of the cycle
+// kernel: the smallest R for which ceil(n / (BLOCK R)) workgroups fit both
+// the target and the co-resident limit.
+igm_status choose_launch(igm_system *s) {
+  hipDeviceProp_t prop;
+  IGM_HIP(hipGetDeviceProperties(&prop, s->device));
+  int target = s->pol.grid_blocks > 0 ? s->pol.grid_blocks : 256;
+  target = std::min(target, 1023);
+  const size_t smem = cycle_smem_bytes(s->pol.m);
+  for (int R : {1, 2, 4, 8, 16}) {
+    int nb = 0;
+    IGM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cycle_kernel(R, s->pol.precond), kCycleBlock, smem));
+    const int64_t cap = std::min<int64_t>((int64_t)nb * prop.multiProcessorCount, target);
+    const int64_t G = (s->n + (int64_t)kCycleBlock * R - 1) / ((int64_t)kCycleBlock * R);
+    if (G <= cap) {
+      s->grid = (int)G;
+      s->rows_per_thread = R;
+      s->max_coresident = nb * prop.multiProcessorCount;
+      return IGM_OK;
+    }
+  }
+  return IGM_ERR_UNSUPPORTED;
+}
+
+igm_status alloc_work(igm_system *s) {
+  const int m = s->pol.m;
+  const int64_t np = s->npad;
+  int64_t extra = 2;
+  if (s->pol.precond == IGM_PRE_ILU0)
+    extra += 1 + (int64_t)(s->hs.flev_ptr.size() - 1) + (int64_t)(s->hs.blev_ptr.size() - 1);
+  const int64_t cap = (int64_t)m * (m + 1) / 2 + (int64_t)m * extra + 16;
+  if (cap > (int64_t)1 << 30) return IGM_ERR_UNSUPPORTED;
+  s->sync_cap = (int32_t)cap;
+  IGM_TRY(dalloc(s, s->d_V, (size_t)(m + 1) * np));
+  IGM_TRY(dalloc(s, s->d_z, np));
+  IGM_TRY(dalloc(s, s->d_w, np));
+  IGM_TRY(dalloc(s, s->d_r, np));
+  IGM_TRY(dalloc(s, s->d_rhat, np));
+  IGM_TRY(dalloc(s, s->d_bk, np));
+  IGM_TRY(dalloc(s, s->d_r0, np));
+  IGM_TRY(dalloc(s, s->d_x, np));
+  IGM_TRY(dalloc(s, s->d_H, (size_t)(m + 1) * m));
+  IGM_TRY(dalloc(s, s->d_c, m));
+  IGM_TRY(dalloc(s, s->d_s, m));
+  IGM_TRY(dalloc(s, s->d_g, m + 1));
+  IGM_TRY(dalloc(s, s->d_state, 1));
+  IGM_TRY(dalloc(s, s->d_sync, (size_t)2 * kSyncGroups * cap));
+  IGM_TRY(dalloc(s, s->d_red, kRedWords));
+  IGM_TRY(dalloc(s, s->d_scal, kScalWords));
+  IGM_TRY(dalloc(s, s->d_parts, 4096));
+  if (hipHostMalloc((void **)&s->h_pinned, 64 * sizeof(double)) != hipSuccess) return IGM_ERR_OOM;
+  return IGM_OK;
+}
+
+igm_status device_norm(igm_system *s, const double *x, int64_t len, double *out_dev) {
+  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+  IGM_HIP(launch_absmax(s->stream, len, x, s->d_red + kRedMuX));
+  IGM_HIP(launch_dnrm_sum(s->stream, len, x, s->d_red + kRedMuX, s->d_red + kRedSumX));
+  IGM_HIP(launch_fin_norm(s->stream, s->d_red, out_dev));
+  return IGM_OK;
+}
+
+// Everything that depends on the policy or the right-hand side.
+igm_status build(igm_system *s) {
+  free_device(s);
+  IGM_TRY(host_setup(s->n, s->row_ptr, s->col, s->ahat, s->bhat, s->pol, s->hs));
+  HostSetup &h = s->hs;
+  s->npad = (s->n + kSlice - 1) / kSlice * kSlice;
+  IGM_TRY(upload(s, s->d_row_ptr, s->row_ptr));
+  IGM_TRY(upload(s, s->d_col, s->col));
+  IGM_TRY(upload(s, s->d_a, h.a));
+  IGM_TRY(upload(s, s->d_ahat, s->ahat));
+  IGM_TRY(upload(s, s->d_b, h.b));
+  IGM_TRY(upload(s, s->d_bhat, s->bhat));
+  IGM_TRY(upload(s, s->d_sell_off, h.sell_off));
+  IGM_TRY(upload(s, s->d_sell_w, h.sell_w));
+  IGM_TRY(upload(s, s->d_sell_col, h.sell_col));
+  for (int l = 0; l < kMaxTerms; ++l) s->d_sell_val[l] = nullptr;
+  for (int l = 0; l < h.nterms; ++l) IGM_TRY(upload(s, s->d_sell_val[l], h.sell_val[l]));
+  if (s->pol.precond != IGM_PRE_NONE) {
+    IGM_TRY(upload(s, s->d_ldiag, h.ldiag));
+    IGM_TRY(upload(s, s->d_udiag, h.udiag));
+    IGM_TRY(upload(s, s->d_lptr, h.lptr));
+    IGM_TRY(upload(s, s->d_uptr, h.uptr));
+    IGM_TRY(upload(s, s->d_lcol, h.lcol));
+    IGM_TRY(upload(s, s->d_ucol, h.ucol));
+    IGM_TRY(upload(s, s->d_lval, h.lval));
+    IGM_TRY(upload(s, s->d_uval, h.uval));
+    std::vector<double> lf(h.lval.begin(), h.lval.end()), uf(h.uval.begin(), h.uval.end());
+    IGM_TRY(upload(s, s->d_lvalf, lf));
+    IGM_TRY(upload(s, s->d_uvalf, uf));
+    IGM_TRY(upload(s, s->d_flev_ptr, h.flev_ptr));
+    IGM_TRY(upload(s, s->d_flev_rows, h.flev_rows));
+    IGM_TRY(upload(s, s->d_blev_ptr, h.blev_ptr));
+    IGM_TRY(upload(s, s->d_blev_rows, h.blev_rows));
+  } else {
+    s->d_ldiag = s->d_udiag = s->d_lptr = s->d_uptr = s->d_lval = s->d_uval = nullptr;
+    s->d_lcol = s->d_ucol = nullptr;
+    s->d_lvalf = s->d_uvalf = nullptr;
+    s->d_flev_ptr = s->d_flev_rows = s->d_blev_ptr = s->d_blev_rows = nullptr;
+    h.flev_ptr.clear();
+    h.blev_ptr.clear();
+  }
+  IGM_TRY(alloc_work(s));
+  IGM_TRY(choose_launch(s));
+  // norms of the scaled and original right-hand sides (denominators of relres)
+  IGM_TRY(device_norm(s, s->d_b, s->n, s->d_scal + kScalNormB));
+  IGM_TRY(device_norm(s, s->d_bhat, s->n, s->d_scal + kScalNormBhat));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  return IGM_OK;
+}
+
+igm_status launch_cycle(igm_system *s, const CycleArgs &a) {
+  const void *k = cycle_kernel(s->rows_per_thread, s->pol.precond);
+  void *args[] = {(void *)&a};
+  IGM_HIP(hipLaunchCooperativeKernel(k, dim3(s->grid), dim3(kCycleBlock), args, cycle_smem_bytes(s->pol.m),
+                                     s->stream));
+  return IGM_OK;
+}
+
+igm_status prepare_cycle(igm_system *s) {
+  IGM_HIP(hipMemsetAsync(s->d_sync, 0, sizeof(unsigned long long) * 2 * kSyncGroups * (size_t)s->sync_cap,
+                         s->stream));
+  CycleState init;
+  memset(&init, 0, sizeof(init));
+  init.first_ovf = kNoEvent;
+  IGM_HIP(hipMemcpyAsync(s->d_state, &init, sizeof(init), hipMemcpyHostToDevice, s->stream));
+  return IGM_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Fig. 1 on the device; x is a device vector of n doubles.
+igm_status solve_dev(igm_system *s, double *x) {
+  auto t0 = std::chrono::steady_clock::now();
+  const igm_policy &p = s->pol;
+  s->hist_ro.clear(); s->hist_rs.clear(); s->hist_gamma.clear(); s->hist_rho.clear(); s->hist_jstar.clear();
+  igm_stats &st = s->stats;
+  st.refinements = 0;
+  st.iterations = 0;
+  st.first_ovf = kNoEvent;
+  st.time_cycle_ms = 0.0;
+  igm_status status = IGM_NOT_CONVERGED;
+  CycleArgs a = make_args(s);
+  a.update = 1;
+  a.x = x;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  IGM_HIP(hipEventCreate(&e0));
+  IGM_HIP(hipEventCreate(&e1));
+  double *hp = s->h_pinned;
+  for (int k = 0;; ++k) {
+    // top of refinement k+1: residuals, relres, gamma
+    IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+    IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
+                            s->d_r, s->d_rhat, s->d_red));
+    IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_r, s->d_red + kRedMuR, s->d_red + kRedSumR));
+    IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_rhat, s->d_red + kRedMuRhat, s->d_red + kRedSumRhat));
+    IGM_HIP(launch_fin_residual(s->stream, s->d_red, s->d_scal + kScalNormB, s->d_scal));
+    IGM_HIP(hipMemcpyAsync(hp, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
+    IGM_HIP(hipStreamSynchronize(s->stream));
+    const double gamma = hp[kScalGamma], ro = hp[kScalRelresOrig], rs = hp[kScalRelresScaled];
+    s->hist_ro.push_back(ro);
+    s->hist_rs.push_back(rs);
+    st.relres_orig = ro;
+    st.relres_scaled = rs;
+    if (!isfinite(ro)) { status = IGM_ERR_RANGE; break; }
+    if (ro < p.tol) { status = IGM_OK; break; }
+    if (k >= p.max_refine) { status = IGM_NOT_CONVERGED; break; }
+    s->hist_gamma.push_back(gamma);
+    if (gamma == 0.0) { s->hist_rho.push_back(0.0); status = IGM_OK; break; }
+    // lines 1'-2, then the int-GMRES call with the fused update
+    IGM_TRY(prepare_cycle(s));
+    IGM_HIP(launch_line1(s->stream, a, s->d_r, s->d_scal, s->d_lvalf, s->d_uvalf, s->d_bk, s->d_r0, s->d_red));
+    IGM_HIP(hipEventRecord(e0, s->stream));
+    IGM_TRY(launch_cycle(s, a));
+    IGM_HIP(hipEventRecord(e1, s->stream));
+    CycleState cs;
+    IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
+    IGM_HIP(hipMemcpyAsync(hp, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
+    IGM_HIP(hipStreamSynchronize(s->stream));
+    float ms = 0.f;
+    IGM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    st.time_cycle_ms += ms;
+    s->hist_rho.push_back(hp[kScalRho]);
+    if (cs.range_err) { status = IGM_ERR_RANGE; break; }
+    if (cs.timeout) { status = IGM_ERR_DEVICE; s->last_error_line = __LINE__; break; }
+    st.refinements += 1;
+    st.iterations += cs.steps;
+    s->hist_jstar.push_back(cs.jstar);
+    if (cs.first_ovf != kNoEvent) { st.first_ovf = cs.first_ovf; status = IGM_ERR_OVERFLOW; break; }
+    if (cs.jstar == 0) { status = IGM_ERR_BREAKDOWN; break; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st.status = status;
+  st.time_solve_ms = ms_since(t0);
+  return status;
+}
+
+void fill_stats_static(igm_system *s) {
+  igm_stats &st = s->stats;
+  st.struct_size = sizeof(igm_stats);
+  st.n = s->n;
+  st.nnz = s->nnz;
+  st.nterms = s->hs.nterms;
+  st.grid_blocks = s->grid;
+  st.rows_per_thread = s->rows_per_thread;
+  st.block_threads = kCycleBlock;
+  st.levels_fwd = s->hs.flev_ptr.empty() ? 0 : (int32_t)s->hs.flev_ptr.size() - 1;
+  st.levels_bwd = s->hs.blev_ptr.empty() ? 0 : (int32_t)s->hs.blev_ptr.size() - 1;
+  st.device_bytes = s->device_bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+igm_status igm_policy_preset(int32_t preset, igm_policy *out) {
+  if (!out) return IGM_ERR_ARG;
+  igm_policy p;
+  memset(&p, 0, sizeof(p));
+  p.struct_size = sizeof(igm_policy);
+  p.df = 30;
+  p.s_terms = 0;
+  p.m = 30;
+  p.max_refine = 2000;
+  p.gtol = -1;
+  p.tol = 1e-10;
+  p.grid_blocks = 0;
+  switch (preset) {
+    case IGM_PRESET_PAPER_NOPREC:  // Sec. VII-B, Table IV
+      p.alpha_a = 16; p.precond = IGM_PRE_NONE;
+      p.b_dot = 16; p.b_axpy = 16; p.b_norm = 16; p.b_div_num = 16; p.b_div_den = 14;
+      p.b_rot = 16; p.b_tmp = 16; p.b_cs_num = 16; p.b_cs_den = 14;
+      break;
+    case IGM_PRESET_PAPER_ILU:  // Sec. VII-C, Table VI
+    case IGM_PRESET_JACOBI:     // the ILU construction on the diagonal only
+      p.alpha_a = 32; p.precond = preset == IGM_PRESET_PAPER_ILU ? IGM_PRE_ILU0 : IGM_PRE_JACOBI;
+      p.b_dot = 0; p.b_axpy = 0; p.b_norm = 0; p.b_div_num = 30; p.b_div_den = 0;
+      p.b_rot = 0; p.b_tmp = 0; p.b_cs_num = 30; p.b_cs_den = 0;
+      break;
+    default:
+      return IGM_ERR_ARG;
+  }
+  *out = p;
+  return IGM_OK;
+}
+
+igm_status igm_create_system(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                             const double *b, const igm_policy *pol, igm_system **out) {
+  if (!out) return IGM_ERR_ARG;
+  *out = nullptr;
+  if (!pol || pol->struct_size != (int32_t)sizeof(igm_policy)) return IGM_ERR_ARG;
+  IGM_TRY(check_policy(*pol));
+  IGM_TRY(validate_csr(n, row_ptr, col, val, b));
+  auto t0 = std::chrono::steady_clock::now();
+  igm_system *s = new (std::nothrow) igm_system();
+  if (!s) return IGM_ERR_OOM;
+  if (hipGetDevice(&s->device) != hipSuccess) { delete s; return IGM_ERR_DEVICE; }
+  s->pol = *pol;
+  s->n = n;
+  s->nnz = row_ptr[n];
+  s->row_ptr.assign(row_ptr, row_ptr + n + 1);
+  s->col.assign(col, col + s->nnz);
+  s->ahat.assign(val, val + s->nnz);
+  s->bhat.assign(b, b + n);
+  igm_status st = build(s);
+  if (st != IGM_OK) {
+    free_device(s);
+    delete s;
+    return st;
+  }
+  s->stats.time_setup_ms = ms_since(t0);
+  fill_stats_static(s);
+  *out = s;
+  return IGM_OK;
+}
+
+igm_status igm_set_policy(igm_system *s, const igm_policy *pol) {
+  if (!s || !pol || pol->struct_size != (int32_t)sizeof(igm_policy)) return IGM_ERR_ARG;
+  IGM_TRY(check_policy(*pol));
+  auto t0 = std::chrono::steady_clock::now();
+  igm_policy old = s->pol;
+  s->pol = *pol;
+  igm_status st = build(s);
+  if (st != IGM_OK) {
+    s->pol = old;
+    igm_status st2 = build(s);
+    (void)st2;
+    fill_stats_static(s);
+    return st;
+  }
+  s->stats.time_setup_ms = ms_since(t0);
+  fill_stats_static(s);
+  return IGM_OK;
+}
+
+igm_status igm_set_rhs(igm_system *s, const double *b) {
+  if (!s || !b) return IGM_ERR_ARG;
+  for (int64_t i = 0; i < s->n; ++i)
+    if (!isfinite(b[i])) return IGM_ERR_ARG;
+  s->bhat.assign(b, b + s->n);
+  for (int64_t i = 0; i < s->n; ++i) s->hs.b[i] = s->bhat[i] / s->hs.dhat[i];  // eq. (eq1)
+  IGM_HIP(hipMemcpy(s->d_bhat, s->bhat.data(), sizeof(double) * s->n, hipMemcpyHostToDevice));
+  IGM_HIP(hipMemcpy(s->d_b, s->hs.b.data(), sizeof(double) * s->n, hipMemcpyHostToDevice));
+  IGM_TRY(device_norm(s, s->d_b, s->n, s->d_scal + kScalNormB));
+  IGM_TRY(device_norm(s, s->d_bhat, s->n, s->d_scal + kScalNormBhat));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  return IGM_OK;
+}
+
+igm_status igm_set_stream(igm_system *s, void *hip_stream) {
+  if (!s) return IGM_ERR_ARG;
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  s->stream = (hipStream_t)hip_stream;
+  return IGM_OK;
+}
+
+igm_status igm_solve_device(igm_system *s, double *x_dev) {
+  if (!s || !x_dev) return IGM_ERR_ARG;
+  return solve_dev(s, x_dev);
+}
+
+igm_status igm_solve(igm_system *s, double *x) {
+  if (!s || !x) return IGM_ERR_ARG;
+  IGM_HIP(hipMemcpyAsync(s->d_x, x, sizeof(double) * s->n, hipMemcpyHostToDevice, s->stream));
+  igm_status st = solve_dev(s, s->d_x);
+  if (st == IGM_ERR_DEVICE) return st;
+  IGM_HIP(hipMemcpyAsync(x, s->d_x, sizeof(double) * s->n, hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  return st;
+}
+
+igm_status igm_get_stats(const igm_system *s, igm_stats *out) {
+  if (!s || !out) return IGM_ERR_ARG;
+  *out = s->stats;
+  out->struct_size = sizeof(igm_stats);
+  out->last_error_line = s->last_error_line;
+  return IGM_OK;
+}
+
+igm_status igm_get_history(const igm_system *s, int32_t cap, double *relres_orig, double *relres_scaled,
+                           double *gamma, double *rho, int32_t *jstar, int32_t *count) {
+  if (!s || cap < 0) return IGM_ERR_ARG;
+  int32_t k = std::min<int32_t>(cap, (int32_t)s->hist_ro.size());
+  for (int32_t i = 0; i < k; ++i) {
+    if (relres_orig) relres_orig[i] = s->hist_ro[i];
+    if (relres_scaled) relres_scaled[i] = s->hist_rs[i];
+    if (gamma) gamma[i] = i < (int32_t)s->hist_gamma.size() ? s->hist_gamma[i] : NAN;
+    if (rho) rho[i] = i < (int32_t)s->hist_rho.size() ? s->hist_rho[i] : NAN;
+    if (jstar) jstar[i] = i < (int32_t)s->hist_jstar.size() ? s->hist_jstar[i] : -1;
+  }
+  if (count) *count = k;
+  return IGM_OK;
+}
+
+igm_status igm_int_cycle(igm_system *s, const int64_t *v1, igm_cycle_trace *t) {
+  if (!s || !v1 || !t || t->m != s->pol.m || !t->H || !t->c || !t->s || !t->g) return IGM_ERR_ARG;
+  const int m = s->pol.m;
+  IGM_HIP(hipMemsetAsync(s->d_V, 0, sizeof(int64_t) * (size_t)(m + 1) * s->npad, s->stream));
+  IGM_HIP(hipMemsetAsync(s->d_H, 0, sizeof(int64_t) * (size_t)(m + 1) * m, s->stream));
+  IGM_HIP(hipMemsetAsync(s->d_c, 0, sizeof(int64_t) * m, s->stream));
+  IGM_HIP(hipMemsetAsync(s->d_s, 0, sizeof(int64_t) * m, s->stream));
+  IGM_HIP(hipMemsetAsync(s->d_g, 0, sizeof(int64_t) * (m + 1), s->stream));
+  IGM_HIP(hipMemcpyAsync(s->d_V, v1, sizeof(int64_t) * s->n, hipMemcpyHostToDevice, s->stream));
+  IGM_TRY(prepare_cycle(s));
+  CycleArgs a = make_args(s);
+  IGM_TRY(launch_cycle(s, a));
+  CycleState cs;
+  IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipMemcpyAsync(t->H, s->d_H, sizeof(int64_t) * (size_t)(m + 1) * m, hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipMemcpyAsync(t->c, s->d_c, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipMemcpyAsync(t->s, s->d_s, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipMemcpyAsync(t->g, s->d_g, sizeof(int64_t) * (m + 1), hipMemcpyDeviceToHost, s->stream));
+  if (t->V)
+    for (int j = 0; j <= m; ++j)
+      IGM_HIP(hipMemcpyAsync(t->V + (size_t)j * s->n, s->d_V + (size_t)j * s->npad, sizeof(int64_t) * s->n,
+                             hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  if (cs.timeout) { s->last_error_line = __LINE__; return IGM_ERR_DEVICE; }
+  t->jstar = cs.jstar;
+  t->breakdown = cs.breakdown;
+  t->steps = cs.steps;
+  t->first_ovf = cs.first_ovf;
+  return IGM_OK;
+}
+
+// ---- kernel-level entry points ---------------------------------------------
+
+// Kernel-level calls: reset the overflow record, record an event pair around
+// the kernels themselves, then read back the event code and the duration.
+static igm_status reset_state(igm_system *s) {
+  IGM_TRY(prepare_cycle(s));
+  if (!s->ev0) {
+    IGM_HIP(hipEventCreate(&s->ev0));
+    IGM_HIP(hipEventCreate(&s->ev1));
+  }
+  IGM_HIP(hipEventRecord(s->ev0, s->stream));
+  return IGM_OK;
+}
+
+static igm_status read_event(igm_system *s, int64_t *first_ovf) {
+  IGM_HIP(hipEventRecord(s->ev1, s->stream));
+  CycleState cs;
+  IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  float ms = 0.f;
+  IGM_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+  s->stats.time_kernel_ms = ms;
+  if (first_ovf) *first_ovf = cs.first_ovf;
+  return IGM_OK;
+}
+
+igm_status igm_spmv(igm_system *s, int32_t nterms, const int64_t *v, int64_t *z, int64_t *first_ovf) {
+  if (!s || !v || !z) return IGM_ERR_ARG;
+  IGM_TRY(reset_state(s));
+  CycleArgs a = make_args(s);
+  int nt = std::max(1, std::min<int>(nterms, s->hs.nterms));
+  IGM_HIP(launch_spmv(s->stream, a, nt, v, z));
+  return read_event(s, first_ovf);
+}
+
+igm_status igm_precond(igm_system *s, const int64_t *z, int64_t *w, int64_t *first_ovf) {
+  if (!s || !z || !w) return IGM_ERR_ARG;
+  IGM_TRY(reset_state(s));
+  CycleArgs a = make_args(s);
+  IGM_HIP(launch_precond(s->stream, a, z, w));
+  return read_event(s, first_ovf);
+}
+
+igm_status igm_dot(igm_system *s, const int64_t *w, const int64_t *v, int64_t *h, int64_t *first_ovf) {
+  if (!s || !w || !v || !h) return IGM_ERR_ARG;
+  IGM_TRY(reset_state(s));
+  int64_t *d_out = (int64_t *)(s->d_scal + kScalOut);
+  IGM_HIP(launch_reduce(s->stream, s->n, w, v, s->pol.b_dot, s->pol.df, 0, s->d_parts, d_out, s->d_state,
+                        ((int64_t)1 << 24) | (3 << 16)));
+  IGM_TRY(read_event(s, first_ovf));
+  IGM_HIP(hipMemcpy(h, d_out, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return IGM_OK;
+}
+
+igm_status igm_axpy(igm_system *s, int64_t h, int64_t *w, const int64_t *v, int64_t *first_ovf) {
+  if (!s || !w || !v) return IGM_ERR_ARG;
+  IGM_TRY(reset_state(s));
+  IGM_HIP(launch_axpy(s->stream, s->n, h, s->pol.b_axpy, s->pol.df, w, v, s->d_state));
+  return read_event(s, first_ovf);
+}
+
+igm_status igm_norm(igm_system *s, const int64_t *w, int64_t *h, int64_t *first_ovf) {
+  if (!s || !w || !h) return IGM_ERR_ARG;
+  IGM_TRY(reset_state(s));
+  int64_t *d_out = (int64_t *)(s->d_scal + kScalOut);
+  IGM_HIP(launch_reduce(s->stream, s->n, w, w, s->pol.b_norm, s->pol.df, 1, s->d_parts, d_out, s->d_state,
+                        ((int64_t)1 << 24) | (4 << 16)));
+  IGM_TRY(read_event(s, first_ovf));
+  IGM_HIP(hipMemcpy(h, d_out, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return IGM_OK;
+}
+
+igm_status igm_normalize(igm_system *s, const int64_t *w, int64_t h, int64_t *v, int64_t *first_ovf) {
+  if (!s || !w || !v) return IGM_ERR_ARG;
+  const int64_t den = h >> s->pol.b_div_den;
+  if (den == 0) return IGM_ERR_BREAKDOWN;
+  IGM_TRY(reset_state(s));
+  IGM_HIP(launch_normalize(s->stream, s->n, w, den, s->pol.b_div_num,
+                           s->pol.df - s->pol.b_div_num - s->pol.b_div_den, v, s->d_state));
+  return read_event(s, first_ovf);
+}
+
+igm_status igm_residual(igm_system *s, const double *x, double *r, double *rhat) {
+  if (!s || !x || !r || !rhat) return IGM_ERR_ARG;
+  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+  IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x, r, rhat,
+                          s->d_red));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  return IGM_OK;
+}
+
+igm_status igm_fp_norm(igm_system *s, const double *x, int64_t len, double *norm) {
+  if (!s || !x || !norm || len < 0 || len >= ((int64_t)1 << 31)) return IGM_ERR_ARG;
+  IGM_TRY(device_norm(s, x, len, s->d_scal + kScalOut));
+  IGM_HIP(hipMemcpyAsync(norm, s->d_scal + kScalOut, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  return IGM_OK;
+}
+
+igm_status igm_line1(igm_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
+                     double *rho) {
+  if (!s || !r || !bk || !r0 || !v1 || !gamma || !rho) return IGM_ERR_ARG;
+  IGM_TRY(reset_state(s));
+  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+  IGM_HIP(launch_absmax(s->stream, s->n, r, s->d_red + kRedMuR));
+  IGM_HIP(hipMemcpyAsync(s->h_pinned, s->d_red + kRedMuR, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  const double g = s->h_pinned[0];
+  *gamma = g;
+  *rho = 0.0;
+  if (g == 0.0) return IGM_OK;
+  IGM_HIP(hipMemcpyAsync(s->d_scal + kScalGamma, s->d_red + kRedMuR, sizeof(double), hipMemcpyDeviceToDevice,
+                         s->stream));
+  CycleArgs a = make_args(s);
+  a.V = v1;  // line 2 writes its output as the first basis vector
+  IGM_HIP(launch_line1(s->stream, a, r, s->d_scal, s->d_lvalf, s->d_uvalf, bk, r0, s->d_red));
+  CycleState cs;
+  IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipMemcpyAsync(s->h_pinned, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(hipStreamSynchronize(s->stream));
+  *rho = s->h_pinned[kScalRho];
+  return cs.range_err ? IGM_ERR_RANGE : IGM_OK;
+}
+
+void igm_destroy(igm_system *s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->ev0) { (void)hipEventDestroy(s->ev0); (void)hipEventDestroy(s->ev1); }
+  free_device(s);
+  delete s;
+}
+
+const char *igm_status_str(igm_status st) {
+  switch (st) {
+    case IGM_OK: return "ok";
+    case IGM_NOT_CONVERGED: return "not converged";
+    case IGM_ERR_ARG: return "invalid argument";
+    case IGM_ERR_SINGULAR_ROW: return "all-zero row";
+    case IGM_ERR_ZERO_PIVOT: return "zero pivot";
+    case IGM_ERR_OVERFLOW: return "fixed-point overflow";
+    case IGM_ERR_RANGE: return "value out of range";
+    case IGM_ERR_OOM: return "out of memory";
+    case IGM_ERR_DEVICE: return "device error";
+    case IGM_ERR_BREAKDOWN: return "breakdown";
+    case IGM_ERR_UNSUPPORTED: return "unsupported size";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

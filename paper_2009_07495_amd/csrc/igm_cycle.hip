@@ -1,0 +1,279 @@
+// The int-GMRES(m) call of the paper (Fig. 2, lines 3-20, with the
+// preconditioned line 5' of Sec. VI and optionally lines 21-23 plus the
+// refinement update of eq. (update)) as one persistent cooperative kernel.
+//
+// Layout: thread t of workgroup b owns rows r = b*BLOCK + t + k*T (k < R,
+// T = gridDim.x*BLOCK) and keeps w_r in registers for the whole Arnoldi step;
+// consecutive lanes own consecutive rows, so every vector access and the
+// SELL-64 matrix stream are coalesced. Each inner product of the modified
+// Gram-Schmidt loop is one exact grid reduction (igm_sync.hpp); the scalar
+// work of lines 12-19 runs in thread 0 of every workgroup on identical data,
+// so all workgroups take the same decisions without extra communication.
+// Workgroup 0 stores H, c, s, g for the caller.
+#include "igm_rows.hpp"
+#include "igm_sync.hpp"
+
+namespace igm {
+
+template <int R, int PRE>
+__global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
+  extern __shared__ int64_t smem[];
+  const int m = a.m;
+  int64_t *sc = smem;             // c_1..c_m
+  int64_t *ss = sc + m;           // s_1..s_m
+  int64_t *sg = ss + m;           // g_1..g_{m+1}
+  int64_t *col = sg + m + 1;      // current column h_{1..j+1, j}
+  double *sy = (double *)(col + m + 1);  // y for lines 21-23
+  __shared__ Acc sh_wave[kCycleBlock / 64];
+  __shared__ Acc sh_sum;
+  __shared__ int sh_abort, sh_stop, sh_jstar, sh_breakdown, sh_steps, sh_update;
+
+  const int tid = threadIdx.x;
+  const int64_t T = (int64_t)gridDim.x * kCycleBlock;
+  const int64_t gt = (int64_t)blockIdx.x * kCycleBlock + tid;
+  const int df = a.df;
+  int64_t *first = &a.state->first_ovf;
+  GridSync gs{a.sync, a.sync_cap, (int)gridDim.x, 0, &a.state->timeout};
+
+  if (tid == 0) {
+    for (int i = 0; i < m; ++i) { sc[i] = 0; ss[i] = 0; }
+    for (int i = 0; i <= m; ++i) { sg[i] = 0; col[i] = 0; }
+    sg[0] = (int64_t)1 << df;  // line 3
+    sh_abort = 0; sh_stop = 0; sh_jstar = m; sh_breakdown = 0; sh_steps = 0;
+  }
+  __syncthreads();
+
+  int64_t w[R];
+  for (int j = 1; j <= m; ++j) {  // line 4
+    const int64_t *__restrict__ vj = a.V + (size_t)(j - 1) * a.npad;
+    // ---- line 5 / 5'
+    if (PRE != IGM_PRE_ILU0) {
+      bool o1 = false, o2 = false;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = gt + k * T;
+        int64_t z = 0;
+        if (row < a.n) {
+          z = spmv_row(a, row, vj, a.nterms, o1);
+          if (PRE == IGM_PRE_JACOBI) z = tdiv(tdiv(z, a.ldiag[row], o2), a.udiag[row], o2);
+        }
+        w[k] = z;
+      }
+      if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
+      if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
+    } else {
+      bool o1 = false, o2 = false;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = gt + k * T;
+        if (row < a.n) a.zbuf[row] = spmv_row(a, row, vj, a.nterms, o1);
+      }
+      if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
+      grid_barrier(gs, &sh_abort);
+      for (int L = 0; L < a.nflev; ++L) {
+        const int32_t lo = a.flev_ptr[L], hi = a.flev_ptr[L + 1];
+        for (int64_t q = lo + gt; q < hi; q += T) {
+          const int64_t row = a.flev_rows[q];
+          a.wbuf[row] = lower_row(a, row, a.zbuf[row], a.wbuf, o2);
+        }
+        grid_barrier(gs, &sh_abort);
+      }
+      for (int L = 0; L < a.nblev; ++L) {
+        const int32_t lo = a.blev_ptr[L], hi = a.blev_ptr[L + 1];
+        for (int64_t q = lo + gt; q < hi; q += T) {
+          const int64_t row = a.blev_rows[q];
+          a.wbuf[row] = upper_row(a, row, a.wbuf[row], a.wbuf, o2);
+        }
+        grid_barrier(gs, &sh_abort);
+      }
+      if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = gt + k * T;
+        w[k] = row < a.n ? a.wbuf[row] : 0;
+      }
+    }
+    // ---- lines 6-9: modified Gram-Schmidt, i increasing
+    for (int i = 1; i <= j; ++i) {
+      const int64_t *__restrict__ vi = a.V + (size_t)(i - 1) * a.npad;
+      int64_t vv[R];
+      Acc acc;
+      acc.zero();
+      bool o = false;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = gt + k * T;
+        vv[k] = row < a.n ? vi[row] : 0;
+        acc.add(mulc(asr(w[k], a.b_dot), vv[k], o));  // line 7: only w is shifted
+      }
+      if (o) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1)));
+      Acc part = block_sum<kCycleBlock>(acc, sh_wave);
+      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort);
+      bool os = false;
+      const int64_t h = asr(tot.value(os), df - a.b_dot);
+      if (os && tid == 0) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1)));
+      if (tid == 0) col[i - 1] = h;
+      // line 8: only h is shifted
+      const int64_t hs = asr(h, a.b_axpy);
+      bool ou = false;
+#pragma unroll
+      for (int k = 0; k < R; ++k) w[k] = subc(w[k], asr(mulc(hs, vv[k], ou), df - a.b_axpy), ou);
+      if (ou) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1) + 1));
+    }
+    // ---- line 10
+    {
+      Acc acc;
+      acc.zero();
+      bool o = false;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t t = asr(w[k], a.b_norm);
+        acc.add(mulc(t, t, o));
+      }
+      if (o) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
+      Acc part = block_sum<kCycleBlock>(acc, sh_wave);
+      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort);
+      bool os = false;
+      const int64_t sq = tot.value(os);
+      const int64_t hn = shl(isqrt64(sq), a.b_norm, os);
+      if (os && tid == 0) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
+      // ---- line 11
+      const int64_t den = asr(hn, a.b_div_den);
+      const bool lucky = den == 0;
+      if (!lucky) {
+        int64_t *__restrict__ vn = a.V + (size_t)j * a.npad;
+        const int e = df - a.b_div_num - a.b_div_den;
+        bool ov = false;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const int64_t row = gt + k * T;
+          if (row < a.n) vn[row] = normalize_elem(w[k], den, a.b_div_num, e, ov);
+        }
+        if (ov) atomicMin((long long *)first, (long long)ev_code(j, 5, 0));
+      }
+      // ---- lines 12-19, thread 0 of every workgroup
+      if (tid == 0) {
+        col[j] = hn;
+        for (int i = 1; i <= j - 1; ++i) {  // lines 12-14
+          const int64_t x0 = asr(col[i - 1], a.b_rot), x1 = asr(col[i], a.b_rot);
+          const int64_t c = sc[i - 1], s = ss[i - 1];
+          bool o = false;
+          const int64_t ms = subc(0, s, o);
+          const int64_t top = addc(mulc(c, x0, o), mulc(s, x1, o), o);
+          const int64_t bot = addc(mulc(ms, x0, o), mulc(c, x1, o), o);
+          col[i - 1] = asr(top, df - a.b_rot);
+          col[i] = asr(bot, df - a.b_rot);
+          if (o) atomicMin((long long *)first, (long long)ev_code(j, 6, i));
+        }
+        bool o = false;  // line 15
+        const int64_t p0 = asr(col[j - 1], a.b_tmp), p1 = asr(col[j], a.b_tmp);
+        const int64_t ssq = addc(mulc(p0, p0, o), mulc(p1, p1, o), o);
+        const int64_t tmp = shl(isqrt64(ssq), a.b_tmp, o);
+        if (o) atomicMin((long long *)first, (long long)ev_code(j, 7, 0));
+        const int64_t den2 = asr(tmp, a.b_cs_den);  // line 16
+        int stop = 0;
+        if (den2 == 0) {
+          sh_breakdown = 2;
+          sh_jstar = j - 1;
+          stop = 1;
+        } else {
+          bool oc = false;
+          const int e2 = df - a.b_cs_num - a.b_cs_den;
+          const int64_t cj = normalize_elem(col[j - 1], den2, a.b_cs_num, e2, oc);
+          const int64_t sj = normalize_elem(col[j], den2, a.b_cs_num, e2, oc);
+          if (oc) atomicMin((long long *)first, (long long)ev_code(j, 8, 0));
+          sc[j - 1] = cj;
+          ss[j - 1] = sj;
+          bool og = false;  // line 17, both from the old g_j
+          const int64_t gj = sg[j - 1];
+          const int64_t msj = subc(0, sj, og);
+          sg[j - 1] = asr(mulc(cj, gj, og), df);
+          sg[j] = asr(mulc(msj, gj, og), df);
+          if (og) atomicMin((long long *)first, (long long)ev_code(j, 9, 0));
+          col[j - 1] = tmp;  // lines 18-19
+          col[j] = 0;
+          if (lucky) {
+            sh_breakdown = 1;
+            sh_jstar = j;
+            stop = 1;
+          } else if (a.gtol >= 0) {
+            const int64_t gn = sg[j] < 0 ? -sg[j] : sg[j];
+            if (gn <= a.gtol) { sh_jstar = j; stop = 1; }
+          }
+        }
+        if (blockIdx.x == 0) {
+          for (int i = 0; i <= j; ++i) a.H[(size_t)i * m + (j - 1)] = col[i];
+          a.c[j - 1] = sc[j - 1];
+          a.s[j - 1] = ss[j - 1];
+          a.g[j - 1] = sg[j - 1];
+          a.g[j] = sg[j];
+        }
+        sh_steps = j;
+        sh_stop = stop;
+      }
+    }
+    // v_{j+1}, H and the overflow record become visible to every workgroup
+    grid_barrier(gs, &sh_abort);
+    if (sh_stop || sh_abort) break;
+  }
+
+  if (tid == 0 && blockIdx.x == 0) {
+    a.state->jstar = sh_jstar;
+    a.state->breakdown = sh_breakdown;
+    a.state->steps = sh_steps;
+  }
+  if (!a.update || sh_abort) return;
+  // ---- lines 21-23 and x += gamma x^(k): each thread updates its own rows
+  if (tid == 0) {
+    const int64_t ev = __hip_atomic_load(first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sh_update = (ev == kNoEvent && sh_jstar > 0);
+    if (sh_update) {
+      const int js = sh_jstar;
+      const double rho = a.scal[1];
+      for (int i = js - 1; i >= 0; --i) {  // back substitution, inner sum k increasing
+        double acc = 0.0;
+        for (int k = i + 1; k < js; ++k) acc = acc + ldexp((double)a.H[(size_t)i * m + k], -df) * sy[k];
+        sy[i] = (ldexp((double)sg[i], -df) - acc) / ldexp((double)a.H[(size_t)i * m + i], -df);
+      }
+      for (int i = 0; i < js; ++i) sy[i] = rho * sy[i];
+    }
+  }
+  __syncthreads();
+  if (!sh_update) return;
+  const int js = sh_jstar;
+  const double gamma = a.scal[0];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int64_t row = gt + k * T;
+    if (row < a.n) {
+      double acc = 0.0;
+      for (int i = 0; i < js; ++i) acc = acc + sy[i] * ldexp((double)a.V[(size_t)i * a.npad + row], -df);
+      a.x[row] = a.x[row] + gamma * acc;
+    }
+  }
+}
+
+template <int R, int PRE>
+static const void *cycle_kernel_ptr() {
+  return (const void *)&k_cycle<R, PRE>;
+}
+
+const void *cycle_kernel(int R, int pre) {
+#define IGM_K(RR)                                               \
+  if (R == RR) {                                                \
+    if (pre == IGM_PRE_NONE) return cycle_kernel_ptr<RR, 0>();  \
+    if (pre == IGM_PRE_JACOBI) return cycle_kernel_ptr<RR, 1>(); \
+    return cycle_kernel_ptr<RR, 2>();                           \
+  }
+  IGM_K(1)
+  IGM_K(2)
+  IGM_K(4)
+  IGM_K(8)
+  IGM_K(16)
+#undef IGM_K
+  return nullptr;
+}
+
+size_t cycle_smem_bytes(int m) { return sizeof(int64_t) * (4 * (size_t)m + 2) + sizeof(double) * (size_t)m; }
+
+}  // namespace igm

@@ -1,0 +1,145 @@
+// Internal structures of the igmres library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/igmres.h"
+
+namespace igm {
+
+constexpr int kMaxTerms = 9;       // A_0 .. A_8
+constexpr int kSlice = 64;         // SELL slice height = wavefront width
+constexpr int kCycleBlock = 512;   // threads per workgroup of the cycle kernel
+constexpr int kSyncGroups = 8;     // arrival words per grid reduction (K)
+constexpr int kMaxRows = 16;       // largest rows-per-thread instantiation
+
+// Device-side record of one int-GMRES call.
+struct CycleState {
+  int64_t first_ovf;     // smallest overflow event code (atomicMin)
+  int32_t jstar, breakdown, steps, timeout;
+  int32_t range_err, pad_;
+};
+
+// Host-side setup products (all derived from the FP64 input).
+struct HostSetup {
+  std::vector<double> dhat, a, b;              // eq. (eq1), (eq3)
+  int nterms = 0;
+  int32_t alpha[kMaxTerms] = {0};
+  std::vector<std::vector<int64_t>> abar;      // eq. (A), on the input pattern
+  std::vector<int64_t> diag_pos;
+  std::vector<double> lu;                      // FP64 ILU(0) of A
+  std::vector<int64_t> ldiag, udiag;           // cast diagonals
+  // strict triangles of the integer factors, CSR
+  std::vector<int64_t> lptr, uptr;
+  std::vector<int32_t> lcol, ucol;
+  std::vector<int64_t> lval, uval;
+  // level sets of the triangular sweeps
+  std::vector<int32_t> flev_ptr, flev_rows, blev_ptr, blev_rows;
+  // SELL-64 layout of the integer matrices
+  int64_t nslices = 0;
+  std::vector<int64_t> sell_off;               // nslices + 1, entries
+  std::vector<int32_t> sell_w;                 // nslices
+  std::vector<int32_t> sell_col;               // padded
+  std::vector<std::vector<int64_t>> sell_val;  // per term
+};
+
+igm_status host_setup(int64_t n, const std::vector<int64_t> &row_ptr, const std::vector<int32_t> &col,
+                      const std::vector<double> &ahat, const std::vector<double> &bhat, const igm_policy &pol,
+                      HostSetup &out);
+igm_status check_policy(const igm_policy &p);
+
+// Host-visible layout of an exact device partial sum (value = hi * 2^40 + lo).
+struct AccWords {
+  int64_t lo, hi;
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Arguments of the persistent cycle kernel.
+struct CycleArgs {
+  int64_t n, npad;
+  int32_t m, df, nterms, precond;
+  int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
+  int32_t nflev, nblev;
+  int64_t gtol;
+  const int64_t *sell_off;
+  const int32_t *sell_w;
+  const int32_t *sell_col;
+  const int64_t *sell_val[kMaxTerms];
+  int32_t alpha[kMaxTerms];
+  const int64_t *ldiag, *udiag;
+  const int64_t *lptr, *uptr;
+  const int32_t *lcol, *ucol;
+  const int64_t *lval, *uval;
+  const int32_t *flev_ptr, *flev_rows, *blev_ptr, *blev_rows;
+  const int32_t *flev_host, *blev_host;  // host copies of the level offsets (launchers only)
+  int64_t *V;      // (m+1) x npad
+  int64_t *zbuf;   // npad (preconditioner path)
+  int64_t *wbuf;   // npad (preconditioner path)
+  int64_t *H, *c, *s, *g;
+  CycleState *state;
+  unsigned long long *sync;  // 2 * kSyncGroups * sync_cap words
+  int32_t sync_cap;
+  int32_t update;            // apply lines 21-23 and x += gamma x^(k)
+  double *x;
+  const double *scal;        // device: {gamma, rho}
+};
+
+const void *cycle_kernel(int R, int pre);
+size_t cycle_smem_bytes(int m);
+
+}  // namespace igm
+
+struct igm_system {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  igm_policy pol{};
+  int64_t n = 0, nnz = 0, npad = 0;
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<double> ahat, bhat;
+  igm::HostSetup hs;
+  double bhat_norm = 0.0, b_norm = 0.0;
+  // device memory
+  std::vector<igm::DevBuf> bufs;
+  int64_t *d_row_ptr = nullptr;
+  int32_t *d_col = nullptr;
+  double *d_a = nullptr, *d_ahat = nullptr, *d_b = nullptr, *d_bhat = nullptr;
+  int64_t *d_sell_off = nullptr;
+  int32_t *d_sell_w = nullptr, *d_sell_col = nullptr;
+  int64_t *d_sell_val[igm::kMaxTerms] = {nullptr};
+  int64_t *d_ldiag = nullptr, *d_udiag = nullptr;
+  int64_t *d_lptr = nullptr, *d_uptr = nullptr;
+  int32_t *d_lcol = nullptr, *d_ucol = nullptr;
+  int64_t *d_lval = nullptr, *d_uval = nullptr;
+  double *d_lvalf = nullptr, *d_uvalf = nullptr;
+  int32_t *d_flev_ptr = nullptr, *d_flev_rows = nullptr, *d_blev_ptr = nullptr, *d_blev_rows = nullptr;
+  // work vectors
+  int64_t *d_V = nullptr, *d_z = nullptr, *d_w = nullptr;
+  double *d_r = nullptr, *d_rhat = nullptr, *d_bk = nullptr, *d_r0 = nullptr, *d_x = nullptr;
+  int64_t *d_H = nullptr, *d_c = nullptr, *d_s = nullptr, *d_g = nullptr;
+  igm::CycleState *d_state = nullptr;
+  unsigned long long *d_sync = nullptr;
+  int32_t sync_cap = 0;
+  unsigned long long *d_red = nullptr;  // scratch words of the FP64 reductions
+  double *d_scal = nullptr;             // device scalars (gamma, rho, relres, norms)
+  igm::AccWords *d_parts = nullptr;     // per-workgroup partial sums of the standalone reductions
+  double *h_pinned = nullptr;           // small pinned staging area
+  int m_alloc = 0;
+  // launch configuration of the cycle kernel
+  int grid = 0, rows_per_thread = 0, max_coresident = 0;
+  // statistics
+  igm_stats stats{};
+  std::vector<double> hist_ro, hist_rs, hist_gamma, hist_rho;
+  std::vector<int32_t> hist_jstar;
+  int64_t device_bytes = 0;
+  int last_error_line = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing of kernel-level calls
+};

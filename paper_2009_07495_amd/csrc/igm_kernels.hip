@@ -1,0 +1,411 @@
+// FP64 refinement kernels (Sec. IV, Fig. 1; Fig. 2 lines 1'-2) and the
+// standalone integer kernels behind the kernel-level entry points.
+//
+// FP64 rules: no contraction (built with -ffp-contract=off), each row sums its
+// products in CSR order, every other step is elementwise, and norms use the
+// order-free construction of dnrm_finish, so results do not depend on the
+// launch shape.
+#include "igm_launch.hpp"
+#include "igm_rows.hpp"
+#include "igm_sync.hpp"
+
+namespace igm {
+
+constexpr int kB = 256;  // threads per workgroup of the elementwise kernels
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long t = (unsigned long long)__shfl_xor((long long)v, o, 64);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// Max of non-negative doubles through their bit patterns (monotone for
+// non-negative values; NaN patterns sort above infinity).
+__device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long *dst) {
+  __shared__ unsigned long long sh[kB / 64];
+  v = wave_max_u64(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    for (int k = 0; k < kB / 64; ++k) m = sh[k] > m ? sh[k] : m;
+    if (m) atomicMax(dst, m);
+  }
+}
+
+// eq. (b): r = b - A x (scaled) and rhat = bhat - Ahat x (original).
+__global__ __launch_bounds__(kB) void k_residual(int64_t n, const int64_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ a,
+                                                 const double *__restrict__ ahat, const double *__restrict__ b,
+                                                 const double *__restrict__ bhat, const double *__restrict__ x,
+                                                 double *r, double *rhat, unsigned long long *red) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  unsigned long long m0 = 0, m1 = 0;
+  if (i < n) {
+    double acc = 0.0, acch = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const double xv = x[col[e]];
+      acc = acc + a[e] * xv;
+      acch = acch + ahat[e] * xv;
+    }
+    const double ri = b[i] - acc, rhi = bhat[i] - acch;
+    r[i] = ri;
+    rhat[i] = rhi;
+    m0 = dbits(fabs(ri));
+    m1 = dbits(fabs(rhi));
+  }
+  block_max_to(m0, red + kRedMuR);
+  __syncthreads();
+  block_max_to(m1, red + kRedMuRhat);
+}
+
+__global__ __launch_bounds__(kB) void k_absmax(int64_t n, const double *__restrict__ x, unsigned long long *dst) {
+  unsigned long long m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+    unsigned long long t = dbits(fabs(x[i]));
+    m = t > m ? t : m;
+  }
+  block_max_to(m, dst);
+}
+
+// Exact sum of floor(2^96 (x_i / mu)^2) as three 40-bit limbs.
+__global__ __launch_bounds__(kB) void k_dnrm_sum(int64_t n, const double *__restrict__ x,
+                                                 const unsigned long long *mu_bits, unsigned long long *limbs) {
+  const double mu = __longlong_as_double((long long)*mu_bits);
+  unsigned long long l0 = 0, l1 = 0, l2 = 0;
+  if (mu > 0.0 && mu <= 1.7976931348623157e308) {
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+      const double t = x[i] / mu;
+      const unsigned __int128 q = fix96(t * t);
+      l0 += (unsigned long long)q & kLimbMask;
+      l1 += (unsigned long long)(q >> 40) & kLimbMask;
+      l2 += (unsigned long long)(q >> 80);
+    }
+  }
+  __shared__ unsigned long long sh[3][kB / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    l0 += (unsigned long long)__shfl_xor((long long)l0, o, 64);
+    l1 += (unsigned long long)__shfl_xor((long long)l1, o, 64);
+    l2 += (unsigned long long)__shfl_xor((long long)l2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = l0;
+    sh[1][threadIdx.x >> 6] = l1;
+    sh[2][threadIdx.x >> 6] = l2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s0 = 0, s1 = 0, s2 = 0;
+    for (int k = 0; k < kB / 64; ++k) { s0 += sh[0][k]; s1 += sh[1][k]; s2 += sh[2][k]; }
+    s1 += s0 >> 40;
+    s0 &= kLimbMask;
+    s2 += s1 >> 40;
+    s1 &= kLimbMask;
+    if (s0) atomicAdd(limbs + 0, s0);
+    if (s1) atomicAdd(limbs + 1, s1);
+    if (s2) atomicAdd(limbs + 2, s2);
+  }
+}
+
+// ||x|| = mu * sqrt(rn(S)) * 2^-48 with S the exact limb sum.
+__device__ double dnrm_finish(const unsigned long long *limbs, unsigned long long mu_bits) {
+  const double mu = __longlong_as_double((long long)mu_bits);
+  if (!(mu > 0.0) || !(mu <= 1.7976931348623157e308)) return mu;
+  unsigned __int128 S = ((unsigned __int128)limbs[2] << 80) + ((unsigned __int128)limbs[1] << 40) +
+                        (unsigned __int128)limbs[0];
+  return mu * ldexp(sqrt(u128_to_double_rn(S)), -48);
+}
+
+__device__ __forceinline__ double relres(double rn, double bn) {
+  if (bn > 0.0) return rn / bn;
+  return rn == 0.0 ? 0.0 : __builtin_inf();
+}
+
+__global__ void k_fin_residual(const unsigned long long *red, const double *norms, double *scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double rn = dnrm_finish(red + kRedSumR, red[kRedMuR]);
+  const double rhn = dnrm_finish(red + kRedSumRhat, red[kRedMuRhat]);
+  scal[kScalGamma] = __longlong_as_double((long long)red[kRedMuR]);
+  scal[kScalRelresOrig] = relres(rhn, norms[1]);
+  scal[kScalRelresScaled] = relres(rn, norms[0]);
+}
+
+__global__ void k_fin_norm(const unsigned long long *red, double *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = dnrm_finish(red + kRedSumX, red[kRedMuX]);
+}
+
+// Line 1' for the diagonal or identity preconditioner, fused with eq. (scale):
+// bk = r / gamma, r0 = (bk / Lbar_ii) / Ubar_ii.
+__global__ __launch_bounds__(kB) void k_scale_diag(int64_t n, const double *__restrict__ r, const double *scal,
+                                                   const int64_t *__restrict__ ld, const int64_t *__restrict__ ud,
+                                                   int pre, double *bk, double *r0, unsigned long long *red) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  unsigned long long mb = 0;
+  if (i < n) {
+    const double g = scal[kScalGamma];
+    const double t = r[i] / g;
+    bk[i] = t;
+    double u = t;
+    if (pre != IGM_PRE_NONE) u = (t / (double)ld[i]) / (double)ud[i];
+    r0[i] = u;
+    mb = dbits(fabs(u));
+  }
+  block_max_to(mb, red + kRedMuR0);
+}
+
+__global__ __launch_bounds__(kB) void k_scale(int64_t n, const double *__restrict__ r, const double *scal, double *bk) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) bk[i] = r[i] / scal[kScalGamma];
+}
+
+// Line 1' with ILU(0), one level of the FP64 substitution with the integer
+// factors converted to double: forward y_i = (bk_i - sum L_ij y_j) / Lbar_ii.
+__global__ __launch_bounds__(kB) void k_fp_lower(int32_t lo, int32_t hi, const int32_t *__restrict__ rows,
+                                                 const int64_t *__restrict__ lptr, const int32_t *__restrict__ lcol,
+                                                 const double *__restrict__ lvalf, const int64_t *__restrict__ ld,
+                                                 const double *__restrict__ bk, double *y) {
+  const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (q >= hi) return;
+  const int64_t i = rows[q];
+  double acc = 0.0;
+  for (int64_t e = lptr[i]; e < lptr[i + 1]; ++e) acc = acc + lvalf[e] * y[lcol[e]];
+  y[i] = (bk[i] - acc) / (double)ld[i];
+}
+
+// backward u_i = (y_i - sum U_ij u_j) / Ubar_ii, in place.
+__global__ __launch_bounds__(kB) void k_fp_upper(int32_t lo, int32_t hi, const int32_t *__restrict__ rows,
+                                                 const int64_t *__restrict__ uptr, const int32_t *__restrict__ ucol,
+                                                 const double *__restrict__ uvalf, const int64_t *__restrict__ ud,
+                                                 double *u) {
+  const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (q >= hi) return;
+  const int64_t i = rows[q];
+  double acc = 0.0;
+  for (int64_t e = uptr[i]; e < uptr[i + 1]; ++e) acc = acc + uvalf[e] * u[ucol[e]];
+  u[i] = (u[i] - acc) / (double)ud[i];
+}
+
+__global__ void k_fin_rho(const unsigned long long *red, double *scal, CycleState *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double rho = dnrm_finish(red + kRedSumR0, red[kRedMuR0]);
+  scal[kScalRho] = rho;
+  if (!(rho > 0.0) || !(rho <= 1.7976931348623157e308)) st->range_err = 1;
+}
+
+// Line 2 (Sec. V-D.1): v1 = trunc(2^df r0 / rho), with a range check.
+__global__ __launch_bounds__(kB) void k_cast_v1(int64_t n, const double *__restrict__ r0, const double *scal, int df,
+                                                int64_t *v1, CycleState *st) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const double rho = scal[kScalRho];
+  const double t = ldexp(r0[i] / rho, df);
+  if (t >= -9223372036854775808.0 && t < 9223372036854775808.0) {
+    v1[i] = (int64_t)t;
+  } else {
+    v1[i] = 0;
+    st->range_err = 1;
+  }
+}
+
+// ---- standalone integer kernels ------------------------------------------
+
+__global__ __launch_bounds__(kB) void k_spmv(CycleArgs a, int nterms, const int64_t *__restrict__ v, int64_t *z) {
+  bool o = false;
+  for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
+    z[row] = spmv_row(a, row, v, nterms, o);
+  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 1, 0));
+}
+
+__global__ __launch_bounds__(kB) void k_diag_solve(CycleArgs a, const int64_t *__restrict__ z, int64_t *w) {
+  bool o = false;
+  for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
+    w[row] = a.precond == IGM_PRE_NONE ? z[row] : tdiv(tdiv(z[row], a.ldiag[row], o), a.udiag[row], o);
+  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 2, 0));
+}
+
+__global__ __launch_bounds__(kB) void k_lower_level(CycleArgs a, int32_t lo, int32_t hi, const int64_t *__restrict__ z,
+                                                    int64_t *y) {
+  const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (q >= hi) return;
+  bool o = false;
+  const int64_t row = a.flev_rows[q];
+  y[row] = lower_row(a, row, z[row], y, o);
+  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 2, 0));
+}
+
+__global__ __launch_bounds__(kB) void k_upper_level(CycleArgs a, int32_t lo, int32_t hi, int64_t *u) {
+  const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (q >= hi) return;
+  bool o = false;
+  const int64_t row = a.blev_rows[q];
+  u[row] = upper_row(a, row, u[row], u, o);
+  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 2, 0));
+}
+
+// Partial sums of line 7 (mode 0: asr(w, b) v) or line 10 (mode 1: asr(w, b)^2),
+// one exact Acc per workgroup.
+__global__ __launch_bounds__(kB) void k_reduce_part(int64_t n, const int64_t *__restrict__ w,
+                                                    const int64_t *__restrict__ v, int b, int mode, Acc *parts,
+                                                    CycleState *st, int64_t code) {
+  __shared__ Acc sh_wave[kB / 64];
+  Acc acc;
+  acc.zero();
+  bool o = false;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+    const int64_t t = asr(w[i], b);
+    acc.add(mulc(t, mode == 0 ? v[i] : t, o));
+  }
+  if (o) atomicMin((long long *)&st->first_ovf, (long long)code);
+  Acc p = block_sum<kB>(acc, sh_wave);
+  if (threadIdx.x == 0) parts[blockIdx.x] = p;
+}
+
+// Finish line 7 (mode 0): asr(S, df - b); line 10 (mode 1): shl(isqrt(S), b).
+__global__ __launch_bounds__(kB) void k_reduce_fin(int nparts, const Acc *parts, int b, int df, int mode,
+                                                   int64_t *out, CycleState *st, int64_t code) {
+  __shared__ Acc sh_wave[kB / 64];
+  Acc acc;
+  acc.zero();
+  for (int k = threadIdx.x; k < nparts; k += kB) acc.add(parts[k]);
+  acc.normalize();
+  Acc t = block_sum<kB>(acc, sh_wave);
+  if (threadIdx.x == 0) {
+    bool o = false;
+    const int64_t S = t.value(o);
+    const int64_t r = mode == 0 ? asr(S, df - b) : shl(isqrt64(S), b, o);
+    if (o) atomicMin((long long *)&st->first_ovf, (long long)code);
+    *out = r;
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_axpy(int64_t n, int64_t h, int b, int df, int64_t *w,
+                                             const int64_t *__restrict__ v, CycleState *st) {
+  bool o = false;
+  const int64_t hs = asr(h, b);
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    w[i] = subc(w[i], asr(mulc(hs, v[i], o), df - b), o);
+  if (o) atomicMin((long long *)&st->first_ovf, (long long)ev_code(1, 3, 1));
+}
+
+__global__ __launch_bounds__(kB) void k_normalize(int64_t n, const int64_t *__restrict__ w, int64_t den, int b1,
+                                                  int e, int64_t *v, CycleState *st) {
+  bool o = false;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    v[i] = normalize_elem(w[i], den, b1, e, o);
+  if (o) atomicMin((long long *)&st->first_ovf, (long long)ev_code(1, 5, 0));
+}
+
+// ---- host launchers --------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+static inline unsigned grid_stride_blocks(int64_t n) {
+  int64_t b = (n + kB - 1) / kB;
+  return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+hipError_t launch_residual(hipStream_t st, int64_t n, const int64_t *rp, const int32_t *col, const double *a,
+                           const double *ahat, const double *b, const double *bhat, const double *x, double *r,
+                           double *rhat, unsigned long long *red) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x, r, rhat, red);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(hipStream_t st, int64_t n, const double *x, unsigned long long *dst) {
+  hipLaunchKernelGGL(k_absmax, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, x, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_dnrm_sum(hipStream_t st, int64_t n, const double *x, const unsigned long long *mu,
+                           unsigned long long *limbs) {
+  hipLaunchKernelGGL(k_dnrm_sum, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, x, mu, limbs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_residual(hipStream_t st, const unsigned long long *red, const double *norms, double *scal) {
+  hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(64), 0, st, red, norms, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_norm(hipStream_t st, const unsigned long long *red, double *out) {
+  hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(64), 0, st, red, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_line1(hipStream_t st, const CycleArgs &a, const double *r, double *scal, const double *lvalf,
+                        const double *uvalf, double *bk, double *r0, unsigned long long *red) {
+  const int64_t n = a.n;
+  if (a.precond != IGM_PRE_ILU0) {
+    hipLaunchKernelGGL(k_scale_diag, dim3(blocks_for(n)), dim3(kB), 0, st, n, r, (const double *)scal, a.ldiag,
+                       a.udiag, a.precond, bk, r0, red);
+  } else {
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kB), 0, st, n, r, (const double *)scal, bk);
+    for (int L = 0; L < a.nflev; ++L) {
+      int32_t lo = a.flev_host[L], hi = a.flev_host[L + 1];
+      hipLaunchKernelGGL(k_fp_lower, dim3(blocks_for(hi - lo)), dim3(kB), 0, st, lo, hi, a.flev_rows, a.lptr,
+                         a.lcol, lvalf, a.ldiag, (const double *)bk, r0);
+    }
+    for (int L = 0; L < a.nblev; ++L) {
+      int32_t lo = a.blev_host[L], hi = a.blev_host[L + 1];
+      hipLaunchKernelGGL(k_fp_upper, dim3(blocks_for(hi - lo)), dim3(kB), 0, st, lo, hi, a.blev_rows, a.uptr,
+                         a.ucol, uvalf, a.udiag, r0);
+    }
+    hipLaunchKernelGGL(k_absmax, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, (const double *)r0,
+                       red + kRedMuR0);
+  }
+  hipLaunchKernelGGL(k_dnrm_sum, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, (const double *)r0,
+                     (const unsigned long long *)(red + kRedMuR0), red + kRedSumR0);
+  hipLaunchKernelGGL(k_fin_rho, dim3(1), dim3(64), 0, st, (const unsigned long long *)red, scal, a.state);
+  hipLaunchKernelGGL(k_cast_v1, dim3(blocks_for(n)), dim3(kB), 0, st, n, (const double *)r0, (const double *)scal,
+                     a.df, a.V, a.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(hipStream_t st, const CycleArgs &a, int nterms, const int64_t *v, int64_t *z) {
+  hipLaunchKernelGGL(k_spmv, dim3(grid_stride_blocks(a.n)), dim3(kB), 0, st, a, nterms, v, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond(hipStream_t st, const CycleArgs &a, const int64_t *z, int64_t *w) {
+  if (a.precond != IGM_PRE_ILU0) {
+    hipLaunchKernelGGL(k_diag_solve, dim3(grid_stride_blocks(a.n)), dim3(kB), 0, st, a, z, w);
+    return hipGetLastError();
+  }
+  for (int L = 0; L < a.nflev; ++L) {
+    int32_t lo = a.flev_host[L], hi = a.flev_host[L + 1];
+    hipLaunchKernelGGL(k_lower_level, dim3(blocks_for(hi - lo)), dim3(kB), 0, st, a, lo, hi, z, w);
+  }
+  for (int L = 0; L < a.nblev; ++L) {
+    int32_t lo = a.blev_host[L], hi = a.blev_host[L + 1];
+    hipLaunchKernelGGL(k_upper_level, dim3(blocks_for(hi - lo)), dim3(kB), 0, st, a, lo, hi, w);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t st, int64_t n, const int64_t *w, const int64_t *v, int b, int df, int mode,
+                         AccWords *parts, int64_t *out, CycleState *state, int64_t code) {
+  static_assert(sizeof(AccWords) == sizeof(Acc), "partial-sum layout");
+  unsigned nb = grid_stride_blocks(n);
+  hipLaunchKernelGGL(k_reduce_part, dim3(nb), dim3(kB), 0, st, n, w, v, b, mode, (Acc *)parts, state, code);
+  hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kB), 0, st, (int)nb, (const Acc *)parts, b, df, mode, out, state,
+                     code);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(hipStream_t st, int64_t n, int64_t h, int b, int df, int64_t *w, const int64_t *v,
+                       CycleState *state) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, h, b, df, w, v, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(hipStream_t st, int64_t n, const int64_t *w, int64_t den, int b1, int e, int64_t *v,
+                            CycleState *state) {
+  hipLaunchKernelGGL(k_normalize, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, w, den, b1, e, v, state);
+  return hipGetLastError();
+}
+
+}  // namespace igm

@@ -1,0 +1,130 @@
+// Grid-wide synchronisation for the persistent (cooperative) cycle kernel.
+//
+// A grid reduction adds, per workgroup, two 64-bit words with one relaxed
+// agent-scope atomic each: (lo << 10) + 1 and (hi << 10) + 1 where lo/hi are
+// the workgroup's exact partial sum split at bit 40. The low 10 bits of every
+// word count its arrivals, so a word is complete when its count equals the
+// number of workgroups mapped to it; no separate counter and no memory fence
+// is needed. Arrivals are spread over kSyncGroups words per limb in separate
+// cache lines (workgroup b uses word b % kSyncGroups) so the memory-side
+// atomics do not serialise on one line; the first wavefront of every
+// workgroup polls all words with one load per lane.
+//
+// A plain barrier (needed when workgroups read vectors other workgroups wrote)
+// adds only to the lo words and wraps the arrival in agent-scope
+// release/acquire fences.
+//
+// Every wait is bounded: after kSpinLimit polls the workgroup records a
+// timeout and the kernel unwinds, so a launch can never hang.
+#pragma once
+
+#include "igm_device.hpp"
+
+namespace igm {
+
+constexpr int kSpinLimit = 1 << 22;
+
+struct GridSync {
+  unsigned long long *words;  // [2 * kSyncGroups][cap]
+  int cap;
+  int nblocks;
+  int next;
+  int *timeout;  // device flag
+};
+
+__device__ __forceinline__ unsigned expected_arrivals(int nblocks, int group) {
+  return group < nblocks ? (unsigned)((nblocks - group + kSyncGroups - 1) / kSyncGroups) : 0u;
+}
+
+// Polls the words of sync slot s (lanes < nwords) until every word holds its
+// expected count. Must be called by all 64 lanes of wavefront 0. Returns the
+// word read by this lane (0 for lanes >= nwords) and sets *to on timeout.
+__device__ __forceinline__ unsigned long long poll_words(const GridSync &gs, int s, int nwords, bool &to) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long x = 0;
+  unsigned expect = lane < nwords ? expected_arrivals(gs.nblocks, lane % kSyncGroups) : 0u;
+  unsigned long long *p = gs.words + (size_t)lane * gs.cap + s;
+  for (int spin = 0;; ++spin) {
+    if (lane < nwords) x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool ok = (unsigned)(x & 1023ull) == expect;
+    if (__all(ok)) break;
+    if (spin >= kSpinLimit) { to = true; break; }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return x;
+}
+
+// Exact sum over the grid of one Acc per workgroup. `part` must hold the
+// workgroup's partial in thread 0; the result is returned to every thread.
+// `abort` is a workgroup-uniform flag set on timeout.
+__device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh_abort) {
+  const int s = gs.next++;
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0 && !*sh_abort) {
+      part.normalize();
+      const int grp = blockIdx.x % kSyncGroups;
+      __hip_atomic_fetch_add(gs.words + (size_t)grp * gs.cap + s, ((unsigned long long)part.lo << 10) + 1ull,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gs.words + (size_t)(kSyncGroups + grp) * gs.cap + s,
+                             ((unsigned long long)part.hi << 10) + 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    bool to = false;
+    unsigned long long x = 0;
+    if (!*sh_abort) x = poll_words(gs, s, 2 * kSyncGroups, to);
+    const int lane = threadIdx.x & 63;
+    Acc r;
+    r.lo = lane < kSyncGroups ? (int64_t)(x >> 10) : 0;
+    r.hi = (lane >= kSyncGroups && lane < 2 * kSyncGroups) ? ((int64_t)x >> 10) : 0;
+    r = wave_sum(r);
+    if (threadIdx.x == 0) {
+      *sh = r;
+      if (to) {
+        *sh_abort = 1;
+        __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  __syncthreads();
+  return *sh;
+}
+
+// Barrier that also publishes global-memory writes of every workgroup to
+// every other workgroup (release before arriving, acquire after the wait).
+__device__ __forceinline__ void grid_barrier(GridSync &gs, int *sh_abort) {
+  const int s = gs.next++;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0 && !*sh_abort) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(gs.words + (size_t)(blockIdx.x % kSyncGroups) * gs.cap + s, 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    bool to = false;
+    if (!*sh_abort) poll_words(gs, s, kSyncGroups, to);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0 && to) {
+      *sh_abort = 1;
+      __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+}
+
+// Workgroup sum of one Acc per thread; result valid in thread 0 only.
+template <int BLOCK>
+__device__ __forceinline__ Acc block_sum(Acc a, Acc *sh_wave) {
+  a = wave_sum(a);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh_wave[wid] = a;
+  __syncthreads();
+  Acc t;
+  t.zero();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) t.add(sh_wave[k]);
+  }
+  return t;
+}
+
+}  // namespace igm

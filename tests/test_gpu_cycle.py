@@ -1,0 +1,196 @@
+"""GPU parity of the persistent int-GMRES(m) kernel and of whole solves.
+
+The cycle trace (rotated H, c, s, g, the whole basis V, j*, breakdown, steps,
+overflow code) must equal the oracle's bit for bit for every launch shape the
+library can pick (workgroup count and rows per thread), and whole solves must
+return the oracle's x bit for bit (the FP64 steps follow the same fixed
+operation order and the norms are order-free)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_07495_amd import binding as B
+from paper_2009_07495_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+CASES = [
+    ("poisson_37x29", lambda: W.poisson2d(37, 29), "paper_noprec", dict(m=20)),
+    ("cd_12x11x9", lambda: W.convdiff3d(12, 11, 9, seed=7), "jacobi", dict(m=25)),
+    ("r27_9x8x6", lambda: W.random27(9, 8, 6, seed=8), "paper_ilu", dict(m=20)),
+    ("dd_257", lambda: W.random_dd(257, 0.03, 9), "paper_ilu", dict(m=30)),
+    ("cd_multiterm", lambda: W.convdiff3d(9, 8, 7, seed=10), "jacobi", dict(m=15, alpha_a=24, s_terms=2)),
+]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+
+    assert T.cuda.is_available(), "GPU tests need a HIP device"
+    return T
+
+
+def first_v1(o, n):
+    r, _ = o.residual(np.zeros(n))
+    return o.line1(r)["v1"]
+
+
+def assert_trace_equal(tg, to, n):
+    for k in ("jstar", "breakdown", "steps", "first_ovf"):
+        assert tg[k] == to[k], (k, tg[k], to[k])
+    assert np.array_equal(tg["H"], to["H"])
+    assert np.array_equal(tg["c"], to["c"]) and np.array_equal(tg["s"], to["s"])
+    assert np.array_equal(tg["g"], to["g"])
+    assert np.array_equal(tg["V"], to["V"])
+
+
+@pytest.mark.parametrize("name,gen,preset,kw", CASES)
+@pytest.mark.parametrize("grid", [0, 1, 3, 7])
+def test_cycle_trace_bit_exact_for_every_launch_shape(orc, torch, name, gen, preset, kw, grid):
+    s = gen()
+    o = orc.OracleSystem.from_system(s, orc.policy(preset, **kw))
+    v1 = first_v1(o, s.n)
+    to = o.cycle(v1)
+    g = B.System.from_system(s, preset, grid_blocks=grid, **kw)
+    st = g.stats()
+    if grid:
+        assert st["grid_blocks"] <= grid
+    tg = g.int_cycle(v1)
+    assert_trace_equal(tg, to, s.n)
+    # a second call on the same system gives the same bits (no state leaks, no races)
+    tg2 = g.int_cycle(v1)
+    assert_trace_equal(tg2, to, s.n)
+
+
+def test_cycle_breakdown_cases(orc, torch):
+    n = 20
+    b = np.zeros(n)
+    b[5] = -2.0
+    s = W.from_dense(3.0 * np.eye(n), b)
+    for preset, kw in (("jacobi", dict(m=10)),):
+        o = orc.OracleSystem.from_system(s, orc.policy(preset, **kw))
+        g = B.System.from_system(s, preset, **kw)
+        v1 = first_v1(o, n)
+        to, tg = o.cycle(v1), g.int_cycle(v1)
+        assert to["breakdown"] == 1
+        assert_trace_equal(tg, to, n)
+        x, st = g.solve()
+        xo, sto = o.solve()
+        assert st == B.OK and np.array_equal(x, xo)
+    a = np.array([[1.0, 1.0], [1.0, 1.0]])
+    s = W.from_dense(a, np.array([1.0, -1.0]))
+    o = orc.OracleSystem.from_system(s, orc.policy("paper_noprec", m=5))
+    g = B.System.from_system(s, "paper_noprec", m=5)
+    v1 = first_v1(o, 2)
+    to, tg = o.cycle(v1), g.int_cycle(v1)
+    assert to["breakdown"] == 2 and to["jstar"] == 0
+    assert_trace_equal(tg, to, 2)
+    x, st = g.solve()
+    assert st == B.ERR_BREAKDOWN and np.all(x == 0)
+
+
+def test_overflow_code_matches(orc, torch):
+    s = W.poisson2d(16)
+    o = orc.OracleSystem.from_system(s, orc.policy("paper_noprec", alpha_a=40))
+    g = B.System.from_system(s, "paper_noprec", alpha_a=40)
+    v1 = first_v1(o, s.n)
+    to, tg = o.cycle(v1), g.int_cycle(v1)
+    assert to["first_ovf"] != orc.NO_EVENT
+    assert_trace_equal(tg, to, s.n)
+    xo, sto = o.solve()
+    x, st = g.solve()
+    assert st == B.ERR_OVERFLOW and sto["status"] == orc.ERR_OVERFLOW
+    assert g.stats()["first_ovf"] == sto["first_ovf"]
+    assert np.array_equal(x, xo)
+
+
+SOLVES = [
+    ("poisson_32", lambda: W.poisson2d(32), "paper_noprec", dict(m=30)),
+    ("cd_16", lambda: W.convdiff3d(16, seed=2), "jacobi", dict(m=50)),
+    ("r27_16x16x8", lambda: W.random27(16, 16, 8, seed=3), "paper_ilu", dict(m=30)),
+    ("dd_64", lambda: W.random_dd(64, 0.2, 11, nonneg_diag=False), "paper_ilu", dict(m=10)),
+    ("cd_multiterm", lambda: W.convdiff3d(9, 8, 7, seed=10), "jacobi", dict(m=15, alpha_a=24, s_terms=2)),
+]
+
+
+@pytest.mark.parametrize("name,gen,preset,kw", SOLVES)
+def test_whole_solve_bit_exact(orc, torch, name, gen, preset, kw):
+    s = gen()
+    o = orc.OracleSystem.from_system(s, orc.policy(preset, **kw))
+    xo, sto = o.solve()
+    g = B.System.from_system(s, preset, **kw)
+    x, st = g.solve()
+    gs = g.stats()
+    assert st == sto["status"] == B.OK
+    assert gs["refinements"] == sto["refinements"] and gs["iterations"] == sto["iterations"]
+    assert np.array_equal(x, xo)
+    h = g.history()
+    assert np.array_equal(h["relres_orig"], sto["hist_relres_orig"])
+    k = gs["refinements"]
+    assert np.array_equal(h["gamma"][:k], sto["hist_gamma"][:k])
+    assert np.array_equal(h["rho"][:k], sto["hist_rho"][:k])
+    assert np.array_equal(h["jstar"][:k], sto["hist_jstar"][:k])
+    assert gs["relres_orig"] < 1e-10
+    # device entry point with a torch buffer: same bits
+    xd = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    assert g.solve_device(xd) == B.OK
+    assert np.array_equal(xd.cpu().numpy(), xo)
+
+
+def test_resume_is_bit_identical(orc, torch):
+    s = W.convdiff3d(12, seed=4)
+    g = B.System.from_system(s, "jacobi", m=20)
+    full, st = g.solve()
+    g.set_policy(B.make_policy("jacobi", m=20, max_refine=2))
+    part, st2 = g.solve()
+    assert st2 == B.NOT_CONVERGED
+    g.set_policy(B.make_policy("jacobi", m=20))
+    rest, st3 = g.solve(part)
+    assert st3 == B.OK and np.array_equal(rest, full)
+
+
+def test_stream_and_rhs_updates(orc, torch):
+    s = W.convdiff3d(10, seed=12)
+    g = B.System.from_system(s, "jacobi", m=20)
+    stream = torch.cuda.Stream()
+    g.set_stream(stream)
+    rng = np.random.default_rng(13)
+    b2 = rng.uniform(-1, 1, s.n)
+    g.set_rhs(b2)
+    x, st = g.solve()
+    s2 = W.System("cd", s.n, s.row_ptr, s.col, s.val, b2)
+    xo, sto = orc.OracleSystem.from_system(s2, orc.policy("jacobi", m=20)).solve()
+    assert st == B.OK and np.array_equal(x, xo)
+    torch.cuda.synchronize()
+
+
+def _golden():
+    path = os.path.join(HERE, "golden", "oracle_runs.json")
+    return json.load(open(path)) if os.path.exists(path) else {}
+
+
+@pytest.mark.parametrize("name", ["poisson2d_64", "convdiff3d_64", "random27_1m"])
+def test_full_size_workload_matches_recorded_oracle_run(torch, name):
+    """Full-size workloads against the oracle's recorded whole-solve results
+    (tests/golden/make_oracle_runs.py): same refinement count, same residual
+    history, and the solution's bytes hash to the oracle's."""
+    gold = _golden().get(name)
+    if gold is None:
+        pytest.skip("no recorded oracle run")
+    gen, preset, m = W.WORKLOADS[name]
+    s = gen()
+    g = B.System.from_system(s, preset, m=m)
+    x, st = g.solve()
+    gs = g.stats()
+    print(name, gs)
+    assert st == B.OK and gs["relres_orig"] <= 1e-10
+    assert gs["refinements"] == gold["refinements"] and gs["iterations"] == gold["iterations"]
+    h = g.history()
+    assert [float(v) for v in h["relres_orig"]] == gold["hist_relres_orig"]
+    assert hashlib.sha256(x.tobytes()).hexdigest() == gold["x_sha256"]
