@@ -147,6 +147,9 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": byts, "avg_launch_ms": avg_cycle_s * 1000.0},
     }
+    ph = g.stats()["phase_us"]
+    out["cycle_phases_us"] = dict(zip(["spmv_precond", "mgs_local", "mgs_grid_wait", "norm", "normalize",
+                                       "givens", "step_barrier", "total"], [round(v, 1) for v in ph]))
     if args.kernels:
         out["kernels"] = kernel_rates(torch, B, W)
     if not args.no_cpu_baseline:

@@ -150,6 +150,11 @@ typedef struct {
   int32_t last_error_line; /* source line of the last HIP error, 0 if none */
   int32_t reserved0_;
   double time_kernel_ms;   /* GPU time of the kernels of the last kernel-level call (igm_spmv ...) */
+  /* Where the last int-GMRES call spent its time, seen by workgroup 0 (us):
+   * 0 SpMV + preconditioner, 1 inner products and updates (local work),
+   * 2 waits for the grid-wide inner-product sums, 3 norm, 4 normalisation,
+   * 5 Givens rotations, 6 end-of-step barriers, 7 the whole call. */
+  double phase_us[8];
   int32_t reserved_[4];
 } igm_stats;
 

@@ -46,10 +46,12 @@ class Stats(C.Structure):
                 ("grid_blocks", C.c_int32), ("rows_per_thread", C.c_int32), ("block_threads", C.c_int32),
                 ("levels_fwd", C.c_int32), ("levels_bwd", C.c_int32), ("device_bytes", C.c_int64),
                 ("last_error_line", C.c_int32), ("reserved0_", C.c_int32), ("time_kernel_ms", C.c_double),
-                ("reserved_", C.c_int32 * 4)]
+                ("phase_us", C.c_double * 8), ("reserved_", C.c_int32 * 4)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if not f.endswith("_")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.endswith("_")}
+        d["phase_us"] = list(self.phase_us)
+        return d
 
 
 class CycleTrace(C.Structure):

@@ -113,22 +113,30 @@ CycleArgs make_args(igm_system *s) {
   return a;
 }
 
-// Choose rows per thread R and the number of workgroups G of the cycle
-// kernel: the smallest R for which ceil(n / (BLOCK R)) workgroups fit both
-// the target and the co-resident limit.
+// Choose the workgroup size B, rows per thread R and number of workgroups G
+// of the cycle kernel: the first (B, R) in order of preference for which
+// G = ceil(n / (B R)) fits both the target and the co-resident limit. Larger
+// workgroups with fewer rows per thread keep the per-thread work of each
+// inner product short; fewer workgroups make each grid reduction cheaper.
 igm_status choose_launch(igm_system *s) {
   hipDeviceProp_t prop;
   IGM_HIP(hipGetDeviceProperties(&prop, s->device));
+  int wall_khz = 0;
+  IGM_HIP(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, s->device));
+  s->wall_us_per_tick = wall_khz > 0 ? 1000.0 / wall_khz : 0.0;
   int target = s->pol.grid_blocks > 0 ? s->pol.grid_blocks : 256;
   target = std::min(target, 1023);
   const size_t smem = cycle_smem_bytes(s->pol.m);
-  for (int R : {1, 2, 4, 8, 16}) {
+  static const int kShapes[][2] = {{1024, 1}, {1024, 2}, {1024, 4}, {512, 8}, {512, 16}};
+  for (const auto &bs : kShapes) {
+    const int B = bs[0], R = bs[1];
     int nb = 0;
-    IGM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cycle_kernel(R, s->pol.precond), kCycleBlock, smem));
+    IGM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cycle_kernel(B, R, s->pol.precond), B, smem));
     const int64_t cap = std::min<int64_t>((int64_t)nb * prop.multiProcessorCount, target);
-    const int64_t G = (s->n + (int64_t)kCycleBlock * R - 1) / ((int64_t)kCycleBlock * R);
-    if (G <= cap) {
+    const int64_t G = (s->n + (int64_t)B * R - 1) / ((int64_t)B * R);
+    if (nb > 0 && G <= cap) {
       s->grid = (int)G;
+      s->block = B;
       s->rows_per_thread = R;
       s->max_coresident = nb * prop.multiProcessorCount;
       return IGM_OK;
@@ -180,7 +188,22 @@ igm_status build(igm_system *s) {
   free_device(s);
   IGM_TRY(host_setup(s->n, s->row_ptr, s->col, s->ahat, s->bhat, s->pol, s->hs));
   HostSetup &h = s->hs;
-  s->npad = (s->n + kSlice - 1) / kSlice * kSlice;
+  // Rows touched by the cycle kernel: every row r < grid * BLOCK * R. The basis,
+  // the SELL slices (zero width) and the diagonals (value 1) are padded to that
+  // many rows so the kernel needs no per-row bounds test; padded rows stay 0.
+  IGM_TRY(choose_launch(s));
+  const int64_t touched = (int64_t)s->grid * s->block * s->rows_per_thread;
+  s->npad = (std::max(s->n, touched) + kSlice - 1) / kSlice * kSlice;
+  {
+    const int64_t ns = s->npad / kSlice;
+    const int64_t end = h.sell_off.back();
+    h.sell_off.resize(ns + 1, end);
+    h.sell_w.resize(ns, 0);
+    if (s->pol.precond != IGM_PRE_NONE) {
+      h.ldiag.resize(s->npad, 1);
+      h.udiag.resize(s->npad, 1);
+    }
+  }
   IGM_TRY(upload(s, s->d_row_ptr, s->row_ptr));
   IGM_TRY(upload(s, s->d_col, s->col));
   IGM_TRY(upload(s, s->d_a, h.a));
@@ -217,7 +240,6 @@ igm_status build(igm_system *s) {
     h.blev_ptr.clear();
   }
   IGM_TRY(alloc_work(s));
-  IGM_TRY(choose_launch(s));
   // norms of the scaled and original right-hand sides (denominators of relres)
   IGM_TRY(device_norm(s, s->d_b, s->n, s->d_scal + kScalNormB));
   IGM_TRY(device_norm(s, s->d_bhat, s->n, s->d_scal + kScalNormBhat));
@@ -226,9 +248,9 @@ igm_status build(igm_system *s) {
 }
 
 igm_status launch_cycle(igm_system *s, const CycleArgs &a) {
-  const void *k = cycle_kernel(s->rows_per_thread, s->pol.precond);
+  const void *k = cycle_kernel(s->block, s->rows_per_thread, s->pol.precond);
   void *args[] = {(void *)&a};
-  IGM_HIP(hipLaunchCooperativeKernel(k, dim3(s->grid), dim3(kCycleBlock), args, cycle_smem_bytes(s->pol.m),
+  IGM_HIP(hipLaunchCooperativeKernel(k, dim3(s->grid), dim3(s->block), args, cycle_smem_bytes(s->pol.m),
                                      s->stream));
   return IGM_OK;
 }
@@ -299,6 +321,7 @@ igm_status solve_dev(igm_system *s, double *x) {
     IGM_HIP(hipEventElapsedTime(&ms, e0, e1));
     st.time_cycle_ms += ms;
     s->hist_rho.push_back(hp[kScalRho]);
+    for (int k = 0; k < 8; ++k) st.phase_us[k] = (double)cs.phase[k] * s->wall_us_per_tick;
     if (cs.range_err) { status = IGM_ERR_RANGE; break; }
     if (cs.timeout) { status = IGM_ERR_DEVICE; s->last_error_line = __LINE__; break; }
     st.refinements += 1;
@@ -322,7 +345,7 @@ void fill_stats_static(igm_system *s) {
   st.nterms = s->hs.nterms;
   st.grid_blocks = s->grid;
   st.rows_per_thread = s->rows_per_thread;
-  st.block_threads = kCycleBlock;
+  st.block_threads = s->block;
   st.levels_fwd = s->hs.flev_ptr.empty() ? 0 : (int32_t)s->hs.flev_ptr.size() - 1;
   st.levels_bwd = s->hs.blev_ptr.empty() ? 0 : (int32_t)s->hs.blev_ptr.size() - 1;
   st.device_bytes = s->device_bytes;
@@ -495,6 +518,7 @@ igm_status igm_int_cycle(igm_system *s, const int64_t *v1, igm_cycle_trace *t) {
                              hipMemcpyDeviceToHost, s->stream));
   IGM_HIP(hipStreamSynchronize(s->stream));
   if (cs.timeout) { s->last_error_line = __LINE__; return IGM_ERR_DEVICE; }
+  for (int k = 0; k < 8; ++k) s->stats.phase_us[k] = (double)cs.phase[k] * s->wall_us_per_tick;
   t->jstar = cs.jstar;
   t->breakdown = cs.breakdown;
   t->steps = cs.steps;

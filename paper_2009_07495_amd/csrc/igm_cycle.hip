@@ -15,8 +15,11 @@
 
 namespace igm {
 
-template <int R, int PRE>
-__global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
+// thread that runs the scalar Givens work (wavefront 1, lane 0)
+constexpr int kGivens = 64;
+
+template <int BLOCK, int R, int PRE>
+__global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   extern __shared__ int64_t smem[];
   const int m = a.m;
   int64_t *sc = smem;             // c_1..c_m
@@ -24,16 +27,27 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
   int64_t *sg = ss + m;           // g_1..g_{m+1}
   int64_t *col = sg + m + 1;      // current column h_{1..j+1, j}
   double *sy = (double *)(col + m + 1);  // y for lines 21-23
-  __shared__ Acc sh_wave[kCycleBlock / 64];
+  __shared__ Acc sh_wave[BLOCK / 64];
   __shared__ Acc sh_sum;
   __shared__ int sh_abort, sh_stop, sh_jstar, sh_breakdown, sh_steps, sh_update;
 
   const int tid = threadIdx.x;
-  const int64_t T = (int64_t)gridDim.x * kCycleBlock;
-  const int64_t gt = (int64_t)blockIdx.x * kCycleBlock + tid;
+  const int64_t T = (int64_t)gridDim.x * BLOCK;
+  const int64_t gt = (int64_t)blockIdx.x * BLOCK + tid;
   const int df = a.df;
   int64_t *first = &a.state->first_ovf;
   GridSync gs{a.sync, a.sync_cap, (int)gridDim.x, 0, &a.state->timeout};
+  // phase clock of thread 0 of workgroup 0 (100 MHz wall clock)
+  const bool timer = blockIdx.x == 0 && tid == 0;
+  uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const uint64_t t_start = timer ? wall_clock64() : 0;
+  uint64_t t_prev = t_start;
+#define IGM_TICK(k)                      \
+  if (timer) {                           \
+    const uint64_t t_ = wall_clock64();  \
+    ph[k] += t_ - t_prev;                \
+    t_prev = t_;                         \
+  }
 
   if (tid == 0) {
     for (int i = 0; i < m; ++i) { sc[i] = 0; ss[i] = 0; }
@@ -50,13 +64,10 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
     if (PRE != IGM_PRE_ILU0) {
       bool o1 = false, o2 = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
+      for (int k = 0; k < R; ++k) {  // padded rows: empty slices, unit diagonals
         const int64_t row = gt + k * T;
-        int64_t z = 0;
-        if (row < a.n) {
-          z = spmv_row(a, row, vj, a.nterms, o1);
-          if (PRE == IGM_PRE_JACOBI) z = tdiv(tdiv(z, a.ldiag[row], o2), a.udiag[row], o2);
-        }
+        int64_t z = spmv_row(a, row, vj, a.nterms, o1);
+        if (PRE == IGM_PRE_JACOBI) z = tdiv(tdiv(z, a.ldiag[row], o2), a.udiag[row], o2);
         w[k] = z;
       }
       if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
@@ -66,7 +77,7 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const int64_t row = gt + k * T;
-        if (row < a.n) a.zbuf[row] = spmv_row(a, row, vj, a.nterms, o1);
+        a.zbuf[row] = spmv_row(a, row, vj, a.nterms, o1);
       }
       if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
       grid_barrier(gs, &sh_abort);
@@ -89,54 +100,88 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
       if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        const int64_t row = gt + k * T;
-        w[k] = row < a.n ? a.wbuf[row] : 0;
+        w[k] = a.wbuf[gt + k * T];  // padded rows hold 0
       }
     }
-    // ---- lines 6-9: modified Gram-Schmidt, i increasing
+    IGM_TICK(0)
+    // ---- lines 6-9: modified Gram-Schmidt, i increasing. v_{i+1} is loaded
+    // before waiting for the grid sum of (w, v_i) so its latency overlaps.
+    // Lines 12-14 need h_{i+1,j} for rotation i only, so thread kGivens
+    // (wavefront 1, idle during the waits) applies rotation q-2 while
+    // wavefront 0 waits for reduction q; the rotated lower entry is carried
+    // in a register of that thread.
+    int64_t vv[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) vv[k] = a.V[gt + k * T];
+    int64_t carry = 0;
+    auto rotate = [&](int i) {  // rotation i (1-based) on (carry, col[i]); kGivens only
+      const int64_t x0 = asr(carry, a.b_rot), x1 = asr(col[i], a.b_rot);
+      const int64_t c = sc[i - 1], s = ss[i - 1];
+      bool o = false;
+      const int64_t ms = subc(0, s, o);
+      const int64_t top = addc(mulw(x0, c, o), mulw(x1, s, o), o);
+      const int64_t bot = addc(mulw(x0, ms, o), mulw(x1, c, o), o);
+      col[i - 1] = asr(top, df - a.b_rot);
+      carry = asr(bot, df - a.b_rot);
+      if (o) atomicMin((long long *)first, (long long)ev_code(j, 6, i));
+    };
     for (int i = 1; i <= j; ++i) {
-      const int64_t *__restrict__ vi = a.V + (size_t)(i - 1) * a.npad;
-      int64_t vv[R];
       Acc acc;
       acc.zero();
       bool o = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const int64_t row = gt + k * T;
-        vv[k] = row < a.n ? vi[row] : 0;
-        acc.add(mulc(asr(w[k], a.b_dot), vv[k], o));  // line 7: only w is shifted
-      }
+      for (int k = 0; k < R; ++k) acc.add(mulw(asr(w[k], a.b_dot), vv[k], o));  // line 7: only w is shifted
       if (o) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1)));
-      Acc part = block_sum<kCycleBlock>(acc, sh_wave);
-      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort);
+      Acc part = block_sum<BLOCK>(acc, sh_wave);
+      int64_t vnext[R];
+      if (i < j) {
+        const int64_t *vi1 = a.V + (size_t)i * a.npad;
+#pragma unroll
+        for (int k = 0; k < R; ++k) vnext[k] = vi1[gt + k * T];
+      }
+      IGM_TICK(1)
+      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort, [&] {
+        if (tid == kGivens && i >= 3) rotate(i - 2);
+      });
+      IGM_TICK(2)
       bool os = false;
       const int64_t h = asr(tot.value(os), df - a.b_dot);
       if (os && tid == 0) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1)));
-      if (tid == 0) col[i - 1] = h;
+      if (tid == kGivens) {
+        col[i - 1] = h;
+        if (i == 1) carry = h;
+      }
       // line 8: only h is shifted
       const int64_t hs = asr(h, a.b_axpy);
       bool ou = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) w[k] = subc(w[k], asr(mulc(hs, vv[k], ou), df - a.b_axpy), ou);
+      for (int k = 0; k < R; ++k) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - a.b_axpy), ou);
       if (ou) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1) + 1));
+      if (i < j) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) vv[k] = vnext[k];
+      }
+      IGM_TICK(1)
     }
-    // ---- line 10
+    // ---- line 10 (the last rotation j-1 runs during this reduction)
     {
       Acc acc;
       acc.zero();
       bool o = false;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        const int64_t t = asr(w[k], a.b_norm);
-        acc.add(mulc(t, t, o));
+        acc.add(sqrc(asr(w[k], a.b_norm), o));
       }
       if (o) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
-      Acc part = block_sum<kCycleBlock>(acc, sh_wave);
-      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort);
+      Acc part = block_sum<BLOCK>(acc, sh_wave);
+      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort, [&] {
+        if (tid == kGivens && j >= 2) rotate(j - 1);
+      });
       bool os = false;
       const int64_t sq = tot.value(os);
       const int64_t hn = shl(isqrt64(sq), a.b_norm, os);
       if (os && tid == 0) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
+      IGM_TICK(3)
       // ---- line 11
       const int64_t den = asr(hn, a.b_div_den);
       const bool lucky = den == 0;
@@ -145,29 +190,17 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
         const int e = df - a.b_div_num - a.b_div_den;
         bool ov = false;
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          const int64_t row = gt + k * T;
-          if (row < a.n) vn[row] = normalize_elem(w[k], den, a.b_div_num, e, ov);
-        }
+        for (int k = 0; k < R; ++k) vn[gt + k * T] = normalize_elem(w[k], den, a.b_div_num, e, ov);
         if (ov) atomicMin((long long *)first, (long long)ev_code(j, 5, 0));
       }
-      // ---- lines 12-19, thread 0 of every workgroup
-      if (tid == 0) {
+      IGM_TICK(4)
+      // ---- lines 15-19 on the rotated column, thread kGivens of every workgroup
+      if (tid == kGivens) {
+        col[j - 1] = carry;
         col[j] = hn;
-        for (int i = 1; i <= j - 1; ++i) {  // lines 12-14
-          const int64_t x0 = asr(col[i - 1], a.b_rot), x1 = asr(col[i], a.b_rot);
-          const int64_t c = sc[i - 1], s = ss[i - 1];
-          bool o = false;
-          const int64_t ms = subc(0, s, o);
-          const int64_t top = addc(mulc(c, x0, o), mulc(s, x1, o), o);
-          const int64_t bot = addc(mulc(ms, x0, o), mulc(c, x1, o), o);
-          col[i - 1] = asr(top, df - a.b_rot);
-          col[i] = asr(bot, df - a.b_rot);
-          if (o) atomicMin((long long *)first, (long long)ev_code(j, 6, i));
-        }
         bool o = false;  // line 15
         const int64_t p0 = asr(col[j - 1], a.b_tmp), p1 = asr(col[j], a.b_tmp);
-        const int64_t ssq = addc(mulc(p0, p0, o), mulc(p1, p1, o), o);
+        const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
         const int64_t tmp = shl(isqrt64(ssq), a.b_tmp, o);
         if (o) atomicMin((long long *)first, (long long)ev_code(j, 7, 0));
         const int64_t den2 = asr(tmp, a.b_cs_den);  // line 16
@@ -187,8 +220,8 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
           bool og = false;  // line 17, both from the old g_j
           const int64_t gj = sg[j - 1];
           const int64_t msj = subc(0, sj, og);
-          sg[j - 1] = asr(mulc(cj, gj, og), df);
-          sg[j] = asr(mulc(msj, gj, og), df);
+          sg[j - 1] = asr(mulw(gj, cj, og), df);
+          sg[j] = asr(mulw(gj, msj, og), df);
           if (og) atomicMin((long long *)first, (long long)ev_code(j, 9, 0));
           col[j - 1] = tmp;  // lines 18-19
           col[j] = 0;
@@ -211,9 +244,11 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
         sh_steps = j;
         sh_stop = stop;
       }
+      IGM_TICK(5)
     }
     // v_{j+1}, H and the overflow record become visible to every workgroup
     grid_barrier(gs, &sh_abort);
+    IGM_TICK(6)
     if (sh_stop || sh_abort) break;
   }
 
@@ -221,7 +256,10 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
     a.state->jstar = sh_jstar;
     a.state->breakdown = sh_breakdown;
     a.state->steps = sh_steps;
+    ph[7] = wall_clock64() - t_start;
+    for (int k = 0; k < 8; ++k) a.state->phase[k] = ph[k];
   }
+#undef IGM_TICK
   if (!a.update || sh_abort) return;
   // ---- lines 21-23 and x += gamma x^(k): each thread updates its own rows
   if (tid == 0) {
@@ -253,23 +291,26 @@ __global__ __launch_bounds__(kCycleBlock) void k_cycle(CycleArgs a) {
   }
 }
 
-template <int R, int PRE>
+template <int BLOCK, int R, int PRE>
 static const void *cycle_kernel_ptr() {
-  return (const void *)&k_cycle<R, PRE>;
+  return (const void *)&k_cycle<BLOCK, R, PRE>;
 }
 
-const void *cycle_kernel(int R, int pre) {
-#define IGM_K(RR)                                               \
-  if (R == RR) {                                                \
-    if (pre == IGM_PRE_NONE) return cycle_kernel_ptr<RR, 0>();  \
-    if (pre == IGM_PRE_JACOBI) return cycle_kernel_ptr<RR, 1>(); \
-    return cycle_kernel_ptr<RR, 2>();                           \
+const void *cycle_kernel(int block, int R, int pre) {
+#define IGM_K(BB, RR)                                                \
+  if (block == BB && R == RR) {                                      \
+    if (pre == IGM_PRE_NONE) return cycle_kernel_ptr<BB, RR, 0>();   \
+    if (pre == IGM_PRE_JACOBI) return cycle_kernel_ptr<BB, RR, 1>(); \
+    return cycle_kernel_ptr<BB, RR, 2>();                            \
   }
-  IGM_K(1)
-  IGM_K(2)
-  IGM_K(4)
-  IGM_K(8)
-  IGM_K(16)
+  IGM_K(1024, 1)
+  IGM_K(1024, 2)
+  IGM_K(1024, 4)
+  IGM_K(512, 1)
+  IGM_K(512, 2)
+  IGM_K(512, 4)
+  IGM_K(512, 8)
+  IGM_K(512, 16)
 #undef IGM_K
   return nullptr;
 }

@@ -43,6 +43,23 @@ __device__ __forceinline__ int64_t mulc(int64_t a, int64_t b, bool &ovf) {
   return p;
 }
 
+// Same result as mulc for a "wide" operand a and a "narrow" operand b (a basis
+// vector element or a rotation coefficient): when a is in [-2^32+1, 2^32] and
+// b in [-2^31, 2^31) the product cannot leave int64 (|a b| <= 2^63 with
+// equality only at -2^63), so a plain 64-bit multiply is exact; otherwise the
+// full 128-bit check runs.
+__device__ __forceinline__ int64_t mulw(int64_t a, int64_t b, bool &ovf) {
+  const bool fits = ((uint64_t)(a + 0xFFFFFFFFll) >> 33) == 0 && ((uint64_t)(b + 0x80000000ll) >> 32) == 0;
+  if (__builtin_expect(fits, 1)) return (int64_t)((uint64_t)a * (uint64_t)b);
+  return mulc(a, b, ovf);
+}
+
+// t * t with the overflow check: exact iff |t| <= floor(sqrt(2^63 - 1)).
+__device__ __forceinline__ int64_t sqrc(int64_t t, bool &ovf) {
+  if ((uint64_t)(t + 3037000499ll) > 6074000998ull) ovf = true;
+  return (int64_t)((uint64_t)t * (uint64_t)t);
+}
+
 __device__ __forceinline__ int64_t addc(int64_t a, int64_t b, bool &ovf) {
   int64_t r;
   if (__builtin_add_overflow(a, b, &r)) ovf = true;
@@ -107,15 +124,36 @@ struct Acc {
   }
 };
 
-__device__ __forceinline__ int64_t shfl_xor64(int64_t v, int o) { return __shfl_xor(v, o, 64); }
+// 64-bit DPP lane move (both 32-bit halves), all lanes active.
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(uint64_t)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xF, 0xF, false);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
 
-// Sum of an Acc over the 64 lanes of a wavefront (result valid in every lane).
+__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Sum of an int64 over the 64 lanes of a wavefront (every lane active; the
+// result is wave-uniform). DPP quad xor-1, quad xor-2, half-row mirror and row
+// mirror leave each 16-lane row's sum in all its lanes; the four row sums are
+// then read out with v_readlane. Integer addition is exact and associative, so
+// the order of the partial sums does not matter.
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+  v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp64<0x141>(v);  // row_half_mirror
+  v += dpp64<0x140>(v);  // row_mirror
+  return readlane64(v, 0) + readlane64(v, 16) + readlane64(v, 32) + readlane64(v, 48);
+}
+
 __device__ __forceinline__ Acc wave_sum(Acc a) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a.lo += shfl_xor64(a.lo, o);
-    a.hi += shfl_xor64(a.hi, o);
-  }
+  a.lo = wave_sum64(a.lo);
+  a.hi = wave_sum64(a.hi);
   return a;
 }
 

@@ -13,7 +13,6 @@ namespace igm {
 
 constexpr int kMaxTerms = 9;       // A_0 .. A_8
 constexpr int kSlice = 64;         // SELL slice height = wavefront width
-constexpr int kCycleBlock = 512;   // threads per workgroup of the cycle kernel
 constexpr int kSyncGroups = 8;     // arrival words per grid reduction (K)
 constexpr int kMaxRows = 16;       // largest rows-per-thread instantiation
 
@@ -22,6 +21,11 @@ struct CycleState {
   int64_t first_ovf;     // smallest overflow event code (atomicMin)
   int32_t jstar, breakdown, steps, timeout;
   int32_t range_err, pad_;
+  // wall-clock ticks spent by workgroup 0 in each phase of the call:
+  // 0 SpMV + preconditioner, 1 inner products/updates (local work),
+  // 2 inner products (grid reduction wait), 3 norm, 4 normalisation,
+  // 5 Givens, 6 end-of-step barrier, 7 whole call
+  uint64_t phase[8];
 };
 
 // Host-side setup products (all derived from the FP64 input).
@@ -92,7 +96,7 @@ struct CycleArgs {
   const double *scal;        // device: {gamma, rho}
 };
 
-const void *cycle_kernel(int R, int pre);
+const void *cycle_kernel(int block, int R, int pre);
 size_t cycle_smem_bytes(int m);
 
 }  // namespace igm
@@ -134,7 +138,7 @@ struct igm_system {
   double *h_pinned = nullptr;           // small pinned staging area
   int m_alloc = 0;
   // launch configuration of the cycle kernel
-  int grid = 0, rows_per_thread = 0, max_coresident = 0;
+  int grid = 0, block = 0, rows_per_thread = 0, max_coresident = 0;
   // statistics
   igm_stats stats{};
   std::vector<double> hist_ro, hist_rs, hist_gamma, hist_rho;
@@ -142,4 +146,5 @@ struct igm_system {
   int64_t device_bytes = 0;
   int last_error_line = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing of kernel-level calls
+  double wall_us_per_tick = 0.0;             // device wall clock period
 };

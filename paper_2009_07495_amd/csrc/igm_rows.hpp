@@ -24,7 +24,7 @@ __device__ __forceinline__ int64_t spmv_row(const CycleArgs &a, int64_t row, con
     acc.zero();
     for (int e = 0; e < wdt; ++e) {
       const int64_t pos = base + (int64_t)e * 64;
-      acc.add(mulc(val[pos], v[a.sell_col[pos]], ovf));
+      acc.add(mulw(val[pos], v[a.sell_col[pos]], ovf));
     }
     int64_t t = acc.value(ovf);
     if (l > 0) t = asr(t, a.alpha[l]);
@@ -40,7 +40,7 @@ __device__ __forceinline__ int64_t lower_row(const CycleArgs &a, int64_t row, in
   Acc acc;
   acc.zero();
   acc.add(zi);
-  for (int64_t e = a.lptr[row]; e < a.lptr[row + 1]; ++e) acc.sub(mulc(a.lval[e], y[a.lcol[e]], ovf));
+  for (int64_t e = a.lptr[row]; e < a.lptr[row + 1]; ++e) acc.sub(mulw(y[a.lcol[e]], a.lval[e], ovf));
   return tdiv(acc.value(ovf), a.ldiag[row], ovf);
 }
 
@@ -51,7 +51,7 @@ __device__ __forceinline__ int64_t upper_row(const CycleArgs &a, int64_t row, in
   Acc acc;
   acc.zero();
   acc.add(yi);
-  for (int64_t e = a.uptr[row]; e < a.uptr[row + 1]; ++e) acc.sub(mulc(a.uval[e], u[a.ucol[e]], ovf));
+  for (int64_t e = a.uptr[row]; e < a.uptr[row + 1]; ++e) acc.sub(mulw(u[a.ucol[e]], a.uval[e], ovf));
   return tdiv(acc.value(ovf), a.udiag[row], ovf);
 }
 

@@ -22,7 +22,12 @@
 
 namespace igm {
 
+#ifndef IGM_POLL_SLEEP
+#define IGM_POLL_SLEEP 1  // s_sleep units (64 clocks) between polls
+#endif
+
 constexpr int kSpinLimit = 1 << 22;
+static_assert(kSyncGroups == 8, "the sum decode reads one 8-lane half-row per limb");
 
 struct GridSync {
   unsigned long long *words;  // [2 * kSyncGroups][cap]
@@ -44,20 +49,24 @@ __device__ __forceinline__ unsigned long long poll_words(const GridSync &gs, int
   unsigned long long x = 0;
   unsigned expect = lane < nwords ? expected_arrivals(gs.nblocks, lane % kSyncGroups) : 0u;
   unsigned long long *p = gs.words + (size_t)lane * gs.cap + s;
+  // one poll in flight, a short sleep between polls: more polling traffic
+  // slows the arriving atomics down
   for (int spin = 0;; ++spin) {
     if (lane < nwords) x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool ok = (unsigned)(x & 1023ull) == expect;
+    const bool ok = (unsigned)(x & 1023ull) == expect;
     if (__all(ok)) break;
     if (spin >= kSpinLimit) { to = true; break; }
-    __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
   }
   return x;
 }
 
 // Exact sum over the grid of one Acc per workgroup. `part` must hold the
 // workgroup's partial in thread 0; the result is returned to every thread.
-// `abort` is a workgroup-uniform flag set on timeout.
-__device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh_abort) {
+// Wavefront 0 arrives and waits; threads of the other wavefronts run `side`
+// meanwhile. `sh_abort` is a workgroup-uniform flag set on timeout.
+template <class Side>
+__device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh_abort, Side side) {
   const int s = gs.next++;
   if (threadIdx.x < 64) {
     if (threadIdx.x == 0 && !*sh_abort) {
@@ -72,11 +81,16 @@ __device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh
     bool to = false;
     unsigned long long x = 0;
     if (!*sh_abort) x = poll_words(gs, s, 2 * kSyncGroups, to);
+    // lanes 0-7 hold the lo words, lanes 8-15 the hi words: three DPP steps
+    // leave each 8-lane half-row's sum in its lanes (read from lanes 0 and 8)
     const int lane = threadIdx.x & 63;
+    int64_t v = lane < kSyncGroups ? (int64_t)(x >> 10) : ((int64_t)x >> 10);
+    v += dpp64<0xB1>(v);
+    v += dpp64<0x4E>(v);
+    v += dpp64<0x141>(v);
     Acc r;
-    r.lo = lane < kSyncGroups ? (int64_t)(x >> 10) : 0;
-    r.hi = (lane >= kSyncGroups && lane < 2 * kSyncGroups) ? ((int64_t)x >> 10) : 0;
-    r = wave_sum(r);
+    r.lo = readlane64(v, 0);
+    r.hi = readlane64(v, kSyncGroups);
     if (threadIdx.x == 0) {
       *sh = r;
       if (to) {
@@ -84,9 +98,15 @@ __device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh
         __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
+  } else {
+    side();
   }
   __syncthreads();
   return *sh;
+}
+
+__device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh_abort) {
+  return grid_sum(gs, part, sh, sh_abort, [] {});
 }
 
 // Barrier that also publishes global-memory writes of every workgroup to
