@@ -6,10 +6,11 @@
 // T = gridDim.x*BLOCK) and keeps w_r in registers for the whole Arnoldi step;
 // consecutive lanes own consecutive rows, so every vector access and the
 // SELL-64 matrix stream are coalesced. Each inner product of the modified
-// Gram-Schmidt loop is one exact grid reduction (igm_sync.hpp); the scalar
-// work of lines 12-19 runs in thread 0 of every workgroup on identical data,
-// so all workgroups take the same decisions without extra communication.
-// Workgroup 0 stores H, c, s, g for the caller.
+// Gram-Schmidt loop is one exact grid reduction (igm_sync.hpp). The scalar
+// work of lines 12-19 runs in thread kGivens of every workgroup on identical
+// data, so all workgroups take the same decisions without extra
+// communication; it is scheduled inside the waits of the grid reductions and
+// barriers. Workgroup 0 stores H, c, s, g for the caller.
 #include "igm_rows.hpp"
 #include "igm_sync.hpp"
 
@@ -27,9 +28,8 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   int64_t *sg = ss + m;           // g_1..g_{m+1}
   int64_t *col = sg + m + 1;      // current column h_{1..j+1, j}
   double *sy = (double *)(col + m + 1);  // y for lines 21-23
-  __shared__ Acc sh_wave[BLOCK / 64];
-  __shared__ Acc sh_sum;
-  __shared__ int sh_abort, sh_stop, sh_jstar, sh_breakdown, sh_steps, sh_update;
+  __shared__ SyncShared ssh;
+  __shared__ int sh_stop, sh_jstar, sh_breakdown, sh_steps, sh_update;
 
   const int tid = threadIdx.x;
   const int64_t T = (int64_t)gridDim.x * BLOCK;
@@ -53,11 +53,84 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     for (int i = 0; i < m; ++i) { sc[i] = 0; ss[i] = 0; }
     for (int i = 0; i <= m; ++i) { sg[i] = 0; col[i] = 0; }
     sg[0] = (int64_t)1 << df;  // line 3
-    sh_abort = 0; sh_stop = 0; sh_jstar = m; sh_breakdown = 0; sh_steps = 0;
+    ssh.abort = 0; ssh.flag = 0;
+    sh_stop = 0; sh_jstar = m; sh_breakdown = 0; sh_steps = 0;
   }
   __syncthreads();
 
+  // reduction finishers (run once per workgroup, in wavefront 0)
+  const int sh_dot = df - a.b_dot;
+  auto fin_dot = [&](int64_t S, bool &o) { return asr(S, sh_dot); };
+  auto fin_norm = [&](int64_t S, bool &o) { return shl(isqrt64(S), a.b_norm, o); };
+  auto no_side = [] {};
+
   int64_t w[R];
+  int64_t carry = 0;  // rotated lower entry of the current column (thread kGivens)
+  int64_t hn = 0;     // h_{j+1,j}
+  bool lucky = false;
+  // rotation i (1-based) of lines 12-14 on (carry, col[i]); thread kGivens only
+  auto rotate = [&](int j, int i) {
+    const int64_t x0 = asr(carry, a.b_rot), x1 = asr(col[i], a.b_rot);
+    const int64_t c = sc[i - 1], s = ss[i - 1];
+    bool o = false;
+    const int64_t ms = subc(0, s, o);
+    const int64_t top = addc(mulw(x0, c, o), mulw(x1, s, o), o);
+    const int64_t bot = addc(mulw(x0, ms, o), mulw(x1, c, o), o);
+    col[i - 1] = asr(top, df - a.b_rot);
+    carry = asr(bot, df - a.b_rot);
+    if (o) atomicMin((long long *)first, (long long)ev_code(j, 6, i));
+  };
+  // lines 15-19 for column j on (carry, hn); thread kGivens only
+  auto givens = [&](int j) {
+    col[j - 1] = carry;
+    col[j] = hn;
+    bool o = false;  // line 15
+    const int64_t p0 = asr(col[j - 1], a.b_tmp), p1 = asr(col[j], a.b_tmp);
+    const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
+    const int64_t tmp = shl(isqrt64(ssq), a.b_tmp, o);
+    if (o) atomicMin((long long *)first, (long long)ev_code(j, 7, 0));
+    const int64_t den2 = asr(tmp, a.b_cs_den);  // line 16
+    int stop = 0;
+    if (den2 == 0) {
+      sh_breakdown = 2;
+      sh_jstar = j - 1;
+      stop = 1;
+    } else {
+      bool oc = false;
+      const int e2 = df - a.b_cs_num - a.b_cs_den;
+      const int64_t cj = normalize_elem(col[j - 1], den2, a.b_cs_num, e2, oc);
+      const int64_t sj = normalize_elem(col[j], den2, a.b_cs_num, e2, oc);
+      if (oc) atomicMin((long long *)first, (long long)ev_code(j, 8, 0));
+      sc[j - 1] = cj;
+      ss[j - 1] = sj;
+      bool og = false;  // line 17, both from the old g_j
+      const int64_t gj = sg[j - 1];
+      const int64_t msj = subc(0, sj, og);
+      sg[j - 1] = asr(mulw(gj, cj, og), df);
+      sg[j] = asr(mulw(gj, msj, og), df);
+      if (og) atomicMin((long long *)first, (long long)ev_code(j, 9, 0));
+      col[j - 1] = tmp;  // lines 18-19
+      col[j] = 0;
+      if (lucky) {
+        sh_breakdown = 1;
+        sh_jstar = j;
+        stop = 1;
+      } else if (a.gtol >= 0) {
+        const int64_t gn = sg[j] < 0 ? -sg[j] : sg[j];
+        if (gn <= a.gtol) { sh_jstar = j; stop = 1; }
+      }
+    }
+    if (blockIdx.x == 0) {
+      for (int i = 0; i <= j; ++i) a.H[(size_t)i * m + (j - 1)] = col[i];
+      a.c[j - 1] = sc[j - 1];
+      a.s[j - 1] = ss[j - 1];
+      a.g[j - 1] = sg[j - 1];
+      a.g[j] = sg[j];
+    }
+    sh_steps = j;
+    sh_stop = stop;
+  };
+
   for (int j = 1; j <= m; ++j) {  // line 4
     const int64_t *__restrict__ vj = a.V + (size_t)(j - 1) * a.npad;
     // ---- line 5 / 5'
@@ -80,14 +153,14 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
         a.zbuf[row] = spmv_row(a, row, vj, a.nterms, o1);
       }
       if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
-      grid_barrier(gs, &sh_abort);
+      grid_barrier(gs, ssh);
       for (int L = 0; L < a.nflev; ++L) {
         const int32_t lo = a.flev_ptr[L], hi = a.flev_ptr[L + 1];
         for (int64_t q = lo + gt; q < hi; q += T) {
           const int64_t row = a.flev_rows[q];
           a.wbuf[row] = lower_row(a, row, a.zbuf[row], a.wbuf, o2);
         }
-        grid_barrier(gs, &sh_abort);
+        grid_barrier(gs, ssh);
       }
       for (int L = 0; L < a.nblev; ++L) {
         const int32_t lo = a.blev_ptr[L], hi = a.blev_ptr[L + 1];
@@ -95,36 +168,20 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
           const int64_t row = a.blev_rows[q];
           a.wbuf[row] = upper_row(a, row, a.wbuf[row], a.wbuf, o2);
         }
-        grid_barrier(gs, &sh_abort);
+        grid_barrier(gs, ssh);
       }
       if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        w[k] = a.wbuf[gt + k * T];  // padded rows hold 0
-      }
+      for (int k = 0; k < R; ++k) w[k] = a.wbuf[gt + k * T];  // padded rows hold 0
     }
     IGM_TICK(0)
     // ---- lines 6-9: modified Gram-Schmidt, i increasing. v_{i+1} is loaded
     // before waiting for the grid sum of (w, v_i) so its latency overlaps.
-    // Lines 12-14 need h_{i+1,j} for rotation i only, so thread kGivens
-    // (wavefront 1, idle during the waits) applies rotation q-2 while
-    // wavefront 0 waits for reduction q; the rotated lower entry is carried
-    // in a register of that thread.
+    // Rotation i of lines 12-14 needs only h_{i+1,j}, so thread kGivens
+    // applies rotation q-2 while wavefront 0 waits for reduction q.
     int64_t vv[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) vv[k] = a.V[gt + k * T];
-    int64_t carry = 0;
-    auto rotate = [&](int i) {  // rotation i (1-based) on (carry, col[i]); kGivens only
-      const int64_t x0 = asr(carry, a.b_rot), x1 = asr(col[i], a.b_rot);
-      const int64_t c = sc[i - 1], s = ss[i - 1];
-      bool o = false;
-      const int64_t ms = subc(0, s, o);
-      const int64_t top = addc(mulw(x0, c, o), mulw(x1, s, o), o);
-      const int64_t bot = addc(mulw(x0, ms, o), mulw(x1, c, o), o);
-      col[i - 1] = asr(top, df - a.b_rot);
-      carry = asr(bot, df - a.b_rot);
-      if (o) atomicMin((long long *)first, (long long)ev_code(j, 6, i));
-    };
     for (int i = 1; i <= j; ++i) {
       Acc acc;
       acc.zero();
@@ -132,7 +189,6 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
 #pragma unroll
       for (int k = 0; k < R; ++k) acc.add(mulw(asr(w[k], a.b_dot), vv[k], o));  // line 7: only w is shifted
       if (o) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1)));
-      Acc part = block_sum<BLOCK>(acc, sh_wave);
       int64_t vnext[R];
       if (i < j) {
         const int64_t *vi1 = a.V + (size_t)i * a.npad;
@@ -140,12 +196,11 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
         for (int k = 0; k < R; ++k) vnext[k] = vi1[gt + k * T];
       }
       IGM_TICK(1)
-      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort, [&] {
-        if (tid == kGivens && i >= 3) rotate(i - 2);
-      });
-      IGM_TICK(2)
       bool os = false;
-      const int64_t h = asr(tot.value(os), df - a.b_dot);
+      const int64_t h = grid_sum<BLOCK>(gs, acc, ssh, fin_dot, [&] {
+        if (tid == kGivens && i >= 3) rotate(j, i - 2);
+      }, os);
+      IGM_TICK(2)
       if (os && tid == 0) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1)));
       if (tid == kGivens) {
         col[i - 1] = h;
@@ -169,88 +224,38 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       acc.zero();
       bool o = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        acc.add(sqrc(asr(w[k], a.b_norm), o));
-      }
+      for (int k = 0; k < R; ++k) acc.add(sqrc(asr(w[k], a.b_norm), o));
       if (o) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
-      Acc part = block_sum<BLOCK>(acc, sh_wave);
-      Acc tot = grid_sum(gs, part, &sh_sum, &sh_abort, [&] {
-        if (tid == kGivens && j >= 2) rotate(j - 1);
-      });
       bool os = false;
-      const int64_t sq = tot.value(os);
-      const int64_t hn = shl(isqrt64(sq), a.b_norm, os);
+      hn = grid_sum<BLOCK>(gs, acc, ssh, fin_norm, [&] {
+        if (tid == kGivens && j >= 2) rotate(j, j - 1);
+      }, os);
       if (os && tid == 0) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
-      IGM_TICK(3)
-      // ---- line 11
-      const int64_t den = asr(hn, a.b_div_den);
-      const bool lucky = den == 0;
-      if (!lucky) {
-        int64_t *__restrict__ vn = a.V + (size_t)j * a.npad;
-        const int e = df - a.b_div_num - a.b_div_den;
-        bool ov = false;
-#pragma unroll
-        for (int k = 0; k < R; ++k) vn[gt + k * T] = normalize_elem(w[k], den, a.b_div_num, e, ov);
-        if (ov) atomicMin((long long *)first, (long long)ev_code(j, 5, 0));
-      }
-      IGM_TICK(4)
-      // ---- lines 15-19 on the rotated column, thread kGivens of every workgroup
-      if (tid == kGivens) {
-        col[j - 1] = carry;
-        col[j] = hn;
-        bool o = false;  // line 15
-        const int64_t p0 = asr(col[j - 1], a.b_tmp), p1 = asr(col[j], a.b_tmp);
-        const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
-        const int64_t tmp = shl(isqrt64(ssq), a.b_tmp, o);
-        if (o) atomicMin((long long *)first, (long long)ev_code(j, 7, 0));
-        const int64_t den2 = asr(tmp, a.b_cs_den);  // line 16
-        int stop = 0;
-        if (den2 == 0) {
-          sh_breakdown = 2;
-          sh_jstar = j - 1;
-          stop = 1;
-        } else {
-          bool oc = false;
-          const int e2 = df - a.b_cs_num - a.b_cs_den;
-          const int64_t cj = normalize_elem(col[j - 1], den2, a.b_cs_num, e2, oc);
-          const int64_t sj = normalize_elem(col[j], den2, a.b_cs_num, e2, oc);
-          if (oc) atomicMin((long long *)first, (long long)ev_code(j, 8, 0));
-          sc[j - 1] = cj;
-          ss[j - 1] = sj;
-          bool og = false;  // line 17, both from the old g_j
-          const int64_t gj = sg[j - 1];
-          const int64_t msj = subc(0, sj, og);
-          sg[j - 1] = asr(mulw(gj, cj, og), df);
-          sg[j] = asr(mulw(gj, msj, og), df);
-          if (og) atomicMin((long long *)first, (long long)ev_code(j, 9, 0));
-          col[j - 1] = tmp;  // lines 18-19
-          col[j] = 0;
-          if (lucky) {
-            sh_breakdown = 1;
-            sh_jstar = j;
-            stop = 1;
-          } else if (a.gtol >= 0) {
-            const int64_t gn = sg[j] < 0 ? -sg[j] : sg[j];
-            if (gn <= a.gtol) { sh_jstar = j; stop = 1; }
-          }
-        }
-        if (blockIdx.x == 0) {
-          for (int i = 0; i <= j; ++i) a.H[(size_t)i * m + (j - 1)] = col[i];
-          a.c[j - 1] = sc[j - 1];
-          a.s[j - 1] = ss[j - 1];
-          a.g[j - 1] = sg[j - 1];
-          a.g[j] = sg[j];
-        }
-        sh_steps = j;
-        sh_stop = stop;
-      }
-      IGM_TICK(5)
     }
-    // v_{j+1}, H and the overflow record become visible to every workgroup
-    grid_barrier(gs, &sh_abort);
+    IGM_TICK(3)
+    // ---- line 11
+    const int64_t den = asr(hn, a.b_div_den);
+    lucky = den == 0;
+    if (!lucky) {
+      int64_t *__restrict__ vn = a.V + (size_t)j * a.npad;
+      const int e = df - a.b_div_num - a.b_div_den;
+      bool ov = false;
+#pragma unroll
+      for (int k = 0; k < R; ++k) vn[gt + k * T] = normalize_elem(w[k], den, a.b_div_num, e, ov);
+      if (ov) atomicMin((long long *)first, (long long)ev_code(j, 5, 0));
+    }
+    IGM_TICK(4)
+    // v_{j+1} and the overflow record become visible to every workgroup; lines
+    // 15-19 (thread kGivens) run while wavefront 0 waits
+    grid_barrier(gs, ssh, [&] {
+      if (tid == kGivens) givens(j);
+    });
     IGM_TICK(6)
-    if (sh_stop || sh_abort) break;
+    if (sh_stop || ssh.abort) break;
   }
+  // publish H, c, s, g of the last step written during the last barrier
+  grid_barrier(gs, ssh, no_side);
+  IGM_TICK(6)
 
   if (tid == 0 && blockIdx.x == 0) {
     a.state->jstar = sh_jstar;
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     for (int k = 0; k < 8; ++k) a.state->phase[k] = ph[k];
   }
 #undef IGM_TICK
-  if (!a.update || sh_abort) return;
+  if (!a.update || ssh.abort) return;
   // ---- lines 21-23 and x += gamma x^(k): each thread updates its own rows
   if (tid == 0) {
     const int64_t ev = __hip_atomic_load(first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

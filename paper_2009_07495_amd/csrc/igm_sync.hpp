@@ -37,6 +37,14 @@ struct GridSync {
   int *timeout;  // device flag
 };
 
+// Workgroup-shared scratch of the reductions.
+struct SyncShared {
+  Acc wave[16];      // per-wavefront partial sums
+  int64_t value;     // broadcast result
+  int flag;          // broadcast overflow flag
+  int abort;         // set on a timed-out wait
+};
+
 __device__ __forceinline__ unsigned expected_arrivals(int nblocks, int group) {
   return group < nblocks ? (unsigned)((nblocks - group + kSyncGroups - 1) / kSyncGroups) : 0u;
 }
@@ -61,29 +69,54 @@ __device__ __forceinline__ unsigned long long poll_words(const GridSync &gs, int
   return x;
 }
 
-// Exact sum over the grid of one Acc per workgroup. `part` must hold the
-// workgroup's partial in thread 0; the result is returned to every thread.
-// Wavefront 0 arrives and waits; threads of the other wavefronts run `side`
-// meanwhile. `sh_abort` is a workgroup-uniform flag set on timeout.
-template <class Side>
-__device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh_abort, Side side) {
+__device__ __forceinline__ void record_timeout(const GridSync &gs, SyncShared &sh) {
+  sh.abort = 1;
+  __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of one int64 over lanes 0..15 of a wavefront, returned to every lane
+// (lanes 16..63 must hold 0).
+__device__ __forceinline__ int64_t row0_sum(int64_t v) {
+  v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp64<0x141>(v);  // row_half_mirror
+  v += dpp64<0x140>(v);  // row_mirror
+  return readlane64(v, 0);
+}
+
+// Exact grid sum of one Acc per thread, finished by `fin(S, ovf)` in wavefront
+// 0 (S = the exact sum reduced to int64, ovf set if it left int64); the
+// finished value and the overflow flag are broadcast to every thread.
+// Threads of wavefronts 1.. run `side` while wavefront 0 waits.
+template <int BLOCK, class Fin, class Side>
+__device__ __forceinline__ int64_t grid_sum(GridSync &gs, Acc a, SyncShared &sh, Fin fin, Side side, bool &ovf) {
+  static_assert(BLOCK / 64 <= 16, "one 16-lane row holds the wavefront partials");
   const int s = gs.next++;
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sh.wave[threadIdx.x >> 6] = a;
+  __syncthreads();
   if (threadIdx.x < 64) {
-    if (threadIdx.x == 0 && !*sh_abort) {
-      part.normalize();
-      const int grp = blockIdx.x % kSyncGroups;
-      __hip_atomic_fetch_add(gs.words + (size_t)grp * gs.cap + s, ((unsigned long long)part.lo << 10) + 1ull,
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gs.words + (size_t)(kSyncGroups + grp) * gs.cap + s,
-                             ((unsigned long long)part.hi << 10) + 1ull, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const int lane = threadIdx.x;
+    Acc p;
+    p.zero();
+    if (lane < BLOCK / 64) p = sh.wave[lane];
+    p.lo = row0_sum(p.lo);
+    p.hi = row0_sum(p.hi);
     bool to = false;
     unsigned long long x = 0;
-    if (!*sh_abort) x = poll_words(gs, s, 2 * kSyncGroups, to);
+    if (!sh.abort) {
+      if (lane == 0) {
+        p.normalize();
+        const int grp = blockIdx.x % kSyncGroups;
+        __hip_atomic_fetch_add(gs.words + (size_t)grp * gs.cap + s, ((unsigned long long)p.lo << 10) + 1ull,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gs.words + (size_t)(kSyncGroups + grp) * gs.cap + s,
+                               ((unsigned long long)p.hi << 10) + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      x = poll_words(gs, s, 2 * kSyncGroups, to);
+    }
     // lanes 0-7 hold the lo words, lanes 8-15 the hi words: three DPP steps
     // leave each 8-lane half-row's sum in its lanes (read from lanes 0 and 8)
-    const int lane = threadIdx.x & 63;
     int64_t v = lane < kSyncGroups ? (int64_t)(x >> 10) : ((int64_t)x >> 10);
     v += dpp64<0xB1>(v);
     v += dpp64<0x4E>(v);
@@ -91,44 +124,47 @@ __device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh
     Acc r;
     r.lo = readlane64(v, 0);
     r.hi = readlane64(v, kSyncGroups);
-    if (threadIdx.x == 0) {
-      *sh = r;
-      if (to) {
-        *sh_abort = 1;
-        __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+    if (lane == 0) {
+      bool o = false;
+      const int64_t S = r.value(o);
+      sh.value = fin(S, o);
+      sh.flag = o;
+      if (to) record_timeout(gs, sh);
     }
   } else {
     side();
   }
   __syncthreads();
-  return *sh;
-}
-
-__device__ __forceinline__ Acc grid_sum(GridSync &gs, Acc part, Acc *sh, int *sh_abort) {
-  return grid_sum(gs, part, sh, sh_abort, [] {});
+  if (sh.flag) ovf = true;
+  return sh.value;
 }
 
 // Barrier that also publishes global-memory writes of every workgroup to
 // every other workgroup (release before arriving, acquire after the wait).
-__device__ __forceinline__ void grid_barrier(GridSync &gs, int *sh_abort) {
+// Threads of wavefronts 1.. run `side` while wavefront 0 waits; writes made by
+// `side` are published by the next barrier.
+template <class Side>
+__device__ __forceinline__ void grid_barrier(GridSync &gs, SyncShared &sh, Side side) {
   const int s = gs.next++;
   __syncthreads();
   if (threadIdx.x < 64) {
-    if (threadIdx.x == 0 && !*sh_abort) {
+    if (threadIdx.x == 0 && !sh.abort) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_fetch_add(gs.words + (size_t)(blockIdx.x % kSyncGroups) * gs.cap + s, 1ull, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     }
     bool to = false;
-    if (!*sh_abort) poll_words(gs, s, kSyncGroups, to);
+    if (!sh.abort) poll_words(gs, s, kSyncGroups, to);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (threadIdx.x == 0 && to) {
-      *sh_abort = 1;
-      __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0 && to) record_timeout(gs, sh);
+  } else {
+    side();
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void grid_barrier(GridSync &gs, SyncShared &sh) {
+  grid_barrier(gs, sh, [] {});
 }
 
 // Workgroup sum of one Acc per thread; result valid in thread 0 only.
