@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,6 +24,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+# Sources the persistent cycle kernel is compiled from: a traffic figure
+# measured with hardware counters is reported only while they are unchanged.
+CYCLE_SOURCES = ("igm_cycle.hip", "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp")
+
+
+def cycle_sources_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in CYCLE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2009_07495_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, grid_blocks: int):
+    """HBM bytes per cycle-kernel launch from the FETCH_SIZE / WRITE_SIZE
+    counter summary in profiles/, if it was taken on the current kernel
+    sources, this workload and this workgroup count; else None."""
+    path = os.path.join(ROOT, "profiles", f"k_cycle_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^\s*([a-z_0-9]+)\s*=\s*(\S+)\s*$", line)
+            if m:
+                kv[m.group(1)] = m.group(2)
+    try:
+        ok = (kv["kernel_sources_sha256"] == cycle_sources_digest() and int(kv["grid_blocks"]) == grid_blocks)
+        return float(kv["traffic_bytes_per_launch"]) if ok else None
+    except KeyError:
+        return None
 
 
 def cycle_bytes(n: int, nnz: int, m_steps: int, precond: int, nnz_l: int, nnz_u: int, nterms: int) -> float:
@@ -65,6 +100,9 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0, help="cycle-kernel workgroups (0 = autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="also time the standalone SpMV and dot kernels")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size kernel for "
+                         "calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1"}))
@@ -76,6 +114,12 @@ def main():
     from paper_2009_07495_amd import workloads as W
 
     assert torch.cuda.is_available()
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     gen, preset, m = W.WORKLOADS[args.workload]
     sysm = gen()
 
@@ -126,6 +170,7 @@ def main():
     byts = cycle_bytes(sysm.n, sysm.nnz, int(round(steps_per_cycle)), pol.precond, nnz_l, nnz_u, st["nterms"])
     avg_cycle_s = cyc_ms / refs / 1000.0
     achieved = byts / avg_cycle_s / 1e9
+    traffic = measured_traffic(args.workload, st["grid_blocks"])
     out = {
         "metric": "GMRES-IR solves/s at relres 1e-10 (integer GMRES(m) inner solver)",
         "value": args.steps / elapsed,
@@ -144,7 +189,7 @@ def main():
                    "grid_blocks": st["grid_blocks"], "rows_per_thread": st["rows_per_thread"],
                    "max_relres": relres},
         "roofline": {"kernel": "k_cycle (persistent int-GMRES call)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": byts, "avg_launch_ms": avg_cycle_s * 1000.0},
     }
     ph = g.stats()["phase_us"]
