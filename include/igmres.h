@@ -231,6 +231,70 @@ igm_status igm_line1(igm_system *s, const double *r, double *bk, double *r0, int
 /* Release all device and host memory of the system. NULL is a no-op. */
 void igm_destroy(igm_system *s);
 
+/* ---- Batched solver: many independent systems in one persistent launch ----
+ * Fig. 1 and Fig. 2 applied to every system of a batch independently, with
+ * one shared policy (no preconditioner or Jacobi; the ILU(0) level sweeps are
+ * not batched). Each system is solved by a team of 1..16 workgroups that claim
+ * it from a device-side queue, largest systems first; all refinements of a
+ * system run inside the launch. The results of a system are bit-identical to
+ * those of igm_solve_device on that system alone. */
+typedef struct igm_batch igm_batch;
+
+/* Build a batch of nsys >= 1 systems from host arrays laid end to end:
+ * n[nsys] rows per system; row_ptr holds nsys arrays of n_s + 1 entries (each
+ * starting at 0 and ending at that system's nnz_s); col and val hold the nnz_s
+ * entries of each system in turn; b holds the n_s entries of each right-hand
+ * side in turn. Every system is set up and validated as igm_create_system
+ * would (same errors); *failed (may be NULL) receives the index of the first
+ * system that failed, -1 if none. IGM_ERR_UNSUPPORTED for the ILU(0)
+ * preconditioner, m > 128, or a system larger than 16 workgroups of the
+ * largest launch shape. On error *out is NULL. */
+igm_status igm_batch_create(int32_t nsys, const int64_t *n, const int64_t *row_ptr, const int32_t *col,
+                            const double *val, const double *b, const igm_policy *pol, int32_t *failed,
+                            igm_batch **out);
+
+/* Use a caller-created HIP stream for all later device work of the batch. */
+igm_status igm_batch_set_stream(igm_batch *bt, void *hip_stream);
+
+/* Launch shape: threads per workgroup and rows per thread, one of (1024, 8),
+ * (1024, 16), (512, 8), (512, 16), (256, 16). System s gets
+ * ceil(n_s / (block * rows_per_thread)) workgroups. IGM_ERR_UNSUPPORTED if a
+ * system would need more than 16 or the device cannot hold that many at once;
+ * IGM_ERR_ARG for a shape not in the list. */
+igm_status igm_batch_set_shape(igm_batch *bt, int32_t block, int32_t rows_per_thread);
+
+/* Time one solve of the batch (from x = 0, in a buffer of the batch; the
+ * caller's memory is not touched) with every usable shape and keep the
+ * fastest. The chosen shape is stored in *block and *rows_per_thread (either
+ * may be NULL). Results do not depend on the shape. */
+igm_status igm_batch_autotune(igm_batch *bt, int32_t *block, int32_t *rows_per_thread);
+
+/* Solve every system. x_dev: device pointer to sum(n_s) doubles laid end to
+ * end in system order: starting iterates in (zeros = the paper's setting),
+ * solutions out. Returns IGM_OK if every system returned IGM_OK,
+ * IGM_ERR_DEVICE on a device failure, otherwise the status of the first
+ * system (in system order) that did not return IGM_OK. */
+igm_status igm_batch_solve_device(igm_batch *bt, double *x_dev);
+
+/* Same with x a host array of sum(n_s) doubles. */
+igm_status igm_batch_solve(igm_batch *bt, double *x);
+
+/* Result of system i in the last solve: status, refinements, iterations,
+ * first_ovf, relres_orig, relres_scaled, time_solve_ms (device wall time from
+ * the start to the end of the system's solve), n, nnz, nterms, grid_blocks
+ * (its team size), block_threads, rows_per_thread. */
+igm_status igm_batch_get_result(const igm_batch *bt, int32_t i, igm_stats *out);
+
+/* Whole-batch statistics of the last solve: status as returned by the solve,
+ * refinements and iterations summed over the systems, time_solve_ms (host
+ * wall time), time_kernel_ms (GPU time of the launch by HIP events),
+ * time_setup_ms, n and nnz summed, grid_blocks / block_threads /
+ * rows_per_thread of the launch, device_bytes. */
+igm_status igm_batch_get_stats(const igm_batch *bt, igm_stats *out);
+
+/* Release all device and host memory of the batch. NULL is a no-op. */
+void igm_batch_destroy(igm_batch *bt);
+
 /* Static description of a status code. */
 const char *igm_status_str(igm_status st);
 

@@ -91,6 +91,16 @@ _SIGS = {
     "igm_line1": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "igm_destroy": [C.c_void_p],
     "igm_status_str": [C.c_int],
+    "igm_batch_create": [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                         C.c_void_p, C.c_void_p],
+    "igm_batch_set_stream": [C.c_void_p, C.c_void_p],
+    "igm_batch_set_shape": [C.c_void_p, C.c_int32, C.c_int32],
+    "igm_batch_autotune": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_batch_solve_device": [C.c_void_p, C.c_void_p],
+    "igm_batch_solve": [C.c_void_p, C.c_void_p],
+    "igm_batch_get_result": [C.c_void_p, C.c_int32, C.c_void_p],
+    "igm_batch_get_stats": [C.c_void_p, C.c_void_p],
+    "igm_batch_destroy": [C.c_void_p],
 }
 EXPORTED = tuple(_SIGS)
 
@@ -107,6 +117,7 @@ def lib():
             fn.argtypes = args
             fn.restype = C.c_int
         L.igm_destroy.restype = None
+        L.igm_batch_destroy.restype = None
         L.igm_status_str.restype = C.c_char_p
         _lib = L
     return _lib
@@ -191,9 +202,9 @@ class System:
         return cls(sysm.n, sysm.row_ptr, sysm.col, sysm.val, sysm.b, pol, **overrides)
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().igm_destroy(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.igm_destroy(self.h)
+        self.h = None
 
     __del__ = close
 
@@ -298,3 +309,79 @@ class System:
         st = lib().igm_line1(self.h, _ptr(r), _ptr(bk), _ptr(r0), _ptr(v1), C.byref(g), C.byref(rho))
         _check(st, "igm_line1", ok=(OK, ERR_RANGE))
         return st, g.value, rho.value
+
+
+class Batch:
+    """One igm_batch: many independent systems solved in one persistent launch
+    (owned; destroyed with the object). Solutions are laid end to end in
+    system order; ``offsets[i]`` is where system i starts."""
+
+    def __init__(self, systems, pol="jacobi", **overrides):
+        if isinstance(pol, str):
+            pol = make_policy(pol, **overrides)
+        self.pol = _policy_struct(pol)
+        ns = len(systems)
+        self.n = np.array([s.n for s in systems], dtype=np.int64)
+        self.nnz = np.array([s.nnz for s in systems], dtype=np.int64)
+        self.offsets = np.zeros(ns + 1, dtype=np.int64)
+        np.cumsum(self.n, out=self.offsets[1:])
+        self.total_n = int(self.offsets[-1])
+        rp = np.ascontiguousarray(np.concatenate([np.asarray(s.row_ptr, dtype=np.int64) for s in systems]))
+        cl = np.ascontiguousarray(np.concatenate([np.asarray(s.col, dtype=np.int32) for s in systems]))
+        vl = np.ascontiguousarray(np.concatenate([np.asarray(s.val, dtype=np.float64) for s in systems]))
+        bb = np.ascontiguousarray(np.concatenate([np.asarray(s.b, dtype=np.float64) for s in systems]))
+        failed = C.c_int32(-1)
+        h = C.c_void_p()
+        st = lib().igm_batch_create(ns, self.n.ctypes.data, rp.ctypes.data, cl.ctypes.data, vl.ctypes.data,
+                                    bb.ctypes.data, C.addressof(self.pol), C.byref(failed), C.byref(h))
+        if st != OK:
+            raise IgmError(st, f"igm_batch_create (system {failed.value})")
+        self.h = h
+        self.nsys = ns
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.igm_batch_destroy(self.h)
+        self.h = None
+
+    __del__ = close
+
+    def set_stream(self, stream):
+        handle = getattr(stream, "cuda_stream", stream)
+        _check(lib().igm_batch_set_stream(self.h, C.c_void_p(handle or 0)), "igm_batch_set_stream")
+
+    def set_shape(self, block: int, rows_per_thread: int) -> int:
+        return lib().igm_batch_set_shape(self.h, int(block), int(rows_per_thread))
+
+    def autotune(self):
+        b, r = C.c_int32(0), C.c_int32(0)
+        _check(lib().igm_batch_autotune(self.h, C.byref(b), C.byref(r)), "igm_batch_autotune")
+        return b.value, r.value
+
+    def solve_device(self, x_dev) -> int:
+        st = lib().igm_batch_solve_device(self.h, _ptr(x_dev))
+        if st == ERR_DEVICE:
+            raise IgmError(st, "igm_batch_solve_device")
+        return st
+
+    def solve(self, x0=None):
+        x = np.zeros(self.total_n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        st = lib().igm_batch_solve(self.h, x.ctypes.data)
+        if st == ERR_DEVICE:
+            raise IgmError(st, "igm_batch_solve")
+        return x, st
+
+    def result(self, i: int) -> dict:
+        s = Stats()
+        s.struct_size = C.sizeof(Stats)
+        _check(lib().igm_batch_get_result(self.h, int(i), C.byref(s)), "igm_batch_get_result")
+        return s.as_dict()
+
+    def results(self) -> list:
+        return [self.result(i) for i in range(self.nsys)]
+
+    def stats(self) -> dict:
+        s = Stats()
+        s.struct_size = C.sizeof(Stats)
+        _check(lib().igm_batch_get_stats(self.h, C.byref(s)), "igm_batch_get_stats")
+        return s.as_dict()

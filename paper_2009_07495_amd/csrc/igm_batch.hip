@@ -1,0 +1,469 @@
+// Batched solver: many independent systems, each solved completely (Fig. 1
+// of the paper: FP64 iterative refinement around int-GMRES(m) calls, Fig. 2
+// with line 5' of Sec. VI) by a team of workgroups inside one persistent
+// cooperative launch.
+//
+// Workgroups claim jobs (system, member) from a queue in the order the host
+// laid out (largest systems first, the members of one system consecutively),
+// so the members of a team start together and every started team can finish.
+// Thread t of member q owns rows q*BLOCK + t + k*T*BLOCK (k < R) of its system
+// and keeps its rows of w (Arnoldi step) and of the FP64 vectors r, rhat and
+// r0 (refinement step) in registers; rows >= n hold zeros. Every reduction is
+// exact (integer sums, maxima, and the order-free FP64 norm), so the bits of a
+// system depend neither on its team size, the launch shape, nor the other
+// systems of the batch: they equal those of the single-system solver.
+#include "igm_batch.hpp"
+#include "igm_rows.hpp"
+#include "igm_team.hpp"
+
+namespace igm {
+
+namespace {
+
+constexpr int kGivensThread = 64;  // runs the scalar work of lines 12-19 (wavefront 1, lane 0)
+constexpr double kDblMax = 1.7976931348623157e308;
+
+__device__ __forceinline__ double relres_of(double rn, double bn) {
+  if (bn > 0.0) return rn / bn;
+  return rn == 0.0 ? 0.0 : __builtin_inf();
+}
+
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v <= kDblMax; }
+
+__device__ __forceinline__ double from_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Adds floor(2^96 (x / mu)^2) to three 32-bit limb sums.
+__device__ __forceinline__ void add_sq_limbs(double x, double mu, unsigned long long (&l)[3]) {
+  const double t = x / mu;
+  const unsigned __int128 q = fix96(t * t);
+  l[0] += (unsigned long long)q & 0xFFFFFFFFull;
+  l[1] += (unsigned long long)(q >> 32) & 0xFFFFFFFFull;
+  l[2] += (unsigned long long)(q >> 64);
+}
+
+// ||x|| = mu * sqrt(rn(S)) * 2^-48 from the exact limb sums S (the
+// order-free FP64 norm; mu = max |x_i|).
+__device__ __forceinline__ double norm_from(const unsigned long long (&l)[3], double mu) {
+  if (!finite_pos(mu)) return mu;
+  const unsigned __int128 S =
+      ((unsigned __int128)l[2] << 64) + ((unsigned __int128)l[1] << 32) + (unsigned __int128)l[0];
+  return mu * ldexp(sqrt(u128_to_double_rn(S)), -48);
+}
+
+// Order-free norms of two register-resident vectors (rows >= n hold 0);
+// returns the norms and the maxima of |x|.
+template <int BLOCK, int R>
+__device__ __forceinline__ void team_norm2(Team &tm, TeamShared &sh, const double (&xa)[R], const double (&xb)[R],
+                                           double &na, double &nb, double &mua, double &mub) {
+  unsigned long long mx[2] = {0, 0};
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const unsigned long long ta = dbits(fabs(xa[k])), tb = dbits(fabs(xb[k]));
+    mx[0] = ta > mx[0] ? ta : mx[0];
+    mx[1] = tb > mx[1] ? tb : mx[1];
+  }
+  team_reduce<BLOCK, 2, true>(tm, sh, mx);
+  mua = from_bits(mx[0]);
+  mub = from_bits(mx[1]);
+  unsigned long long la[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+  if (finite_pos(mua)) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) add_sq_limbs(xa[k], mua, la);
+  }
+  if (finite_pos(mub)) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) add_sq_limbs(xb[k], mub, lb);
+  }
+  team_reduce<BLOCK, 3, false>(tm, sh, la);
+  team_reduce<BLOCK, 3, false>(tm, sh, lb);
+  na = norm_from(la, mua);
+  nb = norm_from(lb, mub);
+}
+
+template <int BLOCK, int R>
+__device__ __forceinline__ double team_norm1(Team &tm, TeamShared &sh, const double (&x)[R]) {
+  unsigned long long mx[1] = {0};
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const unsigned long long t = dbits(fabs(x[k]));
+    mx[0] = t > mx[0] ? t : mx[0];
+  }
+  team_reduce<BLOCK, 1, true>(tm, sh, mx);
+  const double mu = from_bits(mx[0]);
+  unsigned long long l[3] = {0, 0, 0};
+  if (finite_pos(mu)) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) add_sq_limbs(x[k], mu, l);
+  }
+  team_reduce<BLOCK, 3, false>(tm, sh, l);
+  return norm_from(l, mu);
+}
+
+// overflow events travel through the max-reductions as 2^53 - code (0 = none)
+constexpr int64_t kEvBias = (int64_t)1 << 53;
+
+}  // namespace
+
+template <int BLOCK, int R, int PRE>
+__global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
+  extern __shared__ int64_t smem[];
+  const int m = ba.m;
+  int64_t *sc = smem;                               // c_1..c_m
+  int64_t *ss = sc + m;                             // s_1..s_m
+  int64_t *sg = ss + m;                             // g_1..g_{m+1}
+  int64_t *col = sg + m + 1;                        // current column h_{1..j+1, j}
+  int64_t *sH = col + m + 1;                        // H, (m+1) x m, row-major
+  double *sy = (double *)(sH + (size_t)(m + 1) * m);  // y of lines 21-23
+  __shared__ TeamShared tsh;
+  __shared__ int sh_job, sh_stop, sh_jstar, sh_steps;
+  __shared__ long long sh_ovf;  // smallest overflow event of the current call in this workgroup
+
+  const int tid = threadIdx.x;
+  const int df = ba.df;
+
+  for (;;) {
+    if (tid == 0) sh_job = atomicAdd(ba.queue, 1);
+    team_init(tsh);
+    __syncthreads();
+    const int job = __builtin_amdgcn_readfirstlane(sh_job);  // uniform: lets the record load through scalar loads
+    if (job >= ba.njobs) break;
+    const int sid = ba.jobs[2 * job], member = ba.jobs[2 * job + 1];
+    const BatchSys &S = ba.sys[sid];
+    Team tm{S.words, S.team, member, 0, ba.timeout};
+    const int64_t n = S.n, ldv = S.ldv;
+    const int64_t TB = (int64_t)S.team * BLOCK;
+    const int64_t g0 = (int64_t)member * BLOCK + tid;
+    double *__restrict__ x = ba.x + S.x_off;
+    const uint64_t t_begin = wall_clock64();
+
+    // denominators of the two relative residuals
+    double nb, nbh;
+    {
+      double xa[R], xb[R], mua, mub;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = g0 + k * TB;
+        xa[k] = row < n ? S.b[row] : 0.0;
+        xb[k] = row < n ? S.bhat[row] : 0.0;
+      }
+      team_norm2<BLOCK, R>(tm, tsh, xa, xb, nb, nbh, mua, mub);
+    }
+
+    int status = IGM_NOT_CONVERGED, refinements = 0, iterations = 0, jstar_last = -1;
+    int64_t first_ovf = kNoEvent;
+    double ro = 0.0, rs = 0.0;
+    for (int kref = 0;; ++kref) {
+      if (tsh.abort) break;
+      // ---- eq. (b): r = b - A x and rhat = bhat - Ahat x, rows in CSR order
+      double r[R], rh[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = g0 + k * TB;
+        r[k] = 0.0;
+        rh[k] = 0.0;
+        if (row < n) {
+          double acc = 0.0, acch = 0.0;
+          for (int64_t e = S.row_ptr[row]; e < S.row_ptr[row + 1]; ++e) {
+            const double xv = x[S.col[e]];
+            acc = acc + S.a[e] * xv;
+            acch = acch + S.ahat[e] * xv;
+          }
+          r[k] = S.b[row] - acc;
+          rh[k] = S.bhat[row] - acch;
+        }
+      }
+      double nr, nrh, gamma, mu_rh;
+      team_norm2<BLOCK, R>(tm, tsh, r, rh, nr, nrh, gamma, mu_rh);
+      ro = relres_of(nrh, nbh);
+      rs = relres_of(nr, nb);
+      if (tsh.abort) break;
+      if (!(ro <= kDblMax && ro >= -kDblMax)) { status = IGM_ERR_RANGE; break; }
+      if (ro < ba.tol) { status = IGM_OK; break; }
+      if (kref >= ba.max_refine) { status = IGM_NOT_CONVERGED; break; }
+      // gamma = max |r| (eq. (gammak)); gamma == 0 means r == 0
+      if (gamma == 0.0) { status = IGM_OK; break; }
+      // ---- line 1': b^(k) = r / gamma, r0 = Mbar^-1 b^(k) in FP64
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = g0 + k * TB;
+        if (row < n) {
+          const double t = r[k] / gamma;
+          double u = t;
+          if (PRE == IGM_PRE_JACOBI) u = (t / (double)S.ldiag[row]) / (double)S.udiag[row];
+          r[k] = u;
+        }
+      }
+      const double rho = team_norm1<BLOCK, R>(tm, tsh, r);
+      if (tsh.abort) break;
+      if (!finite_pos(rho)) { status = IGM_ERR_RANGE; break; }
+      // ---- line 2: v1 = trunc(2^df r0 / rho)
+      {
+        unsigned long long rerr[1] = {0};
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const int64_t row = g0 + k * TB;
+          if (row < n) {
+            const double t = ldexp(r[k] / rho, df);
+            int64_t v = 0;
+            if (t >= -9223372036854775808.0 && t < 9223372036854775808.0) v = (int64_t)t;
+            else rerr[0] = 1;
+            S.V[row] = v;
+          }
+        }
+        team_reduce<BLOCK, 1, true>(tm, tsh, rerr);
+        if (rerr[0]) { status = IGM_ERR_RANGE; break; }
+      }
+
+      // ---- lines 3-20: the int-GMRES(m) call
+      if (tid == 0) {
+        for (int i = 0; i < m; ++i) { sc[i] = 0; ss[i] = 0; }
+        for (int i = 0; i <= m; ++i) { sg[i] = 0; col[i] = 0; }
+        sg[0] = (int64_t)1 << df;  // line 3
+        sh_stop = 0; sh_jstar = m; sh_steps = 0;
+        sh_ovf = (long long)kNoEvent;
+      }
+      team_barrier(tm, tsh);  // v1 visible to the team
+
+      const int sh_dot = df - ba.b_dot;
+      auto fin_dot = [&](int64_t Sv, bool &o) { return asr(Sv, sh_dot); };
+      auto fin_norm = [&](int64_t Sv, bool &o) { return shl(isqrt64(Sv), ba.b_norm, o); };
+      auto record = [&](int64_t code) { atomicMin(&sh_ovf, (long long)code); };
+
+      int64_t w[R];
+      int64_t carry = 0, hn = 0;
+      bool lucky = false;
+      // rotation i (1-based) of lines 12-14 on (carry, col[i]); thread kGivensThread only
+      auto rotate = [&](int j, int i) {
+        const int64_t x0 = asr(carry, ba.b_rot), x1 = asr(col[i], ba.b_rot);
+        const int64_t c = sc[i - 1], s = ss[i - 1];
+        bool o = false;
+        const int64_t ms = subc(0, s, o);
+        const int64_t top = addc(mulw(x0, c, o), mulw(x1, s, o), o);
+        const int64_t bot = addc(mulw(x0, ms, o), mulw(x1, c, o), o);
+        col[i - 1] = asr(top, df - ba.b_rot);
+        carry = asr(bot, df - ba.b_rot);
+        if (o) record(ev_code(j, 6, i));
+      };
+      // lines 15-19 for column j on (carry, hn); thread kGivensThread only
+      auto givens = [&](int j) {
+        col[j - 1] = carry;
+        col[j] = hn;
+        bool o = false;  // line 15
+        const int64_t p0 = asr(col[j - 1], ba.b_tmp), p1 = asr(col[j], ba.b_tmp);
+        const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
+        const int64_t tmp = shl(isqrt64(ssq), ba.b_tmp, o);
+        if (o) record(ev_code(j, 7, 0));
+        const int64_t den2 = asr(tmp, ba.b_cs_den);  // line 16
+        int stop = 0;
+        if (den2 == 0) {  // line 16 breakdown
+          sh_jstar = j - 1;
+          stop = 1;
+        } else {
+          bool oc = false;
+          const int e2 = df - ba.b_cs_num - ba.b_cs_den;
+          const int64_t cj = normalize_elem(col[j - 1], den2, ba.b_cs_num, e2, oc);
+          const int64_t sj = normalize_elem(col[j], den2, ba.b_cs_num, e2, oc);
+          if (oc) record(ev_code(j, 8, 0));
+          sc[j - 1] = cj;
+          ss[j - 1] = sj;
+          bool og = false;  // line 17, both from the old g_j
+          const int64_t gj = sg[j - 1];
+          const int64_t msj = subc(0, sj, og);
+          sg[j - 1] = asr(mulw(gj, cj, og), df);
+          sg[j] = asr(mulw(gj, msj, og), df);
+          if (og) record(ev_code(j, 9, 0));
+          col[j - 1] = tmp;  // lines 18-19
+          col[j] = 0;
+          if (lucky) {  // line 11 breakdown
+            sh_jstar = j;
+            stop = 1;
+          } else if (ba.gtol >= 0) {
+            const int64_t gn = sg[j] < 0 ? -sg[j] : sg[j];
+            if (gn <= ba.gtol) { sh_jstar = j; stop = 1; }
+          }
+        }
+        for (int i = 0; i <= j; ++i) sH[(size_t)i * m + (j - 1)] = col[i];
+        sh_steps = j;
+        sh_stop = stop;
+      };
+
+      for (int j = 1; j <= m; ++j) {  // line 4
+        const int64_t *__restrict__ vj = S.V + (size_t)(j - 1) * ldv;
+        // ---- line 5 / 5'
+        {
+          bool o1 = false, o2 = false;
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const int64_t row = g0 + k * TB;
+            int64_t z = 0;
+            if (row < n) {
+              z = spmv_row(S, row, vj, S.nterms, o1);
+              if (PRE == IGM_PRE_JACOBI) z = tdiv(tdiv(z, S.ldiag[row], o2), S.udiag[row], o2);
+            }
+            w[k] = z;
+          }
+          if (o1) record(ev_code(j, 1, 0));
+          if (o2) record(ev_code(j, 2, 0));
+        }
+        // ---- lines 6-9: modified Gram-Schmidt, i increasing; v_{i+1} is
+        // loaded before the reduction of (w, v_i) so its latency overlaps,
+        // and rotation i-2 of lines 12-14 runs inside the wait.
+        int64_t vv[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const int64_t row = g0 + k * TB;
+          vv[k] = row < n ? S.V[row] : 0;
+        }
+        for (int i = 1; i <= j; ++i) {
+          Acc acc;
+          acc.zero();
+          bool o = false;
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc.add(mulw(asr(w[k], ba.b_dot), vv[k], o));  // line 7: only w is shifted
+          if (o) record(ev_code(j, 3, 2 * (i - 1)));
+          int64_t vnext[R];
+          if (i < j) {
+            const int64_t *vi1 = S.V + (size_t)i * ldv;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+              const int64_t row = g0 + k * TB;
+              vnext[k] = row < n ? vi1[row] : 0;
+            }
+          }
+          bool os = false;
+          const int64_t h = team_sum<BLOCK>(tm, acc, tsh, fin_dot, [&] {
+            if (tid == kGivensThread && i >= 3) rotate(j, i - 2);
+          }, os);
+          if (os && tid == 0) record(ev_code(j, 3, 2 * (i - 1)));
+          if (tid == kGivensThread) {
+            col[i - 1] = h;
+            if (i == 1) carry = h;
+          }
+          // line 8: only h is shifted
+          const int64_t hs = asr(h, ba.b_axpy);
+          bool ou = false;
+#pragma unroll
+          for (int k = 0; k < R; ++k) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - ba.b_axpy), ou);
+          if (ou) record(ev_code(j, 3, 2 * (i - 1) + 1));
+          if (i < j) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) vv[k] = vnext[k];
+          }
+        }
+        // ---- line 10 (the last rotation j-1 runs during this reduction)
+        {
+          Acc acc;
+          acc.zero();
+          bool o = false;
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc.add(sqrc(asr(w[k], ba.b_norm), o));
+          if (o) record(ev_code(j, 4, 0));
+          bool os = false;
+          hn = team_sum<BLOCK>(tm, acc, tsh, fin_norm, [&] {
+            if (tid == kGivensThread && j >= 2) rotate(j, j - 1);
+          }, os);
+          if (os && tid == 0) record(ev_code(j, 4, 0));
+        }
+        // ---- line 11
+        const int64_t den = asr(hn, ba.b_div_den);
+        lucky = den == 0;
+        if (!lucky) {
+          int64_t *__restrict__ vn = S.V + (size_t)j * ldv;
+          const int e = df - ba.b_div_num - ba.b_div_den;
+          bool ov = false;
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const int64_t row = g0 + k * TB;
+            if (row < n) vn[row] = normalize_elem(w[k], den, ba.b_div_num, e, ov);
+          }
+          if (ov) record(ev_code(j, 5, 0));
+        }
+        // v_{j+1} becomes visible to the team; lines 15-19 run meanwhile
+        team_barrier(tm, tsh, [&] {
+          if (tid == kGivensThread) givens(j);
+        });
+        if (sh_stop || tsh.abort) break;
+      }
+      if (tsh.abort) break;
+
+      // the call's first overflow event over the team
+      int64_t ev;
+      {
+        unsigned long long e1[1] = {0};
+        if (tid == 0 && sh_ovf != (long long)kNoEvent) e1[0] = (unsigned long long)(kEvBias - (int64_t)sh_ovf);
+        team_reduce<BLOCK, 1, true>(tm, tsh, e1);
+        ev = e1[0] ? kEvBias - (int64_t)e1[0] : kNoEvent;
+      }
+      const int js = sh_jstar;
+      refinements += 1;
+      iterations += sh_steps;
+      jstar_last = js;
+      if (tsh.abort) break;
+      if (ev != kNoEvent) { first_ovf = ev; status = IGM_ERR_OVERFLOW; break; }
+      if (js == 0) { status = IGM_ERR_BREAKDOWN; break; }
+
+      // ---- lines 21-23 and x += gamma x^(k) (eq. (update))
+      if (tid == 0) {
+        for (int i = js - 1; i >= 0; --i) {  // back substitution, inner sum k increasing
+          double acc = 0.0;
+          for (int k = i + 1; k < js; ++k) acc = acc + ldexp((double)sH[(size_t)i * m + k], -df) * sy[k];
+          sy[i] = (ldexp((double)sg[i], -df) - acc) / ldexp((double)sH[(size_t)i * m + i], -df);
+        }
+        for (int i = 0; i < js; ++i) sy[i] = rho * sy[i];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = g0 + k * TB;
+        if (row < n) {
+          double acc = 0.0;
+          for (int i = 0; i < js; ++i) acc = acc + sy[i] * ldexp((double)S.V[(size_t)i * ldv + row], -df);
+          x[row] = x[row] + gamma * acc;
+        }
+      }
+      team_barrier(tm, tsh);  // x visible to the team
+    }
+    if (tsh.abort) status = IGM_ERR_DEVICE;
+    if (member == 0 && tid == 0) {
+      BatchResult &res = ba.res[sid];
+      res.status = status;
+      res.refinements = refinements;
+      res.iterations = iterations;
+      res.jstar = jstar_last;
+      res.first_ovf = first_ovf;
+      res.relres_orig = ro;
+      res.relres_scaled = rs;
+      res.t_begin = t_begin;
+      res.t_end = wall_clock64();
+    }
+    __syncthreads();
+  }
+}
+
+template <int BLOCK, int R, int PRE>
+static const void *batch_kernel_ptr() {
+  return (const void *)&k_batch<BLOCK, R, PRE>;
+}
+
+const int kBatchShapes[][2] = {{1024, 8}, {1024, 16}, {512, 8}, {512, 16}, {256, 16}};
+const int kNumBatchShapes = 5;
+
+const void *batch_kernel(int block, int R, int pre) {
+  if (pre == IGM_PRE_ILU0) return nullptr;
+#define IGM_K(BB, RR)                                                  \
+  if (block == BB && R == RR)                                          \
+    return pre == IGM_PRE_NONE ? batch_kernel_ptr<BB, RR, 0>() : batch_kernel_ptr<BB, RR, 1>();
+  IGM_K(1024, 8)
+  IGM_K(1024, 16)
+  IGM_K(512, 8)
+  IGM_K(512, 16)
+  IGM_K(256, 16)
+#undef IGM_K
+  return nullptr;
+}
+
+size_t batch_smem_bytes(int m) {
+  return sizeof(int64_t) * (4 * (size_t)m + 2 + (size_t)(m + 1) * m) + sizeof(double) * (size_t)m;
+}
+
+}  // namespace igm

@@ -55,6 +55,7 @@ igm_status host_setup(int64_t n, const std::vector<int64_t> &row_ptr, const std:
                       const std::vector<double> &ahat, const std::vector<double> &bhat, const igm_policy &pol,
                       HostSetup &out);
 igm_status check_policy(const igm_policy &p);
+igm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b);
 
 // Host-visible layout of an exact device partial sum (value = hi * 2^40 + lo).
 struct AccWords {

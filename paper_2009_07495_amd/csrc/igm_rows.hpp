@@ -11,7 +11,9 @@ namespace igm {
 // asr(A_l v, alpha_l), the matrices in SELL-64 layout (slice = 64 rows stored
 // column-major, so the 64 lanes of a wavefront read consecutive words). Every
 // sum is exact; `ovf` is set if a product, a term or the total leaves int64.
-__device__ __forceinline__ int64_t spmv_row(const CycleArgs &a, int64_t row, const int64_t *__restrict__ v,
+// `a` is any record with the SELL fields of CycleArgs.
+template <class A>
+__device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64_t *__restrict__ v,
                                             int nterms, bool &ovf) {
   const int64_t slice = row >> 6;
   const int64_t base = a.sell_off[slice] + (row & 63);

@@ -252,4 +252,22 @@ igm_status host_setup(int64_t n, const std::vector<int64_t> &rp, const std::vect
   return IGM_OK;
 }
 
+// CSR and right-hand side checks shared by every entry point that takes a
+// host system: rows and columns in range, columns strictly increasing within a
+// row, finite values.
+igm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b) {
+  if (n < 1 || n >= ((int64_t)1 << 31) || !rp || !col || !val || !b) return IGM_ERR_ARG;
+  if (rp[0] != 0) return IGM_ERR_ARG;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return IGM_ERR_ARG;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= n) return IGM_ERR_ARG;
+      if (e > rp[i] && col[e] <= col[e - 1]) return IGM_ERR_ARG;
+      if (!isfinite(val[e])) return IGM_ERR_ARG;
+    }
+    if (!isfinite(b[i])) return IGM_ERR_ARG;
+  }
+  return IGM_OK;
+}
+
 }  // namespace igm

@@ -1,0 +1,224 @@
+// Synchronisation inside a "team": the T workgroups (1 <= T <= kTeamMax) of
+// the batched solver that share one system.
+//
+// T == 1 (the common case) never touches global memory: every reduction is a
+// workgroup reduction through LDS and every barrier is __syncthreads().
+//
+// T > 1: member q publishes a payload word p by one relaxed agent-scope atomic
+// add of (payload << 10) + 1 to word [slot][16 p + q] of the system's exchange
+// area; the first wavefront of every member then polls the words of all
+// members (one load per lane) until each shows one new arrival. The words are
+// never cleared: every lane remembers the value it last saw in each slot (in
+// LDS) and decodes the difference. A slot is reused kTeamSlots exchanges
+// later; by then every member has finished reading it, because no member can
+// start exchange e + 2 before all members arrived at exchange e + 1. The area
+// must be zero when a system's first member starts (it is cleared before each
+// launch). Barriers that publish vectors to other members wrap the exchange in
+// agent-scope release/acquire fences. Every wait is bounded (kSpinLimit).
+#pragma once
+
+#include "igm_sync.hpp"
+
+namespace igm {
+
+constexpr int kTeamMax = 16;    // workgroups per system
+constexpr int kTeamSlots = 4;   // exchanges before a slot is reused
+constexpr int kTeamWords = 64;  // words per slot: 4 payload words x 16 members
+
+struct TeamShared {
+  Acc wave[16];                                     // per-wavefront partial sums
+  unsigned long long part[4][16];                   // per-wavefront partials of team_reduce
+  unsigned long long prev[kTeamSlots][kTeamWords];  // last value seen per exchange word
+  unsigned long long res[4];                        // team_reduce results
+  int64_t value;                                    // broadcast result of team_sum
+  int flag;                                         // broadcast overflow flag of team_sum
+  int abort;                                        // a wait timed out
+};
+
+struct Team {
+  unsigned long long *words;  // [kTeamSlots][kTeamWords]
+  int T, member, e;
+  int *timeout;               // device flag of the launch
+};
+
+__device__ __forceinline__ void team_init(TeamShared &sh) {
+  for (int i = threadIdx.x; i < kTeamSlots * kTeamWords; i += blockDim.x) (&sh.prev[0][0])[i] = 0;
+  if (threadIdx.x == 0) {
+    sh.abort = 0;
+    sh.flag = 0;
+  }
+}
+
+// One exchange among the T > 1 members; wavefront 0 only (all 64 lanes).
+// u0..u3 are this member's payload words (wave-uniform, |u| < 2^53), P <= 4 of
+// them are sent. Lane 16 p + q receives member q's payload word p (0 for
+// q >= T or p >= P). Sets `to` on timeout.
+__device__ __forceinline__ unsigned long long team_exchange(Team &tm, TeamShared &sh, int P, unsigned long long u0,
+                                                            unsigned long long u1, unsigned long long u2,
+                                                            unsigned long long u3, bool &to) {
+  const int lane = threadIdx.x & 63;
+  const int p = lane >> 4, q = lane & 15;
+  const int slot = tm.e % kTeamSlots;
+  tm.e += 1;
+  unsigned long long *w = tm.words + slot * kTeamWords + lane;
+  const bool used = p < P && q < tm.T;
+  const unsigned long long u = p == 0 ? u0 : p == 1 ? u1 : p == 2 ? u2 : u3;
+  if (p < P && q == tm.member) __hip_atomic_fetch_add(w, (u << 10) + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long prev = sh.prev[slot][lane];
+  unsigned long long d = 0;
+  for (int spin = 0;; ++spin) {
+    if (used) d = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - prev;
+    const bool ok = !used || (d & 1023ull) == 1ull;
+    if (__all(ok)) break;
+    if (spin >= kSpinLimit) { to = true; break; }
+    __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
+  }
+  if (used) sh.prev[slot][lane] = prev + d;
+  return used ? (unsigned long long)((int64_t)d >> 10) : 0ull;
+}
+
+__device__ __forceinline__ void team_abort(Team &tm, TeamShared &sh) {
+  sh.abort = 1;
+  __hip_atomic_store(tm.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum over each 16-lane row of a wavefront, left in every lane of the row.
+__device__ __forceinline__ int64_t row16_sum(int64_t v) {
+  v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp64<0x141>(v);  // row_half_mirror
+  v += dpp64<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Exact team sum of one Acc per thread, finished by fin(S, ovf) in one lane
+// and broadcast (value and overflow flag) to every thread of the workgroup.
+// Threads of wavefronts 1.. run `side` meanwhile.
+template <int BLOCK, class Fin, class Side>
+__device__ __forceinline__ int64_t team_sum(Team &tm, Acc a, TeamShared &sh, Fin fin, Side side, bool &ovf) {
+  static_assert(BLOCK / 64 <= 16, "one 16-lane row holds the wavefront partials");
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sh.wave[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    Acc p;
+    p.zero();
+    if (lane < BLOCK / 64) p = sh.wave[lane];
+    p.lo = readlane64(row16_sum(p.lo), 0);
+    p.hi = readlane64(row16_sum(p.hi), 0);
+    bool to = false;
+    if (tm.T > 1 && !sh.abort) {
+      p.normalize();  // lo in [0, 2^40)
+      const int64_t x = (int64_t)team_exchange(tm, sh, 2, (unsigned long long)p.lo, (unsigned long long)p.hi, 0, 0, to);
+      const int64_t v = row16_sum(x);  // row 0: lo limbs of the members, row 1: hi limbs
+      p.lo = readlane64(v, 0);
+      p.hi = readlane64(v, 16);
+    }
+    if (lane == 0) {
+      bool o = false;
+      const int64_t S = p.value(o);
+      sh.value = fin(S, o);
+      sh.flag = o;
+      if (to) team_abort(tm, sh);
+    }
+  } else {
+    side();
+  }
+  __syncthreads();
+  if (sh.flag) ovf = true;
+  return sh.value;
+}
+
+// Barrier of the team that also publishes global-memory writes to the other
+// members. Threads of wavefronts 1.. run `side` while wavefront 0 waits.
+template <class Side>
+__device__ __forceinline__ void team_barrier(Team &tm, TeamShared &sh, Side side) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (tm.T > 1 && !sh.abort) {
+      bool to = false;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      team_exchange(tm, sh, 1, 0, 0, 0, 0, to);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (threadIdx.x == 0 && to) team_abort(tm, sh);
+    }
+  } else {
+    side();
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void team_barrier(Team &tm, TeamShared &sh) {
+  team_barrier(tm, sh, [] {});
+}
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src) {
+  return (unsigned long long)__shfl((long long)v, src, 64);
+}
+
+template <bool MAX>
+__device__ __forceinline__ unsigned long long op_u64(unsigned long long a, unsigned long long b) {
+  return MAX ? (a > b ? a : b) : a + b;
+}
+
+// Reduction over `width` consecutive lanes (a power of two <= 64) with xor
+// shuffles; every lane of each group ends with its group's result.
+template <bool MAX>
+__device__ __forceinline__ unsigned long long lanes_reduce(unsigned long long v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1)
+    v = op_u64<MAX>(v, (unsigned long long)__shfl_xor((long long)v, o, 64));
+  return v;
+}
+
+// Team reduction of P unsigned words per thread (sum, or max), result in every
+// thread. Sums: each workgroup's partial of each word must stay below 2^53.
+// Maxima: any 64-bit value (sent as two 32-bit halves), P <= 2.
+template <int BLOCK, int P, bool MAX>
+__device__ __forceinline__ void team_reduce(Team &tm, TeamShared &sh, unsigned long long (&v)[P]) {
+  static_assert(P >= 1 && P <= (MAX ? 2 : 4), "payload words");
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    v[p] = lanes_reduce<MAX>(v[p], 64);
+    if (lane == 0) sh.part[p][threadIdx.x >> 6] = v[p];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    unsigned long long r[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) r[p] = lanes_reduce<MAX>(lane < BLOCK / 64 ? sh.part[p][lane] : 0ull, 64);
+    if (tm.T > 1 && !sh.abort) {
+      bool to = false;
+      unsigned long long x;
+      if (MAX) {  // words: lo0, hi0, lo1, hi1
+        const unsigned long long m = 0xFFFFFFFFull;
+        x = team_exchange(tm, sh, 2 * P, r[0] & m, r[0] >> 32, P > 1 ? (r[P - 1] & m) : 0,
+                          P > 1 ? (r[P - 1] >> 32) : 0, to);
+        // lane q (< 16) of row 2p joins its high half from row 2p + 1
+        const unsigned long long hi = shfl_u64(x, (lane + 16) & 63);
+        x = (lane >> 4) % 2 == 0 ? (x | (hi << 32)) : 0ull;
+        x = lanes_reduce<true>(x, 16);
+#pragma unroll
+        for (int p = 0; p < P; ++p) r[p] = shfl_u64(x, 32 * p);
+      } else {
+        x = team_exchange(tm, sh, P, r[0], P > 1 ? r[P > 1 ? 1 : 0] : 0, P > 2 ? r[P > 2 ? 2 : 0] : 0,
+                          P > 3 ? r[P > 3 ? 3 : 0] : 0, to);
+        x = lanes_reduce<false>(x, 16);
+#pragma unroll
+        for (int p = 0; p < P; ++p) r[p] = shfl_u64(x, 16 * p);
+      }
+      if (lane == 0 && to) team_abort(tm, sh);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) sh.res[p] = r[p];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < P; ++p) v[p] = sh.res[p];
+  __syncthreads();
+}
+
+}  // namespace igm

@@ -9,10 +9,13 @@ not available here; these seeded stencil families stand in for them:
 
 * ``poisson2d(nx, ny)``   5-point Laplacian, a_ii = 4, neighbours -1,
   Dirichlet boundaries eliminated; b = A * ones so the solution is all ones.
-* ``convdiff3d(nx, ny, nz, seed)`` 7-point convection-diffusion, nonsymmetric
-  M-matrix: cell diffusivity 10**U(-1, 1), harmonic-mean face values, cell
-  Peclet U(0.1, 2.0) per axis, central-difference convection with positive
-  velocity; b ~ U[-1, 1].
+* ``convdiff3d(nx, ny, nz, seed)`` / ``convdiff2d(nx, ny, seed)`` 7-point /
+  5-point convection-diffusion, nonsymmetric M-matrix: cell diffusivity
+  10**U(-1, 1), harmonic-mean face values (boundary faces take the cell
+  value), cell Peclet U(0.1, 2.0) per axis, central-difference convection
+  with positive velocity; b ~ U[-1, 1].
+* ``batch_systems(count, seed)`` many independent 2D/3D convection-diffusion
+  systems with log-uniform sizes (batched solver workload).
 * ``random27(nx, ny, nz, seed)`` 27-point pattern, off-diagonals N(0, 1),
   diagonal 1.1 * sum |off-diagonals|; b ~ U[-1, 1].
 * ``random_dd(n, density, seed)`` small unstructured diagonally dominant
@@ -95,25 +98,32 @@ def poisson2d(nx: int = 64, ny: int | None = None) -> System:
     return sysm
 
 
-def convdiff3d(nx: int = 64, ny: int | None = None, nz: int | None = None, seed: int = 2) -> System:
-    ny = nx if ny is None else ny
-    nz = nx if nz is None else nz
-    n = nx * ny * nz
-    rng = np.random.default_rng(seed)
+def _convdiff(dims, rng, name: str) -> System:
+    """Convection-diffusion on a 2D (5-point) or 3D (7-point) box grid; the
+    coefficient law of the module docstring, draws in the order cell
+    diffusivity, Peclet numbers (cell, axis), right-hand side."""
+    nd = len(dims)
+    n = int(np.prod(dims))
     dcell = 10.0 ** rng.uniform(-1.0, 1.0, size=n)
-    pe = rng.uniform(0.1, 2.0, size=(n, 3))
+    pe = rng.uniform(0.1, 2.0, size=(n, nd))
     b = rng.uniform(-1.0, 1.0, size=n)
-    dims = (nx, ny, nz)
-    strides = (1, nx, nx * ny)
+    strides = [int(np.prod(dims[:a])) for a in range(nd)]
     idx = np.arange(n)
-    coord = (idx % nx, (idx // nx) % ny, idx // (nx * ny))
-    offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
-    row_ptr, col, slot = _stencil_pattern(dims, offs)
+    coord = [(idx // strides[a]) % dims[a] for a in range(nd)]
+    offs = [(0, 0, 0)]
+    for a in range(nd):
+        e = [0, 0, 0]
+        e[a] = -1
+        offs.append(tuple(e))
+        e[a] = 1
+        offs.append(tuple(e))
+    box = tuple(dims) + (1,) * (3 - nd)
+    row_ptr, col, slot = _stencil_pattern(box, offs)
     rows = np.repeat(idx, np.diff(row_ptr))
     # per (cell, axis): face diffusivities toward +e and -e, convection term
-    dplus = np.empty((n, 3))
-    dminus = np.empty((n, 3))
-    for a in range(3):
+    dplus = np.empty((n, nd))
+    dminus = np.empty((n, nd))
+    for a in range(nd):
         c = coord[a]
         nb_p = np.minimum(idx + strides[a], n - 1)
         nb_m = np.maximum(idx - strides[a], 0)
@@ -123,9 +133,9 @@ def convdiff3d(nx: int = 64, ny: int | None = None, nz: int | None = None, seed:
         dminus[:, a] = np.where(c > 0, hm_m, dcell)
     p = pe * np.minimum(dplus, dminus) / 2.0
     diag = (dplus + dminus).sum(axis=1)
-    # slot k in offs: 1 = -x, 2 = +x, 3 = -y, 4 = +y, 5 = -z, 6 = +z
+    # slot k in offs: 0 = centre, 2a+1 = -e_a, 2a+2 = +e_a
     val = np.empty(len(col))
-    for k in range(7):
+    for k in range(2 * nd + 1):
         m = slot == k
         r = rows[m]
         if k == 0:
@@ -136,7 +146,39 @@ def convdiff3d(nx: int = 64, ny: int | None = None, nz: int | None = None, seed:
                 val[m] = -dplus[r, a] + p[r, a]
             else:  # -e neighbour
                 val[m] = -dminus[r, a] - p[r, a]
-    return System(f"convdiff3d_{nx}x{ny}x{nz}_s{seed}", n, row_ptr, col, val, b)
+    return System(name, n, row_ptr, col, val, b)
+
+
+def convdiff3d(nx: int = 64, ny: int | None = None, nz: int | None = None, seed: int = 2) -> System:
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    return _convdiff((nx, ny, nz), np.random.default_rng(seed), f"convdiff3d_{nx}x{ny}x{nz}_s{seed}")
+
+
+def convdiff2d(nx: int = 64, ny: int | None = None, seed: int = 2) -> System:
+    ny = nx if ny is None else ny
+    return _convdiff((nx, ny), np.random.default_rng(seed), f"convdiff2d_{nx}x{ny}_s{seed}")
+
+
+def batch_systems(count: int = 512, seed: int = 4, n_lo: int = 1024, n_hi: int = 65536) -> list:
+    """Independent systems for the batched solver: sizes log-uniform on
+    [n_lo, n_hi], each a 2D 5-point or a 3D 7-point convection-diffusion
+    system (probability 1/2 each) with the coefficient law above. System i
+    draws everything from child i of SeedSequence(seed): target size, family,
+    then its coefficients and right-hand side."""
+    out = []
+    for i, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
+        rng = np.random.default_rng(child)
+        nt = int(round(float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))))
+        if rng.random() < 0.5:
+            nx = max(1, int(round(np.sqrt(nt))))
+            ny = max(1, int(round(nt / nx)))
+            out.append(_convdiff((nx, ny), rng, f"b{i}_convdiff2d_{nx}x{ny}"))
+        else:
+            nx = max(1, int(round(nt ** (1.0 / 3.0))))
+            nz = max(1, int(round(nt / (nx * nx))))
+            out.append(_convdiff((nx, nx, nz), rng, f"b{i}_convdiff3d_{nx}x{nx}x{nz}"))
+    return out
 
 
 def random27(nx: int = 128, ny: int | None = None, nz: int = 64, seed: int = 3) -> System:

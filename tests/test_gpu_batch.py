@@ -1,0 +1,182 @@
+"""GPU parity of the batched solver (many independent systems, one persistent
+launch).
+
+Every system of a batch must come back with the oracle's solution bit for bit
+and the oracle's status, refinement and iteration counts and final relative
+residuals, whatever its team size (workgroups per system), the launch shape,
+and the other systems in the batch. The full 512-system workload is checked on
+sampled systems the oracle solves one by one, plus the convergence of all."""
+import numpy as np
+import pytest
+
+from paper_2009_07495_amd import binding as B
+from paper_2009_07495_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1024, 8), (1024, 16), (512, 8), (512, 16), (256, 16)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+
+    assert T.cuda.is_available(), "GPU tests need a HIP device"
+    return T
+
+
+def mixed_jacobi():
+    """Ragged sizes (not multiples of 64), 2D and 3D stencils, one
+    unstructured system, one single-row system."""
+    return [
+        W.convdiff2d(37, 29, seed=11),
+        W.convdiff3d(12, 11, 9, seed=12),
+        W.random_dd(301, 0.02, 13),
+        W.convdiff2d(91, 77, seed=14),       # 7007 rows: two workgroups at 4096 rows each
+        W.from_dense(np.array([[2.5]]), np.array([-1.5])),
+        W.convdiff3d(23, 19, 17, seed=15),   # 7429 rows
+        W.convdiff2d(5, 3, seed=16),
+    ]
+
+
+def oracle_solve(orc, s, preset, **kw):
+    o = orc.OracleSystem.from_system(s, orc.policy(preset, **kw))
+    return o.solve()
+
+
+def check_against_oracle(bt, x, systems, refs):
+    for i, (s, (xo, so)) in enumerate(zip(systems, refs)):
+        r = bt.result(i)
+        xi = x[bt.offsets[i]:bt.offsets[i + 1]]
+        assert r["status"] == so["status"], (i, s.name, r["status"], so["status"])
+        assert r["refinements"] == so["refinements"], (i, s.name)
+        assert r["iterations"] == so["iterations"], (i, s.name)
+        assert r["first_ovf"] == so["first_ovf"], (i, s.name)
+        assert r["relres_orig"] == so["relres_orig"] and r["relres_scaled"] == so["relres_scaled"], (i, s.name)
+        assert np.array_equal(xi, xo), (i, s.name, np.abs(xi - xo).max())
+
+
+@pytest.mark.parametrize("block,rows", SHAPES)
+def test_batch_bit_exact_every_shape(orc, torch, block, rows):
+    systems = mixed_jacobi()
+    refs = [oracle_solve(orc, s, "jacobi", m=20) for s in systems]
+    bt = B.Batch(systems, "jacobi", m=20)
+    assert bt.set_shape(block, rows) == B.OK
+    teams = [bt.result(i)["grid_blocks"] for i in range(bt.nsys)]
+    assert teams == [-(-s.n // (block * rows)) for s in systems]
+    x = torch.zeros(bt.total_n, dtype=torch.float64, device="cuda")
+    assert bt.solve_device(x) == B.OK
+    check_against_oracle(bt, x.cpu().numpy(), systems, refs)
+    # a second solve of the same batch from zero gives the same bits
+    x.zero_()
+    assert bt.solve_device(x) == B.OK
+    check_against_oracle(bt, x.cpu().numpy(), systems, refs)
+
+
+def test_batch_teams_of_many_workgroups(orc, torch):
+    """Systems split over up to 8 workgroups of 256 threads x 16 rows."""
+    systems = [W.convdiff2d(181, 179, seed=21), W.convdiff3d(20, 20, 13, seed=22), W.convdiff2d(30, 30, seed=23)]
+    refs = [oracle_solve(orc, s, "jacobi", m=30) for s in systems]
+    bt = B.Batch(systems, "jacobi", m=30)
+    assert bt.set_shape(256, 16) == B.OK
+    assert [bt.result(i)["grid_blocks"] for i in range(3)] == [8, 2, 1]
+    x, st = bt.solve()
+    assert st == B.OK
+    check_against_oracle(bt, x, systems, refs)
+
+
+def test_batch_paper_noprec_preset(orc, torch):
+    systems = [W.poisson2d(37, 29), W.poisson2d(20, 20), W.poisson2d(64)]
+    refs = [oracle_solve(orc, s, "paper_noprec", m=30) for s in systems]
+    bt = B.Batch(systems, "paper_noprec", m=30)
+    x, st = bt.solve()
+    assert st == B.OK
+    check_against_oracle(bt, x, systems, refs)
+    # Poisson right-hand sides are A * ones
+    assert np.abs(x - 1.0).max() < 1e-8
+
+
+def test_batch_matches_single_system_solver(torch):
+    systems = [W.convdiff3d(14, 13, 12, seed=31), W.convdiff2d(70, 61, seed=32)]
+    bt = B.Batch(systems, "jacobi", m=25)
+    xb, st = bt.solve()
+    assert st == B.OK
+    for i, s in enumerate(systems):
+        g = B.System.from_system(s, "jacobi", m=25)
+        xs, st1 = g.solve()
+        assert st1 == B.OK
+        assert np.array_equal(xb[bt.offsets[i]:bt.offsets[i + 1]], xs)
+        assert bt.result(i)["refinements"] == g.stats()["refinements"]
+
+
+def test_batch_status_cases(orc, torch):
+    """A breakdown system, a system stopped by the refinement limit and a
+    normal one in the same batch: each gets its own status; the batch returns
+    the first non-OK status in system order."""
+    n = 20
+    b = np.zeros(n)
+    b[5] = -2.0
+    brk = W.from_dense(3.0 * np.eye(n), b)        # A = cI: exact after one column
+    slow = W.convdiff3d(11, 10, 9, seed=41)
+    ok = W.convdiff2d(16, 15, seed=42)
+    systems = [ok, slow, brk]
+    kw = dict(m=5, max_refine=3)
+    refs = [oracle_solve(orc, s, "jacobi", **kw) for s in systems]
+    bt = B.Batch(systems, "jacobi", **kw)
+    x, st = bt.solve()
+    check_against_oracle(bt, x, systems, refs)
+    statuses = [r["status"] for r in bt.results()]
+    first_bad = next((s for s in statuses if s != B.OK), B.OK)
+    assert st == first_bad
+    assert refs[1][1]["status"] == B.NOT_CONVERGED
+
+
+def test_batch_start_iterate(orc, torch):
+    systems = [W.convdiff2d(33, 31, seed=51), W.convdiff3d(9, 9, 9, seed=52)]
+    bt = B.Batch(systems, "jacobi", m=10)
+    rng = np.random.default_rng(5)
+    x0 = rng.uniform(-1, 1, bt.total_n)
+    x, st = bt.solve(x0)
+    assert st == B.OK
+    for i, s in enumerate(systems):
+        o = orc.OracleSystem.from_system(s, orc.policy("jacobi", m=10))
+        xo, so = o.solve(x0[bt.offsets[i]:bt.offsets[i + 1]])
+        assert np.array_equal(x[bt.offsets[i]:bt.offsets[i + 1]], xo)
+        assert bt.result(i)["refinements"] == so["refinements"]
+
+
+def test_batch_rejects_bad_input(torch):
+    good = W.convdiff2d(8, 8, seed=1)
+    bad = W.convdiff2d(8, 8, seed=2)
+    bad.col = bad.col.copy()
+    bad.col[3] = 10_000  # column out of range
+    with pytest.raises(B.IgmError) as e:
+        B.Batch([good, bad], "jacobi", m=10)
+    assert e.value.status == B.ERR_ARG and "system 1" in str(e.value)
+    with pytest.raises(B.IgmError) as e:
+        B.Batch([good], "paper_ilu", m=10)
+    assert e.value.status == B.ERR_UNSUPPORTED
+    bt = B.Batch([good], "jacobi", m=10)
+    assert bt.set_shape(300, 8) == B.ERR_ARG
+    assert bt.set_shape(1024, 8) == B.OK
+
+
+@pytest.mark.slow
+def test_batch_full_512_sampled(orc, torch):
+    """The 512-system workload at full size: every system converges, the
+    launch shape is autotuned, and sampled systems (smallest, median,
+    largest, and a few more) equal the oracle bit for bit."""
+    systems = W.batch_systems(512, seed=4)
+    bt = B.Batch(systems, "jacobi", m=30)
+    block, rows = bt.autotune()
+    assert (block, rows) in SHAPES
+    x = torch.zeros(bt.total_n, dtype=torch.float64, device="cuda")
+    assert bt.solve_device(x) == B.OK
+    res = bt.results()
+    assert all(r["status"] == B.OK and r["relres_orig"] < 1e-10 for r in res)
+    xh = x.cpu().numpy()
+    order = np.argsort([s.n for s in systems])
+    for i in sorted({int(order[0]), int(order[len(order) // 2]), int(order[-1]), 7, 301}):
+        xo, so = oracle_solve(orc, systems[i], "jacobi", m=30)
+        assert np.array_equal(xh[bt.offsets[i]:bt.offsets[i + 1]], xo), (i, systems[i].name)
+        assert res[i]["refinements"] == so["refinements"] and res[i]["iterations"] == so["iterations"]
