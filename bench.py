@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0, help="cycle-kernel workgroups (0 = autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="also time the standalone SpMV and dot kernels")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batched solver section")
+    ap.add_argument("--batch-steps", type=int, default=3, help="timed solves of the whole batch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel for "
                          "calibrating hardware byte counters)")
@@ -192,14 +194,104 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": byts, "avg_launch_ms": avg_cycle_s * 1000.0},
     }
+    # where the time goes: one more solve with the phase clock on (not timed)
+    g.set_policy(B.make_policy(preset, m=m, grid_blocks=best[0], phase_clock=1))
+    x.zero_()
+    assert g.solve_device(x) == B.OK
     ph = g.stats()["phase_us"]
     out["cycle_phases_us"] = dict(zip(["spmv_precond", "mgs_local", "mgs_grid_wait", "norm", "normalize",
                                        "givens", "step_barrier", "total"], [round(v, 1) for v in ph]))
     if args.kernels:
         out["kernels"] = kernel_rates(torch, B, W)
+    if not args.no_batch:
+        out["batched"] = batched(torch, B, W, args.batch_steps, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysm, preset, m, int(round(refs / args.steps)))
     print(json.dumps(out))
+
+
+def batch_bytes(n: int, nnz: int, m: int, refinements: int) -> float:
+    """Algorithmic HBM bytes of one system's solve in the batched kernel
+    (Jacobi, one term): per refinement the int-GMRES call (see cycle_bytes)
+    plus the FP64 residual (20 B per nonzero, row pointers, b, bhat, x, 48 B
+    per row) and line 1'/2 (x, diagonals, v1)."""
+    return refinements * (cycle_bytes(n, nnz, m, 1, 0, 0, 1) + 20 * nnz + 48 * n + 40 * n)
+
+
+def batched(torch, B, W, steps: int, with_cpu: bool) -> dict:
+    """The 512-system workload (2D/3D convection-diffusion, n log-uniform in
+    [1k, 64k], Jacobi, GMRES(30)) solved by the batched persistent kernel,
+    beside the plain loop of single-system solves on the same GPU."""
+    systems = W.batch_systems(512, seed=4)
+    m = 30
+    bt = B.Batch(systems, "jacobi", m=m)
+    block, rows = bt.autotune()
+    x = torch.zeros(bt.total_n, dtype=torch.float64, device="cuda")
+    x.zero_()
+    assert bt.solve_device(x) == B.OK
+    times = []
+    for _ in range(steps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = bt.solve_device(x)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        assert rc == B.OK, rc
+    res = bt.results()
+    st = bt.stats()
+    t = float(np.median(times))
+    bt.set_phase_clock(True)
+    x.zero_()
+    assert bt.solve_device(x) == B.OK
+    names = ["spmv_precond", "mgs_local", "mgs_wait", "norm", "normalize", "fp64_refinement", "step_barrier", "total"]
+    ph = np.sum([r["phase_us"] for r in bt.results()], axis=0) / max(sum(r["refinements"] for r in res), 1)
+    byts = sum(batch_bytes(r["n"], r["nnz"], m, r["refinements"]) for r in res)
+    lat = np.array([r["time_solve_ms"] for r in res])
+    bt.close()
+    # plain loop: one single-system solve after another (system resident, setup not timed)
+    g0 = B.System.from_system(systems[0], "jacobi", m=m)
+    xw = torch.zeros(systems[0].n, dtype=torch.float64, device="cuda")
+    g0.solve_device(xw)
+    g0.close()
+    plain = 0.0
+    for s in systems:
+        g = B.System.from_system(s, "jacobi", m=m)
+        xs = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = g.solve_device(xs)
+        torch.cuda.synchronize()
+        plain += time.perf_counter() - t0
+        assert rc == B.OK, rc
+        g.close()
+    out = {"workload": f"batch512: 512 systems, n log-uniform [1k, 64k] (sum n {bt.total_n}), 2D 5-point / 3D 7-point "
+                       f"convection-diffusion, jacobi, GMRES({m})+FP64 IR, tol 1e-10",
+           "solves_per_s": len(systems) / t, "ms_per_batch": 1000.0 * t, "kernel_ms": st["time_kernel_ms"],
+           "plain_loop_solves_per_s": len(systems) / plain, "plain_loop_s": plain,
+           "speedup_vs_plain_loop": plain / t, "block": block, "rows_per_thread": rows,
+           "grid_blocks": st["grid_blocks"], "refinements": st["refinements"],
+           "max_relres": max(r["relres_orig"] for r in res),
+           "algorithmic_gb_s": byts / t / 1e9, "per_system_ms_p50": float(np.percentile(lat, 50)),
+           "per_system_ms_p99": float(np.percentile(lat, 99)),
+           "phases_us_per_refinement": dict(zip(names, [round(float(v), 1) for v in ph]))}
+    if with_cpu:
+        from oracle import oracle as O
+
+        sample = systems[:6]
+        t0 = time.perf_counter()
+        for s in sample:
+            O.OracleSystem.from_system(s, O.policy("jacobi", m=m)).solve()
+        dt = time.perf_counter() - t0
+        # the oracle's refinement counts equal the GPU's (bit-exact), so the
+        # work of a system scales with rows x refinements
+        work = [r["n"] * r["refinements"] for r in res]
+        scale = sum(work) / sum(work[: len(sample)])
+        out["cpu_baseline"] = {"value": len(systems) / (dt * scale), "unit": "solves/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"first {len(sample)} of the 512 systems ({dt:.1f} s), scaled by "
+                                         f"rows x refinements to the whole batch"}
+    return out
 
 
 def kernel_rates(torch, B, W) -> dict:

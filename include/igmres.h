@@ -88,7 +88,8 @@ typedef struct {
   int64_t gtol;         /* end a cycle early when |g_{j+1}| <= gtol (Sec. V-A); < 0 = never */
   double tol;           /* stop when ||bhat - Ahat x|| / ||bhat|| < tol (Sec. III) */
   int32_t grid_blocks;  /* launch tuning: workgroups of the cycle kernel; 0 = automatic */
-  int32_t reserved_[7];
+  int32_t phase_clock;  /* 1 = record where int-GMRES calls spend their time (igm_stats.phase_us); costs a few % */
+  int32_t reserved_[6];
 } igm_policy;
 
 /* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,
@@ -150,7 +151,8 @@ typedef struct {
   int32_t last_error_line; /* source line of the last HIP error, 0 if none */
   int32_t reserved0_;
   double time_kernel_ms;   /* GPU time of the kernels of the last kernel-level call (igm_spmv ...) */
-  /* Where the last int-GMRES call spent its time, seen by workgroup 0 (us):
+  /* Where the last int-GMRES call spent its time, seen by workgroup 0 (us;
+   * recorded only with igm_policy.phase_clock = 1, zeros otherwise):
    * 0 SpMV + preconditioner, 1 inner products and updates (local work),
    * 2 waits for the grid-wide inner-product sums, 3 norm, 4 normalisation,
    * 5 Givens rotations, 6 end-of-step barriers, 7 the whole call. */
@@ -262,6 +264,12 @@ igm_status igm_batch_set_stream(igm_batch *bt, void *hip_stream);
  * system would need more than 16 or the device cannot hold that many at once;
  * IGM_ERR_ARG for a shape not in the list. */
 igm_status igm_batch_set_shape(igm_batch *bt, int32_t block, int32_t rows_per_thread);
+
+/* Record (1) or not (0) per-phase clocks of each system's solve, returned in
+ * igm_batch_get_result's phase_us (0 SpMV + preconditioner, 1 inner products
+ * and updates, 2 waits for their sums, 3 norm, 4 normalisation, 5 FP64
+ * refinement steps, 6 end-of-step barriers, 7 whole solve). Costs a few %. */
+igm_status igm_batch_set_phase_clock(igm_batch *bt, int32_t on);
 
 /* Time one solve of the batch (from x = 0, in a buffer of the batch; the
  * caller's memory is not touched) with every usable shape and keep the

@@ -30,11 +30,11 @@ _POLICY_INT_FIELDS = ("df", "alpha_a", "s_terms", "m", "precond", "b_dot", "b_ax
 class Policy(C.Structure):
     _fields_ = ([("struct_size", C.c_int32)] + [(f, C.c_int32) for f in _POLICY_INT_FIELDS]
                 + [("gtol", C.c_int64), ("tol", C.c_double), ("grid_blocks", C.c_int32),
-                   ("reserved_", C.c_int32 * 7)])
+                   ("phase_clock", C.c_int32), ("reserved_", C.c_int32 * 6)])
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f in _POLICY_INT_FIELDS}
-        d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks)
+        d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks, phase_clock=self.phase_clock)
         return d
 
 
@@ -96,6 +96,7 @@ _SIGS = {
     "igm_batch_set_stream": [C.c_void_p, C.c_void_p],
     "igm_batch_set_shape": [C.c_void_p, C.c_int32, C.c_int32],
     "igm_batch_autotune": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_batch_set_phase_clock": [C.c_void_p, C.c_int32],
     "igm_batch_solve_device": [C.c_void_p, C.c_void_p],
     "igm_batch_solve": [C.c_void_p, C.c_void_p],
     "igm_batch_get_result": [C.c_void_p, C.c_int32, C.c_void_p],
@@ -352,6 +353,9 @@ class Batch:
 
     def set_shape(self, block: int, rows_per_thread: int) -> int:
         return lib().igm_batch_set_shape(self.h, int(block), int(rows_per_thread))
+
+    def set_phase_clock(self, on: bool):
+        _check(lib().igm_batch_set_phase_clock(self.h, int(bool(on))), "igm_batch_set_phase_clock")
 
     def autotune(self):
         b, r = C.c_int32(0), C.c_int32(0)

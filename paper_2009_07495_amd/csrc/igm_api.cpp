@@ -93,6 +93,7 @@ CycleArgs make_args(igm_system *s) {
   a.sync = s->d_sync;
   a.sync_cap = s->sync_cap;
   a.update = 0;
+  a.phase_clock = p.phase_clock;
   a.x = nullptr;
   a.scal = s->d_scal;
   return a;

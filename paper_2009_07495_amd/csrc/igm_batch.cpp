@@ -169,6 +169,7 @@ igm_status run(igm_batch *bt, double *x_dev) {
   a.b_div_num = p.b_div_num; a.b_div_den = p.b_div_den; a.b_rot = p.b_rot; a.b_tmp = p.b_tmp;
   a.b_cs_num = p.b_cs_num; a.b_cs_den = p.b_cs_den;
   a.max_refine = p.max_refine;
+  a.phase_clock = p.phase_clock;
   a.gtol = p.gtol;
   a.tol = p.tol;
   a.queue = bt->d_ctl;
@@ -422,6 +423,12 @@ igm_status igm_batch_set_shape(igm_batch *bt, int32_t block, int32_t rows_per_th
   return st;
 }
 
+igm_status igm_batch_set_phase_clock(igm_batch *bt, int32_t on) {
+  if (!bt || on < 0 || on > 1) return IGM_ERR_ARG;
+  bt->pol.phase_clock = on;
+  return IGM_OK;
+}
+
 igm_status igm_batch_autotune(igm_batch *bt, int32_t *block, int32_t *rows_per_thread) {
   if (!bt) return IGM_ERR_ARG;
   int best_b = bt->block, best_r = bt->rows;
@@ -482,6 +489,7 @@ igm_status igm_batch_get_result(const igm_batch *bt, int32_t i, igm_stats *out) 
   out->grid_blocks = bt->team.empty() ? 0 : bt->team[i];
   out->block_threads = bt->block;
   out->rows_per_thread = bt->rows;
+  for (int k = 0; k < 8; ++k) out->phase_us[k] = (double)r.phase[k] * bt->wall_us_per_tick;
   return IGM_OK;
 }
 

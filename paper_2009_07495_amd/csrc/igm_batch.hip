@@ -105,7 +105,7 @@ constexpr int64_t kEvBias = (int64_t)1 << 53;
 }  // namespace
 
 template <int BLOCK, int R, int PRE>
-__global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
+__global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
   extern __shared__ int64_t smem[];
   const int m = ba.m;
   int64_t *sc = smem;                               // c_1..c_m
@@ -133,8 +133,21 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
     const int64_t n = S.n, ldv = S.ldv;
     const int64_t TB = (int64_t)S.team * BLOCK;
     const int64_t g0 = (int64_t)member * BLOCK + tid;
+    // row slots k < nk hold at least one row of this wavefront (wave-uniform)
+    const int64_t wbase = (int64_t)member * BLOCK + (tid & ~63);
+    const int nk = __builtin_amdgcn_readfirstlane(
+        wbase < n ? (int)((n - wbase + TB - 1) / TB < R ? (n - wbase + TB - 1) / TB : R) : 0);
     double *__restrict__ x = ba.x + S.x_off;
     const uint64_t t_begin = wall_clock64();
+    const bool timer = ba.phase_clock && member == 0 && tid == 0;
+    uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t t_prev = t_begin;
+#define IGM_TICK(k)                      \
+  if (timer) {                           \
+    const uint64_t t_ = wall_clock64();  \
+    ph[k] += t_ - t_prev;                \
+    t_prev = t_;                         \
+  }
 
     // denominators of the two relative residuals
     double nb, nbh;
@@ -213,6 +226,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
         team_reduce<BLOCK, 1, true>(tm, tsh, rerr);
         if (rerr[0]) { status = IGM_ERR_RANGE; break; }
       }
+      IGM_TICK(5)
 
       // ---- lines 3-20: the int-GMRES(m) call
       if (tid == 0) {
@@ -305,6 +319,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
           if (o1) record(ev_code(j, 1, 0));
           if (o2) record(ev_code(j, 2, 0));
         }
+        IGM_TICK(0)
         // ---- lines 6-9: modified Gram-Schmidt, i increasing; v_{i+1} is
         // loaded before the reduction of (w, v_i) so its latency overlaps,
         // and rotation i-2 of lines 12-14 runs inside the wait.
@@ -319,7 +334,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
           acc.zero();
           bool o = false;
 #pragma unroll
-          for (int k = 0; k < R; ++k) acc.add(mulw(asr(w[k], ba.b_dot), vv[k], o));  // line 7: only w is shifted
+          for (int k = 0; k < R; ++k)  // line 7: only w is shifted
+            if (k < nk) acc.add(mulw(asr(w[k], ba.b_dot), vv[k], o));
           if (o) record(ev_code(j, 3, 2 * (i - 1)));
           int64_t vnext[R];
           if (i < j) {
@@ -330,10 +346,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
               vnext[k] = row < n ? vi1[row] : 0;
             }
           }
+          IGM_TICK(1)
           bool os = false;
           const int64_t h = team_sum<BLOCK>(tm, acc, tsh, fin_dot, [&] {
             if (tid == kGivensThread && i >= 3) rotate(j, i - 2);
           }, os);
+          IGM_TICK(2)
           if (os && tid == 0) record(ev_code(j, 3, 2 * (i - 1)));
           if (tid == kGivensThread) {
             col[i - 1] = h;
@@ -343,12 +361,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
           const int64_t hs = asr(h, ba.b_axpy);
           bool ou = false;
 #pragma unroll
-          for (int k = 0; k < R; ++k) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - ba.b_axpy), ou);
+          for (int k = 0; k < R; ++k)
+            if (k < nk) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - ba.b_axpy), ou);
           if (ou) record(ev_code(j, 3, 2 * (i - 1) + 1));
           if (i < j) {
 #pragma unroll
             for (int k = 0; k < R; ++k) vv[k] = vnext[k];
           }
+          IGM_TICK(1)
         }
         // ---- line 10 (the last rotation j-1 runs during this reduction)
         {
@@ -356,7 +376,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
           acc.zero();
           bool o = false;
 #pragma unroll
-          for (int k = 0; k < R; ++k) acc.add(sqrc(asr(w[k], ba.b_norm), o));
+          for (int k = 0; k < R; ++k)
+            if (k < nk) acc.add(sqrc(asr(w[k], ba.b_norm), o));
           if (o) record(ev_code(j, 4, 0));
           bool os = false;
           hn = team_sum<BLOCK>(tm, acc, tsh, fin_norm, [&] {
@@ -364,6 +385,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
           }, os);
           if (os && tid == 0) record(ev_code(j, 4, 0));
         }
+        IGM_TICK(3)
         // ---- line 11
         const int64_t den = asr(hn, ba.b_div_den);
         lucky = den == 0;
@@ -378,10 +400,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
           }
           if (ov) record(ev_code(j, 5, 0));
         }
+        IGM_TICK(4)
         // v_{j+1} becomes visible to the team; lines 15-19 run meanwhile
         team_barrier(tm, tsh, [&] {
           if (tid == kGivensThread) givens(j);
         });
+        IGM_TICK(6)
         if (sh_stop || tsh.abort) break;
       }
       if (tsh.abort) break;
@@ -422,7 +446,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
         }
       }
       team_barrier(tm, tsh);  // x visible to the team
+      IGM_TICK(5)
     }
+#undef IGM_TICK
     if (tsh.abort) status = IGM_ERR_DEVICE;
     if (member == 0 && tid == 0) {
       BatchResult &res = ba.res[sid];
@@ -435,6 +461,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs ba) {
       res.relres_scaled = rs;
       res.t_begin = t_begin;
       res.t_end = wall_clock64();
+      for (int k = 0; k < 7; ++k) res.phase[k] = ph[k];
+      res.phase[7] = res.t_end - t_begin;
     }
     __syncthreads();
   }
@@ -445,7 +473,7 @@ static const void *batch_kernel_ptr() {
   return (const void *)&k_batch<BLOCK, R, PRE>;
 }
 
-const int kBatchShapes[][2] = {{1024, 8}, {1024, 16}, {512, 8}, {512, 16}, {256, 16}};
+const int kBatchShapes[][2] = {{1024, 8}, {1024, 4}, {512, 8}, {256, 8}, {256, 16}};
 const int kNumBatchShapes = 5;
 
 const void *batch_kernel(int block, int R, int pre) {
@@ -454,9 +482,9 @@ const void *batch_kernel(int block, int R, int pre) {
   if (block == BB && R == RR)                                          \
     return pre == IGM_PRE_NONE ? batch_kernel_ptr<BB, RR, 0>() : batch_kernel_ptr<BB, RR, 1>();
   IGM_K(1024, 8)
-  IGM_K(1024, 16)
+  IGM_K(1024, 4)
   IGM_K(512, 8)
-  IGM_K(512, 16)
+  IGM_K(256, 8)
   IGM_K(256, 16)
 #undef IGM_K
   return nullptr;

@@ -34,6 +34,11 @@ struct BatchResult {
   int64_t first_ovf;
   double relres_orig, relres_scaled;
   uint64_t t_begin, t_end;  // device wall clock (start and end of the solve)
+  // wall-clock ticks of the first member's thread 0 per phase: 0 SpMV +
+  // preconditioner, 1 inner products and updates (local work), 2 waits for
+  // the inner-product sums, 3 norm, 4 normalisation, 5 FP64 refinement steps
+  // (residual, norms, lines 1'-2, lines 21-23), 6 end-of-step barriers
+  uint64_t phase[8];
 };
 
 struct BatchArgs {
@@ -43,6 +48,7 @@ struct BatchArgs {
   int32_t m, df, precond;
   int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
   int32_t max_refine;
+  int32_t phase_clock;  // record the phase clocks of each system's first member
   int64_t gtol;
   double tol;
   int32_t *queue;  // next job to claim

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   int64_t *first = &a.state->first_ovf;
   GridSync gs{a.sync, a.sync_cap, (int)gridDim.x, 0, &a.state->timeout};
   // phase clock of thread 0 of workgroup 0 (100 MHz wall clock)
-  const bool timer = blockIdx.x == 0 && tid == 0;
+  const bool timer = a.phase_clock && blockIdx.x == 0 && tid == 0;
   uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const uint64_t t_start = timer ? wall_clock64() : 0;
   uint64_t t_prev = t_start;

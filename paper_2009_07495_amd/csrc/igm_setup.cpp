@@ -24,6 +24,7 @@ igm_status check_policy(const igm_policy &p) {
   if (!shift_ok(p.b_div_num, 62) || !shift_ok(p.b_div_den, 62)) return IGM_ERR_ARG;
   if (!shift_ok(p.b_cs_num, 62) || !shift_ok(p.b_cs_den, 62)) return IGM_ERR_ARG;
   if (p.max_refine < 0 || !(p.tol >= 0.0) || p.grid_blocks < 0) return IGM_ERR_ARG;
+  if (p.phase_clock < 0 || p.phase_clock > 1) return IGM_ERR_ARG;
   return IGM_OK;
 }
 

@@ -4,45 +4,47 @@
 // T == 1 (the common case) never touches global memory: every reduction is a
 // workgroup reduction through LDS and every barrier is __syncthreads().
 //
-// T > 1: member q publishes a payload word p by one relaxed agent-scope atomic
-// add of (payload << 10) + 1 to word [slot][16 p + q] of the system's exchange
-// area; the first wavefront of every member then polls the words of all
-// members (one load per lane) until each shows one new arrival. The words are
-// never cleared: every lane remembers the value it last saw in each slot (in
-// LDS) and decodes the difference. A slot is reused kTeamSlots exchanges
-// later; by then every member has finished reading it, because no member can
-// start exchange e + 2 before all members arrived at exchange e + 1. The area
-// must be zero when a system's first member starts (it is cleared before each
-// launch). Barriers that publish vectors to other members wrap the exchange in
-// agent-scope release/acquire fences. Every wait is bounded (kSpinLimit).
+// T > 1: member q publishes payload word p by one relaxed agent-scope atomic
+// add of (payload << 10) + 1 to word [slot][p][q] of the system's exchange
+// area; lane q of the first wavefront of every member then polls member q's
+// words until each shows one new arrival, so every lane ends up holding one
+// member's payload. The words are never cleared: every lane remembers the
+// value it last saw in each slot (in LDS) and decodes the difference. A slot
+// is reused kTeamSlots exchanges later; by then every member has finished
+// reading it, because no member can start exchange e + 2 before all members
+// arrived at exchange e + 1. The area must be zero when a system's first
+// member starts (it is cleared before each launch). Barriers that publish
+// vectors to other members wrap the exchange in agent-scope release/acquire
+// fences. Every wait is bounded (kSpinLimit).
 #pragma once
 
 #include "igm_sync.hpp"
 
 namespace igm {
 
-constexpr int kTeamMax = 16;    // workgroups per system
+constexpr int kTeamMax = 64;    // workgroups per system (one lane each)
 constexpr int kTeamSlots = 4;   // exchanges before a slot is reused
-constexpr int kTeamWords = 64;  // words per slot: 4 payload words x 16 members
+constexpr int kTeamPay = 4;     // payload words per exchange
+constexpr int kTeamWords = kTeamPay * kTeamMax;  // words per slot
 
 struct TeamShared {
-  Acc wave[16];                                     // per-wavefront partial sums
-  unsigned long long part[4][16];                   // per-wavefront partials of team_reduce
-  unsigned long long prev[kTeamSlots][kTeamWords];  // last value seen per exchange word
-  unsigned long long res[4];                        // team_reduce results
-  int64_t value;                                    // broadcast result of team_sum
-  int flag;                                         // broadcast overflow flag of team_sum
-  int abort;                                        // a wait timed out
+  Acc wave[16];                                             // per-wavefront partial sums
+  unsigned long long part[4][16];                           // per-wavefront partials of team_reduce
+  unsigned long long prev[kTeamSlots][kTeamPay][kTeamMax];  // last value seen per exchange word
+  unsigned long long res[4];                                // team_reduce results
+  int64_t value;                                            // broadcast result of team_sum
+  int flag;                                                 // broadcast overflow flag of team_sum
+  int abort;                                                // a wait timed out
 };
 
 struct Team {
-  unsigned long long *words;  // [kTeamSlots][kTeamWords]
+  unsigned long long *words;  // [kTeamSlots][kTeamPay][kTeamMax]
   int T, member, e;
   int *timeout;               // device flag of the launch
 };
 
 __device__ __forceinline__ void team_init(TeamShared &sh) {
-  for (int i = threadIdx.x; i < kTeamSlots * kTeamWords; i += blockDim.x) (&sh.prev[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < kTeamSlots * kTeamWords; i += blockDim.x) (&sh.prev[0][0][0])[i] = 0;
   if (threadIdx.x == 0) {
     sh.abort = 0;
     sh.flag = 0;
@@ -50,31 +52,43 @@ __device__ __forceinline__ void team_init(TeamShared &sh) {
 }
 
 // One exchange among the T > 1 members; wavefront 0 only (all 64 lanes).
-// u0..u3 are this member's payload words (wave-uniform, |u| < 2^53), P <= 4 of
-// them are sent. Lane 16 p + q receives member q's payload word p (0 for
-// q >= T or p >= P). Sets `to` on timeout.
-__device__ __forceinline__ unsigned long long team_exchange(Team &tm, TeamShared &sh, int P, unsigned long long u0,
-                                                            unsigned long long u1, unsigned long long u2,
-                                                            unsigned long long u3, bool &to) {
-  const int lane = threadIdx.x & 63;
-  const int p = lane >> 4, q = lane & 15;
+// u[0..P) are this member's payload words (wave-uniform, |u| < 2^53). On
+// return lane q holds member q's payload words in u[0..P) (zeros for
+// q >= T). Sets `to` on timeout.
+template <int P>
+__device__ __forceinline__ void team_exchange(Team &tm, TeamShared &sh, unsigned long long (&u)[P], bool &to) {
+  static_assert(P >= 1 && P <= kTeamPay, "payload words");
+  const int q = threadIdx.x & 63;
   const int slot = tm.e % kTeamSlots;
   tm.e += 1;
-  unsigned long long *w = tm.words + slot * kTeamWords + lane;
-  const bool used = p < P && q < tm.T;
-  const unsigned long long u = p == 0 ? u0 : p == 1 ? u1 : p == 2 ? u2 : u3;
-  if (p < P && q == tm.member) __hip_atomic_fetch_add(w, (u << 10) + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const unsigned long long prev = sh.prev[slot][lane];
-  unsigned long long d = 0;
+  unsigned long long *w = tm.words + slot * kTeamWords + q;
+  if (q == tm.member) {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      __hip_atomic_fetch_add(w + p * kTeamMax, (u[p] << 10) + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const bool used = q < tm.T;
+  unsigned long long d[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) d[p] = 0;
   for (int spin = 0;; ++spin) {
-    if (used) d = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - prev;
-    const bool ok = !used || (d & 1023ull) == 1ull;
+    bool ok = true;
+    if (used) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        d[p] = __hip_atomic_load(w + p * kTeamMax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - sh.prev[slot][p][q];
+        ok = ok && (d[p] & 1023ull) == 1ull;
+      }
+    }
     if (__all(ok)) break;
     if (spin >= kSpinLimit) { to = true; break; }
     __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
   }
-  if (used) sh.prev[slot][lane] = prev + d;
-  return used ? (unsigned long long)((int64_t)d >> 10) : 0ull;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (used) sh.prev[slot][p][q] += d[p];
+    u[p] = used ? (unsigned long long)((int64_t)d[p] >> 10) : 0ull;
+  }
 }
 
 __device__ __forceinline__ void team_abort(Team &tm, TeamShared &sh) {
@@ -110,10 +124,10 @@ __device__ __forceinline__ int64_t team_sum(Team &tm, Acc a, TeamShared &sh, Fin
     bool to = false;
     if (tm.T > 1 && !sh.abort) {
       p.normalize();  // lo in [0, 2^40)
-      const int64_t x = (int64_t)team_exchange(tm, sh, 2, (unsigned long long)p.lo, (unsigned long long)p.hi, 0, 0, to);
-      const int64_t v = row16_sum(x);  // row 0: lo limbs of the members, row 1: hi limbs
-      p.lo = readlane64(v, 0);
-      p.hi = readlane64(v, 16);
+      unsigned long long u[2] = {(unsigned long long)p.lo, (unsigned long long)p.hi};
+      team_exchange<2>(tm, sh, u, to);  // lane q: member q's limbs
+      p.lo = wave_sum64((int64_t)u[0]);
+      p.hi = wave_sum64((int64_t)u[1]);
     }
     if (lane == 0) {
       bool o = false;
@@ -138,8 +152,9 @@ __device__ __forceinline__ void team_barrier(Team &tm, TeamShared &sh, Side side
   if (threadIdx.x < 64) {
     if (tm.T > 1 && !sh.abort) {
       bool to = false;
+      unsigned long long u[1] = {0};
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      team_exchange(tm, sh, 1, 0, 0, 0, 0, to);
+      team_exchange<1>(tm, sh, u, to);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (threadIdx.x == 0 && to) team_abort(tm, sh);
     }
@@ -151,10 +166,6 @@ __device__ __forceinline__ void team_barrier(Team &tm, TeamShared &sh, Side side
 
 __device__ __forceinline__ void team_barrier(Team &tm, TeamShared &sh) {
   team_barrier(tm, sh, [] {});
-}
-
-__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src) {
-  return (unsigned long long)__shfl((long long)v, src, 64);
 }
 
 template <bool MAX>
@@ -190,23 +201,20 @@ __device__ __forceinline__ void team_reduce(Team &tm, TeamShared &sh, unsigned l
     for (int p = 0; p < P; ++p) r[p] = lanes_reduce<MAX>(lane < BLOCK / 64 ? sh.part[p][lane] : 0ull, 64);
     if (tm.T > 1 && !sh.abort) {
       bool to = false;
-      unsigned long long x;
-      if (MAX) {  // words: lo0, hi0, lo1, hi1
-        const unsigned long long m = 0xFFFFFFFFull;
-        x = team_exchange(tm, sh, 2 * P, r[0] & m, r[0] >> 32, P > 1 ? (r[P - 1] & m) : 0,
-                          P > 1 ? (r[P - 1] >> 32) : 0, to);
-        // lane q (< 16) of row 2p joins its high half from row 2p + 1
-        const unsigned long long hi = shfl_u64(x, (lane + 16) & 63);
-        x = (lane >> 4) % 2 == 0 ? (x | (hi << 32)) : 0ull;
-        x = lanes_reduce<true>(x, 16);
+      if constexpr (MAX) {  // each value travels as two 32-bit halves
+        unsigned long long u[2 * P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) r[p] = shfl_u64(x, 32 * p);
+        for (int p = 0; p < P; ++p) {
+          u[2 * p] = r[p] & 0xFFFFFFFFull;
+          u[2 * p + 1] = r[p] >> 32;
+        }
+        team_exchange<2 * P>(tm, sh, u, to);
+#pragma unroll
+        for (int p = 0; p < P; ++p) r[p] = lanes_reduce<true>(u[2 * p] | (u[2 * p + 1] << 32), 64);
       } else {
-        x = team_exchange(tm, sh, P, r[0], P > 1 ? r[P > 1 ? 1 : 0] : 0, P > 2 ? r[P > 2 ? 2 : 0] : 0,
-                          P > 3 ? r[P > 3 ? 3 : 0] : 0, to);
-        x = lanes_reduce<false>(x, 16);
+        team_exchange<P>(tm, sh, r, to);
 #pragma unroll
-        for (int p = 0; p < P; ++p) r[p] = shfl_u64(x, 16 * p);
+        for (int p = 0; p < P; ++p) r[p] = lanes_reduce<false>(r[p], 64);
       }
       if (lane == 0 && to) team_abort(tm, sh);
     }

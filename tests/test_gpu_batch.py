@@ -14,7 +14,7 @@ from paper_2009_07495_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(1024, 8), (1024, 16), (512, 8), (512, 16), (256, 16)]
+SHAPES = [(1024, 8), (1024, 4), (512, 8), (256, 8), (256, 16)]
 
 
 @pytest.fixture(scope="module")
@@ -74,15 +74,18 @@ def test_batch_bit_exact_every_shape(orc, torch, block, rows):
 
 
 def test_batch_teams_of_many_workgroups(orc, torch):
-    """Systems split over up to 8 workgroups of 256 threads x 16 rows."""
-    systems = [W.convdiff2d(181, 179, seed=21), W.convdiff3d(20, 20, 13, seed=22), W.convdiff2d(30, 30, seed=23)]
+    """Systems split over up to 25 workgroups of 256 threads x 8 rows (and
+    8 workgroups of 256 x 16)."""
+    systems = [W.convdiff2d(181, 179, seed=21), W.convdiff3d(20, 20, 13, seed=22), W.convdiff2d(30, 30, seed=23),
+               W.convdiff3d(37, 37, 37, seed=24)]
     refs = [oracle_solve(orc, s, "jacobi", m=30) for s in systems]
     bt = B.Batch(systems, "jacobi", m=30)
-    assert bt.set_shape(256, 16) == B.OK
-    assert [bt.result(i)["grid_blocks"] for i in range(3)] == [8, 2, 1]
-    x, st = bt.solve()
-    assert st == B.OK
-    check_against_oracle(bt, x, systems, refs)
+    for shape, teams in (((256, 16), [8, 2, 1, 13]), ((256, 8), [16, 3, 1, 25])):
+        assert bt.set_shape(*shape) == B.OK
+        assert [bt.result(i)["grid_blocks"] for i in range(4)] == teams
+        x, st = bt.solve()
+        assert st == B.OK
+        check_against_oracle(bt, x, systems, refs)
 
 
 def test_batch_paper_noprec_preset(orc, torch):
