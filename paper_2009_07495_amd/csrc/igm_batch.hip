@@ -312,7 +312,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
             int64_t z = 0;
             if (row < n) {
               z = spmv_row(S, row, vj, S.nterms, o1);
-              if (PRE == IGM_PRE_JACOBI) z = tdiv(tdiv(z, S.ldiag[row], o2), S.udiag[row], o2);
+              if (PRE == IGM_PRE_JACOBI) z = tdiv_diag(tdiv_diag(z, S.ldiag[row], o2), S.udiag[row], o2);
             }
             w[k] = z;
           }

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       for (int k = 0; k < R; ++k) {  // padded rows: empty slices, unit diagonals
         const int64_t row = gt + k * T;
         int64_t z = spmv_row(a, row, vj, a.nterms, o1);
-        if (PRE == IGM_PRE_JACOBI) z = tdiv(tdiv(z, a.ldiag[row], o2), a.udiag[row], o2);
+        if (PRE == IGM_PRE_JACOBI) z = tdiv_diag(tdiv_diag(z, a.ldiag[row], o2), a.udiag[row], o2);
         w[k] = z;
       }
       if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));

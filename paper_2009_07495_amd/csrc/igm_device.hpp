@@ -83,6 +83,15 @@ __device__ __forceinline__ int64_t tdiv(int64_t a, int64_t d, bool &ovf) {
   return a / d;
 }
 
+// tdiv for a divisor that is usually a power of two (the cast Jacobi
+// diagonals of diagonally dominant stencil matrices): for d = 2^k > 0 the
+// truncating quotient is (a + (d - 1 if a < 0)) >> k, exactly; other divisors
+// take the general division.
+__device__ __forceinline__ int64_t tdiv_diag(int64_t a, int64_t d, bool &ovf) {
+  if (d > 0 && (d & (d - 1)) == 0) return (a + ((a >> 63) & (d - 1))) >> __builtin_ctzll((uint64_t)d);
+  return tdiv(a, d, ovf);
+}
+
 // floor(sqrt(x)) by the bitwise (digit-by-digit) method, integers only;
 // x <= 0 gives 0.
 __device__ __forceinline__ int64_t isqrt64(int64_t xs) {

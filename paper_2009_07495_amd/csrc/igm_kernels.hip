@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kB) void k_spmv(CycleArgs a, int nterms, const int6
 __global__ __launch_bounds__(kB) void k_diag_solve(CycleArgs a, const int64_t *__restrict__ z, int64_t *w) {
   bool o = false;
   for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
-    w[row] = a.precond == IGM_PRE_NONE ? z[row] : tdiv(tdiv(z[row], a.ldiag[row], o), a.udiag[row], o);
+    w[row] = a.precond == IGM_PRE_NONE ? z[row] : tdiv_diag(tdiv_diag(z[row], a.ldiag[row], o), a.udiag[row], o);
   if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 2, 0));
 }
 

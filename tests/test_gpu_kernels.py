@@ -18,6 +18,9 @@ SYSTEMS = [
     ("cd_10x9x7", lambda: W.convdiff3d(10, 9, 7, seed=4), "jacobi", {}),
     ("r27_9x7x5", lambda: W.random27(9, 7, 5, seed=5), "paper_ilu", {}),
     ("dd_200_multiterm", lambda: W.random_dd(200, 0.04, 6), "paper_noprec", dict(s_terms=3)),
+    # Jacobi with diagonals that are not the row maximum and of both signs:
+    # cast diagonals that are not powers of two (general division path)
+    ("dd_weakdiag_jacobi", lambda: W.random_dd(257, 0.05, 7, dominance=0.1, nonneg_diag=False), "jacobi", {}),
 ]
 
 
