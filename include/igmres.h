@@ -235,11 +235,11 @@ void igm_destroy(igm_system *s);
 
 /* ---- Batched solver: many independent systems in one persistent launch ----
  * Fig. 1 and Fig. 2 applied to every system of a batch independently, with
- * one shared policy (no preconditioner or Jacobi; the ILU(0) level sweeps are
- * not batched). Each system is solved by a team of 1..16 workgroups that claim
- * it from a device-side queue, largest systems first; all refinements of a
- * system run inside the launch. The results of a system are bit-identical to
- * those of igm_solve_device on that system alone. */
+ * one shared policy (any preconditioner; m <= 64). Each system is solved by a
+ * team of 1..256 workgroups that claim it from a device-side queue, largest
+ * systems first; all refinements of a system run inside the launch. The
+ * results of a system are bit-identical to those of igm_solve_device on that
+ * system alone. */
 typedef struct igm_batch igm_batch;
 
 /* Build a batch of nsys >= 1 systems from host arrays laid end to end:
@@ -248,9 +248,8 @@ typedef struct igm_batch igm_batch;
  * entries of each system in turn; b holds the n_s entries of each right-hand
  * side in turn. Every system is set up and validated as igm_create_system
  * would (same errors); *failed (may be NULL) receives the index of the first
- * system that failed, -1 if none. IGM_ERR_UNSUPPORTED for the ILU(0)
- * preconditioner, m > 128, or a system larger than 16 workgroups of the
- * largest launch shape. On error *out is NULL. */
+ * system that failed, -1 if none. IGM_ERR_UNSUPPORTED for m > 64 or a system
+ * larger than 256 workgroups of every launch shape. On error *out is NULL. */
 igm_status igm_batch_create(int32_t nsys, const int64_t *n, const int64_t *row_ptr, const int32_t *col,
                             const double *val, const double *b, const igm_policy *pol, int32_t *failed,
                             igm_batch **out);
@@ -259,10 +258,10 @@ igm_status igm_batch_create(int32_t nsys, const int64_t *n, const int64_t *row_p
 igm_status igm_batch_set_stream(igm_batch *bt, void *hip_stream);
 
 /* Launch shape: threads per workgroup and rows per thread, one of (1024, 8),
- * (1024, 16), (512, 8), (512, 16), (256, 16). System s gets
+ * (1024, 4), (512, 8), (256, 8), (256, 16). System s gets
  * ceil(n_s / (block * rows_per_thread)) workgroups. IGM_ERR_UNSUPPORTED if a
- * system would need more than 16 or the device cannot hold that many at once;
- * IGM_ERR_ARG for a shape not in the list. */
+ * system would need more than 256 or the device cannot hold that many at
+ * once; IGM_ERR_ARG for a shape not in the list. */
 igm_status igm_batch_set_shape(igm_batch *bt, int32_t block, int32_t rows_per_thread);
 
 /* Record (1) or not (0) per-phase clocks of each system's solve, returned in

@@ -1,6 +1,7 @@
-// C ABI of the batched solver: setup of many systems (host threads), one
-// device arena per array kind, the job order of the persistent kernel, launch
-// shapes and their autotuning, and per-system results.
+// Batched solver (C ABI) and the host helpers it shares with the served
+// solver: per-system preparation (validation and host setup, in parallel
+// threads), one device region per system, the job order of the persistent
+// kernel, launch shapes and their autotuning, and per-system results.
 #include <math.h>
 #include <string.h>
 
@@ -9,6 +10,7 @@
 #include <chrono>
 #include <new>
 #include <numeric>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -17,12 +19,164 @@
 
 using namespace igm;
 
+namespace igm {
+
+namespace {
+
+constexpr size_t kSegAlign = 256;  // every array of a region starts 256-byte aligned
+
+size_t align_up(size_t v) { return (v + kSegAlign - 1) / kSegAlign * kSegAlign; }
+
+// Walks the arrays of one system's region in a fixed order; used both to size
+// the region and to place the arrays.
+template <class F>
+void walk_region(const HostSystem &hs, bool own_x, F &&f) {
+  const HostSetup &h = hs.h;
+  const size_t n = (size_t)hs.n, nz = (size_t)hs.nnz;
+  const size_t ldv = (size_t)((hs.n + 15) / 16 * 16);
+  f("row_ptr", sizeof(int64_t) * (n + 1));
+  f("col", sizeof(int32_t) * nz);
+  f("a", sizeof(double) * nz);
+  f("ahat", sizeof(double) * nz);
+  f("b", sizeof(double) * n);
+  f("bhat", sizeof(double) * n);
+  f("sell_off", sizeof(int64_t) * h.sell_off.size());
+  f("sell_w", sizeof(int32_t) * h.sell_w.size());
+  f("sell_col", sizeof(int32_t) * h.sell_col.size());
+  for (int l = 0; l < hs.nterms; ++l) f("sell_val", sizeof(int64_t) * h.sell_val[l].size());
+  if (hs.pol.precond != IGM_PRE_NONE) {
+    f("ldiag", sizeof(int64_t) * n);
+    f("udiag", sizeof(int64_t) * n);
+  }
+  if (hs.pol.precond == IGM_PRE_ILU0) {
+    f("lptr", sizeof(int64_t) * h.lptr.size());
+    f("uptr", sizeof(int64_t) * h.uptr.size());
+    f("lcol", sizeof(int32_t) * h.lcol.size());
+    f("ucol", sizeof(int32_t) * h.ucol.size());
+    f("lval", sizeof(int64_t) * h.lval.size());
+    f("uval", sizeof(int64_t) * h.uval.size());
+    f("lvalf", sizeof(double) * hs.lvalf.size());
+    f("uvalf", sizeof(double) * hs.uvalf.size());
+    f("flev_ptr", sizeof(int32_t) * h.flev_ptr.size());
+    f("flev_rows", sizeof(int32_t) * h.flev_rows.size());
+    f("blev_ptr", sizeof(int32_t) * h.blev_ptr.size());
+    f("blev_rows", sizeof(int32_t) * h.blev_rows.size());
+    f("zbuf", sizeof(int64_t) * n);
+    f("wbuf", sizeof(int64_t) * n);
+    f("fbuf", sizeof(double) * n);
+  }
+  f("V", sizeof(int64_t) * (size_t)(hs.pol.m + 1) * ldv);
+  if (own_x) f("x", sizeof(double) * n);
+  f("words", sizeof(unsigned long long) * (size_t)kTeamSlots * kTeamWords);
+}
+
+}  // namespace
+
+igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                          const double *b, const igm_policy &pol, HostSystem &out) {
+  if (pol.struct_size != (int32_t)sizeof(igm_policy)) return IGM_ERR_ARG;
+  igm_status st = check_policy(pol);
+  if (st != IGM_OK) return st;
+  if (pol.m > kMaxBatchM) return IGM_ERR_UNSUPPORTED;
+  st = validate_csr(n, row_ptr, col, val, b);
+  if (st != IGM_OK) return st;
+  out.n = n;
+  out.nnz = row_ptr[n];
+  out.pol = pol;
+  out.row_ptr.assign(row_ptr, row_ptr + n + 1);
+  out.col.assign(col, col + out.nnz);
+  out.ahat.assign(val, val + out.nnz);
+  out.bhat.assign(b, b + n);
+  st = host_setup(n, out.row_ptr, out.col, out.ahat, out.bhat, pol, out.h);
+  if (st != IGM_OK) return st;
+  out.nterms = std::min(pol.s_terms + 1, out.h.nterms);
+  if (pol.precond == IGM_PRE_ILU0) {
+    out.lvalf.assign(out.h.lval.begin(), out.h.lval.end());
+    out.uvalf.assign(out.h.uval.begin(), out.h.uval.end());
+  }
+  return IGM_OK;
+}
+
+size_t system_bytes(const HostSystem &hs, bool own_x) {
+  size_t total = 0;
+  walk_region(hs, own_x, [&](const char *, size_t bytes) { total += align_up(bytes); });
+  return total;
+}
+
+hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_t st, BatchSys &S) {
+  const HostSetup &h = hs.h;
+  const igm_policy &p = hs.pol;
+  memset(&S, 0, sizeof(S));
+  S.n = hs.n;
+  S.ldv = (hs.n + 15) / 16 * 16;
+  S.team = 1;
+  S.nterms = hs.nterms;
+  S.m = p.m; S.df = p.df; S.precond = p.precond; S.max_refine = p.max_refine;
+  S.b_dot = p.b_dot; S.b_axpy = p.b_axpy; S.b_norm = p.b_norm;
+  S.b_div_num = p.b_div_num; S.b_div_den = p.b_div_den; S.b_rot = p.b_rot; S.b_tmp = p.b_tmp;
+  S.b_cs_num = p.b_cs_num; S.b_cs_den = p.b_cs_den;
+  S.gtol = p.gtol;
+  S.tol = p.tol;
+  for (int l = 0; l < kMaxTerms; ++l) S.alpha[l] = h.alpha[l];
+  if (p.precond == IGM_PRE_ILU0) {
+    S.nflev = h.flev_ptr.empty() ? 0 : (int32_t)h.flev_ptr.size() - 1;
+    S.nblev = h.blev_ptr.empty() ? 0 : (int32_t)h.blev_ptr.size() - 1;
+  }
+  size_t off = 0;
+  int term = 0;
+  hipError_t err = hipSuccess;
+  auto put = [&](const void *src, void *dst, size_t bytes) {
+    if (err == hipSuccess && bytes && src) err = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  walk_region(hs, own_x, [&](const char *name, size_t bytes) {
+    char *d = base + off;
+    off += align_up(bytes);
+    const std::string nm(name);
+    if (nm == "row_ptr") { put(hs.row_ptr.data(), d, bytes); S.row_ptr = (const int64_t *)d; }
+    else if (nm == "col") { put(hs.col.data(), d, bytes); S.col = (const int32_t *)d; }
+    else if (nm == "a") { put(h.a.data(), d, bytes); S.a = (const double *)d; }
+    else if (nm == "ahat") { put(hs.ahat.data(), d, bytes); S.ahat = (const double *)d; }
+    else if (nm == "b") { put(h.b.data(), d, bytes); S.b = (const double *)d; }
+    else if (nm == "bhat") { put(hs.bhat.data(), d, bytes); S.bhat = (const double *)d; }
+    else if (nm == "sell_off") { put(h.sell_off.data(), d, bytes); S.sell_off = (const int64_t *)d; }
+    else if (nm == "sell_w") { put(h.sell_w.data(), d, bytes); S.sell_w = (const int32_t *)d; }
+    else if (nm == "sell_col") { put(h.sell_col.data(), d, bytes); S.sell_col = (const int32_t *)d; }
+    else if (nm == "sell_val") { put(h.sell_val[term].data(), d, bytes); S.sell_val[term++] = (const int64_t *)d; }
+    else if (nm == "ldiag") { put(h.ldiag.data(), d, bytes); S.ldiag = (const int64_t *)d; }
+    else if (nm == "udiag") { put(h.udiag.data(), d, bytes); S.udiag = (const int64_t *)d; }
+    else if (nm == "lptr") { put(h.lptr.data(), d, bytes); S.lptr = (const int64_t *)d; }
+    else if (nm == "uptr") { put(h.uptr.data(), d, bytes); S.uptr = (const int64_t *)d; }
+    else if (nm == "lcol") { put(h.lcol.data(), d, bytes); S.lcol = (const int32_t *)d; }
+    else if (nm == "ucol") { put(h.ucol.data(), d, bytes); S.ucol = (const int32_t *)d; }
+    else if (nm == "lval") { put(h.lval.data(), d, bytes); S.lval = (const int64_t *)d; }
+    else if (nm == "uval") { put(h.uval.data(), d, bytes); S.uval = (const int64_t *)d; }
+    else if (nm == "lvalf") { put(hs.lvalf.data(), d, bytes); S.lvalf = (const double *)d; }
+    else if (nm == "uvalf") { put(hs.uvalf.data(), d, bytes); S.uvalf = (const double *)d; }
+    else if (nm == "flev_ptr") { put(h.flev_ptr.data(), d, bytes); S.flev_ptr = (const int32_t *)d; }
+    else if (nm == "flev_rows") { put(h.flev_rows.data(), d, bytes); S.flev_rows = (const int32_t *)d; }
+    else if (nm == "blev_ptr") { put(h.blev_ptr.data(), d, bytes); S.blev_ptr = (const int32_t *)d; }
+    else if (nm == "blev_rows") { put(h.blev_rows.data(), d, bytes); S.blev_rows = (const int32_t *)d; }
+    else if (nm == "zbuf") S.zbuf = (int64_t *)d;
+    else if (nm == "wbuf") S.wbuf = (int64_t *)d;
+    else if (nm == "fbuf") S.fbuf = (double *)d;
+    else if (nm == "V") S.V = (int64_t *)d;
+    else if (nm == "x") S.x = (double *)d;
+    else if (nm == "words") {
+      S.words = (unsigned long long *)d;
+      if (err == hipSuccess) err = hipMemsetAsync(d, 0, bytes, st);
+    }
+  });
+  return err;
+}
+
+}  // namespace igm
+
 struct igm_batch {
   int device = 0;
   hipStream_t stream = nullptr;
   igm_policy pol{};
   int32_t nsys = 0;
-  std::vector<int64_t> n, nnz;
+  std::vector<int64_t> n, nnz, x_off;
   std::vector<int32_t> nterms;
   int64_t total_n = 0, total_nnz = 0;
   std::vector<BatchSys> sys;  // host copy of the device records
@@ -34,8 +188,8 @@ struct igm_batch {
   int32_t *d_ctl = nullptr;  // [0] job queue, [1] timeout flag
   BatchResult *d_res = nullptr;
   std::vector<BatchResult> res;
-  unsigned long long *d_words = nullptr;
-  double *d_x = nullptr;  // solution buffer of igm_batch_solve and the autotuner
+  double *d_x = nullptr;      // solution buffer of igm_batch_solve and the autotuner
+  double *x_bound = nullptr;  // solution vector the uploaded records point into
   int block = 0, rows = 0, grid = 0;
   std::vector<int32_t> team;
   igm_stats stats{};
@@ -61,35 +215,19 @@ namespace {
     if (st_ != IGM_OK) return st_; \
   } while (0)
 
-constexpr int kMaxBatchM = 64;  // H lives in LDS: (m+1) m words
-constexpr int64_t kAlign = 32;  // elements: every per-system segment starts 256-byte aligned (int64)
-
-int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 template <class T>
-igm_status arena(igm_batch *bt, T *&p, int64_t count) {
-  const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+igm_status dev_alloc(igm_batch *bt, T *&p, size_t count) {
+  const size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
   void *q = nullptr;
   if (hipMalloc(&q, bytes) != hipSuccess) return IGM_ERR_OOM;
   bt->bufs.push_back(q);
   bt->device_bytes += (int64_t)bytes;
   p = (T *)q;
   return IGM_OK;
-}
-
-// Offsets of per-system segments of `len[s]` elements, each aligned.
-int64_t layout(const std::vector<int64_t> &len, std::vector<int64_t> &off) {
-  off.resize(len.size());
-  int64_t t = 0;
-  for (size_t s = 0; s < len.size(); ++s) {
-    off[s] = t;
-    t += round_up(len[s], kAlign);
-  }
-  return t;
 }
 
 void free_batch(igm_batch *bt) {
@@ -102,7 +240,7 @@ void free_batch(igm_batch *bt) {
 
 // Team sizes, job order (largest systems first, members consecutive), grid.
 igm_status apply_shape(igm_batch *bt, int block, int rows) {
-  const void *k = batch_kernel(block, rows, bt->pol.precond);
+  const void *k = batch_kernel(block, rows);
   if (!k) return IGM_ERR_ARG;
   hipDeviceProp_t prop;
   BT_HIP(hipGetDeviceProperties(&prop, bt->device));
@@ -133,7 +271,7 @@ igm_status apply_shape(igm_batch *bt, int block, int rows) {
       jobs.push_back(q);
     }
   for (int32_t s = 0; s < bt->nsys; ++s) bt->sys[s].team = team[s];
-  BT_HIP(hipMemcpy(bt->d_sys, bt->sys.data(), sizeof(BatchSys) * bt->nsys, hipMemcpyHostToDevice));
+  bt->x_bound = nullptr;  // records are re-uploaded before the next solve
   BT_HIP(hipMemcpy(bt->d_jobs, jobs.data(), sizeof(int32_t) * jobs.size(), hipMemcpyHostToDevice));
   bt->team = team;
   bt->njobs = (int32_t)njobs;
@@ -145,10 +283,15 @@ igm_status apply_shape(igm_batch *bt, int block, int rows) {
 
 igm_status run(igm_batch *bt, double *x_dev) {
   auto t0 = std::chrono::steady_clock::now();
-  const igm_policy &p = bt->pol;
+  if (bt->x_bound != x_dev) {  // point the records at this solution vector
+    for (int32_t s = 0; s < bt->nsys; ++s) bt->sys[s].x = x_dev + bt->x_off[s];
+    BT_HIP(hipMemcpyAsync(bt->d_sys, bt->sys.data(), sizeof(BatchSys) * bt->nsys, hipMemcpyHostToDevice,
+                          bt->stream));
+    bt->x_bound = x_dev;
+  }
   BT_HIP(hipMemsetAsync(bt->d_ctl, 0, 2 * sizeof(int32_t), bt->stream));
-  BT_HIP(hipMemsetAsync(bt->d_words, 0, sizeof(unsigned long long) * kTeamSlots * kTeamWords * (size_t)bt->nsys,
-                        bt->stream));
+  for (int32_t s = 0; s < bt->nsys; ++s)
+    BT_HIP(hipMemsetAsync(bt->sys[s].words, 0, sizeof(unsigned long long) * kTeamSlots * kTeamWords, bt->stream));
   for (auto &r : bt->res) {
     memset(&r, 0, sizeof(r));
     r.status = IGM_ERR_DEVICE;  // overwritten by the system's first member
@@ -162,24 +305,15 @@ igm_status run(igm_batch *bt, double *x_dev) {
   a.sys = bt->d_sys;
   a.jobs = bt->d_jobs;
   a.njobs = bt->njobs;
-  a.m = p.m;
-  a.df = p.df;
-  a.precond = p.precond;
-  a.b_dot = p.b_dot; a.b_axpy = p.b_axpy; a.b_norm = p.b_norm;
-  a.b_div_num = p.b_div_num; a.b_div_den = p.b_div_den; a.b_rot = p.b_rot; a.b_tmp = p.b_tmp;
-  a.b_cs_num = p.b_cs_num; a.b_cs_den = p.b_cs_den;
-  a.max_refine = p.max_refine;
-  a.phase_clock = p.phase_clock;
-  a.gtol = p.gtol;
-  a.tol = p.tol;
+  a.phase_clock = bt->pol.phase_clock;
   a.queue = bt->d_ctl;
   a.timeout = bt->d_ctl + 1;
-  a.res = bt->d_res;
-  a.x = x_dev;
+  a.ring = 0;
   void *args[] = {(void *)&a};
-  const void *k = batch_kernel(bt->block, bt->rows, p.precond);
+  const void *k = batch_kernel(bt->block, bt->rows);
   BT_HIP(hipEventRecord(bt->ev0, bt->stream));
-  BT_HIP(hipLaunchCooperativeKernel(k, dim3(bt->grid), dim3(bt->block), args, batch_smem_bytes(p.m), bt->stream));
+  BT_HIP(hipLaunchCooperativeKernel(k, dim3(bt->grid), dim3(bt->block), args, batch_smem_bytes(bt->pol.m),
+                                    bt->stream));
   BT_HIP(hipEventRecord(bt->ev1, bt->stream));
   int32_t ctl[2] = {0, 0};
   BT_HIP(hipMemcpyAsync(bt->res.data(), bt->d_res, sizeof(BatchResult) * bt->nsys, hipMemcpyDeviceToHost,
@@ -209,43 +343,30 @@ igm_status run(igm_batch *bt, double *x_dev) {
 igm_status setup(igm_batch *bt, const int64_t *n, const int64_t *row_ptr, const int32_t *col, const double *val,
                  const double *b, int32_t *failed) {
   const int32_t ns = bt->nsys;
-  const igm_policy &p = bt->pol;
-  // offsets of each system in the caller's arrays, validation
+  // offsets of each system in the caller's arrays
   std::vector<int64_t> rp_off(ns), nz_off(ns), b_off(ns);
   int64_t trp = 0, tnz = 0, tb = 0;
-  bt->n.resize(ns);
-  bt->nnz.resize(ns);
   for (int32_t s = 0; s < ns; ++s) {
     if (n[s] < 1 || n[s] >= ((int64_t)1 << 31)) { if (failed) *failed = s; return IGM_ERR_ARG; }
     rp_off[s] = trp;
     nz_off[s] = tnz;
     b_off[s] = tb;
-    const int64_t *rp = row_ptr + trp;
-    if (rp[0] != 0 || rp[n[s]] < 0) { if (failed) *failed = s; return IGM_ERR_ARG; }
-    igm_status v = validate_csr(n[s], rp, col + tnz, val + tnz, b + tb);
-    if (v != IGM_OK) { if (failed) *failed = s; return v; }
-    bt->n[s] = n[s];
-    bt->nnz[s] = rp[n[s]];
+    const int64_t nz = row_ptr[trp + n[s]];
+    if (nz < 0) { if (failed) *failed = s; return IGM_ERR_ARG; }
     trp += n[s] + 1;
-    tnz += rp[n[s]];
+    tnz += nz;
     tb += n[s];
   }
-  bt->total_n = tb;
-  bt->total_nnz = tnz;
-  // host setup of every system, in parallel
-  std::vector<HostSetup> hs(ns);
+  // validation and host setup of every system, in parallel
+  std::vector<HostSystem> hs(ns);
   std::vector<igm_status> sst(ns, IGM_OK);
   std::atomic<int32_t> next(0);
   auto worker = [&] {
     for (;;) {
       const int32_t s = next.fetch_add(1);
       if (s >= ns) break;
-      const int64_t *rp = row_ptr + rp_off[s];
-      std::vector<int64_t> rpv(rp, rp + n[s] + 1);
-      std::vector<int32_t> cv(col + nz_off[s], col + nz_off[s] + bt->nnz[s]);
-      std::vector<double> av(val + nz_off[s], val + nz_off[s] + bt->nnz[s]);
-      std::vector<double> bv(b + b_off[s], b + b_off[s] + n[s]);
-      sst[s] = host_setup(n[s], rpv, cv, av, bv, p, hs[s]);
+      sst[s] = prepare_system(n[s], row_ptr + rp_off[s], col + nz_off[s], val + nz_off[s], b + b_off[s], bt->pol,
+                              hs[s]);
     }
   };
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -255,104 +376,39 @@ igm_status setup(igm_batch *bt, const int64_t *n, const int64_t *row_ptr, const 
   for (auto &t : pool) t.join();
   for (int32_t s = 0; s < ns; ++s)
     if (sst[s] != IGM_OK) { if (failed) *failed = s; return sst[s]; }
-
-  // arenas
-  const int m = p.m;
-  bt->nterms.resize(ns);
-  int max_terms = 1;
-  std::vector<int64_t> L_rp(ns), L_nz(ns), L_n(ns), L_soff(ns), L_sw(ns), L_sent(ns), L_V(ns), L_W(ns);
+  // one allocation holds every system's region
+  std::vector<size_t> roff(ns);
+  size_t total = 0;
   for (int32_t s = 0; s < ns; ++s) {
-    bt->nterms[s] = std::min(p.s_terms + 1, hs[s].nterms);
-    max_terms = std::max(max_terms, bt->nterms[s]);
-    L_rp[s] = n[s] + 1;
-    L_nz[s] = bt->nnz[s];
-    L_n[s] = n[s];
-    L_soff[s] = (int64_t)hs[s].sell_off.size();
-    L_sw[s] = (int64_t)hs[s].sell_w.size();
-    L_sent[s] = (int64_t)hs[s].sell_col.size();
-    L_V[s] = (int64_t)(m + 1) * round_up(n[s], 16);
-    L_W[s] = (int64_t)kTeamSlots * kTeamWords;
+    roff[s] = total;
+    total += system_bytes(hs[s], false);
   }
-  std::vector<int64_t> O_rp, O_nz, O_n, O_soff, O_sw, O_sent, O_V, O_W;
-  int64_t *d_rp, *d_soff, *d_ld = nullptr, *d_ud = nullptr, *d_V;
-  int64_t *d_sval[kMaxTerms] = {nullptr};
-  int32_t *d_col, *d_sw, *d_scol;
-  double *d_a, *d_ah, *d_b, *d_bh;
-  BT_TRY(arena(bt, d_rp, layout(L_rp, O_rp)));
-  const int64_t tot_nz = layout(L_nz, O_nz);
-  BT_TRY(arena(bt, d_col, tot_nz));
-  BT_TRY(arena(bt, d_a, tot_nz));
-  BT_TRY(arena(bt, d_ah, tot_nz));
-  const int64_t tot_n = layout(L_n, O_n);
-  BT_TRY(arena(bt, d_b, tot_n));
-  BT_TRY(arena(bt, d_bh, tot_n));
-  if (p.precond == IGM_PRE_JACOBI) {
-    BT_TRY(arena(bt, d_ld, tot_n));
-    BT_TRY(arena(bt, d_ud, tot_n));
-  }
-  BT_TRY(arena(bt, d_soff, layout(L_soff, O_soff)));
-  BT_TRY(arena(bt, d_sw, layout(L_sw, O_sw)));
-  const int64_t tot_sent = layout(L_sent, O_sent);
-  BT_TRY(arena(bt, d_scol, tot_sent));
-  for (int l = 0; l < max_terms; ++l) BT_TRY(arena(bt, d_sval[l], tot_sent));
-  BT_TRY(arena(bt, d_V, layout(L_V, O_V)));
-  BT_TRY(arena(bt, bt->d_words, layout(L_W, O_W)));
-  BT_TRY(arena(bt, bt->d_x, bt->total_n));
-  BT_TRY(arena(bt, bt->d_sys, ns));
-  int64_t max_jobs = (int64_t)ns * kTeamMax * 2;
-  BT_TRY(arena(bt, bt->d_jobs, max_jobs));
-  BT_TRY(arena(bt, bt->d_ctl, 2));
-  BT_TRY(arena(bt, bt->d_res, ns));
-  BT_HIP(hipMemset(d_V, 0, sizeof(int64_t) * (size_t)(O_V.back() + round_up(L_V.back(), kAlign))));
+  char *d_all = nullptr;
+  BT_TRY(dev_alloc(bt, d_all, total));
+  bt->n.resize(ns);
+  bt->nnz.resize(ns);
+  bt->nterms.resize(ns);
+  bt->x_off.resize(ns);
   bt->sys.resize(ns);
   bt->res.resize(ns);
   int64_t xo = 0;
   for (int32_t s = 0; s < ns; ++s) {
-    const HostSetup &h = hs[s];
-    BatchSys &S = bt->sys[s];
-    memset(&S, 0, sizeof(S));
-    S.n = n[s];
-    S.ldv = round_up(n[s], 16);
-    S.x_off = xo;
-    xo += n[s];
-    S.team = 1;
-    S.nterms = bt->nterms[s];
-    for (int l = 0; l < kMaxTerms; ++l) S.alpha[l] = h.alpha[l];
-    const size_t nn = (size_t)n[s], nz = (size_t)bt->nnz[s];
-    auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
-      return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
-    };
-    BT_HIP(up(d_rp + O_rp[s], row_ptr + rp_off[s], sizeof(int64_t) * (nn + 1)));
-    BT_HIP(up(d_col + O_nz[s], col + nz_off[s], sizeof(int32_t) * nz));
-    BT_HIP(up(d_a + O_nz[s], h.a.data(), sizeof(double) * nz));
-    BT_HIP(up(d_ah + O_nz[s], val + nz_off[s], sizeof(double) * nz));
-    BT_HIP(up(d_b + O_n[s], h.b.data(), sizeof(double) * nn));
-    BT_HIP(up(d_bh + O_n[s], b + b_off[s], sizeof(double) * nn));
-    BT_HIP(up(d_soff + O_soff[s], h.sell_off.data(), sizeof(int64_t) * h.sell_off.size()));
-    BT_HIP(up(d_sw + O_sw[s], h.sell_w.data(), sizeof(int32_t) * h.sell_w.size()));
-    BT_HIP(up(d_scol + O_sent[s], h.sell_col.data(), sizeof(int32_t) * h.sell_col.size()));
-    for (int l = 0; l < S.nterms; ++l) {
-      BT_HIP(up(d_sval[l] + O_sent[s], h.sell_val[l].data(), sizeof(int64_t) * h.sell_val[l].size()));
-      S.sell_val[l] = d_sval[l] + O_sent[s];
-    }
-    if (p.precond == IGM_PRE_JACOBI) {
-      BT_HIP(up(d_ld + O_n[s], h.ldiag.data(), sizeof(int64_t) * nn));
-      BT_HIP(up(d_ud + O_n[s], h.udiag.data(), sizeof(int64_t) * nn));
-      S.ldiag = d_ld + O_n[s];
-      S.udiag = d_ud + O_n[s];
-    }
-    S.row_ptr = d_rp + O_rp[s];
-    S.col = d_col + O_nz[s];
-    S.a = d_a + O_nz[s];
-    S.ahat = d_ah + O_nz[s];
-    S.b = d_b + O_n[s];
-    S.bhat = d_bh + O_n[s];
-    S.sell_off = d_soff + O_soff[s];
-    S.sell_w = d_sw + O_sw[s];
-    S.sell_col = d_scol + O_sent[s];
-    S.V = d_V + O_V[s];
-    S.words = bt->d_words + O_W[s];
+    BT_HIP(place_system(hs[s], d_all + roff[s], false, bt->stream, bt->sys[s]));
+    bt->n[s] = hs[s].n;
+    bt->nnz[s] = hs[s].nnz;
+    bt->nterms[s] = hs[s].nterms;
+    bt->x_off[s] = xo;
+    xo += hs[s].n;
   }
+  bt->total_n = xo;
+  bt->total_nnz = tnz;
+  BT_TRY(dev_alloc(bt, bt->d_x, (size_t)bt->total_n));
+  BT_TRY(dev_alloc(bt, bt->d_sys, (size_t)ns));
+  BT_TRY(dev_alloc(bt, bt->d_jobs, (size_t)ns * kTeamMax * 2));
+  BT_TRY(dev_alloc(bt, bt->d_ctl, 2));
+  BT_TRY(dev_alloc(bt, bt->d_res, (size_t)ns));
+  for (int32_t s = 0; s < ns; ++s) bt->sys[s].res = bt->d_res + s;
+  BT_HIP(hipStreamSynchronize(bt->stream));  // the host vectors die here
   return IGM_OK;
 }
 
@@ -381,7 +437,7 @@ igm_status igm_batch_create(int32_t nsys, const int64_t *n, const int64_t *row_p
   if (pol->struct_size != (int32_t)sizeof(igm_policy)) return IGM_ERR_ARG;
   igm_status st = check_policy(*pol);
   if (st != IGM_OK) return st;
-  if (pol->precond == IGM_PRE_ILU0 || pol->m > kMaxBatchM) return IGM_ERR_UNSUPPORTED;
+  if (pol->m > kMaxBatchM) return IGM_ERR_UNSUPPORTED;
   auto t0 = std::chrono::steady_clock::now();
   igm_batch *bt = new (std::nothrow) igm_batch();
   if (!bt) return IGM_ERR_OOM;

@@ -1,11 +1,15 @@
-// Batched solver: many independent systems, each solved completely (Fig. 1
-// of the paper: FP64 iterative refinement around int-GMRES(m) calls, Fig. 2
-// with line 5' of Sec. VI) by a team of workgroups inside one persistent
-// cooperative launch.
+// Batched and served solver: many independent systems, each solved
+// completely (Fig. 1 of the paper: FP64 iterative refinement around
+// int-GMRES(m) calls, Fig. 2 with line 5' of Sec. VI) by a team of workgroups
+// inside one persistent cooperative launch. Every system carries its own
+// policy (shifts, m, preconditioner: none, Jacobi or ILU(0)).
 //
-// Workgroups claim jobs (system, member) from a queue in the order the host
-// laid out (largest systems first, the members of one system consecutively),
-// so the members of a team start together and every started team can finish.
+// Workgroups claim jobs (system, member) from a queue: in batch mode a list
+// the host laid out before the launch (largest systems first), in served mode
+// a ring in pinned host memory that the host appends to while the kernel runs
+// (a workgroup whose claim is not yet published waits, bounded, for it). The
+// members of one system are consecutive, so they start together and every
+// started team can finish.
 // Thread t of member q owns rows q*BLOCK + t + k*T*BLOCK (k < R) of its system
 // and keeps its rows of w (Arnoldi step) and of the FP64 vectors r, rhat and
 // r0 (refinement step) in registers; rows >= n hold zeros. Every reduction is
@@ -104,31 +108,65 @@ constexpr int64_t kEvBias = (int64_t)1 << 53;
 
 }  // namespace
 
-template <int BLOCK, int R, int PRE>
+template <int BLOCK, int R>
 __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
   extern __shared__ int64_t smem[];
-  const int m = ba.m;
-  int64_t *sc = smem;                               // c_1..c_m
-  int64_t *ss = sc + m;                             // s_1..s_m
-  int64_t *sg = ss + m;                             // g_1..g_{m+1}
-  int64_t *col = sg + m + 1;                        // current column h_{1..j+1, j}
-  int64_t *sH = col + m + 1;                        // H, (m+1) x m, row-major
-  double *sy = (double *)(sH + (size_t)(m + 1) * m);  // y of lines 21-23
   __shared__ TeamShared tsh;
-  __shared__ int sh_job, sh_stop, sh_jstar, sh_steps;
+  __shared__ int sh_job, sh_sid, sh_member, sh_stop, sh_jstar, sh_steps;
   __shared__ long long sh_ovf;  // smallest overflow event of the current call in this workgroup
 
   const int tid = threadIdx.x;
-  const int df = ba.df;
 
   for (;;) {
-    if (tid == 0) sh_job = atomicAdd(ba.queue, 1);
+    // ---- claim the next job: (system, member)
+    if (tid == 0) {
+      const int c = atomicAdd(ba.queue, 1);
+      int job = -1;  // -1: nothing left, leave
+      int sid = 0, member = 0;
+      if (ba.ring == 0) {
+        if (c < ba.njobs) {
+          job = c;
+          sid = ba.jobs[2 * c];
+          member = ba.jobs[2 * c + 1];
+        }
+      } else {
+        // served mode: wait (bounded) until the host has published job c
+        for (int64_t idle = 0;; ++idle) {
+          if (c < __hip_atomic_load(ba.host_published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
+            job = c;
+            break;
+          }
+          if (__hip_atomic_load(ba.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) || idle >= ba.idle_polls)
+            break;
+          __builtin_amdgcn_s_sleep(127);
+        }
+        if (job >= 0) {
+          const int64_t e = 2 * (int64_t)(c % ba.ring);
+          sid = __hip_atomic_load(ba.host_jobs + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          member = __hip_atomic_load(ba.host_jobs + e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      sh_job = job;
+      sh_sid = sid;
+      sh_member = member;
+    }
     team_init(tsh);
     __syncthreads();
-    const int job = __builtin_amdgcn_readfirstlane(sh_job);  // uniform: lets the record load through scalar loads
-    if (job >= ba.njobs) break;
-    const int sid = ba.jobs[2 * job], member = ba.jobs[2 * job + 1];
+    // uniform values: the record then loads through scalar loads
+    const int job = __builtin_amdgcn_readfirstlane(sh_job);
+    if (job < 0) break;
+    const int sid = __builtin_amdgcn_readfirstlane(sh_sid);
+    const int member = __builtin_amdgcn_readfirstlane(sh_member);
+    // the host wrote this slot's inputs before publishing the job
+    if (ba.ring) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     const BatchSys &S = ba.sys[sid];
+    const int m = S.m, df = S.df, pre = S.precond;
+    int64_t *sc = smem;                                 // c_1..c_m
+    int64_t *ss = sc + m;                               // s_1..s_m
+    int64_t *sg = ss + m;                               // g_1..g_{m+1}
+    int64_t *col = sg + m + 1;                          // current column h_{1..j+1, j}
+    int64_t *sH = col + m + 1;                          // H, (m+1) x m, row-major
+    double *sy = (double *)(sH + (size_t)(m + 1) * m);  // y of lines 21-23
     Team tm{S.words, S.team, member, 0, ba.timeout};
     const int64_t n = S.n, ldv = S.ldv;
     const int64_t TB = (int64_t)S.team * BLOCK;
@@ -137,7 +175,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
     const int64_t wbase = (int64_t)member * BLOCK + (tid & ~63);
     const int nk = __builtin_amdgcn_readfirstlane(
         wbase < n ? (int)((n - wbase + TB - 1) / TB < R ? (n - wbase + TB - 1) / TB : R) : 0);
-    double *__restrict__ x = ba.x + S.x_off;
+    double *__restrict__ x = S.x;
     const uint64_t t_begin = wall_clock64();
     const bool timer = ba.phase_clock && member == 0 && tid == 0;
     uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -191,8 +229,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
       rs = relres_of(nr, nb);
       if (tsh.abort) break;
       if (!(ro <= kDblMax && ro >= -kDblMax)) { status = IGM_ERR_RANGE; break; }
-      if (ro < ba.tol) { status = IGM_OK; break; }
-      if (kref >= ba.max_refine) { status = IGM_NOT_CONVERGED; break; }
+      if (ro < S.tol) { status = IGM_OK; break; }
+      if (kref >= S.max_refine) { status = IGM_NOT_CONVERGED; break; }
       // gamma = max |r| (eq. (gammak)); gamma == 0 means r == 0
       if (gamma == 0.0) { status = IGM_OK; break; }
       // ---- line 1': b^(k) = r / gamma, r0 = Mbar^-1 b^(k) in FP64
@@ -202,8 +240,42 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
         if (row < n) {
           const double t = r[k] / gamma;
           double u = t;
-          if (PRE == IGM_PRE_JACOBI) u = (t / (double)S.ldiag[row]) / (double)S.udiag[row];
+          if (pre == IGM_PRE_JACOBI) u = (t / (double)S.ldiag[row]) / (double)S.udiag[row];
           r[k] = u;
+        }
+      }
+      if (pre == IGM_PRE_ILU0) {
+        // FP64 forward and backward substitution with the integer factors
+        // (converted exactly), level by level, in place in fbuf; each row
+        // sums in CSR order and then divides by its diagonal
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const int64_t row = g0 + k * TB;
+          if (row < n) S.fbuf[row] = r[k];
+        }
+        team_barrier(tm, tsh);
+        for (int L = 0; L < S.nflev; ++L) {
+          for (int64_t q = S.flev_ptr[L] + g0; q < S.flev_ptr[L + 1]; q += TB) {
+            const int64_t i = S.flev_rows[q];
+            double acc = 0.0;
+            for (int64_t e = S.lptr[i]; e < S.lptr[i + 1]; ++e) acc = acc + S.lvalf[e] * S.fbuf[S.lcol[e]];
+            S.fbuf[i] = (S.fbuf[i] - acc) / (double)S.ldiag[i];
+          }
+          team_barrier(tm, tsh);
+        }
+        for (int L = 0; L < S.nblev; ++L) {
+          for (int64_t q = S.blev_ptr[L] + g0; q < S.blev_ptr[L + 1]; q += TB) {
+            const int64_t i = S.blev_rows[q];
+            double acc = 0.0;
+            for (int64_t e = S.uptr[i]; e < S.uptr[i + 1]; ++e) acc = acc + S.uvalf[e] * S.fbuf[S.ucol[e]];
+            S.fbuf[i] = (S.fbuf[i] - acc) / (double)S.udiag[i];
+          }
+          team_barrier(tm, tsh);
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const int64_t row = g0 + k * TB;
+          r[k] = row < n ? S.fbuf[row] : 0.0;
         }
       }
       const double rho = team_norm1<BLOCK, R>(tm, tsh, r);
@@ -238,9 +310,9 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
       }
       team_barrier(tm, tsh);  // v1 visible to the team
 
-      const int sh_dot = df - ba.b_dot;
+      const int sh_dot = df - S.b_dot;
       auto fin_dot = [&](int64_t Sv, bool &o) { return asr(Sv, sh_dot); };
-      auto fin_norm = [&](int64_t Sv, bool &o) { return shl(isqrt64(Sv), ba.b_norm, o); };
+      auto fin_norm = [&](int64_t Sv, bool &o) { return shl(isqrt64(Sv), S.b_norm, o); };
       auto record = [&](int64_t code) { atomicMin(&sh_ovf, (long long)code); };
 
       int64_t w[R];
@@ -248,14 +320,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
       bool lucky = false;
       // rotation i (1-based) of lines 12-14 on (carry, col[i]); thread kGivensThread only
       auto rotate = [&](int j, int i) {
-        const int64_t x0 = asr(carry, ba.b_rot), x1 = asr(col[i], ba.b_rot);
+        const int64_t x0 = asr(carry, S.b_rot), x1 = asr(col[i], S.b_rot);
         const int64_t c = sc[i - 1], s = ss[i - 1];
         bool o = false;
         const int64_t ms = subc(0, s, o);
         const int64_t top = addc(mulw(x0, c, o), mulw(x1, s, o), o);
         const int64_t bot = addc(mulw(x0, ms, o), mulw(x1, c, o), o);
-        col[i - 1] = asr(top, df - ba.b_rot);
-        carry = asr(bot, df - ba.b_rot);
+        col[i - 1] = asr(top, df - S.b_rot);
+        carry = asr(bot, df - S.b_rot);
         if (o) record(ev_code(j, 6, i));
       };
       // lines 15-19 for column j on (carry, hn); thread kGivensThread only
@@ -263,20 +335,20 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
         col[j - 1] = carry;
         col[j] = hn;
         bool o = false;  // line 15
-        const int64_t p0 = asr(col[j - 1], ba.b_tmp), p1 = asr(col[j], ba.b_tmp);
+        const int64_t p0 = asr(col[j - 1], S.b_tmp), p1 = asr(col[j], S.b_tmp);
         const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
-        const int64_t tmp = shl(isqrt64(ssq), ba.b_tmp, o);
+        const int64_t tmp = shl(isqrt64(ssq), S.b_tmp, o);
         if (o) record(ev_code(j, 7, 0));
-        const int64_t den2 = asr(tmp, ba.b_cs_den);  // line 16
+        const int64_t den2 = asr(tmp, S.b_cs_den);  // line 16
         int stop = 0;
         if (den2 == 0) {  // line 16 breakdown
           sh_jstar = j - 1;
           stop = 1;
         } else {
           bool oc = false;
-          const int e2 = df - ba.b_cs_num - ba.b_cs_den;
-          const int64_t cj = normalize_elem(col[j - 1], den2, ba.b_cs_num, e2, oc);
-          const int64_t sj = normalize_elem(col[j], den2, ba.b_cs_num, e2, oc);
+          const int e2 = df - S.b_cs_num - S.b_cs_den;
+          const int64_t cj = normalize_elem(col[j - 1], den2, S.b_cs_num, e2, oc);
+          const int64_t sj = normalize_elem(col[j], den2, S.b_cs_num, e2, oc);
           if (oc) record(ev_code(j, 8, 0));
           sc[j - 1] = cj;
           ss[j - 1] = sj;
@@ -291,9 +363,9 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
           if (lucky) {  // line 11 breakdown
             sh_jstar = j;
             stop = 1;
-          } else if (ba.gtol >= 0) {
+          } else if (S.gtol >= 0) {
             const int64_t gn = sg[j] < 0 ? -sg[j] : sg[j];
-            if (gn <= ba.gtol) { sh_jstar = j; stop = 1; }
+            if (gn <= S.gtol) { sh_jstar = j; stop = 1; }
           }
         }
         for (int i = 0; i <= j; ++i) sH[(size_t)i * m + (j - 1)] = col[i];
@@ -312,11 +384,39 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
             int64_t z = 0;
             if (row < n) {
               z = spmv_row(S, row, vj, S.nterms, o1);
-              if (PRE == IGM_PRE_JACOBI) z = tdiv_diag(tdiv_diag(z, S.ldiag[row], o2), S.udiag[row], o2);
+              if (pre == IGM_PRE_JACOBI) z = tdiv_diag(tdiv_diag(z, S.ldiag[row], o2), S.udiag[row], o2);
             }
             w[k] = z;
           }
           if (o1) record(ev_code(j, 1, 0));
+          if (pre == IGM_PRE_ILU0) {
+            // line 5': integer forward and backward substitution, level by level
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+              const int64_t row = g0 + k * TB;
+              if (row < n) S.zbuf[row] = w[k];
+            }
+            team_barrier(tm, tsh);
+            for (int L = 0; L < S.nflev; ++L) {
+              for (int64_t q = S.flev_ptr[L] + g0; q < S.flev_ptr[L + 1]; q += TB) {
+                const int64_t row = S.flev_rows[q];
+                S.wbuf[row] = lower_row(S, row, S.zbuf[row], S.wbuf, o2);
+              }
+              team_barrier(tm, tsh);
+            }
+            for (int L = 0; L < S.nblev; ++L) {
+              for (int64_t q = S.blev_ptr[L] + g0; q < S.blev_ptr[L + 1]; q += TB) {
+                const int64_t row = S.blev_rows[q];
+                S.wbuf[row] = upper_row(S, row, S.wbuf[row], S.wbuf, o2);
+              }
+              team_barrier(tm, tsh);
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+              const int64_t row = g0 + k * TB;
+              w[k] = row < n ? S.wbuf[row] : 0;
+            }
+          }
           if (o2) record(ev_code(j, 2, 0));
         }
         IGM_TICK(0)
@@ -335,7 +435,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
           bool o = false;
 #pragma unroll
           for (int k = 0; k < R; ++k)  // line 7: only w is shifted
-            if (k < nk) acc.add(mulw(asr(w[k], ba.b_dot), vv[k], o));
+            if (k < nk) acc.add(mulw(asr(w[k], S.b_dot), vv[k], o));
           if (o) record(ev_code(j, 3, 2 * (i - 1)));
           int64_t vnext[R];
           if (i < j) {
@@ -358,11 +458,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
             if (i == 1) carry = h;
           }
           // line 8: only h is shifted
-          const int64_t hs = asr(h, ba.b_axpy);
+          const int64_t hs = asr(h, S.b_axpy);
           bool ou = false;
 #pragma unroll
           for (int k = 0; k < R; ++k)
-            if (k < nk) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - ba.b_axpy), ou);
+            if (k < nk) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - S.b_axpy), ou);
           if (ou) record(ev_code(j, 3, 2 * (i - 1) + 1));
           if (i < j) {
 #pragma unroll
@@ -377,7 +477,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
           bool o = false;
 #pragma unroll
           for (int k = 0; k < R; ++k)
-            if (k < nk) acc.add(sqrc(asr(w[k], ba.b_norm), o));
+            if (k < nk) acc.add(sqrc(asr(w[k], S.b_norm), o));
           if (o) record(ev_code(j, 4, 0));
           bool os = false;
           hn = team_sum<BLOCK>(tm, acc, tsh, fin_norm, [&] {
@@ -387,16 +487,16 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
         }
         IGM_TICK(3)
         // ---- line 11
-        const int64_t den = asr(hn, ba.b_div_den);
+        const int64_t den = asr(hn, S.b_div_den);
         lucky = den == 0;
         if (!lucky) {
           int64_t *__restrict__ vn = S.V + (size_t)j * ldv;
-          const int e = df - ba.b_div_num - ba.b_div_den;
+          const int e = df - S.b_div_num - S.b_div_den;
           bool ov = false;
 #pragma unroll
           for (int k = 0; k < R; ++k) {
             const int64_t row = g0 + k * TB;
-            if (row < n) vn[row] = normalize_elem(w[k], den, ba.b_div_num, e, ov);
+            if (row < n) vn[row] = normalize_elem(w[k], den, S.b_div_num, e, ov);
           }
           if (ov) record(ev_code(j, 5, 0));
         }
@@ -450,8 +550,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
     }
 #undef IGM_TICK
     if (tsh.abort) status = IGM_ERR_DEVICE;
+    // every member's writes of x are published before the result is
+    team_barrier(tm, tsh);
     if (member == 0 && tid == 0) {
-      BatchResult &res = ba.res[sid];
+      BatchResult &res = *S.res;
       res.status = status;
       res.refinements = refinements;
       res.iterations = iterations;
@@ -463,24 +565,26 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
       res.t_end = wall_clock64();
       for (int k = 0; k < 7; ++k) res.phase[k] = ph[k];
       res.phase[7] = res.t_end - t_begin;
+      if (ba.ring) {  // served mode: results and x reach memory, then the host is told
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __hip_atomic_store(ba.host_done + sid, S.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
     __syncthreads();
   }
 }
 
-template <int BLOCK, int R, int PRE>
+template <int BLOCK, int R>
 static const void *batch_kernel_ptr() {
-  return (const void *)&k_batch<BLOCK, R, PRE>;
+  return (const void *)&k_batch<BLOCK, R>;
 }
 
 const int kBatchShapes[][2] = {{1024, 8}, {1024, 4}, {512, 8}, {256, 8}, {256, 16}};
 const int kNumBatchShapes = 5;
 
-const void *batch_kernel(int block, int R, int pre) {
-  if (pre == IGM_PRE_ILU0) return nullptr;
-#define IGM_K(BB, RR)                                                  \
-  if (block == BB && R == RR)                                          \
-    return pre == IGM_PRE_NONE ? batch_kernel_ptr<BB, RR, 0>() : batch_kernel_ptr<BB, RR, 1>();
+const void *batch_kernel(int block, int R) {
+#define IGM_K(BB, RR) \
+  if (block == BB && R == RR) return batch_kernel_ptr<BB, RR>();
   IGM_K(1024, 8)
   IGM_K(1024, 4)
   IGM_K(512, 8)

@@ -1,20 +1,30 @@
-// Device records of the batched solver (many independent systems, one
-// persistent launch).
+// Device records of the batched and served solvers (many independent
+// systems, one persistent launch).
 #pragma once
+
+#include <vector>
 
 #include "igm_internal.hpp"
 
 namespace igm {
 
-// One system of a batch: read-only inputs and setup products, its Krylov
-// basis and its team exchange area. Field names of the integer matrix match
-// CycleArgs so the per-row SpMV serves both kernels.
+struct BatchResult;
+
+// One system: its policy, read-only inputs and setup products, its Krylov
+// basis, work vectors and team exchange area. Field names of the integer
+// matrix and factors match CycleArgs so the per-row kernels serve all paths.
 struct BatchSys {
   int64_t n;       // rows
   int64_t ldv;     // leading dimension of V (n rounded up to 16)
-  int64_t x_off;   // offset of this system's unknowns in the solution vector
   int32_t team;    // workgroups that share the system
   int32_t nterms;  // integer matrix terms used by line 5
+  int32_t m, df, precond, max_refine;
+  int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
+  int32_t nflev, nblev;  // ILU level sets
+  int32_t seq;           // served mode: request number reported on completion
+  int32_t pad_;
+  int64_t gtol;
+  double tol;
   int32_t alpha[kMaxTerms];
   const int64_t *row_ptr;
   const int32_t *col;
@@ -23,9 +33,18 @@ struct BatchSys {
   const int32_t *sell_w;
   const int32_t *sell_col;
   const int64_t *sell_val[kMaxTerms];
-  const int64_t *ldiag, *udiag;  // cast diagonals of the Jacobi preconditioner
+  const int64_t *ldiag, *udiag;  // cast diagonals (Jacobi, ILU)
+  const int64_t *lptr, *uptr;    // strict triangles of the integer ILU factors
+  const int32_t *lcol, *ucol;
+  const int64_t *lval, *uval;
+  const double *lvalf, *uvalf;   // the same values in FP64 (line 1')
+  const int32_t *flev_ptr, *flev_rows, *blev_ptr, *blev_rows;
   int64_t *V;                    // (m+1) x ldv basis
-  unsigned long long *words;     // kTeamSlots x kTeamWords exchange words
+  int64_t *zbuf, *wbuf;          // ILU: SpMV output and preconditioned vector
+  double *fbuf;                  // ILU: FP64 substitution of line 1'
+  double *x;                     // solution (in: start, out: result)
+  unsigned long long *words;     // team exchange words
+  BatchResult *res;              // written by the first member
 };
 
 // Outcome of one system, written by its first member.
@@ -42,22 +61,52 @@ struct BatchResult {
 };
 
 struct BatchArgs {
-  const BatchSys *sys;
-  const int32_t *jobs;  // pairs (system, member) in claim order
-  int32_t njobs;
-  int32_t m, df, precond;
-  int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
-  int32_t max_refine;
+  BatchSys *sys;        // system records (served mode: one per slot)
+  const int32_t *jobs;  // batch mode: pairs (system, member) in claim order
+  int32_t njobs;        // batch mode: number of jobs
   int32_t phase_clock;  // record the phase clocks of each system's first member
-  int64_t gtol;
-  double tol;
-  int32_t *queue;  // next job to claim
-  int32_t *timeout;
-  BatchResult *res;
-  double *x;  // concatenated solutions (in: start, out: result)
+  int32_t *queue;       // next claim
+  int32_t *timeout;     // set when a team wait timed out
+  // served mode: the host publishes jobs while the kernel runs (pinned host memory)
+  const int32_t *host_jobs;       // ring of pairs (slot, member)
+  const int64_t *host_published;  // jobs published so far
+  const int32_t *host_stop;       // 1 = exit once no published job is left
+  int32_t *host_done;             // per slot: seq of the last completed request
+  int32_t ring;                   // capacity of host_jobs in pairs (0 = batch mode)
+  int32_t pad_;
+  int64_t idle_polls;             // served mode: exit after this many polls without work
 };
 
-const void *batch_kernel(int block, int R, int pre);
+// ---- host side, shared by the batched and the served solver ----
+
+// A validated system with its host setup products (everything the device
+// needs, in the layouts the kernels read).
+struct HostSystem {
+  int64_t n = 0, nnz = 0;
+  igm_policy pol{};
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<double> ahat, bhat;
+  HostSetup h;
+  int nterms = 1;
+  std::vector<double> lvalf, uvalf;  // FP64 copies of the integer factors (line 1')
+};
+
+// Largest m of the batched kernel (H lives in LDS).
+constexpr int kMaxBatchM = 64;
+
+// Validates (as igm_create_system) and runs the host setup of one system.
+igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                          const double *b, const igm_policy &pol, HostSystem &out);
+// Device bytes of one system's region (inputs, setup products, basis, work
+// vectors, exchange words; the solution vector only if own_x).
+size_t system_bytes(const HostSystem &hs, bool own_x);
+// Queues the uploads of one system into the region at `base` on `st` and
+// fills its record (team = 1, res = nullptr; x = the region's own vector if
+// own_x, else left null). The host vectors must live until `st` has drained.
+hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_t st, BatchSys &S);
+
+const void *batch_kernel(int block, int R);
 size_t batch_smem_bytes(int m);
 // the (block, rows per thread) shapes instantiated for the batched kernel
 extern const int kBatchShapes[][2];

@@ -37,7 +37,8 @@ __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64
 
 // Line 5' forward substitution for one row: y_i = tdiv(z_i - sum_{j<i}
 // Lbar_ij y_j, Lbar_ii).
-__device__ __forceinline__ int64_t lower_row(const CycleArgs &a, int64_t row, int64_t zi,
+template <class A>
+__device__ __forceinline__ int64_t lower_row(const A &a, int64_t row, int64_t zi,
                                              const int64_t *__restrict__ y, bool &ovf) {
   Acc acc;
   acc.zero();
@@ -48,7 +49,8 @@ __device__ __forceinline__ int64_t lower_row(const CycleArgs &a, int64_t row, in
 
 // Line 5' backward substitution for one row: u_i = tdiv(y_i - sum_{j>i}
 // Ubar_ij u_j, Ubar_ii).
-__device__ __forceinline__ int64_t upper_row(const CycleArgs &a, int64_t row, int64_t yi,
+template <class A>
+__device__ __forceinline__ int64_t upper_row(const A &a, int64_t row, int64_t yi,
                                              const int64_t *__restrict__ u, bool &ovf) {
   Acc acc;
   acc.zero();

@@ -22,8 +22,8 @@
 
 namespace igm {
 
-constexpr int kTeamMax = 64;    // workgroups per system (one lane each)
-constexpr int kTeamSlots = 4;   // exchanges before a slot is reused
+constexpr int kTeamMax = 256;   // workgroups per system
+constexpr int kTeamSlots = 2;   // exchanges before a slot is reused
 constexpr int kTeamPay = 4;     // payload words per exchange
 constexpr int kTeamWords = kTeamPay * kTeamMax;  // words per slot
 
@@ -52,32 +52,53 @@ __device__ __forceinline__ void team_init(TeamShared &sh) {
 }
 
 // One exchange among the T > 1 members; wavefront 0 only (all 64 lanes).
-// u[0..P) are this member's payload words (wave-uniform, |u| < 2^53). On
-// return lane q holds member q's payload words in u[0..P) (zeros for
-// q >= T). Sets `to` on timeout.
-template <int P>
+// u[0..P) are this member's payload words (wave-uniform). SUM: each word
+// |u| < 2^53, and on return lane q holds the sum of the words of members
+// q, q + 64, q + 128, ... (< T). MAX: each word is any 64-bit value (sent as
+// two 32-bit halves, 2P <= kTeamPay) and lane q receives the maximum over the
+// same members. Sets `to` on timeout.
+template <int P, bool MAX>
 __device__ __forceinline__ void team_exchange(Team &tm, TeamShared &sh, unsigned long long (&u)[P], bool &to) {
-  static_assert(P >= 1 && P <= kTeamPay, "payload words");
+  constexpr int W = MAX ? 2 * P : P;  // words per member
+  static_assert(P >= 1 && W <= kTeamPay, "payload words");
   const int q = threadIdx.x & 63;
   const int slot = tm.e % kTeamSlots;
   tm.e += 1;
-  unsigned long long *w = tm.words + slot * kTeamWords + q;
-  if (q == tm.member) {
+  unsigned long long *base = tm.words + slot * kTeamWords;
+  unsigned long long wv[W];
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-      __hip_atomic_fetch_add(w + p * kTeamMax, (u[p] << 10) + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int p = 0; p < P; ++p) {
+    if (MAX) {
+      wv[2 * p] = u[p] & 0xFFFFFFFFull;
+      wv[2 * p + 1] = u[p] >> 32;
+    } else {
+      wv[p] = u[p];
+    }
   }
-  const bool used = q < tm.T;
-  unsigned long long d[P];
+  if (q == (tm.member & 63)) {
 #pragma unroll
-  for (int p = 0; p < P; ++p) d[p] = 0;
+    for (int w = 0; w < W; ++w)
+      __hip_atomic_fetch_add(base + w * kTeamMax + tm.member, (wv[w] << 10) + 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+  constexpr int G = kTeamMax / 64;  // member groups per lane
+  unsigned long long d[G][W];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[g][w] = 0;
   for (int spin = 0;; ++spin) {
     bool ok = true;
-    if (used) {
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        d[p] = __hip_atomic_load(w + p * kTeamMax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - sh.prev[slot][p][q];
-        ok = ok && (d[p] & 1023ull) == 1ull;
+    for (int g = 0; g < G; ++g) {
+      const int mq = q + 64 * g;
+      if (mq < tm.T) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          d[g][w] = __hip_atomic_load(base + w * kTeamMax + mq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                    sh.prev[slot][w][mq];
+          ok = ok && (d[g][w] & 1023ull) == 1ull;
+        }
       }
     }
     if (__all(ok)) break;
@@ -85,9 +106,27 @@ __device__ __forceinline__ void team_exchange(Team &tm, TeamShared &sh, unsigned
     __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
   }
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    if (used) sh.prev[slot][p][q] += d[p];
-    u[p] = used ? (unsigned long long)((int64_t)d[p] >> 10) : 0ull;
+  for (int p = 0; p < P; ++p) u[p] = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int mq = q + 64 * g;
+    if (mq < tm.T) {
+      unsigned long long pay[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        sh.prev[slot][w][mq] += d[g][w];
+        pay[w] = (unsigned long long)((int64_t)d[g][w] >> 10);
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if (MAX) {
+          const unsigned long long v = pay[2 * p] | (pay[2 * p + 1] << 32);
+          u[p] = v > u[p] ? v : u[p];
+        } else {
+          u[p] += pay[p];
+        }
+      }
+    }
   }
 }
 
@@ -125,7 +164,7 @@ __device__ __forceinline__ int64_t team_sum(Team &tm, Acc a, TeamShared &sh, Fin
     if (tm.T > 1 && !sh.abort) {
       p.normalize();  // lo in [0, 2^40)
       unsigned long long u[2] = {(unsigned long long)p.lo, (unsigned long long)p.hi};
-      team_exchange<2>(tm, sh, u, to);  // lane q: member q's limbs
+      team_exchange<2, false>(tm, sh, u, to);  // lane q: limbs of members q, q + 64, ...
       p.lo = wave_sum64((int64_t)u[0]);
       p.hi = wave_sum64((int64_t)u[1]);
     }
@@ -154,7 +193,7 @@ __device__ __forceinline__ void team_barrier(Team &tm, TeamShared &sh, Side side
       bool to = false;
       unsigned long long u[1] = {0};
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      team_exchange<1>(tm, sh, u, to);
+      team_exchange<1, false>(tm, sh, u, to);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (threadIdx.x == 0 && to) team_abort(tm, sh);
     }
@@ -201,21 +240,9 @@ __device__ __forceinline__ void team_reduce(Team &tm, TeamShared &sh, unsigned l
     for (int p = 0; p < P; ++p) r[p] = lanes_reduce<MAX>(lane < BLOCK / 64 ? sh.part[p][lane] : 0ull, 64);
     if (tm.T > 1 && !sh.abort) {
       bool to = false;
-      if constexpr (MAX) {  // each value travels as two 32-bit halves
-        unsigned long long u[2 * P];
+      team_exchange<P, MAX>(tm, sh, r, to);
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-          u[2 * p] = r[p] & 0xFFFFFFFFull;
-          u[2 * p + 1] = r[p] >> 32;
-        }
-        team_exchange<2 * P>(tm, sh, u, to);
-#pragma unroll
-        for (int p = 0; p < P; ++p) r[p] = lanes_reduce<true>(u[2 * p] | (u[2 * p + 1] << 32), 64);
-      } else {
-        team_exchange<P>(tm, sh, r, to);
-#pragma unroll
-        for (int p = 0; p < P; ++p) r[p] = lanes_reduce<false>(r[p], 64);
-      }
+      for (int p = 0; p < P; ++p) r[p] = lanes_reduce<MAX>(r[p], 64);
       if (lane == 0 && to) team_abort(tm, sh);
     }
     if (lane == 0) {

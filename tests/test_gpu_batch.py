@@ -88,6 +88,21 @@ def test_batch_teams_of_many_workgroups(orc, torch):
         check_against_oracle(bt, x, systems, refs)
 
 
+@pytest.mark.parametrize("block,rows", [(1024, 4), (256, 8)])
+def test_batch_ilu_bit_exact(orc, torch, block, rows):
+    """ILU(0) preconditioned systems (Sec. VI): level-scheduled integer sweeps
+    and the FP64 substitution of line 1' inside a team, including teams of
+    several workgroups (the 4800- and 7007-row systems at 2048 rows each)."""
+    systems = [W.random27(9, 8, 6, seed=61), W.random_dd(300, 0.05, 62), W.random27(20, 20, 12, seed=63),
+               W.convdiff2d(91, 77, seed=64), W.random27(5, 4, 3, seed=65)]
+    refs = [oracle_solve(orc, s, "paper_ilu", m=30) for s in systems]
+    bt = B.Batch(systems, "paper_ilu", m=30)
+    assert bt.set_shape(block, rows) == B.OK
+    x, st = bt.solve()
+    assert st == B.OK
+    check_against_oracle(bt, x, systems, refs)
+
+
 def test_batch_paper_noprec_preset(orc, torch):
     systems = [W.poisson2d(37, 29), W.poisson2d(20, 20), W.poisson2d(64)]
     refs = [oracle_solve(orc, s, "paper_noprec", m=30) for s in systems]
@@ -157,7 +172,7 @@ def test_batch_rejects_bad_input(torch):
         B.Batch([good, bad], "jacobi", m=10)
     assert e.value.status == B.ERR_ARG and "system 1" in str(e.value)
     with pytest.raises(B.IgmError) as e:
-        B.Batch([good], "paper_ilu", m=10)
+        B.Batch([good], "jacobi", m=65)  # H of the call lives in LDS: m <= 64
     assert e.value.status == B.ERR_UNSUPPORTED
     bt = B.Batch([good], "jacobi", m=10)
     assert bt.set_shape(300, 8) == B.ERR_ARG
