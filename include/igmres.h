@@ -42,6 +42,7 @@ typedef struct igm_system igm_system;
 typedef enum {
   IGM_OK = 0,
   IGM_NOT_CONVERGED = 1,      /* warning: refinement limit reached; x holds the last iterate */
+  IGM_PENDING = 2,            /* served request not finished yet (igm_server_wait timed out) */
   IGM_ERR_ARG = -1,           /* invalid argument, CSR or policy */
   IGM_ERR_SINGULAR_ROW = -2,  /* a row of Ahat is all zero: eq. (eq3) undefined */
   IGM_ERR_ZERO_PIVOT = -3,    /* zero ILU(0) pivot, missing diagonal, or a cast diagonal of 0 */
@@ -301,6 +302,86 @@ igm_status igm_batch_get_stats(const igm_batch *bt, igm_stats *out);
 
 /* Release all device and host memory of the batch. NULL is a no-op. */
 void igm_batch_destroy(igm_batch *bt);
+
+/* ---- Served solver: continuous batching of a stream of solve requests ----
+ * A persistent kernel stays resident on the device and takes jobs from a ring
+ * in pinned host memory while it runs. Submitted requests are prepared on
+ * host threads (validation, scaling, integer matrices, preconditioner) into
+ * a staging area of pinned host memory, then admitted as soon as a slot,
+ * device memory for the request's whole footprint (inputs, factors, Krylov
+ * basis, work vectors) and enough idle workgroups for its team are free;
+ * requests that do not fit wait while smaller ones behind them may pass. The
+ * kernel's workgroups copy an admitted request's inputs to the device
+ * themselves and write x back to the staging area, so no runtime copy runs
+ * while the kernel is resident. Requests overlap on the device, each solved
+ * as by the batched solver (bit-identical to igm_solve_device on the system
+ * alone). The kernel occupies all but reserve_cus compute units until the
+ * server is destroyed. Thread-safe: submit, poll and wait may be called from
+ * any threads. */
+typedef struct igm_server igm_server;
+
+typedef struct {
+  int32_t struct_size;      /* sizeof(igm_server_config) */
+  int32_t block;            /* launch shape: (1024, 4) or (512, 8); 0 = (1024, 4) */
+  int32_t rows_per_thread;
+  int32_t max_slots;        /* requests resident at once; 0 = 256 */
+  int32_t setup_threads;    /* host threads preparing requests; 0 = 8 */
+  int32_t reserve_cus;      /* compute units left to other kernels (the runtime's copy kernels,
+                               the application); 0 = 8, < 0 = none */
+  int64_t pool_bytes;       /* device memory for resident requests; 0 = 16 GiB */
+  int64_t stage_bytes;      /* pinned host memory for prepared requests and results; 0 = 4 GiB */
+  int32_t reserved_[6];
+} igm_server_config;
+
+/* Start a server on the current device. Errors: IGM_ERR_ARG, IGM_ERR_OOM,
+ * IGM_ERR_DEVICE, IGM_ERR_UNSUPPORTED (shape). */
+igm_status igm_server_create(const igm_server_config *cfg, igm_server **out);
+
+/* Submit one solve (the arguments of igm_create_system plus an optional
+ * starting iterate x0[n], NULL = zeros). Host arrays are copied during the
+ * call. *ticket receives the request's number. Errors found while preparing
+ * the request (IGM_ERR_ARG, IGM_ERR_SINGULAR_ROW, ...) and requests that can
+ * never fit (IGM_ERR_UNSUPPORTED: m > 64, footprint above the pool, more than
+ * 256 or than all resident workgroups) are reported as the request's status. */
+igm_status igm_server_submit(igm_server *sv, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const double *val, const double *b, const double *x0, const igm_policy *pol,
+                             int64_t *ticket);
+
+/* Non-blocking check of a request (returns IGM_OK). If it has finished,
+ * *done = 1, x (host,
+ * n doubles, may be NULL) receives the solution, *stats (may be NULL) its
+ * statistics, and the request is forgotten (a ticket is collected once).
+ * Statistics of a served request: status, refinements, iterations,
+ * first_ovf, relres_orig/scaled, n, nnz, grid_blocks (team size);
+ * time_solve_ms = submission to result (latency), time_setup_ms = submission
+ * to prepared, time_cycle_ms = admission to result, time_kernel_ms = device
+ * time of the solve. IGM_ERR_ARG for an unknown ticket. */
+igm_status igm_server_poll(igm_server *sv, int64_t ticket, int32_t *done, double *x, igm_stats *stats);
+
+/* Blocking version of igm_server_poll with a timeout in ms (< 0 = no limit):
+ * IGM_OK once the request has finished (its own status is stats->status),
+ * IGM_PENDING if the timeout expired (the request stays pending). */
+igm_status igm_server_wait(igm_server *sv, int64_t ticket, double timeout_ms, double *x, igm_stats *stats);
+
+typedef struct {
+  int32_t struct_size;
+  int32_t slots_used;       /* requests resident now */
+  int64_t submitted, completed, prepared_waiting, resident;
+  int64_t pool_bytes, pool_used, pool_peak;
+  int64_t workgroups, workgroups_busy;
+  int32_t block_threads, rows_per_thread;
+  int64_t setup_waiting;    /* submitted, not yet prepared */
+  int64_t jobs_published;   /* workgroup jobs handed to the persistent kernel so far */
+  int32_t kernel_alive;     /* the persistent kernel is running */
+  int32_t reserved_[5];
+} igm_server_stats;
+
+igm_status igm_server_get_stats(igm_server *sv, igm_server_stats *out);
+
+/* Finish every request already submitted (waiting at most timeout_ms, < 0 =
+ * no limit), stop the persistent kernel and release everything. NULL is a
+ * no-op. */
+void igm_server_destroy(igm_server *sv, double timeout_ms);
 
 /* Static description of a status code. */
 const char *igm_status_str(igm_status st);

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libigmres.so")
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
 ERR_ARG, ERR_SINGULAR_ROW, ERR_ZERO_PIVOT, ERR_OVERFLOW = -1, -2, -3, -4
 ERR_RANGE, ERR_OOM, ERR_DEVICE, ERR_BREAKDOWN, ERR_UNSUPPORTED = -5, -6, -7, -8, -9
 PRE_NONE, PRE_JACOBI, PRE_ILU0 = 0, 1, 2
@@ -102,6 +102,13 @@ _SIGS = {
     "igm_batch_get_result": [C.c_void_p, C.c_int32, C.c_void_p],
     "igm_batch_get_stats": [C.c_void_p, C.c_void_p],
     "igm_batch_destroy": [C.c_void_p],
+    "igm_server_create": [C.c_void_p, C.c_void_p],
+    "igm_server_submit": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.c_void_p, C.c_void_p],
+    "igm_server_poll": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_server_wait": [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p],
+    "igm_server_get_stats": [C.c_void_p, C.c_void_p],
+    "igm_server_destroy": [C.c_void_p, C.c_double],
 }
 EXPORTED = tuple(_SIGS)
 
@@ -119,6 +126,7 @@ def lib():
             fn.restype = C.c_int
         L.igm_destroy.restype = None
         L.igm_batch_destroy.restype = None
+        L.igm_server_destroy.restype = None
         L.igm_status_str.restype = C.c_char_p
         _lib = L
     return _lib
@@ -388,4 +396,90 @@ class Batch:
         s = Stats()
         s.struct_size = C.sizeof(Stats)
         _check(lib().igm_batch_get_stats(self.h, C.byref(s)), "igm_batch_get_stats")
+        return s.as_dict()
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("block", C.c_int32), ("rows_per_thread", C.c_int32),
+                ("max_slots", C.c_int32), ("setup_threads", C.c_int32), ("reserve_cus", C.c_int32),
+                ("pool_bytes", C.c_int64), ("stage_bytes", C.c_int64), ("reserved_", C.c_int32 * 6)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("slots_used", C.c_int32), ("submitted", C.c_int64),
+                ("completed", C.c_int64), ("prepared_waiting", C.c_int64), ("resident", C.c_int64),
+                ("pool_bytes", C.c_int64), ("pool_used", C.c_int64), ("pool_peak", C.c_int64),
+                ("workgroups", C.c_int64), ("workgroups_busy", C.c_int64), ("block_threads", C.c_int32),
+                ("rows_per_thread", C.c_int32), ("setup_waiting", C.c_int64), ("jobs_published", C.c_int64),
+                ("kernel_alive", C.c_int32), ("reserved_", C.c_int32 * 5)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if not f.endswith("_")}
+
+
+class Server:
+    """One igm_server: a persistent kernel that solves submitted requests as
+    they arrive (continuous batching). Owned; closing drains it."""
+
+    def __init__(self, block=0, rows_per_thread=0, max_slots=0, setup_threads=0, pool_bytes=0, reserve_cus=0,
+                 stage_bytes=0):
+        cfg = ServerConfig(C.sizeof(ServerConfig), block, rows_per_thread, max_slots, setup_threads, reserve_cus,
+                           int(pool_bytes), int(stage_bytes))
+        h = C.c_void_p()
+        _check(lib().igm_server_create(C.byref(cfg), C.byref(h)), "igm_server_create")
+        self.h = h
+        self._n = {}
+
+    def close(self, timeout_ms: float = 60000.0):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.igm_server_destroy(self.h, float(timeout_ms))
+        self.h = None
+
+    def __del__(self):
+        self.close(10000.0)
+
+    def submit(self, sysm, pol="jacobi", x0=None, **overrides) -> int:
+        if isinstance(pol, str):
+            pol = make_policy(pol, **overrides)
+        ps = _policy_struct(pol)
+        rp = np.ascontiguousarray(sysm.row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(sysm.col, dtype=np.int32)
+        vl = np.ascontiguousarray(sysm.val, dtype=np.float64)
+        bb = np.ascontiguousarray(sysm.b, dtype=np.float64)
+        xx = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        t = C.c_int64(-1)
+        _check(lib().igm_server_submit(self.h, int(sysm.n), rp.ctypes.data, cl.ctypes.data, vl.ctypes.data,
+                                       bb.ctypes.data, None if xx is None else xx.ctypes.data,
+                                       C.addressof(ps), C.byref(t)), "igm_server_submit")
+        self._n[t.value] = int(sysm.n)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, x, stats); x and stats are None until done."""
+        x = np.zeros(max(self._n.get(ticket, 0), 1))  # unknown tickets: the library reports ERR_ARG
+        s = Stats()
+        s.struct_size = C.sizeof(Stats)
+        done = C.c_int32(0)
+        _check(lib().igm_server_poll(self.h, int(ticket), C.byref(done), x.ctypes.data, C.byref(s)),
+               "igm_server_poll")
+        if not done.value:
+            return False, None, None
+        n = self._n.pop(ticket)
+        return True, x[:n], s.as_dict()
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        """(x, stats) once the request has finished; raises IgmError(PENDING) on timeout."""
+        x = np.zeros(max(self._n.get(ticket, 0), 1))  # unknown tickets: the library reports ERR_ARG
+        s = Stats()
+        s.struct_size = C.sizeof(Stats)
+        st = lib().igm_server_wait(self.h, int(ticket), float(timeout_ms), x.ctypes.data, C.byref(s))
+        if st != OK:
+            raise IgmError(st, f"igm_server_wait (server: {self.stats()})")
+        n = self._n.pop(ticket)
+        return x[:n], s.as_dict()
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        s.struct_size = C.sizeof(ServerStats)
+        _check(lib().igm_server_get_stats(self.h, C.byref(s)), "igm_server_get_stats")
         return s.as_dict()

@@ -648,6 +648,7 @@ const char *igm_status_str(igm_status st) {
   switch (st) {
     case IGM_OK: return "ok";
     case IGM_NOT_CONVERGED: return "not converged";
+    case IGM_PENDING: return "pending";
     case IGM_ERR_ARG: return "invalid argument";
     case IGM_ERR_SINGULAR_ROW: return "all-zero row";
     case IGM_ERR_ZERO_PIVOT: return "zero pivot";

@@ -34,6 +34,7 @@ void walk_region(const HostSystem &hs, bool own_x, F &&f) {
   const HostSetup &h = hs.h;
   const size_t n = (size_t)hs.n, nz = (size_t)hs.nnz;
   const size_t ldv = (size_t)((hs.n + 15) / 16 * 16);
+  // data: inputs and setup products, x, exchange words
   f("row_ptr", sizeof(int64_t) * (n + 1));
   f("col", sizeof(int32_t) * nz);
   f("a", sizeof(double) * nz);
@@ -61,13 +62,52 @@ void walk_region(const HostSystem &hs, bool own_x, F &&f) {
     f("flev_rows", sizeof(int32_t) * h.flev_rows.size());
     f("blev_ptr", sizeof(int32_t) * h.blev_ptr.size());
     f("blev_rows", sizeof(int32_t) * h.blev_rows.size());
+  }
+  if (own_x) f("x", sizeof(double) * n);
+  f("words", sizeof(unsigned long long) * (size_t)kTeamSlots * kTeamWords);
+  // work arrays (written before they are read)
+  if (hs.pol.precond == IGM_PRE_ILU0) {
     f("zbuf", sizeof(int64_t) * n);
     f("wbuf", sizeof(int64_t) * n);
     f("fbuf", sizeof(double) * n);
   }
   f("V", sizeof(int64_t) * (size_t)(hs.pol.m + 1) * ldv);
-  if (own_x) f("x", sizeof(double) * n);
-  f("words", sizeof(unsigned long long) * (size_t)kTeamSlots * kTeamWords);
+}
+
+bool is_work_array(const char *name) {
+  const std::string nm(name);
+  return nm == "zbuf" || nm == "wbuf" || nm == "fbuf" || nm == "V";
+}
+
+// Host source of a data array of the region (nullptr for x and words).
+const void *array_source(const HostSystem &hs, const char *name, int &term) {
+  const HostSetup &h = hs.h;
+  const std::string nm(name);
+  if (nm == "row_ptr") return hs.row_ptr.data();
+  if (nm == "col") return hs.col.data();
+  if (nm == "a") return h.a.data();
+  if (nm == "ahat") return hs.ahat.data();
+  if (nm == "b") return h.b.data();
+  if (nm == "bhat") return hs.bhat.data();
+  if (nm == "sell_off") return h.sell_off.data();
+  if (nm == "sell_w") return h.sell_w.data();
+  if (nm == "sell_col") return h.sell_col.data();
+  if (nm == "sell_val") return h.sell_val[term++].data();
+  if (nm == "ldiag") return h.ldiag.data();
+  if (nm == "udiag") return h.udiag.data();
+  if (nm == "lptr") return h.lptr.data();
+  if (nm == "uptr") return h.uptr.data();
+  if (nm == "lcol") return h.lcol.data();
+  if (nm == "ucol") return h.ucol.data();
+  if (nm == "lval") return h.lval.data();
+  if (nm == "uval") return h.uval.data();
+  if (nm == "lvalf") return hs.lvalf.data();
+  if (nm == "uvalf") return hs.uvalf.data();
+  if (nm == "flev_ptr") return h.flev_ptr.data();
+  if (nm == "flev_rows") return h.flev_rows.data();
+  if (nm == "blev_ptr") return h.blev_ptr.data();
+  if (nm == "blev_rows") return h.blev_rows.data();
+  return nullptr;
 }
 
 }  // namespace
@@ -103,7 +143,7 @@ size_t system_bytes(const HostSystem &hs, bool own_x) {
   return total;
 }
 
-hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_t st, BatchSys &S) {
+void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
   const HostSetup &h = hs.h;
   const igm_policy &p = hs.pol;
   memset(&S, 0, sizeof(S));
@@ -124,47 +164,94 @@ hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_
   }
   size_t off = 0;
   int term = 0;
-  hipError_t err = hipSuccess;
-  auto put = [&](const void *src, void *dst, size_t bytes) {
-    if (err == hipSuccess && bytes && src) err = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
-  };
   walk_region(hs, own_x, [&](const char *name, size_t bytes) {
     char *d = base + off;
     off += align_up(bytes);
     const std::string nm(name);
-    if (nm == "row_ptr") { put(hs.row_ptr.data(), d, bytes); S.row_ptr = (const int64_t *)d; }
-    else if (nm == "col") { put(hs.col.data(), d, bytes); S.col = (const int32_t *)d; }
-    else if (nm == "a") { put(h.a.data(), d, bytes); S.a = (const double *)d; }
-    else if (nm == "ahat") { put(hs.ahat.data(), d, bytes); S.ahat = (const double *)d; }
-    else if (nm == "b") { put(h.b.data(), d, bytes); S.b = (const double *)d; }
-    else if (nm == "bhat") { put(hs.bhat.data(), d, bytes); S.bhat = (const double *)d; }
-    else if (nm == "sell_off") { put(h.sell_off.data(), d, bytes); S.sell_off = (const int64_t *)d; }
-    else if (nm == "sell_w") { put(h.sell_w.data(), d, bytes); S.sell_w = (const int32_t *)d; }
-    else if (nm == "sell_col") { put(h.sell_col.data(), d, bytes); S.sell_col = (const int32_t *)d; }
-    else if (nm == "sell_val") { put(h.sell_val[term].data(), d, bytes); S.sell_val[term++] = (const int64_t *)d; }
-    else if (nm == "ldiag") { put(h.ldiag.data(), d, bytes); S.ldiag = (const int64_t *)d; }
-    else if (nm == "udiag") { put(h.udiag.data(), d, bytes); S.udiag = (const int64_t *)d; }
-    else if (nm == "lptr") { put(h.lptr.data(), d, bytes); S.lptr = (const int64_t *)d; }
-    else if (nm == "uptr") { put(h.uptr.data(), d, bytes); S.uptr = (const int64_t *)d; }
-    else if (nm == "lcol") { put(h.lcol.data(), d, bytes); S.lcol = (const int32_t *)d; }
-    else if (nm == "ucol") { put(h.ucol.data(), d, bytes); S.ucol = (const int32_t *)d; }
-    else if (nm == "lval") { put(h.lval.data(), d, bytes); S.lval = (const int64_t *)d; }
-    else if (nm == "uval") { put(h.uval.data(), d, bytes); S.uval = (const int64_t *)d; }
-    else if (nm == "lvalf") { put(hs.lvalf.data(), d, bytes); S.lvalf = (const double *)d; }
-    else if (nm == "uvalf") { put(hs.uvalf.data(), d, bytes); S.uvalf = (const double *)d; }
-    else if (nm == "flev_ptr") { put(h.flev_ptr.data(), d, bytes); S.flev_ptr = (const int32_t *)d; }
-    else if (nm == "flev_rows") { put(h.flev_rows.data(), d, bytes); S.flev_rows = (const int32_t *)d; }
-    else if (nm == "blev_ptr") { put(h.blev_ptr.data(), d, bytes); S.blev_ptr = (const int32_t *)d; }
-    else if (nm == "blev_rows") { put(h.blev_rows.data(), d, bytes); S.blev_rows = (const int32_t *)d; }
+    if (nm == "row_ptr") S.row_ptr = (const int64_t *)d;
+    else if (nm == "col") S.col = (const int32_t *)d;
+    else if (nm == "a") S.a = (const double *)d;
+    else if (nm == "ahat") S.ahat = (const double *)d;
+    else if (nm == "b") S.b = (const double *)d;
+    else if (nm == "bhat") S.bhat = (const double *)d;
+    else if (nm == "sell_off") S.sell_off = (const int64_t *)d;
+    else if (nm == "sell_w") S.sell_w = (const int32_t *)d;
+    else if (nm == "sell_col") S.sell_col = (const int32_t *)d;
+    else if (nm == "sell_val") S.sell_val[term++] = (const int64_t *)d;
+    else if (nm == "ldiag") S.ldiag = (const int64_t *)d;
+    else if (nm == "udiag") S.udiag = (const int64_t *)d;
+    else if (nm == "lptr") S.lptr = (const int64_t *)d;
+    else if (nm == "uptr") S.uptr = (const int64_t *)d;
+    else if (nm == "lcol") S.lcol = (const int32_t *)d;
+    else if (nm == "ucol") S.ucol = (const int32_t *)d;
+    else if (nm == "lval") S.lval = (const int64_t *)d;
+    else if (nm == "uval") S.uval = (const int64_t *)d;
+    else if (nm == "lvalf") S.lvalf = (const double *)d;
+    else if (nm == "uvalf") S.uvalf = (const double *)d;
+    else if (nm == "flev_ptr") S.flev_ptr = (const int32_t *)d;
+    else if (nm == "flev_rows") S.flev_rows = (const int32_t *)d;
+    else if (nm == "blev_ptr") S.blev_ptr = (const int32_t *)d;
+    else if (nm == "blev_rows") S.blev_rows = (const int32_t *)d;
     else if (nm == "zbuf") S.zbuf = (int64_t *)d;
     else if (nm == "wbuf") S.wbuf = (int64_t *)d;
     else if (nm == "fbuf") S.fbuf = (double *)d;
     else if (nm == "V") S.V = (int64_t *)d;
     else if (nm == "x") S.x = (double *)d;
-    else if (nm == "words") {
-      S.words = (unsigned long long *)d;
-      if (err == hipSuccess) err = hipMemsetAsync(d, 0, bytes, st);
+    else if (nm == "words") S.words = (unsigned long long *)d;
+  });
+}
+
+size_t image_bytes(const HostSystem &hs) {
+  size_t total = 0;
+  bool work = false;
+  walk_region(hs, true, [&](const char *name, size_t bytes) {
+    work = work || is_work_array(name);
+    if (!work) total += align_up(bytes);
+  });
+  return total;
+}
+
+void build_image(const HostSystem &hs, char *img, const double *x0) {
+  size_t off = 0;
+  int term = 0;
+  bool work = false;
+  walk_region(hs, true, [&](const char *name, size_t bytes) {
+    work = work || is_work_array(name);
+    if (work) return;
+    char *d = img + off;
+    const size_t span = align_up(bytes);
+    off += span;
+    const std::string nm(name);
+    if (nm == "x" && x0) {
+      memcpy(d, x0, bytes);
+      memset(d + bytes, 0, span - bytes);
+      return;
     }
+    const void *src = array_source(hs, name, term);
+    if (src && bytes) memcpy(d, src, bytes);
+    memset(d + (src ? bytes : 0), 0, src ? span - bytes : span);
+  });
+}
+
+hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_t st, BatchSys &S) {
+  record_for(hs, own_x, base, S);
+  size_t off = 0;
+  int term = 0;
+  hipError_t err = hipSuccess;
+  walk_region(hs, own_x, [&](const char *name, size_t bytes) {
+    char *d = base + off;
+    off += align_up(bytes);
+    if (err != hipSuccess || is_work_array(name) || !bytes) return;
+    const std::string nm(name);
+    if (nm == "x") return;  // the caller's
+    if (nm == "words") {
+      // cleared by a copy (a copy engine rather than a fill kernel)
+      static const std::vector<unsigned long long> zeros((size_t)kTeamSlots * kTeamWords, 0ull);
+      err = hipMemcpyAsync(d, zeros.data(), bytes, hipMemcpyHostToDevice, st);
+      return;
+    }
+    const void *src = array_source(hs, name, term);
+    if (src) err = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, st);
   });
   return err;
 }

@@ -108,10 +108,11 @@ constexpr int64_t kEvBias = (int64_t)1 << 53;
 
 }  // namespace
 
-template <int BLOCK, int R>
+template <int BLOCK, int R, bool SERVED>
 __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
   extern __shared__ int64_t smem[];
   __shared__ TeamShared tsh;
+  __shared__ BatchSys srec;  // served mode: this job's record, read coherently
   __shared__ int sh_job, sh_sid, sh_member, sh_stop, sh_jstar, sh_steps;
   __shared__ long long sh_ovf;  // smallest overflow event of the current call in this workgroup
 
@@ -123,14 +124,15 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
       const int c = atomicAdd(ba.queue, 1);
       int job = -1;  // -1: nothing left, leave
       int sid = 0, member = 0;
-      if (ba.ring == 0) {
+      if (!SERVED) {
         if (c < ba.njobs) {
           job = c;
           sid = ba.jobs[2 * c];
           member = ba.jobs[2 * c + 1];
         }
       } else {
-        // served mode: wait (bounded) until the host has published job c
+        // served mode: wait (bounded) until the host has published job c;
+        // the pause between polls of host memory grows to ~16 x 8k clocks
         for (int64_t idle = 0;; ++idle) {
           if (c < __hip_atomic_load(ba.host_published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
             job = c;
@@ -138,7 +140,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
           }
           if (__hip_atomic_load(ba.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) || idle >= ba.idle_polls)
             break;
-          __builtin_amdgcn_s_sleep(127);
+          const int pauses = idle < 64 ? 1 : 16;
+          for (int k = 0; k < pauses; ++k) __builtin_amdgcn_s_sleep(127);
         }
         if (job >= 0) {
           const int64_t e = 2 * (int64_t)(c % ba.ring);
@@ -157,9 +160,47 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
     if (job < 0) break;
     const int sid = __builtin_amdgcn_readfirstlane(sh_sid);
     const int member = __builtin_amdgcn_readfirstlane(sh_member);
-    // the host wrote this slot's inputs before publishing the job
-    if (ba.ring) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-    const BatchSys &S = ba.sys[sid];
+    if (SERVED) {
+      // the host wrote this slot's record and inputs before publishing the
+      // job; the record is read with coherent loads into LDS (a slot's record
+      // changes between requests)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      static_assert(sizeof(BatchSys) % 8 == 0, "record copied in 64-bit words");
+      const unsigned long long *src = (const unsigned long long *)(ba.sys + sid);
+      for (int i = tid; i < (int)(sizeof(BatchSys) / 8); i += BLOCK)
+        ((unsigned long long *)&srec)[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __syncthreads();
+    }
+    const BatchSys &S = SERVED ? srec : ba.sys[sid];
+    if (SERVED) {
+      // the members copy the staged inputs (pinned host memory) into the
+      // request's device region, each its share, then meet on the slot's
+      // arrival counter (monotonic: the target counts every member of every
+      // request the slot has held)
+      const int64_t units = S.up_bytes / 16;
+      const int64_t per = (units + S.team - 1) / S.team;
+      const int64_t lo = (int64_t)member * per, hi = lo + per < units ? lo + per : units;
+      const uint4 *__restrict__ src = (const uint4 *)S.src;
+      uint4 *__restrict__ dst = (uint4 *)S.dst;
+      for (int64_t i = lo + tid; i < hi; i += BLOCK) dst[i] = src[i];
+      __syncthreads();
+      if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(S.arrive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int spin = 0;; ++spin) {
+          if ((int64_t)__hip_atomic_load(S.arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= S.arrive_target)
+            break;
+          if (spin >= kSpinLimit) {
+            tsh.abort = 1;
+            __hip_atomic_store(ba.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+    }
     const int m = S.m, df = S.df, pre = S.precond;
     int64_t *sc = smem;                                 // c_1..c_m
     int64_t *ss = sc + m;                               // s_1..s_m
@@ -550,6 +591,13 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
     }
 #undef IGM_TICK
     if (tsh.abort) status = IGM_ERR_DEVICE;
+    if (SERVED) {  // x back to the requester's pinned buffer
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int64_t row = g0 + k * TB;
+        if (row < n) S.x_out[row] = x[row];
+      }
+    }
     // every member's writes of x are published before the result is
     team_barrier(tm, tsh);
     if (member == 0 && tid == 0) {
@@ -565,7 +613,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
       res.t_end = wall_clock64();
       for (int k = 0; k < 7; ++k) res.phase[k] = ph[k];
       res.phase[7] = res.t_end - t_begin;
-      if (ba.ring) {  // served mode: results and x reach memory, then the host is told
+      if (SERVED) {  // results and x reach memory, then the host is told
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
         __hip_atomic_store(ba.host_done + sid, S.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       }
@@ -574,9 +622,9 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
   }
 }
 
-template <int BLOCK, int R>
+template <int BLOCK, int R, bool SERVED>
 static const void *batch_kernel_ptr() {
-  return (const void *)&k_batch<BLOCK, R>;
+  return (const void *)&k_batch<BLOCK, R, SERVED>;
 }
 
 const int kBatchShapes[][2] = {{1024, 8}, {1024, 4}, {512, 8}, {256, 8}, {256, 16}};
@@ -584,13 +632,19 @@ const int kNumBatchShapes = 5;
 
 const void *batch_kernel(int block, int R) {
 #define IGM_K(BB, RR) \
-  if (block == BB && R == RR) return batch_kernel_ptr<BB, RR>();
+  if (block == BB && R == RR) return batch_kernel_ptr<BB, RR, false>();
   IGM_K(1024, 8)
   IGM_K(1024, 4)
   IGM_K(512, 8)
   IGM_K(256, 8)
   IGM_K(256, 16)
 #undef IGM_K
+  return nullptr;
+}
+
+const void *serve_kernel(int block, int R) {
+  if (block == 1024 && R == 4) return batch_kernel_ptr<1024, 4, true>();
+  if (block == 512 && R == 8) return batch_kernel_ptr<512, 8, true>();
   return nullptr;
 }
 

@@ -45,6 +45,15 @@ struct BatchSys {
   double *x;                     // solution (in: start, out: result)
   unsigned long long *words;     // team exchange words
   BatchResult *res;              // written by the first member
+  // served mode: the members first copy the staged inputs (pinned host
+  // memory, up_bytes from src) into the region at dst, meet on the arrival
+  // counter, and finally copy x out to x_out (pinned host memory)
+  const char *src;
+  char *dst;
+  int64_t up_bytes;
+  double *x_out;
+  unsigned long long *arrive;
+  int64_t arrive_target;
 };
 
 // Outcome of one system, written by its first member.
@@ -101,12 +110,24 @@ igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col,
 // Device bytes of one system's region (inputs, setup products, basis, work
 // vectors, exchange words; the solution vector only if own_x).
 size_t system_bytes(const HostSystem &hs, bool own_x);
+// Leading part of the region (own_x) that holds data: inputs, setup
+// products, x and the exchange words; the work arrays follow it.
+size_t image_bytes(const HostSystem &hs);
+// Writes that leading part into img (host memory): the arrays, x = x0 (zeros
+// if x0 is null), zero exchange words.
+void build_image(const HostSystem &hs, char *img, const double *x0);
+// The record of a system placed at device address base (own_x), pointers
+// only (team = 1, no result, served fields unset).
+void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S);
 // Queues the uploads of one system into the region at `base` on `st` and
 // fills its record (team = 1, res = nullptr; x = the region's own vector if
 // own_x, else left null). The host vectors must live until `st` has drained.
 hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_t st, BatchSys &S);
 
 const void *batch_kernel(int block, int R);
+// the served variant (jobs from a host ring, records read coherently):
+// shapes (1024, 4) and (512, 8)
+const void *serve_kernel(int block, int R);
 size_t batch_smem_bytes(int m);
 // the (block, rows per thread) shapes instantiated for the batched kernel
 extern const int kBatchShapes[][2];

@@ -16,6 +16,9 @@ not available here; these seeded stencil families stand in for them:
   with positive velocity; b ~ U[-1, 1].
 * ``batch_systems(count, seed)`` many independent 2D/3D convection-diffusion
   systems with log-uniform sizes (batched solver workload).
+* ``served_requests(count, seed)`` / ``arrival_times`` a stream of requests
+  from the three families above with Poisson arrivals (served solver
+  workload).
 * ``random27(nx, ny, nz, seed)`` 27-point pattern, off-diagonals N(0, 1),
   diagonal 1.1 * sum |off-diagonals|; b ~ U[-1, 1].
 * ``random_dd(n, density, seed)`` small unstructured diagonally dominant
@@ -215,6 +218,35 @@ def random_dd(n: int, density: float = 0.1, seed: int = 0, dominance: float = 1.
     r, c = np.nonzero(mask)
     b = rng.uniform(-1.0, 1.0, size=n)
     return System(f"random_dd_{n}_s{seed}", n, row_ptr, c.astype(np.int32), vals[r, c].astype(np.float64), b)
+
+
+def served_requests(count: int = 20000, seed: int = 5, n_lo: int = 4096, n_hi: int = 1 << 20):
+    """Request stream for the served solver, one (system, preset) at a time:
+    sizes log-uniform on [n_lo, n_hi], family uniform over 2D 5-point
+    convection-diffusion (jacobi), 3D 7-point convection-diffusion (jacobi)
+    and the 27-point random family (paper_ilu). Request i draws everything
+    from child i of SeedSequence(seed)."""
+    for i, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
+        rng = np.random.default_rng(child)
+        nt = int(round(float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))))
+        fam = int(rng.integers(3))
+        if fam == 0:
+            nx = max(1, int(round(np.sqrt(nt))))
+            ny = max(1, int(round(nt / nx)))
+            yield _convdiff((nx, ny), rng, f"r{i}_convdiff2d_{nx}x{ny}"), "jacobi"
+        else:
+            nx = max(1, int(round(nt ** (1.0 / 3.0))))
+            nz = max(1, int(round(nt / (nx * nx))))
+            if fam == 1:
+                yield _convdiff((nx, nx, nz), rng, f"r{i}_convdiff3d_{nx}x{nx}x{nz}"), "jacobi"
+            else:
+                yield random27(nx, nx, nz, seed=int(rng.integers(1 << 31))), "paper_ilu"
+
+
+def arrival_times(count: int, rate_per_s: float = 2000.0, seed: int = 5) -> np.ndarray:
+    """Poisson arrivals: cumulative sums of exponential gaps (seconds)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(count + 1)[count])
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))
 
 
 def from_dense(a: np.ndarray, b: np.ndarray, name: str = "dense") -> System:

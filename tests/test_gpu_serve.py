@@ -1,0 +1,135 @@
+"""GPU parity of the served solver (continuous batching on a persistent
+kernel).
+
+Requests are submitted while earlier ones are on the GPU; each must come back
+with the oracle's solution bit for bit (and its status, refinement and
+iteration counts), the same alone as in a mix with other requests, also when
+admission has to wait for device memory or when a request is split over a
+team of workgroups."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2009_07495_amd import binding as B
+from paper_2009_07495_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+
+    assert T.cuda.is_available(), "GPU tests need a HIP device"
+    return T
+
+
+def mix():
+    return [
+        (W.convdiff2d(37, 29, seed=71), "jacobi"),
+        (W.random27(9, 8, 6, seed=72), "paper_ilu"),
+        (W.convdiff3d(12, 11, 9, seed=73), "jacobi"),
+        (W.random_dd(301, 0.03, 74), "paper_ilu"),
+        (W.poisson2d(33, 30), "paper_noprec"),
+        (W.random27(14, 13, 11, seed=75), "paper_ilu"),
+        (W.convdiff2d(91, 77, seed=76), "jacobi"),
+        (W.from_dense(np.array([[2.5]]), np.array([-1.5])), "jacobi"),
+    ]
+
+
+def oracle(orc, s, preset, **kw):
+    return orc.OracleSystem.from_system(s, orc.policy(preset, **kw)).solve()
+
+
+def check(x, st, ref):
+    xo, so = ref
+    assert st["status"] == so["status"]
+    assert st["refinements"] == so["refinements"] and st["iterations"] == so["iterations"]
+    assert st["relres_orig"] == so["relres_orig"]
+    assert np.array_equal(x, xo)
+
+
+def test_served_mix_bit_exact(orc, torch):
+    reqs = mix()
+    refs = [oracle(orc, s, p, m=30) for s, p in reqs]
+    sv = B.Server()
+    tickets = []
+    for k, (s, p) in enumerate(reqs):
+        tickets.append(sv.submit(s, p, m=30))
+        time.sleep(0.002 * (k % 3))  # some arrive while others run
+    for t, ref in zip(tickets, refs):
+        x, st = sv.wait(t, 20000)
+        check(x, st, ref)
+        assert st["time_solve_ms"] >= st["time_kernel_ms"] >= 0
+    stats = sv.stats()
+    assert stats["submitted"] == stats["completed"] == len(reqs)
+    sv.close(30000)
+
+
+def test_same_alone_and_in_mix(orc, torch):
+    """A request's bits do not depend on what else is on the GPU."""
+    target = (W.random27(12, 11, 10, seed=81), "paper_ilu")
+    other = (W.convdiff3d(14, 13, 12, seed=82), "jacobi")
+    sv = B.Server()
+    alone, _ = sv.wait(sv.submit(*target, m=30), 20000)
+    ts = [sv.submit(*other, m=30) for _ in range(6)]
+    t = sv.submit(*target, m=30)
+    ts += [sv.submit(*other, m=30) for _ in range(6)]
+    mixed, st = sv.wait(t, 20000)
+    for u in ts:
+        sv.wait(u, 20000)
+    sv.close(30000)
+    assert np.array_equal(alone, mixed)
+    check(mixed, st, oracle(orc, target[0], target[1], m=30))
+
+
+def test_admission_waits_for_device_memory(orc, torch):
+    """A pool that holds about two requests at a time: the rest wait for
+    memory, pass each other when smaller, and all finish bit-exact."""
+    reqs = [(W.convdiff3d(10 + k, 9 + k, 8, seed=90 + k), "jacobi") for k in range(8)]
+    refs = [oracle(orc, s, p, m=20) for s, p in reqs]
+    sv = B.Server(pool_bytes=24 << 20, max_slots=4)
+    tickets = [sv.submit(s, p, m=20) for s, p in reqs]
+    for t, ref in zip(tickets, refs):
+        x, st = sv.wait(t, 20000)
+        check(x, st, ref)
+    stats = sv.stats()
+    assert 0 < stats["pool_peak"] <= stats["pool_bytes"]
+    sv.close(30000)
+
+
+def test_team_requests(orc, torch):
+    """Requests split over several workgroups (512 threads x 8 rows each)."""
+    reqs = [(W.convdiff2d(160, 130, seed=101), "jacobi"), (W.random27(20, 20, 12, seed=102), "paper_ilu")]
+    refs = [oracle(orc, s, p, m=30) for s, p in reqs]
+    sv = B.Server(block=512, rows_per_thread=8)
+    tickets = [sv.submit(s, p, m=30) for s, p in reqs]
+    for t, ref, (s, _) in zip(tickets, refs, reqs):
+        x, st = sv.wait(t, 20000)
+        assert st["grid_blocks"] == -(-s.n // 4096)
+        check(x, st, ref)
+    sv.close(30000)
+
+
+def test_bad_requests_and_start_iterate(orc, torch):
+    sv = B.Server()
+    good = W.convdiff2d(20, 19, seed=111)
+    bad = W.convdiff2d(8, 8, seed=112)
+    bad.col = bad.col.copy()
+    bad.col[2] = 999
+    t_bad = sv.submit(bad, "jacobi", m=10)
+    t_big_m = sv.submit(good, "jacobi", m=65)
+    x0 = np.random.default_rng(3).uniform(-1, 1, good.n)
+    t_x0 = sv.submit(good, "jacobi", x0=x0, m=10)
+    _, st = sv.wait(t_bad, 20000)
+    assert st["status"] == B.ERR_ARG
+    _, st = sv.wait(t_big_m, 20000)
+    assert st["status"] == B.ERR_UNSUPPORTED
+    x, st = sv.wait(t_x0, 20000)
+    o = orc.OracleSystem.from_system(good, orc.policy("jacobi", m=10))
+    xo, so = o.solve(x0)
+    assert np.array_equal(x, xo) and st["refinements"] == so["refinements"]
+    with pytest.raises(B.IgmError):
+        sv.wait(12345, 10)
+    sv.close(30000)
