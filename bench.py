@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="also time the standalone SpMV and dot kernels")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batched solver section")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served solver section")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests in the served trace")
+    ap.add_argument("--serve-distinct", type=int, default=24, help="distinct systems the trace draws from")
     ap.add_argument("--batch-steps", type=int, default=3, help="timed solves of the whole batch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel for "
@@ -123,6 +126,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     gen, preset, m = W.WORKLOADS[args.workload]
+    progress(f"single-system solver: {args.workload}")
     sysm = gen()
 
     # autotune the workgroup count of the cycle kernel (bits do not depend on it)
@@ -204,7 +208,11 @@ def main():
     if args.kernels:
         out["kernels"] = kernel_rates(torch, B, W)
     if not args.no_batch:
+        progress("batched solver: 512 systems")
         out["batched"] = batched(torch, B, W, args.batch_steps, not args.no_cpu_baseline)
+    if not args.no_serve:
+        progress("served solver: request stream")
+        out["served"] = served(B, W, args.serve_requests, args.serve_distinct)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysm, preset, m, int(round(refs / args.steps)))
     print(json.dumps(out))
@@ -292,6 +300,65 @@ def batched(torch, B, W, steps: int, with_cpu: bool) -> dict:
                                "sample": f"first {len(sample)} of the 512 systems ({dt:.1f} s), scaled by "
                                          f"rows x refinements to the whole batch"}
     return out
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def served(B, W, count: int, distinct: int, rate: float = 2000.0) -> dict:
+    """The served workload: Poisson arrivals (mean 2000 requests/s) of solves
+    with n log-uniform in [4096, 1M] from the three families (2D/3D
+    convection-diffusion with Jacobi, 27-point random with ILU(0)),
+    GMRES(30), through the server; latency = submission to result, host setup
+    included. Beside it the plain per-request loop (create, solve, destroy)
+    over the same trace."""
+    import itertools
+
+    pool = list(itertools.islice(W.served_requests(distinct, seed=5), distinct))
+    reqs = [pool[i % distinct] for i in range(count)]
+    arrivals = W.arrival_times(count, rate, seed=5)
+    sv = B.Server()
+    w = sv.submit(W.convdiff2d(40, 40, seed=1), "jacobi", m=30)  # warm-up
+    sv.wait(w, 120000)
+    t0 = time.perf_counter()
+    subs = []
+    for (s, preset), ta in zip(reqs, arrivals):
+        d = t0 + ta - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        subs.append((sv.submit(s, preset, m=30), time.perf_counter() - t0))
+    lat, setup, dev, ok, relres = [], [], [], 0, 0.0
+    last = 0.0
+    for t, ts in subs:
+        _, st = sv.wait(t, 600000)
+        lat.append(st["time_solve_ms"])
+        setup.append(st["time_setup_ms"])
+        dev.append(st["time_kernel_ms"])
+        ok += st["status"] == B.OK
+        relres = max(relres, st["relres_orig"])
+        last = max(last, ts + st["time_solve_ms"] / 1000.0)
+    sst = sv.stats()
+    sv.close()
+    progress(f"served {count} requests in {last:.2f} s; plain per-request loop next")
+    plain = 0.0
+    for s, preset in reqs:
+        t = time.perf_counter()
+        g = B.System.from_system(s, preset, m=30)
+        _, st = g.solve()
+        g.close()
+        plain += time.perf_counter() - t
+        assert st == B.OK
+    lat = np.array(lat)
+    return {"workload": f"served: {count} requests (drawn from {distinct} distinct systems, n log-uniform "
+                        f"[4096, 1M], 2D/3D convection-diffusion with jacobi and 27-point random with ILU(0), "
+                        f"GMRES(30)+FP64 IR, tol 1e-10), Poisson arrivals at {rate:.0f}/s",
+            "solves_per_s": count / last, "completed_ok": ok, "requests": count, "max_relres": relres,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "setup_ms_p50": float(np.percentile(setup, 50)), "device_ms_p50": float(np.percentile(dev, 50)),
+            "plain_loop_solves_per_s": count / plain, "speedup_vs_plain_loop": plain / last,
+            "sustainable_at_offered_rate": bool(count / last >= 0.95 * rate),
+            "workgroups": sst["workgroups"], "pool_peak_bytes": sst["pool_peak"]}
 
 
 def kernel_rates(torch, B, W) -> dict:

@@ -322,7 +322,7 @@ typedef struct igm_server igm_server;
 
 typedef struct {
   int32_t struct_size;      /* sizeof(igm_server_config) */
-  int32_t block;            /* launch shape: (1024, 4) or (512, 8); 0 = (1024, 4) */
+  int32_t block;            /* launch shape: (1024, 8), (1024, 4) or (512, 8); 0 = (1024, 8) */
   int32_t rows_per_thread;
   int32_t max_slots;        /* requests resident at once; 0 = 256 */
   int32_t setup_threads;    /* host threads preparing requests; 0 = 8 */

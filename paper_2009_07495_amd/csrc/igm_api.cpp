@@ -83,6 +83,7 @@ CycleArgs make_args(igm_system *s) {
   a.blev_ptr = s->d_blev_ptr; a.blev_rows = s->d_blev_rows;
   a.nflev = s->hs.flev_ptr.empty() ? 0 : (int32_t)s->hs.flev_ptr.size() - 1;
   a.nblev = s->hs.blev_ptr.empty() ? 0 : (int32_t)s->hs.blev_ptr.size() - 1;
+  a.max_level = max_level_rows(s->hs);
   a.flev_host = s->hs.flev_ptr.data();
   a.blev_host = s->hs.blev_ptr.data();
   a.V = s->d_V;

@@ -161,6 +161,7 @@ void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
   if (p.precond == IGM_PRE_ILU0) {
     S.nflev = h.flev_ptr.empty() ? 0 : (int32_t)h.flev_ptr.size() - 1;
     S.nblev = h.blev_ptr.empty() ? 0 : (int32_t)h.blev_ptr.size() - 1;
+    S.max_level = max_level_rows(h);
   }
   size_t off = 0;
   int term = 0;

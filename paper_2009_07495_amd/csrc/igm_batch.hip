@@ -25,6 +25,9 @@ namespace igm {
 namespace {
 
 constexpr int kGivensThread = 64;  // runs the scalar work of lines 12-19 (wavefront 1, lane 0)
+// ILU sweeps run in one workgroup when every level has at most this many
+// rows per thread
+constexpr int kSweepRows = 8;
 constexpr double kDblMax = 1.7976931348623157e308;
 
 __device__ __forceinline__ double relres_of(double rn, double bn) {
@@ -253,16 +256,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
         const int64_t row = g0 + k * TB;
         r[k] = 0.0;
         rh[k] = 0.0;
-        if (row < n) {
-          double acc = 0.0, acch = 0.0;
-          for (int64_t e = S.row_ptr[row]; e < S.row_ptr[row + 1]; ++e) {
-            const double xv = x[S.col[e]];
-            acc = acc + S.a[e] * xv;
-            acch = acch + S.ahat[e] * xv;
-          }
-          r[k] = S.b[row] - acc;
-          rh[k] = S.bhat[row] - acch;
-        }
+        if (row < n)
+          residual_row(S.row_ptr[row], S.row_ptr[row + 1], S.col, S.a, S.ahat, x, S.b[row], S.bhat[row], r[k], rh[k]);
       }
       double nr, nrh, gamma, mu_rh;
       team_norm2<BLOCK, R>(tm, tsh, r, rh, nr, nrh, gamma, mu_rh);
@@ -289,34 +284,64 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
         // FP64 forward and backward substitution with the integer factors
         // (converted exactly), level by level, in place in fbuf; each row
         // sums in CSR order and then divides by its diagonal
+        // fbuf passes between members through device-coherent stores and
+        // loads: the level barriers need no cache write-back or invalidation
 #pragma unroll
         for (int k = 0; k < R; ++k) {
           const int64_t row = g0 + k * TB;
-          if (row < n) S.fbuf[row] = r[k];
+          if (row < n) st_coh(S.fbuf + row, r[k]);
         }
-        team_barrier(tm, tsh);
+        team_barrier_coh(tm, tsh);
+        if (S.max_level <= kSweepRows * BLOCK) {
+          // every level fits in one workgroup: member 0 runs both sweeps
+          // alone (levels separated by workgroup barriers) while the others
+          // wait at the barrier that publishes the result
+          if (member == 0) {
+            for (int L = 0; L < S.nflev; ++L) {
+              for (int64_t q = S.flev_ptr[L] + tid; q < S.flev_ptr[L + 1]; q += BLOCK) {
+                const int64_t i = S.flev_rows[q];
+                S.fbuf[i] = fp_sub_row(S.lptr[i], S.lptr[i + 1], S.lcol, S.lvalf, S.fbuf, ld_coh(S.fbuf + i),
+                                       (double)S.ldiag[i]);
+              }
+              __syncthreads();
+            }
+            for (int L = 0; L < S.nblev; ++L) {
+              for (int64_t q = S.blev_ptr[L] + tid; q < S.blev_ptr[L + 1]; q += BLOCK) {
+                const int64_t i = S.blev_rows[q];
+                S.fbuf[i] = fp_sub_row(S.uptr[i], S.uptr[i + 1], S.ucol, S.uvalf, S.fbuf, S.fbuf[i],
+                                       (double)S.udiag[i]);
+              }
+              __syncthreads();
+            }
+          }
+          team_barrier(tm, tsh);
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const int64_t row = g0 + k * TB;
+            r[k] = row < n ? S.fbuf[row] : 0.0;
+          }
+        } else {
         for (int L = 0; L < S.nflev; ++L) {
           for (int64_t q = S.flev_ptr[L] + g0; q < S.flev_ptr[L + 1]; q += TB) {
             const int64_t i = S.flev_rows[q];
-            double acc = 0.0;
-            for (int64_t e = S.lptr[i]; e < S.lptr[i + 1]; ++e) acc = acc + S.lvalf[e] * S.fbuf[S.lcol[e]];
-            S.fbuf[i] = (S.fbuf[i] - acc) / (double)S.ldiag[i];
+            st_coh(S.fbuf + i, fp_sub_row<true>(S.lptr[i], S.lptr[i + 1], S.lcol, S.lvalf, S.fbuf, ld_coh(S.fbuf + i),
+                                                (double)S.ldiag[i]));
           }
-          team_barrier(tm, tsh);
+          team_barrier_coh(tm, tsh);
         }
         for (int L = 0; L < S.nblev; ++L) {
           for (int64_t q = S.blev_ptr[L] + g0; q < S.blev_ptr[L + 1]; q += TB) {
             const int64_t i = S.blev_rows[q];
-            double acc = 0.0;
-            for (int64_t e = S.uptr[i]; e < S.uptr[i + 1]; ++e) acc = acc + S.uvalf[e] * S.fbuf[S.ucol[e]];
-            S.fbuf[i] = (S.fbuf[i] - acc) / (double)S.udiag[i];
+            st_coh(S.fbuf + i, fp_sub_row<true>(S.uptr[i], S.uptr[i + 1], S.ucol, S.uvalf, S.fbuf, ld_coh(S.fbuf + i),
+                                                (double)S.udiag[i]));
           }
-          team_barrier(tm, tsh);
+          team_barrier_coh(tm, tsh);
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) {
           const int64_t row = g0 + k * TB;
-          r[k] = row < n ? S.fbuf[row] : 0.0;
+          r[k] = row < n ? ld_coh(S.fbuf + row) : 0.0;
+        }
         }
       }
       const double rho = team_norm1<BLOCK, R>(tm, tsh, r);
@@ -432,30 +457,57 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
           if (o1) record(ev_code(j, 1, 0));
           if (pre == IGM_PRE_ILU0) {
             // line 5': integer forward and backward substitution, level by level
+            // z, y and u pass between members through device-coherent
+            // stores and loads: no cache write-back or invalidation per level
 #pragma unroll
             for (int k = 0; k < R; ++k) {
               const int64_t row = g0 + k * TB;
-              if (row < n) S.zbuf[row] = w[k];
+              if (row < n) st_coh(S.zbuf + row, w[k]);
             }
-            team_barrier(tm, tsh);
+            team_barrier_coh(tm, tsh);
+            if (S.max_level <= kSweepRows * BLOCK) {  // member 0 alone, as for line 1'
+              if (member == 0) {
+                for (int L = 0; L < S.nflev; ++L) {
+                  for (int64_t q = S.flev_ptr[L] + tid; q < S.flev_ptr[L + 1]; q += BLOCK) {
+                    const int64_t row = S.flev_rows[q];
+                    S.wbuf[row] = lower_row(S, row, ld_coh(S.zbuf + row), S.wbuf, o2);
+                  }
+                  __syncthreads();
+                }
+                for (int L = 0; L < S.nblev; ++L) {
+                  for (int64_t q = S.blev_ptr[L] + tid; q < S.blev_ptr[L + 1]; q += BLOCK) {
+                    const int64_t row = S.blev_rows[q];
+                    S.wbuf[row] = upper_row(S, row, S.wbuf[row], S.wbuf, o2);
+                  }
+                  __syncthreads();
+                }
+              }
+              team_barrier(tm, tsh);
+#pragma unroll
+              for (int k = 0; k < R; ++k) {
+                const int64_t row = g0 + k * TB;
+                w[k] = row < n ? S.wbuf[row] : 0;
+              }
+            } else {
             for (int L = 0; L < S.nflev; ++L) {
               for (int64_t q = S.flev_ptr[L] + g0; q < S.flev_ptr[L + 1]; q += TB) {
                 const int64_t row = S.flev_rows[q];
-                S.wbuf[row] = lower_row(S, row, S.zbuf[row], S.wbuf, o2);
+                st_coh(S.wbuf + row, lower_row<true>(S, row, ld_coh(S.zbuf + row), S.wbuf, o2));
               }
-              team_barrier(tm, tsh);
+              team_barrier_coh(tm, tsh);
             }
             for (int L = 0; L < S.nblev; ++L) {
               for (int64_t q = S.blev_ptr[L] + g0; q < S.blev_ptr[L + 1]; q += TB) {
                 const int64_t row = S.blev_rows[q];
-                S.wbuf[row] = upper_row(S, row, S.wbuf[row], S.wbuf, o2);
+                st_coh(S.wbuf + row, upper_row<true>(S, row, ld_coh(S.wbuf + row), S.wbuf, o2));
               }
-              team_barrier(tm, tsh);
+              team_barrier_coh(tm, tsh);
             }
 #pragma unroll
             for (int k = 0; k < R; ++k) {
               const int64_t row = g0 + k * TB;
-              w[k] = row < n ? S.wbuf[row] : 0;
+              w[k] = row < n ? ld_coh(S.wbuf + row) : 0;
+            }
             }
           }
           if (o2) record(ev_code(j, 2, 0));
@@ -643,6 +695,7 @@ const void *batch_kernel(int block, int R) {
 }
 
 const void *serve_kernel(int block, int R) {
+  if (block == 1024 && R == 8) return batch_kernel_ptr<1024, 8, true>();
   if (block == 1024 && R == 4) return batch_kernel_ptr<1024, 4, true>();
   if (block == 512 && R == 8) return batch_kernel_ptr<512, 8, true>();
   return nullptr;

@@ -22,7 +22,7 @@ struct BatchSys {
   int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
   int32_t nflev, nblev;  // ILU level sets
   int32_t seq;           // served mode: request number reported on completion
-  int32_t pad_;
+  int32_t max_level;     // rows of the largest ILU level set
   int64_t gtol;
   double tol;
   int32_t alpha[kMaxTerms];
@@ -126,7 +126,7 @@ hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_
 
 const void *batch_kernel(int block, int R);
 // the served variant (jobs from a host ring, records read coherently):
-// shapes (1024, 4) and (512, 8)
+// shapes (1024, 8), (1024, 4) and (512, 8)
 const void *serve_kernel(int block, int R);
 size_t batch_smem_bytes(int m);
 // the (block, rows per thread) shapes instantiated for the batched kernel

@@ -18,6 +18,9 @@ namespace igm {
 
 // thread that runs the scalar Givens work (wavefront 1, lane 0)
 constexpr int kGivens = 64;
+// ILU sweeps run in one workgroup when every level has at most this many
+// rows per thread
+constexpr int kSweepRows = 8;
 
 template <int BLOCK, int R, int PRE>
 __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
@@ -146,33 +149,62 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
       if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
     } else {
+      // z, y and u pass between workgroups through device-coherent stores
+      // and loads, so the level barriers need no cache write-back or
+      // invalidation and the factors stay cached across levels
       bool o1 = false, o2 = false;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const int64_t row = gt + k * T;
-        a.zbuf[row] = spmv_row(a, row, vj, a.nterms, o1);
+        st_coh(a.zbuf + row, spmv_row(a, row, vj, a.nterms, o1));
       }
       if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
-      grid_barrier(gs, ssh);
+      grid_barrier_coh(gs, ssh);
+      if (a.max_level <= kSweepRows * BLOCK) {
+        // every level fits in one workgroup: workgroup 0 runs both sweeps
+        // alone (levels separated by workgroup barriers, y and u in its own
+        // caches) while the others wait at the barrier that publishes u
+        if (blockIdx.x == 0) {
+          for (int L = 0; L < a.nflev; ++L) {
+            for (int64_t q = a.flev_ptr[L] + tid; q < a.flev_ptr[L + 1]; q += BLOCK) {
+              const int64_t row = a.flev_rows[q];
+              a.wbuf[row] = lower_row(a, row, ld_coh(a.zbuf + row), a.wbuf, o2);
+            }
+            __syncthreads();
+          }
+          for (int L = 0; L < a.nblev; ++L) {
+            for (int64_t q = a.blev_ptr[L] + tid; q < a.blev_ptr[L + 1]; q += BLOCK) {
+              const int64_t row = a.blev_rows[q];
+              a.wbuf[row] = upper_row(a, row, a.wbuf[row], a.wbuf, o2);
+            }
+            __syncthreads();
+          }
+        }
+        grid_barrier(gs, ssh);
+        if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
+#pragma unroll
+        for (int k = 0; k < R; ++k) w[k] = a.wbuf[gt + k * T];  // padded rows hold 0
+      } else {
       for (int L = 0; L < a.nflev; ++L) {
         const int32_t lo = a.flev_ptr[L], hi = a.flev_ptr[L + 1];
         for (int64_t q = lo + gt; q < hi; q += T) {
           const int64_t row = a.flev_rows[q];
-          a.wbuf[row] = lower_row(a, row, a.zbuf[row], a.wbuf, o2);
+          st_coh(a.wbuf + row, lower_row<true>(a, row, ld_coh(a.zbuf + row), a.wbuf, o2));
         }
-        grid_barrier(gs, ssh);
+        grid_barrier_coh(gs, ssh);
       }
       for (int L = 0; L < a.nblev; ++L) {
         const int32_t lo = a.blev_ptr[L], hi = a.blev_ptr[L + 1];
         for (int64_t q = lo + gt; q < hi; q += T) {
           const int64_t row = a.blev_rows[q];
-          a.wbuf[row] = upper_row(a, row, a.wbuf[row], a.wbuf, o2);
+          st_coh(a.wbuf + row, upper_row<true>(a, row, ld_coh(a.wbuf + row), a.wbuf, o2));
         }
-        grid_barrier(gs, ssh);
+        grid_barrier_coh(gs, ssh);
       }
       if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
 #pragma unroll
-      for (int k = 0; k < R; ++k) w[k] = a.wbuf[gt + k * T];  // padded rows hold 0
+      for (int k = 0; k < R; ++k) w[k] = ld_coh(a.wbuf + gt + k * T);  // padded rows hold 0
+      }
     }
     IGM_TICK(0)
     // ---- lines 6-9: modified Gram-Schmidt, i increasing. v_{i+1} is loaded

@@ -168,6 +168,27 @@ __device__ __forceinline__ Acc wave_sum(Acc a) {
 
 __device__ __forceinline__ unsigned long long dbits(double d) { return (unsigned long long)__double_as_longlong(d); }
 
+// Device-coherent accesses (agent scope): they bypass the caches that are
+// private to one chiplet, so values written by one workgroup are seen by all
+// others once the writer's stores have completed, without cache write-back
+// or invalidation. Used for the vectors the level-scheduled triangular
+// sweeps exchange between workgroups.
+__device__ __forceinline__ int64_t ld_coh(const int64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(int64_t *p, int64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double *p) {
+  return __longlong_as_double(__hip_atomic_load((const long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_coh(double *p, double v) {
+  __hip_atomic_store((long long *)p, __double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until this wavefront's outstanding memory operations have completed
+// (s_waitcnt vmcnt(0); the other counters are left at their maxima).
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // floor(q * 2^96) for 0 <= q <= 1 as a 128-bit integer (q a double).
 __device__ __forceinline__ unsigned __int128 fix96(double q) {
   uint64_t b = dbits(q);

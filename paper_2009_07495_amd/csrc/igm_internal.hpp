@@ -55,6 +55,8 @@ igm_status host_setup(int64_t n, const std::vector<int64_t> &row_ptr, const std:
                       const std::vector<double> &ahat, const std::vector<double> &bhat, const igm_policy &pol,
                       HostSetup &out);
 igm_status check_policy(const igm_policy &p);
+// Rows of the largest level set of the ILU sweeps (0 without ILU).
+int32_t max_level_rows(const HostSetup &h);
 igm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b);
 
 // Host-visible layout of an exact device partial sum (value = hi * 2^40 + lo).
@@ -73,6 +75,7 @@ struct CycleArgs {
   int32_t m, df, nterms, precond;
   int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
   int32_t nflev, nblev;
+  int32_t max_level;  // rows of the largest ILU level set
   int64_t gtol;
   const int64_t *sell_off;
   const int32_t *sell_w;

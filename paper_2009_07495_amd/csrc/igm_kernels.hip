@@ -45,13 +45,8 @@ __global__ __launch_bounds__(kB) void k_residual(int64_t n, const int64_t *__res
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   unsigned long long m0 = 0, m1 = 0;
   if (i < n) {
-    double acc = 0.0, acch = 0.0;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      const double xv = x[col[e]];
-      acc = acc + a[e] * xv;
-      acch = acch + ahat[e] * xv;
-    }
-    const double ri = b[i] - acc, rhi = bhat[i] - acch;
+    double ri, rhi;
+    residual_row(rp[i], rp[i + 1], col, a, ahat, x, b[i], bhat[i], ri, rhi);
     r[i] = ri;
     rhat[i] = rhi;
     m0 = dbits(fabs(ri));
@@ -171,9 +166,7 @@ __global__ __launch_bounds__(kB) void k_fp_lower(int32_t lo, int32_t hi, const i
   const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
   if (q >= hi) return;
   const int64_t i = rows[q];
-  double acc = 0.0;
-  for (int64_t e = lptr[i]; e < lptr[i + 1]; ++e) acc = acc + lvalf[e] * y[lcol[e]];
-  y[i] = (bk[i] - acc) / (double)ld[i];
+  y[i] = fp_sub_row(lptr[i], lptr[i + 1], lcol, lvalf, y, bk[i], (double)ld[i]);
 }
 
 // backward u_i = (y_i - sum U_ij u_j) / Ubar_ii, in place.
@@ -184,9 +177,7 @@ __global__ __launch_bounds__(kB) void k_fp_upper(int32_t lo, int32_t hi, const i
   const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
   if (q >= hi) return;
   const int64_t i = rows[q];
-  double acc = 0.0;
-  for (int64_t e = uptr[i]; e < uptr[i + 1]; ++e) acc = acc + uvalf[e] * u[ucol[e]];
-  u[i] = (u[i] - acc) / (double)ud[i];
+  u[i] = fp_sub_row(uptr[i], uptr[i + 1], ucol, uvalf, u, u[i], (double)ud[i]);
 }
 
 __global__ void k_fin_rho(const unsigned long long *red, double *scal, CycleState *st) {

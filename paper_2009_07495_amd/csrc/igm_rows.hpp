@@ -7,6 +7,37 @@
 
 namespace igm {
 
+// Entries of one sparse row are visited in chunks: the column indices and
+// values of a chunk are loaded together, then its gathered operands, then
+// the chunk is consumed in ascending entry order. One row thus waits for two
+// memory round trips per chunk instead of one per entry, and every sum keeps
+// the order of the row (FP64 sums round exactly as the plain loop).
+constexpr int kRowChunk = 8;
+
+// op(val[e], x[col[e]]) for e = lo .. hi-1 in increasing order; COH: the
+// gathered x are read with device-coherent loads.
+template <bool COH = false, class TV, class TX, class Op>
+__device__ __forceinline__ void row_visit(int64_t lo, int64_t hi, const int32_t *__restrict__ col,
+                                          const TV *__restrict__ val, const TX *x, Op op) {
+  for (int64_t e0 = lo; e0 < hi; e0 += kRowChunk) {
+    int32_t c[kRowChunk];
+    TV v[kRowChunk];
+    TX xv[kRowChunk];
+#pragma unroll
+    for (int k = 0; k < kRowChunk; ++k)
+      if (e0 + k < hi) {
+        c[k] = col[e0 + k];
+        v[k] = val[e0 + k];
+      }
+#pragma unroll
+    for (int k = 0; k < kRowChunk; ++k)
+      if (e0 + k < hi) xv[k] = COH ? ld_coh(x + c[k]) : x[c[k]];
+#pragma unroll
+    for (int k = 0; k < kRowChunk; ++k)
+      if (e0 + k < hi) op(v[k], xv[k]);
+  }
+}
+
 // Line 5 for one row (Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_l
 // asr(A_l v, alpha_l), the matrices in SELL-64 layout (slice = 64 rows stored
 // column-major, so the 64 lanes of a wavefront read consecutive words). Every
@@ -24,9 +55,22 @@ __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64
     const int64_t *__restrict__ val = a.sell_val[l];
     Acc acc;
     acc.zero();
-    for (int e = 0; e < wdt; ++e) {
-      const int64_t pos = base + (int64_t)e * 64;
-      acc.add(mulw(val[pos], v[a.sell_col[pos]], ovf));
+    for (int e0 = 0; e0 < wdt; e0 += kRowChunk) {
+      int64_t vv[kRowChunk], xv[kRowChunk];
+      int32_t c[kRowChunk];
+#pragma unroll
+      for (int k = 0; k < kRowChunk; ++k)
+        if (e0 + k < wdt) {
+          const int64_t pos = base + (int64_t)(e0 + k) * 64;
+          vv[k] = val[pos];
+          c[k] = a.sell_col[pos];
+        }
+#pragma unroll
+      for (int k = 0; k < kRowChunk; ++k)
+        if (e0 + k < wdt) xv[k] = v[c[k]];
+#pragma unroll
+      for (int k = 0; k < kRowChunk; ++k)
+        if (e0 + k < wdt) acc.add(mulw(vv[k], xv[k], ovf));
     }
     int64_t t = acc.value(ovf);
     if (l > 0) t = asr(t, a.alpha[l]);
@@ -36,27 +80,68 @@ __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64
 }
 
 // Line 5' forward substitution for one row: y_i = tdiv(z_i - sum_{j<i}
-// Lbar_ij y_j, Lbar_ii).
-template <class A>
-__device__ __forceinline__ int64_t lower_row(const A &a, int64_t row, int64_t zi,
-                                             const int64_t *__restrict__ y, bool &ovf) {
+// Lbar_ij y_j, Lbar_ii) (COH: y read with device-coherent loads).
+template <bool COH = false, class A>
+__device__ __forceinline__ int64_t lower_row(const A &a, int64_t row, int64_t zi, const int64_t *y, bool &ovf) {
   Acc acc;
   acc.zero();
   acc.add(zi);
-  for (int64_t e = a.lptr[row]; e < a.lptr[row + 1]; ++e) acc.sub(mulw(y[a.lcol[e]], a.lval[e], ovf));
+  row_visit<COH>(a.lptr[row], a.lptr[row + 1], a.lcol, a.lval, y,
+                 [&](int64_t l, int64_t yj) { acc.sub(mulw(yj, l, ovf)); });
   return tdiv(acc.value(ovf), a.ldiag[row], ovf);
 }
 
 // Line 5' backward substitution for one row: u_i = tdiv(y_i - sum_{j>i}
 // Ubar_ij u_j, Ubar_ii).
-template <class A>
-__device__ __forceinline__ int64_t upper_row(const A &a, int64_t row, int64_t yi,
-                                             const int64_t *__restrict__ u, bool &ovf) {
+template <bool COH = false, class A>
+__device__ __forceinline__ int64_t upper_row(const A &a, int64_t row, int64_t yi, const int64_t *u, bool &ovf) {
   Acc acc;
   acc.zero();
   acc.add(yi);
-  for (int64_t e = a.uptr[row]; e < a.uptr[row + 1]; ++e) acc.sub(mulw(u[a.ucol[e]], a.uval[e], ovf));
+  row_visit<COH>(a.uptr[row], a.uptr[row + 1], a.ucol, a.uval, u,
+                 [&](int64_t uv, int64_t uj) { acc.sub(mulw(uj, uv, ovf)); });
   return tdiv(acc.value(ovf), a.udiag[row], ovf);
+}
+
+// FP64 row of the triangular substitution of line 1': (b - sum_e f_e x_col) /
+// d, the sum in CSR order.
+template <bool COH = false>
+__device__ __forceinline__ double fp_sub_row(int64_t lo, int64_t hi, const int32_t *__restrict__ col,
+                                             const double *__restrict__ f, const double *x, double b, double d) {
+  double acc = 0.0;
+  row_visit<COH>(lo, hi, col, f, x, [&](double fv, double xv) { acc = acc + fv * xv; });
+  return (b - acc) / d;
+}
+
+// FP64 residual row of eq. (b): r = b - A x and rhat = bhat - Ahat x with the
+// same gathered x, each sum in CSR order.
+__device__ __forceinline__ void residual_row(int64_t lo, int64_t hi, const int32_t *__restrict__ col,
+                                             const double *__restrict__ a, const double *__restrict__ ahat,
+                                             const double *__restrict__ x, double b, double bhat, double &r,
+                                             double &rhat) {
+  double acc = 0.0, acch = 0.0;
+  for (int64_t e0 = lo; e0 < hi; e0 += kRowChunk) {
+    int32_t c[kRowChunk];
+    double av[kRowChunk], hv[kRowChunk], xv[kRowChunk];
+#pragma unroll
+    for (int k = 0; k < kRowChunk; ++k)
+      if (e0 + k < hi) {
+        c[k] = col[e0 + k];
+        av[k] = a[e0 + k];
+        hv[k] = ahat[e0 + k];
+      }
+#pragma unroll
+    for (int k = 0; k < kRowChunk; ++k)
+      if (e0 + k < hi) xv[k] = x[c[k]];
+#pragma unroll
+    for (int k = 0; k < kRowChunk; ++k)
+      if (e0 + k < hi) {
+        acc = acc + av[k] * xv[k];
+        acch = acch + hv[k] * xv[k];
+      }
+  }
+  r = b - acc;
+  rhat = bhat - acch;
 }
 
 // Line 11 for one element: sc(tdiv(shl(w, b1), den), df - b1 - b2).

@@ -434,9 +434,9 @@ igm_status igm_server_create(const igm_server_config *cfg, igm_server **out) {
     if (cfg->struct_size != (int32_t)sizeof(igm_server_config)) return IGM_ERR_ARG;
     c = *cfg;
   }
-  if (c.block == 0 && c.rows_per_thread == 0) {
+  if (c.block == 0 && c.rows_per_thread == 0) {  // 8192 rows per workgroup: 1M rows fit in 128
     c.block = 1024;
-    c.rows_per_thread = 4;
+    c.rows_per_thread = 8;
   }
   if (!serve_kernel(c.block, c.rows_per_thread)) return IGM_ERR_UNSUPPORTED;
   if (c.max_slots == 0) c.max_slots = 256;

@@ -253,6 +253,13 @@ igm_status host_setup(int64_t n, const std::vector<int64_t> &rp, const std::vect
   return IGM_OK;
 }
 
+int32_t max_level_rows(const HostSetup &h) {
+  int32_t mx = 0;
+  for (size_t L = 0; L + 1 < h.flev_ptr.size(); ++L) mx = std::max(mx, h.flev_ptr[L + 1] - h.flev_ptr[L]);
+  for (size_t L = 0; L + 1 < h.blev_ptr.size(); ++L) mx = std::max(mx, h.blev_ptr[L + 1] - h.blev_ptr[L]);
+  return mx;
+}
+
 // CSR and right-hand side checks shared by every entry point that takes a
 // host system: rows and columns in range, columns strictly increasing within a
 // row, finite values.

@@ -167,6 +167,25 @@ __device__ __forceinline__ void grid_barrier(GridSync &gs, SyncShared &sh) {
   grid_barrier(gs, sh, [] {});
 }
 
+// Barrier for data exchanged only through device-coherent stores and loads
+// (ld_coh / st_coh): each wavefront waits for its own stores to complete,
+// then the workgroups meet; no cache write-back or invalidation, so cached
+// read-only data stays cached.
+__device__ __forceinline__ void grid_barrier_coh(GridSync &gs, SyncShared &sh) {
+  const int s = gs.next++;
+  wait_vm();
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0 && !sh.abort)
+      __hip_atomic_fetch_add(gs.words + (size_t)(blockIdx.x % kSyncGroups) * gs.cap + s, 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    bool to = false;
+    if (!sh.abort) poll_words(gs, s, kSyncGroups, to);
+    if (threadIdx.x == 0 && to) record_timeout(gs, sh);
+  }
+  __syncthreads();
+}
+
 // Workgroup sum of one Acc per thread; result valid in thread 0 only.
 template <int BLOCK>
 __device__ __forceinline__ Acc block_sum(Acc a, Acc *sh_wave) {

@@ -207,6 +207,21 @@ __device__ __forceinline__ void team_barrier(Team &tm, TeamShared &sh) {
   team_barrier(tm, sh, [] {});
 }
 
+// Team barrier for data exchanged only through device-coherent stores and
+// loads (ld_coh / st_coh): each wavefront waits for its own stores to
+// complete, then the members meet; no cache write-back or invalidation.
+__device__ __forceinline__ void team_barrier_coh(Team &tm, TeamShared &sh) {
+  wait_vm();
+  __syncthreads();
+  if (threadIdx.x < 64 && tm.T > 1 && !sh.abort) {
+    bool to = false;
+    unsigned long long u[1] = {0};
+    team_exchange<1, false>(tm, sh, u, to);
+    if (threadIdx.x == 0 && to) team_abort(tm, sh);
+  }
+  __syncthreads();
+}
+
 template <bool MAX>
 __device__ __forceinline__ unsigned long long op_u64(unsigned long long a, unsigned long long b) {
   return MAX ? (a > b ? a : b) : a + b;
