@@ -89,6 +89,8 @@ CycleArgs make_args(igm_system *s) {
   a.V = s->d_V;
   a.zbuf = s->d_z;
   a.wbuf = s->d_w;
+  a.lev_cnt = s->d_levcnt;
+  a.sweep_threads = sweep_threads(s->block, s->grid, a.max_level);
   a.H = s->d_H; a.c = s->d_c; a.s = s->d_s; a.g = s->d_g;
   a.state = s->d_state;
   a.sync = s->d_sync;
@@ -114,8 +116,11 @@ igm_status choose_launch(igm_system *s) {
   int target = s->pol.grid_blocks > 0 ? s->pol.grid_blocks : 256;
   target = std::min(target, 1023);
   const size_t smem = cycle_smem_bytes(s->pol.m);
+  // ILU(0): the sweeps hold a row's structure in registers while they wait,
+  // which the 512-thread shapes (256 registers per thread) keep without spills
   static const int kShapes[][2] = {{1024, 1}, {1024, 2}, {1024, 4}, {512, 8}, {512, 16}};
-  for (const auto &bs : kShapes) {
+  static const int kShapesIlu[][2] = {{512, 1}, {512, 2}, {512, 4}, {512, 8}, {512, 16}};
+  for (const auto &bs : s->pol.precond == IGM_PRE_ILU0 ? kShapesIlu : kShapes) {
     const int B = bs[0], R = bs[1];
     int nb = 0;
     IGM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cycle_kernel(B, R, s->pol.precond), B, smem));
@@ -137,13 +142,16 @@ igm_status alloc_work(igm_system *s) {
   const int64_t np = s->npad;
   int64_t extra = 2;
   if (s->pol.precond == IGM_PRE_ILU0)
-    extra += 1 + (int64_t)(s->hs.flev_ptr.size() - 1) + (int64_t)(s->hs.blev_ptr.size() - 1);
+    extra += 3;  // barriers around the two sweeps
   const int64_t cap = (int64_t)m * (m + 1) / 2 + (int64_t)m * extra + 16;
   if (cap > (int64_t)1 << 30) return IGM_ERR_UNSUPPORTED;
   s->sync_cap = (int32_t)cap;
   IGM_TRY(dalloc(s, s->d_V, (size_t)(m + 1) * np));
   IGM_TRY(dalloc(s, s->d_z, np));
   IGM_TRY(dalloc(s, s->d_w, np));
+  s->d_levcnt = nullptr;
+  if (s->pol.precond == IGM_PRE_ILU0)
+    IGM_TRY(dalloc(s, s->d_levcnt, ((s->hs.flev_ptr.size() - 1) + (s->hs.blev_ptr.size() - 1)) * kLevStride));
   IGM_TRY(dalloc(s, s->d_r, np));
   IGM_TRY(dalloc(s, s->d_rhat, np));
   IGM_TRY(dalloc(s, s->d_bk, np));

@@ -70,13 +70,14 @@ void walk_region(const HostSystem &hs, bool own_x, F &&f) {
     f("zbuf", sizeof(int64_t) * n);
     f("wbuf", sizeof(int64_t) * n);
     f("fbuf", sizeof(double) * n);
+    f("lev_cnt", sizeof(unsigned) * (h.flev_ptr.size() - 1 + h.blev_ptr.size() - 1) * kLevStride);
   }
   f("V", sizeof(int64_t) * (size_t)(hs.pol.m + 1) * ldv);
 }
 
 bool is_work_array(const char *name) {
   const std::string nm(name);
-  return nm == "zbuf" || nm == "wbuf" || nm == "fbuf" || nm == "V";
+  return nm == "zbuf" || nm == "wbuf" || nm == "fbuf" || nm == "lev_cnt" || nm == "V";
 }
 
 // Host source of a data array of the region (nullptr for x and words).
@@ -196,6 +197,7 @@ void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
     else if (nm == "zbuf") S.zbuf = (int64_t *)d;
     else if (nm == "wbuf") S.wbuf = (int64_t *)d;
     else if (nm == "fbuf") S.fbuf = (double *)d;
+    else if (nm == "lev_cnt") S.lev_cnt = (unsigned *)d;
     else if (nm == "V") S.V = (int64_t *)d;
     else if (nm == "x") S.x = (double *)d;
     else if (nm == "words") S.words = (unsigned long long *)d;
@@ -358,7 +360,10 @@ igm_status apply_shape(igm_batch *bt, int block, int rows) {
       jobs.push_back(s);
       jobs.push_back(q);
     }
-  for (int32_t s = 0; s < bt->nsys; ++s) bt->sys[s].team = team[s];
+  for (int32_t s = 0; s < bt->nsys; ++s) {
+    bt->sys[s].team = team[s];
+    bt->sys[s].sweep_threads = sweep_threads(block, team[s], bt->sys[s].max_level);
+  }
   bt->x_bound = nullptr;  // records are re-uploaded before the next solve
   BT_HIP(hipMemcpy(bt->d_jobs, jobs.data(), sizeof(int32_t) * jobs.size(), hipMemcpyHostToDevice));
   bt->team = team;

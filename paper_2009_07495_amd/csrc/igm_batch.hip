@@ -18,16 +18,18 @@
 // systems of the batch: they equal those of the single-system solver.
 #include "igm_batch.hpp"
 #include "igm_rows.hpp"
+#include "igm_sweep.hpp"
 #include "igm_team.hpp"
 
 namespace igm {
 
+// entries of an ILU row loaded before a sweep waits (the kernel is short of
+// registers; the single-system kernel loads 16)
+constexpr int kBatchSweepPre = 8;
+
 namespace {
 
 constexpr int kGivensThread = 64;  // runs the scalar work of lines 12-19 (wavefront 1, lane 0)
-// ILU sweeps run in one workgroup when every level has at most this many
-// rows per thread
-constexpr int kSweepRows = 8;
 constexpr double kDblMax = 1.7976931348623157e308;
 
 __device__ __forceinline__ double relres_of(double rn, double bn) {
@@ -231,6 +233,17 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
     t_prev = t_;                         \
   }
 
+    // ILU level counters start from zero for every solve; the exchanges of
+    // the norms below order these stores before any member's first sweep
+    if (pre == IGM_PRE_ILU0 && S.team > 1) {
+      for (int64_t i = g0; i < (int64_t)S.nflev + S.nblev; i += TB) st_coh(S.lev_cnt + i * kLevStride, 0u);
+      wait_vm();
+    }
+    unsigned sround = 0;  // sweeps run since the counters were cleared
+    const int64_t spos0 = (int64_t)member * S.sweep_threads + tid;
+    const int64_t sstride = (int64_t)S.team * S.sweep_threads;
+    const bool sweeper = tid < S.sweep_threads;
+
     // denominators of the two relative residuals
     double nb, nbh;
     {
@@ -282,66 +295,55 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
       }
       if (pre == IGM_PRE_ILU0) {
         // FP64 forward and backward substitution with the integer factors
-        // (converted exactly), level by level, in place in fbuf; each row
-        // sums in CSR order and then divides by its diagonal
-        // fbuf passes between members through device-coherent stores and
-        // loads: the level barriers need no cache write-back or invalidation
+        // (converted exactly) in place in fbuf; each row sums in CSR order
+        // and then divides by its diagonal
 #pragma unroll
         for (int k = 0; k < R; ++k) {
           const int64_t row = g0 + k * TB;
           if (row < n) st_coh(S.fbuf + row, r[k]);
         }
         team_barrier_coh(tm, tsh);
-        if (S.max_level <= kSweepRows * BLOCK) {
-          // every level fits in one workgroup: member 0 runs both sweeps
-          // alone (levels separated by workgroup barriers) while the others
-          // wait at the barrier that publishes the result
-          if (member == 0) {
-            for (int L = 0; L < S.nflev; ++L) {
-              for (int64_t q = S.flev_ptr[L] + tid; q < S.flev_ptr[L + 1]; q += BLOCK) {
-                const int64_t i = S.flev_rows[q];
-                S.fbuf[i] = fp_sub_row(S.lptr[i], S.lptr[i + 1], S.lcol, S.lvalf, S.fbuf, ld_coh(S.fbuf + i),
-                                       (double)S.ldiag[i]);
-              }
-              __syncthreads();
+        if (S.team == 1) {
+          // one workgroup: levels separated by workgroup barriers
+          for (int L = 0; L < S.nflev; ++L) {
+            for (int64_t q = S.flev_ptr[L] + tid; q < S.flev_ptr[L + 1]; q += BLOCK) {
+              const int64_t i = S.flev_rows[q];
+              S.fbuf[i] = fp_sub_row(S.lptr[i], S.lptr[i + 1], S.lcol, S.lvalf, S.fbuf, ld_coh(S.fbuf + i),
+                                     (double)S.ldiag[i]);
             }
-            for (int L = 0; L < S.nblev; ++L) {
-              for (int64_t q = S.blev_ptr[L] + tid; q < S.blev_ptr[L + 1]; q += BLOCK) {
-                const int64_t i = S.blev_rows[q];
-                S.fbuf[i] = fp_sub_row(S.uptr[i], S.uptr[i + 1], S.ucol, S.uvalf, S.fbuf, S.fbuf[i],
-                                       (double)S.udiag[i]);
-              }
-              __syncthreads();
-            }
+            __syncthreads();
           }
-          team_barrier(tm, tsh);
+          for (int L = 0; L < S.nblev; ++L) {
+            for (int64_t q = S.blev_ptr[L] + tid; q < S.blev_ptr[L + 1]; q += BLOCK) {
+              const int64_t i = S.blev_rows[q];
+              S.fbuf[i] = fp_sub_row(S.uptr[i], S.uptr[i + 1], S.ucol, S.uvalf, S.fbuf, S.fbuf[i],
+                                     (double)S.udiag[i]);
+            }
+            __syncthreads();
+          }
 #pragma unroll
           for (int k = 0; k < R; ++k) {
             const int64_t row = g0 + k * TB;
             r[k] = row < n ? S.fbuf[row] : 0.0;
           }
         } else {
-        for (int L = 0; L < S.nflev; ++L) {
-          for (int64_t q = S.flev_ptr[L] + g0; q < S.flev_ptr[L + 1]; q += TB) {
-            const int64_t i = S.flev_rows[q];
-            st_coh(S.fbuf + i, fp_sub_row<true>(S.lptr[i], S.lptr[i + 1], S.lcol, S.lvalf, S.fbuf, ld_coh(S.fbuf + i),
-                                                (double)S.ldiag[i]));
-          }
+          // several members: each row waits only for the level below it
+          bool fo = false, to = false;
+          if (sweeper && !tsh.abort)
+            level_sweep<true, true, kBatchSweepPre>(S, S.flev_ptr, S.flev_rows, S.nflev, S.lev_cnt, sround, spos0, sstride, S.fbuf,
+                                    S.fbuf, fo, to);
           team_barrier_coh(tm, tsh);
-        }
-        for (int L = 0; L < S.nblev; ++L) {
-          for (int64_t q = S.blev_ptr[L] + g0; q < S.blev_ptr[L + 1]; q += TB) {
-            const int64_t i = S.blev_rows[q];
-            st_coh(S.fbuf + i, fp_sub_row<true>(S.uptr[i], S.uptr[i + 1], S.ucol, S.uvalf, S.fbuf, ld_coh(S.fbuf + i),
-                                                (double)S.udiag[i]));
-          }
+          if (sweeper && !tsh.abort)
+            level_sweep<false, true, kBatchSweepPre>(S, S.blev_ptr, S.blev_rows, S.nblev, S.lev_cnt + (int64_t)S.nflev * kLevStride,
+                                     sround, spos0, sstride, S.fbuf, S.fbuf, fo, to);
+          ++sround;
+          if (to) team_abort(tm, tsh);
           team_barrier_coh(tm, tsh);
-        }
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          const int64_t row = g0 + k * TB;
-          r[k] = row < n ? ld_coh(S.fbuf + row) : 0.0;
-        }
+          for (int k = 0; k < R; ++k) {
+            const int64_t row = g0 + k * TB;
+            r[k] = row < n ? ld_coh(S.fbuf + row) : 0.0;
+          }
         }
       }
       const double rho = team_norm1<BLOCK, R>(tm, tsh, r);
@@ -456,58 +458,52 @@ __global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
           }
           if (o1) record(ev_code(j, 1, 0));
           if (pre == IGM_PRE_ILU0) {
-            // line 5': integer forward and backward substitution, level by level
-            // z, y and u pass between members through device-coherent
-            // stores and loads: no cache write-back or invalidation per level
+            // line 5': integer forward and backward substitution; z, y and u
+            // pass between members through device-coherent stores and loads
 #pragma unroll
             for (int k = 0; k < R; ++k) {
               const int64_t row = g0 + k * TB;
               if (row < n) st_coh(S.zbuf + row, w[k]);
             }
             team_barrier_coh(tm, tsh);
-            if (S.max_level <= kSweepRows * BLOCK) {  // member 0 alone, as for line 1'
-              if (member == 0) {
-                for (int L = 0; L < S.nflev; ++L) {
-                  for (int64_t q = S.flev_ptr[L] + tid; q < S.flev_ptr[L + 1]; q += BLOCK) {
-                    const int64_t row = S.flev_rows[q];
-                    S.wbuf[row] = lower_row(S, row, ld_coh(S.zbuf + row), S.wbuf, o2);
-                  }
-                  __syncthreads();
+            if (S.team == 1) {  // one workgroup, as for line 1'
+              for (int L = 0; L < S.nflev; ++L) {
+                for (int64_t q = S.flev_ptr[L] + tid; q < S.flev_ptr[L + 1]; q += BLOCK) {
+                  const int64_t row = S.flev_rows[q];
+                  S.wbuf[row] = lower_row(S, row, ld_coh(S.zbuf + row), S.wbuf, o2);
                 }
-                for (int L = 0; L < S.nblev; ++L) {
-                  for (int64_t q = S.blev_ptr[L] + tid; q < S.blev_ptr[L + 1]; q += BLOCK) {
-                    const int64_t row = S.blev_rows[q];
-                    S.wbuf[row] = upper_row(S, row, S.wbuf[row], S.wbuf, o2);
-                  }
-                  __syncthreads();
-                }
+                __syncthreads();
               }
-              team_barrier(tm, tsh);
+              for (int L = 0; L < S.nblev; ++L) {
+                for (int64_t q = S.blev_ptr[L] + tid; q < S.blev_ptr[L + 1]; q += BLOCK) {
+                  const int64_t row = S.blev_rows[q];
+                  S.wbuf[row] = upper_row(S, row, S.wbuf[row], S.wbuf, o2);
+                }
+                __syncthreads();
+              }
 #pragma unroll
               for (int k = 0; k < R; ++k) {
                 const int64_t row = g0 + k * TB;
                 w[k] = row < n ? S.wbuf[row] : 0;
               }
             } else {
-            for (int L = 0; L < S.nflev; ++L) {
-              for (int64_t q = S.flev_ptr[L] + g0; q < S.flev_ptr[L + 1]; q += TB) {
-                const int64_t row = S.flev_rows[q];
-                st_coh(S.wbuf + row, lower_row<true>(S, row, ld_coh(S.zbuf + row), S.wbuf, o2));
-              }
+              bool to = false;
+              if (sweeper && !tsh.abort)
+                level_sweep<true, false, kBatchSweepPre>(S, S.flev_ptr, S.flev_rows, S.nflev, S.lev_cnt, sround, spos0, sstride,
+                                         S.zbuf, S.wbuf, o2, to);
               team_barrier_coh(tm, tsh);
-            }
-            for (int L = 0; L < S.nblev; ++L) {
-              for (int64_t q = S.blev_ptr[L] + g0; q < S.blev_ptr[L + 1]; q += TB) {
-                const int64_t row = S.blev_rows[q];
-                st_coh(S.wbuf + row, upper_row<true>(S, row, ld_coh(S.wbuf + row), S.wbuf, o2));
-              }
+              if (sweeper && !tsh.abort)
+                level_sweep<false, false, kBatchSweepPre>(S, S.blev_ptr, S.blev_rows, S.nblev,
+                                          S.lev_cnt + (int64_t)S.nflev * kLevStride, sround, spos0, sstride, S.wbuf,
+                                          S.wbuf, o2, to);
+              ++sround;
+              if (to) team_abort(tm, tsh);
               team_barrier_coh(tm, tsh);
-            }
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-              const int64_t row = g0 + k * TB;
-              w[k] = row < n ? ld_coh(S.wbuf + row) : 0;
-            }
+              for (int k = 0; k < R; ++k) {
+                const int64_t row = g0 + k * TB;
+                w[k] = row < n ? ld_coh(S.wbuf + row) : 0;
+              }
             }
           }
           if (o2) record(ev_code(j, 2, 0));

@@ -23,6 +23,7 @@ struct BatchSys {
   int32_t nflev, nblev;  // ILU level sets
   int32_t seq;           // served mode: request number reported on completion
   int32_t max_level;     // rows of the largest ILU level set
+  int32_t sweep_threads; // ILU, teams of several workgroups: threads per member in the sweeps
   int64_t gtol;
   double tol;
   int32_t alpha[kMaxTerms];
@@ -42,6 +43,7 @@ struct BatchSys {
   int64_t *V;                    // (m+1) x ldv basis
   int64_t *zbuf, *wbuf;          // ILU: SpMV output and preconditioned vector
   double *fbuf;                  // ILU: FP64 substitution of line 1'
+  unsigned *lev_cnt;             // ILU: level completion counters (cleared by the kernel)
   double *x;                     // solution (in: start, out: result)
   unsigned long long *words;     // team exchange words
   BatchResult *res;              // written by the first member

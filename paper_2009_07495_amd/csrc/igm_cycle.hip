@@ -12,15 +12,13 @@
 // communication; it is scheduled inside the waits of the grid reductions and
 // barriers. Workgroup 0 stores H, c, s, g for the caller.
 #include "igm_rows.hpp"
+#include "igm_sweep.hpp"
 #include "igm_sync.hpp"
 
 namespace igm {
 
 // thread that runs the scalar Givens work (wavefront 1, lane 0)
 constexpr int kGivens = 64;
-// ILU sweeps run in one workgroup when every level has at most this many
-// rows per thread
-constexpr int kSweepRows = 8;
 
 template <int BLOCK, int R, int PRE>
 __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
@@ -59,6 +57,10 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     ssh.abort = 0; ssh.flag = 0;
     sh_stop = 0; sh_jstar = m; sh_breakdown = 0; sh_steps = 0;
   }
+  // level counters of the ILU sweeps start from zero in every launch (the
+  // grid barrier before the first sweep orders these stores)
+  if (PRE == IGM_PRE_ILU0)
+    for (int64_t i = gt; i < (int64_t)a.nflev + a.nblev; i += T) st_coh(a.lev_cnt + i * kLevStride, 0u);
   __syncthreads();
 
   // reduction finishers (run once per workgroup, in wavefront 0)
@@ -150,9 +152,10 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
     } else {
       // z, y and u pass between workgroups through device-coherent stores
-      // and loads, so the level barriers need no cache write-back or
-      // invalidation and the factors stay cached across levels
-      bool o1 = false, o2 = false;
+      // and loads; the rows of each sweep wait only for the level below
+      // them (igm_sweep.hpp), and three grid barriers per step separate the
+      // SpMV, the two sweeps and the read-back of u
+      bool o1 = false, o2 = false, to = false;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const int64_t row = gt + k * T;
@@ -160,51 +163,20 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       }
       if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
       grid_barrier_coh(gs, ssh);
-      if (a.max_level <= kSweepRows * BLOCK) {
-        // every level fits in one workgroup: workgroup 0 runs both sweeps
-        // alone (levels separated by workgroup barriers, y and u in its own
-        // caches) while the others wait at the barrier that publishes u
-        if (blockIdx.x == 0) {
-          for (int L = 0; L < a.nflev; ++L) {
-            for (int64_t q = a.flev_ptr[L] + tid; q < a.flev_ptr[L + 1]; q += BLOCK) {
-              const int64_t row = a.flev_rows[q];
-              a.wbuf[row] = lower_row(a, row, ld_coh(a.zbuf + row), a.wbuf, o2);
-            }
-            __syncthreads();
-          }
-          for (int L = 0; L < a.nblev; ++L) {
-            for (int64_t q = a.blev_ptr[L] + tid; q < a.blev_ptr[L + 1]; q += BLOCK) {
-              const int64_t row = a.blev_rows[q];
-              a.wbuf[row] = upper_row(a, row, a.wbuf[row], a.wbuf, o2);
-            }
-            __syncthreads();
-          }
-        }
-        grid_barrier(gs, ssh);
-        if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
-#pragma unroll
-        for (int k = 0; k < R; ++k) w[k] = a.wbuf[gt + k * T];  // padded rows hold 0
-      } else {
-      for (int L = 0; L < a.nflev; ++L) {
-        const int32_t lo = a.flev_ptr[L], hi = a.flev_ptr[L + 1];
-        for (int64_t q = lo + gt; q < hi; q += T) {
-          const int64_t row = a.flev_rows[q];
-          st_coh(a.wbuf + row, lower_row<true>(a, row, ld_coh(a.zbuf + row), a.wbuf, o2));
-        }
-        grid_barrier_coh(gs, ssh);
-      }
-      for (int L = 0; L < a.nblev; ++L) {
-        const int32_t lo = a.blev_ptr[L], hi = a.blev_ptr[L + 1];
-        for (int64_t q = lo + gt; q < hi; q += T) {
-          const int64_t row = a.blev_rows[q];
-          st_coh(a.wbuf + row, upper_row<true>(a, row, ld_coh(a.wbuf + row), a.wbuf, o2));
-        }
-        grid_barrier_coh(gs, ssh);
-      }
+      const int64_t pos0 = (int64_t)blockIdx.x * a.sweep_threads + tid;
+      const int64_t stride = (int64_t)gridDim.x * a.sweep_threads;
+      if (tid < a.sweep_threads && !ssh.abort)
+        level_sweep<true, false>(a, a.flev_ptr, a.flev_rows, a.nflev, a.lev_cnt, (unsigned)(j - 1), pos0, stride,
+                          a.zbuf, a.wbuf, o2, to);
+      grid_barrier_coh(gs, ssh);
+      if (tid < a.sweep_threads && !ssh.abort)
+        level_sweep<false, false>(a, a.blev_ptr, a.blev_rows, a.nblev, a.lev_cnt + (int64_t)a.nflev * kLevStride,
+                           (unsigned)(j - 1), pos0, stride, a.wbuf, a.wbuf, o2, to);
+      if (to) __hip_atomic_store(&a.state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      grid_barrier_coh(gs, ssh);
       if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
 #pragma unroll
       for (int k = 0; k < R; ++k) w[k] = ld_coh(a.wbuf + gt + k * T);  // padded rows hold 0
-      }
     }
     IGM_TICK(0)
     // ---- lines 6-9: modified Gram-Schmidt, i increasing. v_{i+1} is loaded

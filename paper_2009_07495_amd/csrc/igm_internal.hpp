@@ -57,6 +57,11 @@ igm_status host_setup(int64_t n, const std::vector<int64_t> &row_ptr, const std:
 igm_status check_policy(const igm_policy &p);
 // Rows of the largest level set of the ILU sweeps (0 without ILU).
 int32_t max_level_rows(const HostSetup &h);
+// Threads per workgroup that take part in the counter-driven ILU sweeps of a
+// grid of `grid` workgroups of `block` threads: whole wavefronts, enough that
+// about four times the widest level is in flight, at most the workgroup. The
+// environment variable IGM_SWEEP_THREADS (a multiple of 64) overrides it.
+int32_t sweep_threads(int block, int grid, int32_t max_level);
 igm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b);
 
 // Host-visible layout of an exact device partial sum (value = hi * 2^40 + lo).
@@ -68,6 +73,12 @@ struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
 };
+
+// Spacing (32-bit words) of the completion counters of the ILU sweeps.
+#ifndef IGM_LEV_STRIDE
+#define IGM_LEV_STRIDE 32
+#endif
+constexpr int kLevStride = IGM_LEV_STRIDE;
 
 // Arguments of the persistent cycle kernel.
 struct CycleArgs {
@@ -91,6 +102,8 @@ struct CycleArgs {
   int64_t *V;      // (m+1) x npad
   int64_t *zbuf;   // npad (preconditioner path)
   int64_t *wbuf;   // npad (preconditioner path)
+  unsigned *lev_cnt;      // ILU: completion counters (igm_sweep.hpp), nflev forward then nblev backward
+  int32_t sweep_threads;  // ILU: threads per workgroup taking part in the sweeps (multiple of 64)
   int64_t *H, *c, *s, *g;
   CycleState *state;
   unsigned long long *sync;  // 2 * kSyncGroups * sync_cap words
@@ -132,6 +145,7 @@ struct igm_system {
   int32_t *d_flev_ptr = nullptr, *d_flev_rows = nullptr, *d_blev_ptr = nullptr, *d_blev_rows = nullptr;
   // work vectors
   int64_t *d_V = nullptr, *d_z = nullptr, *d_w = nullptr;
+  unsigned *d_levcnt = nullptr;
   double *d_r = nullptr, *d_rhat = nullptr, *d_bk = nullptr, *d_r0 = nullptr, *d_x = nullptr;
   int64_t *d_H = nullptr, *d_c = nullptr, *d_s = nullptr, *d_g = nullptr;
   igm::CycleState *d_state = nullptr;

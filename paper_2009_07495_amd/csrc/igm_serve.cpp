@@ -262,9 +262,11 @@ void publish(igm_server *sv, Request *r) {
   S.zbuf = rebase(S.zbuf, base);
   S.wbuf = rebase(S.wbuf, base);
   S.fbuf = rebase(S.fbuf, base);
+  S.lev_cnt = rebase(S.lev_cnt, base);
   S.x = rebase(S.x, base);
   S.words = rebase(S.words, base);
   S.team = r->team;
+  S.sweep_threads = sweep_threads(sv->block, r->team, S.max_level);
   S.seq = r->seq;
   S.res = sv->dh_res + r->slot;
   S.src = sv->dh_stage + r->stage_off;

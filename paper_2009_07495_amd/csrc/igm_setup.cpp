@@ -5,6 +5,7 @@
 // Every FP64 step follows a fixed operation order with no contraction, so the
 // products are reproducible bit for bit.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -251,6 +252,16 @@ igm_status host_setup(int64_t n, const std::vector<int64_t> &rp, const std::vect
   }
   build_sell(n, rp, col, h);
   return IGM_OK;
+}
+
+int32_t sweep_threads(int block, int grid, int32_t max_level) {
+  if (const char *e = std::getenv("IGM_SWEEP_THREADS")) {
+    const int v = std::atoi(e);
+    if (v >= 64 && v % 64 == 0) return std::min(v, block);
+  }
+  const int64_t want = (4 * (int64_t)max_level + grid - 1) / std::max(grid, 1);
+  const int64_t t = (want + 63) / 64 * 64;
+  return (int32_t)std::max<int64_t>(64, std::min<int64_t>(t, block));
 }
 
 int32_t max_level_rows(const HostSetup &h) {
