@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 # Sources the persistent cycle kernel is compiled from: a traffic figure
 # measured with hardware counters is reported only while they are unchanged.
-CYCLE_SOURCES = ("igm_cycle.hip", "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp")
+CYCLE_SOURCES = ("igm_cycle.hip", "igm_sweep.hpp", "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp")
 
 
 def cycle_sources_digest() -> str:
