@@ -355,7 +355,8 @@ def served(B, W, count: int, distinct: int, rate: float = 2000.0) -> dict:
                         f"GMRES(30)+FP64 IR, tol 1e-10), Poisson arrivals at {rate:.0f}/s",
             "solves_per_s": count / last, "completed_ok": ok, "requests": count, "max_relres": relres,
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-            "setup_ms_p50": float(np.percentile(setup, 50)), "device_ms_p50": float(np.percentile(dev, 50)),
+            "setup_ms_p50": float(np.percentile(setup, 50)), "setup_ms_p99": float(np.percentile(setup, 99)),
+            "device_ms_p50": float(np.percentile(dev, 50)), "device_ms_p99": float(np.percentile(dev, 99)),
             "plain_loop_solves_per_s": count / plain, "speedup_vs_plain_loop": plain / last,
             "sustainable_at_offered_rate": bool(count / last >= 0.95 * rate),
             "workgroups": sst["workgroups"], "pool_peak_bytes": sst["pool_peak"]}

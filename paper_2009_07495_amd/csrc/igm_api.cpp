@@ -9,6 +9,7 @@
 #include <new>
 
 #include "igm_launch.hpp"
+#include "igm_par.hpp"
 
 using namespace igm;
 
@@ -41,8 +42,8 @@ igm_status dalloc(igm_system *s, T *&p, size_t count) {
   return IGM_OK;
 }
 
-template <class T>
-igm_status upload(igm_system *s, T *&p, const std::vector<T> &v) {
+template <class T, class A>
+igm_status upload(igm_system *s, T *&p, const std::vector<T, A> &v) {
   IGM_TRY(dalloc(s, p, v.size()));
   if (!v.empty()) IGM_HIP(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
   return IGM_OK;
@@ -219,7 +220,9 @@ igm_status build(igm_system *s) {
     IGM_TRY(upload(s, s->d_ucol, h.ucol));
     IGM_TRY(upload(s, s->d_lval, h.lval));
     IGM_TRY(upload(s, s->d_uval, h.uval));
-    std::vector<double> lf(h.lval.begin(), h.lval.end()), uf(h.uval.begin(), h.uval.end());
+    hvec<double> lf, uf;
+    par_assign(lf, h.lval.data(), (int64_t)h.lval.size());
+    par_assign(uf, h.uval.data(), (int64_t)h.uval.size());
     IGM_TRY(upload(s, s->d_lvalf, lf));
     IGM_TRY(upload(s, s->d_uvalf, uf));
     IGM_TRY(upload(s, s->d_flev_ptr, h.flev_ptr));
@@ -395,10 +398,10 @@ igm_status igm_create_system(int64_t n, const int64_t *row_ptr, const int32_t *c
   s->pol = *pol;
   s->n = n;
   s->nnz = row_ptr[n];
-  s->row_ptr.assign(row_ptr, row_ptr + n + 1);
-  s->col.assign(col, col + s->nnz);
-  s->ahat.assign(val, val + s->nnz);
-  s->bhat.assign(b, b + n);
+  par_assign(s->row_ptr, row_ptr, n + 1);
+  par_assign(s->col, col, s->nnz);
+  par_assign(s->ahat, val, s->nnz);
+  par_assign(s->bhat, b, n);
   igm_status st = build(s);
   if (st != IGM_OK) {
     free_device(s);

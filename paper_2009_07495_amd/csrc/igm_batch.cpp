@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "igm_batch.hpp"
+#include "igm_par.hpp"
 #include "igm_team.hpp"
 
 using namespace igm;
@@ -124,16 +125,16 @@ igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col,
   out.n = n;
   out.nnz = row_ptr[n];
   out.pol = pol;
-  out.row_ptr.assign(row_ptr, row_ptr + n + 1);
-  out.col.assign(col, col + out.nnz);
-  out.ahat.assign(val, val + out.nnz);
-  out.bhat.assign(b, b + n);
+  par_assign(out.row_ptr, row_ptr, n + 1);
+  par_assign(out.col, col, out.nnz);
+  par_assign(out.ahat, val, out.nnz);
+  par_assign(out.bhat, b, n);
   st = host_setup(n, out.row_ptr, out.col, out.ahat, out.bhat, pol, out.h);
   if (st != IGM_OK) return st;
   out.nterms = std::min(pol.s_terms + 1, out.h.nterms);
   if (pol.precond == IGM_PRE_ILU0) {
-    out.lvalf.assign(out.h.lval.begin(), out.h.lval.end());
-    out.uvalf.assign(out.h.uval.begin(), out.h.uval.end());
+    par_assign(out.lvalf, out.h.lval.data(), (int64_t)out.h.lval.size());
+    par_assign(out.uvalf, out.h.uval.data(), (int64_t)out.h.uval.size());
   }
   return IGM_OK;
 }

@@ -95,12 +95,12 @@ struct BatchArgs {
 struct HostSystem {
   int64_t n = 0, nnz = 0;
   igm_policy pol{};
-  std::vector<int64_t> row_ptr;
-  std::vector<int32_t> col;
-  std::vector<double> ahat, bhat;
+  hvec<int64_t> row_ptr;
+  hvec<int32_t> col;
+  hvec<double> ahat, bhat;
   HostSetup h;
   int nterms = 1;
-  std::vector<double> lvalf, uvalf;  // FP64 copies of the integer factors (line 1')
+  hvec<double> lvalf, uvalf;  // FP64 copies of the integer factors (line 1')
 };
 
 // Largest m of the batched kernel (H lives in LDS).

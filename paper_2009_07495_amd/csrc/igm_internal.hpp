@@ -4,12 +4,40 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/igmres.h"
 
 namespace igm {
+
+// Allocator that leaves elements default-initialised (no zero fill for plain
+// numbers), so the parallel pass that writes every element of a fresh setup
+// array also takes its page faults in parallel.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+  template <class U>
+  void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new ((void *)p) U;
+  }
+  template <class U, class... Args>
+  void construct(U *p, Args &&...args) {
+    ::new ((void *)p) U(std::forward<Args>(args)...);
+  }
+};
+// Host array of the setup: resize(n) leaves the new elements unset.
+template <class T>
+using hvec = std::vector<T, NoInitAlloc<T>>;
 
 constexpr int kMaxTerms = 9;       // A_0 .. A_8
 constexpr int kSlice = 64;         // SELL slice height = wavefront width
@@ -30,29 +58,29 @@ struct CycleState {
 
 // Host-side setup products (all derived from the FP64 input).
 struct HostSetup {
-  std::vector<double> dhat, a, b;              // eq. (eq1), (eq3)
+  hvec<double> dhat, a, b;                     // eq. (eq1), (eq3)
   int nterms = 0;
   int32_t alpha[kMaxTerms] = {0};
-  std::vector<std::vector<int64_t>> abar;      // eq. (A), on the input pattern
-  std::vector<int64_t> diag_pos;
-  std::vector<double> lu;                      // FP64 ILU(0) of A
-  std::vector<int64_t> ldiag, udiag;           // cast diagonals
+  std::vector<hvec<int64_t>> abar;             // eq. (A), on the input pattern
+  hvec<int64_t> diag_pos;
+  hvec<double> lu;                             // FP64 ILU(0) of A
+  hvec<int64_t> ldiag, udiag;                  // cast diagonals
   // strict triangles of the integer factors, CSR
-  std::vector<int64_t> lptr, uptr;
-  std::vector<int32_t> lcol, ucol;
-  std::vector<int64_t> lval, uval;
+  hvec<int64_t> lptr, uptr;
+  hvec<int32_t> lcol, ucol;
+  hvec<int64_t> lval, uval;
   // level sets of the triangular sweeps
-  std::vector<int32_t> flev_ptr, flev_rows, blev_ptr, blev_rows;
+  hvec<int32_t> flev_ptr, flev_rows, blev_ptr, blev_rows;
   // SELL-64 layout of the integer matrices
   int64_t nslices = 0;
-  std::vector<int64_t> sell_off;               // nslices + 1, entries
-  std::vector<int32_t> sell_w;                 // nslices
-  std::vector<int32_t> sell_col;               // padded
-  std::vector<std::vector<int64_t>> sell_val;  // per term
+  hvec<int64_t> sell_off;                      // nslices + 1, entries
+  hvec<int32_t> sell_w;                        // nslices
+  hvec<int32_t> sell_col;                      // padded
+  std::vector<hvec<int64_t>> sell_val;         // per term
 };
 
-igm_status host_setup(int64_t n, const std::vector<int64_t> &row_ptr, const std::vector<int32_t> &col,
-                      const std::vector<double> &ahat, const std::vector<double> &bhat, const igm_policy &pol,
+igm_status host_setup(int64_t n, const hvec<int64_t> &row_ptr, const hvec<int32_t> &col,
+                      const hvec<double> &ahat, const hvec<double> &bhat, const igm_policy &pol,
                       HostSetup &out);
 igm_status check_policy(const igm_policy &p);
 // Rows of the largest level set of the ILU sweeps (0 without ILU).
@@ -124,9 +152,9 @@ struct igm_system {
   hipStream_t stream = nullptr;
   igm_policy pol{};
   int64_t n = 0, nnz = 0, npad = 0;
-  std::vector<int64_t> row_ptr;
-  std::vector<int32_t> col;
-  std::vector<double> ahat, bhat;
+  igm::hvec<int64_t> row_ptr;
+  igm::hvec<int32_t> col;
+  igm::hvec<double> ahat, bhat;
   igm::HostSetup hs;
   double bhat_norm = 0.0, b_norm = 0.0;
   // device memory

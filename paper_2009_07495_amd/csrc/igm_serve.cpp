@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "igm_batch.hpp"
+#include "igm_par.hpp"
 #include "igm_team.hpp"
 
 using namespace igm;
@@ -103,9 +104,9 @@ struct Request {
   int64_t ticket = 0;
   int64_t n = 0, nnz = 0;
   igm_policy pol{};
-  std::vector<int64_t> rp;
-  std::vector<int32_t> col;
-  std::vector<double> val, b, x0;
+  hvec<int64_t> rp;
+  hvec<int32_t> col;
+  hvec<double> val, b, x0;
   BatchSys rec{};  // record against kFakeBase
   size_t bytes = 0;  // device region
   size_t img = 0;    // staged data part
@@ -189,10 +190,10 @@ void setup_worker(igm_server *sv) {
     }
     HostSystem hs;
     igm_status st = prepare_system(r->n, r->rp.data(), r->col.data(), r->val.data(), r->b.data(), r->pol, hs);
-    std::vector<int64_t>().swap(r->rp);
-    std::vector<int32_t>().swap(r->col);
-    std::vector<double>().swap(r->val);
-    std::vector<double>().swap(r->b);
+    hvec<int64_t>().swap(r->rp);
+    hvec<int32_t>().swap(r->col);
+    hvec<double>().swap(r->val);
+    hvec<double>().swap(r->b);
     if (st == IGM_OK) {
       r->bytes = round_region(system_bytes(hs, true));
       r->img = round_region(image_bytes(hs));
@@ -217,7 +218,7 @@ void setup_worker(igm_server *sv) {
       build_image(hs, sv->h_stage + r->stage_off, r->x0.empty() ? nullptr : r->x0.data());
       record_for(hs, true, (char *)kFakeBase, r->rec);
       r->x_off = (size_t)((const char *)r->rec.x - (const char *)kFakeBase);
-      std::vector<double>().swap(r->x0);
+      hvec<double>().swap(r->x0);
     }
     std::lock_guard<std::mutex> lk(sv->mu);
     r->t_prepared = Clock::now();
@@ -519,10 +520,10 @@ igm_status igm_server_submit(igm_server *sv, int64_t n, const int64_t *row_ptr, 
   r->n = n;
   r->nnz = row_ptr[n];
   r->pol = *pol;
-  r->rp.assign(row_ptr, row_ptr + n + 1);
-  r->col.assign(col, col + r->nnz);
-  r->val.assign(val, val + r->nnz);
-  r->b.assign(b, b + n);
+  par_assign(r->rp, row_ptr, n + 1);
+  par_assign(r->col, col, r->nnz);
+  par_assign(r->val, val, r->nnz);
+  par_assign(r->b, b, n);
   if (x0) r->x0.assign(x0, x0 + n);
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->stopping) return IGM_ERR_ARG;

@@ -11,8 +11,53 @@
 #include <algorithm>
 
 #include "igm_internal.hpp"
+#include "igm_par.hpp"
 
 namespace igm {
+
+namespace {
+
+std::atomic<int> g_setups{0};
+
+// First error in row order over the chunks of a parallel pass: each chunk
+// records its first failing row (chunks are in row order, so the smallest
+// recorded row is the one the serial loop would have stopped at).
+struct FirstError {
+  std::vector<int64_t> row;
+  std::vector<igm_status> st;
+  explicit FirstError(int nt) : row(std::max(nt, 1), INT64_MAX), st(std::max(nt, 1), IGM_OK) {}
+  void set(int c, int64_t r, igm_status s) {
+    if (r < row[c]) {
+      row[c] = r;
+      st[c] = s;
+    }
+  }
+  igm_status first() const {
+    int64_t best = INT64_MAX;
+    igm_status s = IGM_OK;
+    for (size_t c = 0; c < row.size(); ++c)
+      if (row[c] < best) {
+        best = row[c];
+        s = st[c];
+      }
+    return s;
+  }
+};
+
+}  // namespace
+
+SetupRegion::SetupRegion() { g_setups.fetch_add(1); }
+SetupRegion::~SetupRegion() { g_setups.fetch_sub(1); }
+
+int setup_thread_count() {
+  int hw = 0;
+  if (const char *e = std::getenv("IGM_SETUP_THREADS")) hw = std::atoi(e);
+  if (hw < 1 || hw > 64) {
+    const unsigned c = std::thread::hardware_concurrency();
+    hw = c ? (int)std::min(c, 16u) : 1;
+  }
+  return std::max(1, hw / std::max(1, g_setups.load()));
+}
 
 static bool shift_ok(int32_t b, int32_t hi) { return b >= 0 && b <= hi; }
 
@@ -40,41 +85,55 @@ static inline int64_t cast_i64(double y, bool &bad) {
 
 // eq. (eq3): dhat_i = max_j |ahat_ij| / 2^alpha_a; eq. (eq1): A = Dhat^-1 Ahat,
 // b = Dhat^-1 bhat, one division per entry.
-static igm_status scale_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector<double> &ahat,
-                             const std::vector<double> &bhat, int alpha, HostSetup &h) {
+static igm_status scale_rows(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<double> &ahat,
+                             const hvec<double> &bhat, int alpha, HostSetup &h) {
   h.dhat.resize(n);
   h.a.resize(ahat.size());
   h.b.resize(n);
-  for (int64_t i = 0; i < n; ++i) {
-    double mu = 0.0;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) mu = std::max(mu, fabs(ahat[e]));
-    if (mu == 0.0) return IGM_ERR_SINGULAR_ROW;
-    double d = ldexp(mu, -alpha);
-    if (d == 0.0 || !isfinite(d)) return IGM_ERR_RANGE;
-    h.dhat[i] = d;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) h.a[e] = ahat[e] / d;
-    h.b[i] = bhat[i] / d;
-  }
-  return IGM_OK;
+  FirstError fe(nt);
+  par_ranges(nt, n, [&](int c, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      double mu = 0.0;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) mu = std::max(mu, fabs(ahat[e]));
+      if (mu == 0.0) return fe.set(c, i, IGM_ERR_SINGULAR_ROW);
+      double d = ldexp(mu, -alpha);
+      if (d == 0.0 || !isfinite(d)) return fe.set(c, i, IGM_ERR_RANGE);
+      h.dhat[i] = d;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) h.a[e] = ahat[e] / d;
+      h.b[i] = bhat[i] / d;
+    }
+  });
+  return fe.first();
 }
 
 // Sec. IV-B: A_0 = trunc(A); remainders R_l give alpha_l = alpha_a -
 // floor(log2 max|R_l|) (eq. (alpha1)) and A_l = trunc(2^alpha_l R_l).
-static igm_status split_terms(const igm_policy &p, HostSetup &h) {
-  size_t nnz = h.a.size();
-  bool bad = false;
-  std::vector<double> rem(nnz);
-  h.abar.assign(1, std::vector<int64_t>(nnz));
+static igm_status split_terms(int nt, const igm_policy &p, HostSetup &h) {
+  const int64_t nnz = (int64_t)h.a.size();
+  std::atomic<bool> bad{false};
+  // the remainders are needed only for terms beyond A_0
+  hvec<double> rem(p.s_terms > 0 ? nnz : 0);
+  h.abar.assign(1, hvec<int64_t>(nnz));
   h.alpha[0] = 0;
-  for (size_t e = 0; e < nnz; ++e) {
-    int64_t t = cast_i64(h.a[e], bad);
-    h.abar[0][e] = t;
-    rem[e] = h.a[e] - (double)t;
-  }
+  par_ranges(nt, nnz, [&](int, int64_t lo, int64_t hi) {
+    bool b = false;
+    for (int64_t e = lo; e < hi; ++e) {
+      int64_t t = cast_i64(h.a[e], b);
+      h.abar[0][e] = t;
+      if (p.s_terms > 0) rem[e] = h.a[e] - (double)t;
+    }
+    if (b) bad = true;
+  });
   h.nterms = 1;
   for (int l = 1; l <= p.s_terms; ++l) {
+    std::vector<double> cmax(std::max(nt, 1), 0.0);  // the maximum is the same in any order
+    par_ranges(nt, nnz, [&](int c, int64_t lo, int64_t hi) {
+      double mu = 0.0;
+      for (int64_t e = lo; e < hi; ++e) mu = std::max(mu, fabs(rem[e]));
+      cmax[c] = mu;
+    });
     double mu = 0.0;
-    for (size_t e = 0; e < nnz; ++e) mu = std::max(mu, fabs(rem[e]));
+    for (double v : cmax) mu = std::max(mu, v);
     if (mu == 0.0) break;
     int ex = 0;
     frexp(mu, &ex);
@@ -82,12 +141,17 @@ static igm_status split_terms(const igm_policy &p, HostSetup &h) {
     if (al > 1070) break;
     h.alpha[l] = al;
     h.abar.emplace_back(nnz);
-    for (size_t e = 0; e < nnz; ++e) {
-      double t = ldexp(rem[e], al);
-      int64_t q = cast_i64(t, bad);
-      h.abar[l][e] = q;
-      rem[e] = ldexp(t - (double)q, -al);
-    }
+    hvec<int64_t> &q_l = h.abar[l];
+    par_ranges(nt, nnz, [&](int, int64_t lo, int64_t hi) {
+      bool b = false;
+      for (int64_t e = lo; e < hi; ++e) {
+        double t = ldexp(rem[e], al);
+        int64_t q = cast_i64(t, b);
+        q_l[e] = q;
+        rem[e] = ldexp(t - (double)q, -al);
+      }
+      if (b) bad = true;
+    });
     h.nterms = l + 1;
   }
   return bad ? IGM_ERR_RANGE : IGM_OK;
@@ -95,17 +159,23 @@ static igm_status split_terms(const igm_policy &p, HostSetup &h) {
 
 // FP64 ILU(0) on the pattern, row-oriented: for row i and each k < i of the
 // row (increasing), l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the j > k
-// of row k that also occur in row i.
-static igm_status ilu0_fp(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
+// of row k that also occur in row i. Row i changes only its own entries and
+// reads rows k < i of its strict lower part, so the rows of one level set of
+// that part (every row one level above the rows it reads) are independent:
+// threads share each level, in level order, with the same operations per row.
+static igm_status ilu0_fp(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
                           HostSetup &h) {
-  h.lu = h.a;
-  std::vector<int64_t> where(n, -1);
-  for (int64_t i = 0; i < n; ++i) {
+  const int64_t nnz = rp[n];
+  h.lu.resize(nnz);
+  par_ranges(nt, nnz, [&](int, int64_t lo, int64_t hi) { std::copy(h.a.begin() + lo, h.a.begin() + hi, h.lu.begin() + lo); });
+  // one row: returns false on a zero pivot
+  auto row_ilu = [&](int64_t i, std::vector<int64_t> &where) {
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) where[col[e]] = e;
+    bool ok = true;
     for (int64_t e = rp[i]; e < rp[i + 1] && col[e] < i; ++e) {
       int64_t k = col[e];
       double piv = h.lu[h.diag_pos[k]];
-      if (piv == 0.0) return IGM_ERR_ZERO_PIVOT;
+      if (piv == 0.0) { ok = false; break; }
       double lik = h.lu[e] / piv;
       h.lu[e] = lik;
       for (int64_t f = h.diag_pos[k] + 1; f < rp[k + 1]; ++f) {
@@ -114,49 +184,120 @@ static igm_status ilu0_fp(int64_t n, const std::vector<int64_t> &rp, const std::
       }
     }
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) where[col[e]] = -1;
-    if (h.lu[h.diag_pos[i]] == 0.0) return IGM_ERR_ZERO_PIVOT;
+    return ok && h.lu[h.diag_pos[i]] != 0.0;
+  };
+  if (nt <= 1 || n < 32768) {
+    std::vector<int64_t> where(n, -1);
+    for (int64_t i = 0; i < n; ++i)
+      if (!row_ilu(i, where)) return IGM_ERR_ZERO_PIVOT;
+    return IGM_OK;
   }
-  return IGM_OK;
+  // level sets of the strict lower pattern, rows increasing inside a level
+  std::vector<int32_t> lev(n);
+  int32_t nlev = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t l = 0;
+    for (int64_t e = rp[i]; e < rp[i + 1] && col[e] < i; ++e) l = std::max(l, lev[col[e]] + 1);
+    lev[i] = l;
+    nlev = std::max(nlev, l + 1);
+  }
+  std::vector<int64_t> ptr(nlev + 1, 0);
+  for (int64_t i = 0; i < n; ++i) ptr[lev[i] + 1]++;
+  for (int32_t k = 0; k < nlev; ++k) ptr[k + 1] += ptr[k];
+  std::vector<int32_t> rows(n);
+  {
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i) rows[fill[lev[i]]++] = (int32_t)i;
+  }
+  std::atomic<int32_t> zero_level{INT32_MAX};  // first level with a zero pivot
+  SpinBarrier bar(nt);
+  auto work = [&](int t) {
+    std::vector<int64_t> where(n, -1);
+    for (int32_t L = 0; L < nlev; ++L) {
+      const int64_t lo = ptr[L], cnt = ptr[L + 1] - lo, per = (cnt + nt - 1) / nt;
+      const int64_t q0 = lo + t * per, q1 = std::min(lo + cnt, q0 + per);
+      for (int64_t q = q0; q < q1; ++q)
+        if (!row_ilu(rows[q], where)) {
+          int32_t z = zero_level.load();
+          while (L < z && !zero_level.compare_exchange_weak(z, L)) {
+          }
+        }
+      bar.wait();
+      if (zero_level.load() <= L) break;  // set only during levels <= L: every thread stops here
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto &x : th) x.join();
+  return zero_level.load() != INT32_MAX ? IGM_ERR_ZERO_PIVOT : IGM_OK;
 }
 
 // eqs. (dl), (dl2), (l1), (u1): Lbar = trunc(L |D|^1/2), Ubar = trunc(sgn(D)
 // |D|^1/2 U) with U unit upper (stored entries divided by the pivot).
-static igm_status cast_factors(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
-                               const std::vector<double> &piv, bool offdiag, HostSetup &h) {
-  bool bad = false;
+static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
+                               const hvec<double> &piv, bool offdiag, HostSetup &h) {
   h.ldiag.resize(n);
   h.udiag.resize(n);
-  std::vector<double> sq(n);
-  for (int64_t i = 0; i < n; ++i) {
-    if (piv[i] == 0.0 || !isfinite(piv[i])) return IGM_ERR_ZERO_PIVOT;
-    sq[i] = sqrt(fabs(piv[i]));
-  }
+  hvec<double> sq(n);
+  std::atomic<bool> zero{false};
+  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      if (piv[i] == 0.0 || !isfinite(piv[i])) { zero = true; return; }
+      sq[i] = sqrt(fabs(piv[i]));
+    }
+  });
+  if (zero) return IGM_ERR_ZERO_PIVOT;
+  // row offsets of the strict triangles
   h.lptr.assign(n + 1, 0);
   h.uptr.assign(n + 1, 0);
-  h.lcol.clear(); h.ucol.clear(); h.lval.clear(); h.uval.clear();
-  for (int64_t i = 0; i < n; ++i) {
-    double su = piv[i] < 0.0 ? -sq[i] : sq[i];
-    h.ldiag[i] = cast_i64(sq[i], bad);
-    h.udiag[i] = cast_i64(su, bad);
-    if (bad) return IGM_ERR_RANGE;
-    if (h.ldiag[i] == 0 || h.udiag[i] == 0) return IGM_ERR_ZERO_PIVOT;
-    if (offdiag) {
-      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-        int32_t j = col[e];
-        if (j < i) {
-          h.lcol.push_back(j);
-          h.lval.push_back(cast_i64(h.lu[e] * sq[j], bad));
-        } else if (j > i) {
-          h.ucol.push_back(j);
-          h.uval.push_back(cast_i64(su * (h.lu[e] / piv[i]), bad));
+  if (offdiag) {
+    par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i) {
+        int64_t nl = 0, nu = 0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+          nl += col[e] < i;
+          nu += col[e] > i;
+        }
+        h.lptr[i + 1] = nl;
+        h.uptr[i + 1] = nu;
+      }
+    });
+    for (int64_t i = 0; i < n; ++i) {
+      h.lptr[i + 1] += h.lptr[i];
+      h.uptr[i + 1] += h.uptr[i];
+    }
+  }
+  h.lcol.resize(h.lptr[n]);
+  h.lval.resize(h.lptr[n]);
+  h.ucol.resize(h.uptr[n]);
+  h.uval.resize(h.uptr[n]);
+  FirstError fe(nt);
+  par_ranges(nt, n, [&](int c, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      bool bad = false;
+      double su = piv[i] < 0.0 ? -sq[i] : sq[i];
+      h.ldiag[i] = cast_i64(sq[i], bad);
+      h.udiag[i] = cast_i64(su, bad);
+      if (bad) return fe.set(c, i, IGM_ERR_RANGE);
+      if (h.ldiag[i] == 0 || h.udiag[i] == 0) return fe.set(c, i, IGM_ERR_ZERO_PIVOT);
+      if (offdiag) {
+        int64_t pl = h.lptr[i], pu = h.uptr[i];
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+          int32_t j = col[e];
+          if (j < i) {
+            h.lcol[pl] = j;
+            h.lval[pl++] = cast_i64(h.lu[e] * sq[j], bad);
+          } else if (j > i) {
+            h.ucol[pu] = j;
+            h.uval[pu++] = cast_i64(su * (h.lu[e] / piv[i]), bad);
+          }
         }
       }
+      if (bad) return fe.set(c, i, IGM_ERR_RANGE);
     }
-    h.lptr[i + 1] = (int64_t)h.lcol.size();
-    h.uptr[i + 1] = (int64_t)h.ucol.size();
-    if (bad) return IGM_ERR_RANGE;
-  }
-  return IGM_OK;
+  });
+  return fe.first();
 }
 
 // Level sets: a row's forward level is one more than the largest level of the
@@ -164,7 +305,7 @@ static igm_status cast_factors(int64_t n, const std::vector<int64_t> &rp, const 
 // likewise on the strict upper part in decreasing order.
 static void level_sets(int64_t n, HostSetup &h) {
   std::vector<int32_t> lev(n);
-  auto group = [&](std::vector<int32_t> &ptr, std::vector<int32_t> &rows, int32_t nlev) {
+  auto group = [&](hvec<int32_t> &ptr, hvec<int32_t> &rows, int32_t nlev) {
     ptr.assign(nlev + 1, 0);
     for (int64_t i = 0; i < n; ++i) ptr[lev[i] + 1]++;
     for (int32_t k = 0; k < nlev; ++k) ptr[k + 1] += ptr[k];
@@ -192,7 +333,8 @@ static void level_sets(int64_t n, HostSetup &h) {
 
 // SELL-64: rows in slices of 64, each slice stored column-major with the width
 // of its longest row; padding entries have value 0 and point at the row itself.
-static void build_sell(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col, HostSetup &h) {
+static void build_sell(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
+                       HostSetup &h) {
   int64_t ns = (n + kSlice - 1) / kSlice;
   h.nslices = ns;
   h.sell_off.assign(ns + 1, 0);
@@ -204,53 +346,61 @@ static void build_sell(int64_t n, const std::vector<int64_t> &rp, const std::vec
     h.sell_off[s + 1] = h.sell_off[s] + w * kSlice;
   }
   int64_t tot = h.sell_off[ns];
-  h.sell_col.assign(tot, 0);
-  h.sell_val.assign(h.nterms, std::vector<int64_t>(tot, 0));
-  for (int64_t s = 0; s < ns; ++s) {
-    for (int lane = 0; lane < kSlice; ++lane) {
-      int64_t i = s * kSlice + lane;
-      for (int64_t k = 0; k < h.sell_w[s]; ++k) {
-        int64_t pos = h.sell_off[s] + k * kSlice + lane;
-        int64_t e = (i < n) ? rp[i] + k : -1;
-        if (i < n && e < rp[i + 1]) {
-          h.sell_col[pos] = col[e];
-          for (int l = 0; l < h.nterms; ++l) h.sell_val[l][pos] = h.abar[l][e];
-        } else {
-          h.sell_col[pos] = (int32_t)std::min<int64_t>(i, n - 1);
+  h.sell_col.resize(tot);
+  h.sell_val.assign(h.nterms, hvec<int64_t>());
+  for (int l = 0; l < h.nterms; ++l) h.sell_val[l].resize(tot);
+  par_ranges(nt, ns, [&](int, int64_t s0, int64_t s1) {
+    for (int64_t s = s0; s < s1; ++s) {
+      for (int lane = 0; lane < kSlice; ++lane) {
+        int64_t i = s * kSlice + lane;
+        for (int64_t k = 0; k < h.sell_w[s]; ++k) {
+          int64_t pos = h.sell_off[s] + k * kSlice + lane;
+          int64_t e = (i < n) ? rp[i] + k : -1;
+          if (i < n && e < rp[i + 1]) {
+            h.sell_col[pos] = col[e];
+            for (int l = 0; l < h.nterms; ++l) h.sell_val[l][pos] = h.abar[l][e];
+          } else {
+            h.sell_col[pos] = (int32_t)std::min<int64_t>(i, n - 1);
+            for (int l = 0; l < h.nterms; ++l) h.sell_val[l][pos] = 0;
+          }
         }
       }
     }
-  }
+  });
 }
 
-igm_status host_setup(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
-                      const std::vector<double> &ahat, const std::vector<double> &bhat, const igm_policy &pol,
+igm_status host_setup(int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
+                      const hvec<double> &ahat, const hvec<double> &bhat, const igm_policy &pol,
                       HostSetup &h) {
+  SetupRegion region;
+  const int nt = setup_thread_count();
   h = HostSetup();
-  igm_status st = scale_rows(n, rp, ahat, bhat, pol.alpha_a, h);
+  igm_status st = scale_rows(nt, n, rp, ahat, bhat, pol.alpha_a, h);
   if (st != IGM_OK) return st;
-  st = split_terms(pol, h);
+  st = split_terms(nt, pol, h);
   if (st != IGM_OK) return st;
   h.diag_pos.assign(n, -1);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-      if (col[e] == i) h.diag_pos[i] = e;
+  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i)
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+        if (col[e] == i) h.diag_pos[i] = e;
+  });
   if (pol.precond != IGM_PRE_NONE) {
     for (int64_t i = 0; i < n; ++i)
       if (h.diag_pos[i] < 0) return IGM_ERR_ZERO_PIVOT;
-    std::vector<double> piv(n);
+    hvec<double> piv(n);
     if (pol.precond == IGM_PRE_ILU0) {
-      st = ilu0_fp(n, rp, col, h);
+      st = ilu0_fp(nt, n, rp, col, h);
       if (st != IGM_OK) return st;
       for (int64_t i = 0; i < n; ++i) piv[i] = h.lu[h.diag_pos[i]];
     } else {
       for (int64_t i = 0; i < n; ++i) piv[i] = h.a[h.diag_pos[i]];
     }
-    st = cast_factors(n, rp, col, piv, pol.precond == IGM_PRE_ILU0, h);
+    st = cast_factors(nt, n, rp, col, piv, pol.precond == IGM_PRE_ILU0, h);
     if (st != IGM_OK) return st;
     level_sets(n, h);
   }
-  build_sell(n, rp, col, h);
+  build_sell(nt, n, rp, col, h);
   return IGM_OK;
 }
 
@@ -277,16 +427,24 @@ int32_t max_level_rows(const HostSetup &h) {
 igm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b) {
   if (n < 1 || n >= ((int64_t)1 << 31) || !rp || !col || !val || !b) return IGM_ERR_ARG;
   if (rp[0] != 0) return IGM_ERR_ARG;
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t i = 0; i < n; ++i)
     if (rp[i + 1] < rp[i]) return IGM_ERR_ARG;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      if (col[e] < 0 || col[e] >= n) return IGM_ERR_ARG;
-      if (e > rp[i] && col[e] <= col[e - 1]) return IGM_ERR_ARG;
-      if (!isfinite(val[e])) return IGM_ERR_ARG;
+  std::atomic<bool> bad{false};
+  par_ranges(setup_thread_count(), n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        if (col[e] < 0 || col[e] >= n || (e > rp[i] && col[e] <= col[e - 1]) || !isfinite(val[e])) {
+          bad = true;
+          return;
+        }
+      }
+      if (!isfinite(b[i])) {
+        bad = true;
+        return;
+      }
     }
-    if (!isfinite(b[i])) return IGM_ERR_ARG;
-  }
-  return IGM_OK;
+  });
+  return bad ? IGM_ERR_ARG : IGM_OK;
 }
 
 }  // namespace igm
