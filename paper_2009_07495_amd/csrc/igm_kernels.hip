@@ -5,8 +5,11 @@
 // products in CSR order, every other step is elementwise, and norms use the
 // order-free construction of dnrm_finish, so results do not depend on the
 // launch shape.
+#include <algorithm>
+
 #include "igm_launch.hpp"
 #include "igm_rows.hpp"
+#include "igm_sweep.hpp"
 #include "igm_sync.hpp"
 
 namespace igm {
@@ -157,27 +160,29 @@ __global__ __launch_bounds__(kB) void k_scale(int64_t n, const double *__restric
   if (i < n) bk[i] = r[i] / scal[kScalGamma];
 }
 
-// Line 1' with ILU(0), one level of the FP64 substitution with the integer
-// factors converted to double: forward y_i = (bk_i - sum L_ij y_j) / Lbar_ii.
-__global__ __launch_bounds__(kB) void k_fp_lower(int32_t lo, int32_t hi, const int32_t *__restrict__ rows,
-                                                 const int64_t *__restrict__ lptr, const int32_t *__restrict__ lcol,
-                                                 const double *__restrict__ lvalf, const int64_t *__restrict__ ld,
-                                                 const double *__restrict__ bk, double *y) {
-  const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (q >= hi) return;
-  const int64_t i = rows[q];
-  y[i] = fp_sub_row(lptr[i], lptr[i + 1], lcol, lvalf, y, bk[i], (double)ld[i]);
-}
+// Line 1' with ILU(0): the FP64 substitution with the integer factors
+// converted to double, forward y_i = (bk_i - sum L_ij y_j) / Lbar_ii, then
+// backward u_i = (y_i - sum U_ij u_j) / Ubar_ii in place; each row sums in CSR
+// order. One launch per direction; every row waits only for the level below
+// it (igm_sweep.hpp), so the launch must be co-resident (cooperative).
+struct FpFactors {
+  const int64_t *lptr, *uptr;
+  const int32_t *lcol, *ucol;
+  const double *lvalf, *uvalf;
+  const int64_t *ldiag, *udiag;
+};
 
-// backward u_i = (y_i - sum U_ij u_j) / Ubar_ii, in place.
-__global__ __launch_bounds__(kB) void k_fp_upper(int32_t lo, int32_t hi, const int32_t *__restrict__ rows,
-                                                 const int64_t *__restrict__ uptr, const int32_t *__restrict__ ucol,
-                                                 const double *__restrict__ uvalf, const int64_t *__restrict__ ud,
-                                                 double *u) {
-  const int64_t q = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (q >= hi) return;
-  const int64_t i = rows[q];
-  u[i] = fp_sub_row(uptr[i], uptr[i + 1], ucol, uvalf, u, u[i], (double)ud[i]);
+constexpr int kSweepBlock = 64;  // one wavefront per workgroup
+
+template <bool LOWER>
+__global__ __launch_bounds__(kSweepBlock) void k_fp_sweep(FpFactors f, const int32_t *__restrict__ lev_ptr,
+                                                          const int32_t *__restrict__ lev_rows, int nlev,
+                                                          unsigned *cnt, const double *src, double *dst,
+                                                          CycleState *state) {
+  bool ovf = false, to = false;
+  level_sweep<LOWER, true>(f, lev_ptr, lev_rows, nlev, cnt, 0u, (int64_t)blockIdx.x * kSweepBlock + threadIdx.x,
+                           (int64_t)gridDim.x * kSweepBlock, src, dst, ovf, to);
+  if (to) __hip_atomic_store(&state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_fin_rho(const unsigned long long *red, double *scal, CycleState *st) {
@@ -335,16 +340,31 @@ hipError_t launch_line1(hipStream_t st, const CycleArgs &a, const double *r, dou
                        a.udiag, a.precond, bk, r0, red);
   } else {
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kB), 0, st, n, r, (const double *)scal, bk);
-    for (int L = 0; L < a.nflev; ++L) {
-      int32_t lo = a.flev_host[L], hi = a.flev_host[L + 1];
-      hipLaunchKernelGGL(k_fp_lower, dim3(blocks_for(hi - lo)), dim3(kB), 0, st, lo, hi, a.flev_rows, a.lptr,
-                         a.lcol, lvalf, a.ldiag, (const double *)bk, r0);
-    }
-    for (int L = 0; L < a.nblev; ++L) {
-      int32_t lo = a.blev_host[L], hi = a.blev_host[L + 1];
-      hipLaunchKernelGGL(k_fp_upper, dim3(blocks_for(hi - lo)), dim3(kB), 0, st, lo, hi, a.blev_rows, a.uptr,
-                         a.ucol, uvalf, a.udiag, r0);
-    }
+    // the level counters of the integer sweeps serve here too (k_cycle
+    // clears them again at its own start)
+    hipError_t e = hipMemsetAsync(a.lev_cnt, 0, sizeof(unsigned) * ((size_t)a.nflev + a.nblev) * kLevStride, st);
+    if (e != hipSuccess) return e;
+    FpFactors f{a.lptr, a.uptr, a.lcol, a.ucol, lvalf, uvalf, a.ldiag, a.udiag};
+    // about four times the widest level in flight, at most the co-resident limit
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fp_sweep<true>, kSweepBlock, 0);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const int64_t want = (4 * (int64_t)a.max_level + kSweepBlock - 1) / kSweepBlock;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)std::max(per_cu, 1) * cus));
+    const double *cbk = bk;
+    const double *cr0 = r0;
+    unsigned *cf = a.lev_cnt, *cb = a.lev_cnt + (size_t)a.nflev * kLevStride;
+    int nf = a.nflev, nbl = a.nblev;
+    CycleState *state = a.state;
+    void *argf[] = {&f, (void *)&a.flev_ptr, (void *)&a.flev_rows, &nf, &cf, &cbk, &r0, &state};
+    e = hipLaunchCooperativeKernel((const void *)k_fp_sweep<true>, dim3(grid), dim3(kSweepBlock), argf, 0, st);
+    if (e != hipSuccess) return e;
+    void *argb[] = {&f, (void *)&a.blev_ptr, (void *)&a.blev_rows, &nbl, &cb, &cr0, &r0, &state};
+    e = hipLaunchCooperativeKernel((const void *)k_fp_sweep<false>, dim3(grid), dim3(kSweepBlock), argb, 0, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_absmax, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, (const double *)r0,
                        red + kRedMuR0);
   }

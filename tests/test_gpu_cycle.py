@@ -180,6 +180,22 @@ def test_stream_and_rhs_updates(orc, torch):
     torch.cuda.synchronize()
 
 
+def test_setup_thread_count_does_not_change_bits(torch, monkeypatch):
+    """The host setup splits its passes (and the FP64 ILU(0) by level sets)
+    over threads; one thread and many must give the same solve bit for bit
+    (64,000 rows: above the size where the passes run in parallel)."""
+    s = W.random27(40, 40, 40, seed=21)
+    out = []
+    for threads in ("1", "8"):
+        monkeypatch.setenv("IGM_SETUP_THREADS", threads)
+        g = B.System.from_system(s, "paper_ilu", m=30)
+        x, st = g.solve()
+        assert st == B.OK
+        out.append((x, g.stats()["refinements"]))
+        g.close()
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
 def _golden():
     path = os.path.join(HERE, "golden", "oracle_runs.json")
     return json.load(open(path)) if os.path.exists(path) else {}
