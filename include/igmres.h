@@ -259,7 +259,7 @@ igm_status igm_batch_create(int32_t nsys, const int64_t *n, const int64_t *row_p
 igm_status igm_batch_set_stream(igm_batch *bt, void *hip_stream);
 
 /* Launch shape: threads per workgroup and rows per thread, one of (1024, 8),
- * (1024, 4), (512, 8), (256, 8), (256, 16). System s gets
+ * (1024, 4), (512, 8), (512, 16), (256, 8), (256, 16). System s gets
  * ceil(n_s / (block * rows_per_thread)) workgroups. IGM_ERR_UNSUPPORTED if a
  * system would need more than 256 or the device cannot hold that many at
  * once; IGM_ERR_ARG for a shape not in the list. */
@@ -322,7 +322,7 @@ typedef struct igm_server igm_server;
 
 typedef struct {
   int32_t struct_size;      /* sizeof(igm_server_config) */
-  int32_t block;            /* launch shape: (1024, 8), (1024, 4) or (512, 8); 0 = (1024, 8) */
+  int32_t block;            /* launch shape: (1024, 8), (1024, 4), (512, 8) or (512, 16); 0 = (512, 16) */
   int32_t rows_per_thread;
   int32_t max_slots;        /* requests resident at once; 0 = 256 */
   int32_t setup_threads;    /* host threads preparing requests; 0 = 8 */

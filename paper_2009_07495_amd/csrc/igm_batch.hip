@@ -113,8 +113,19 @@ constexpr int64_t kEvBias = (int64_t)1 << 53;
 
 }  // namespace
 
+// minimum wavefronts per SIMD the compiler must allow, which bounds the
+// registers per thread (4 -> 128, 2 -> 256). A 1024-thread workgroup always
+// has 4 per SIMD; smaller workgroups get 256 registers (one or two resident
+// per compute unit): the kernel then spills far less, which measured faster
+// than more resident workgroups.
+#ifndef IGM_BATCH_WAVES_SMALL
+#define IGM_BATCH_WAVES_SMALL 2
+#endif
+template <int BLOCK>
+constexpr int batch_waves() { return BLOCK >= 1024 ? 4 : IGM_BATCH_WAVES_SMALL; }
+
 template <int BLOCK, int R, bool SERVED>
-__global__ __launch_bounds__(BLOCK, 4) void k_batch(BatchArgs ba) {
+__global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs ba) {
   extern __shared__ int64_t smem[];
   __shared__ TeamShared tsh;
   __shared__ BatchSys srec;  // served mode: this job's record, read coherently
@@ -675,8 +686,8 @@ static const void *batch_kernel_ptr() {
   return (const void *)&k_batch<BLOCK, R, SERVED>;
 }
 
-const int kBatchShapes[][2] = {{1024, 8}, {1024, 4}, {512, 8}, {256, 8}, {256, 16}};
-const int kNumBatchShapes = 5;
+const int kBatchShapes[][2] = {{1024, 8}, {1024, 4}, {512, 8}, {512, 16}, {256, 8}, {256, 16}};
+const int kNumBatchShapes = 6;
 
 const void *batch_kernel(int block, int R) {
 #define IGM_K(BB, RR) \
@@ -684,6 +695,7 @@ const void *batch_kernel(int block, int R) {
   IGM_K(1024, 8)
   IGM_K(1024, 4)
   IGM_K(512, 8)
+  IGM_K(512, 16)
   IGM_K(256, 8)
   IGM_K(256, 16)
 #undef IGM_K
@@ -694,6 +706,7 @@ const void *serve_kernel(int block, int R) {
   if (block == 1024 && R == 8) return batch_kernel_ptr<1024, 8, true>();
   if (block == 1024 && R == 4) return batch_kernel_ptr<1024, 4, true>();
   if (block == 512 && R == 8) return batch_kernel_ptr<512, 8, true>();
+  if (block == 512 && R == 16) return batch_kernel_ptr<512, 16, true>();
   return nullptr;
 }
 

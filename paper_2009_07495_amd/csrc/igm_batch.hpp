@@ -128,7 +128,7 @@ hipError_t place_system(const HostSystem &hs, char *base, bool own_x, hipStream_
 
 const void *batch_kernel(int block, int R);
 // the served variant (jobs from a host ring, records read coherently):
-// shapes (1024, 8), (1024, 4) and (512, 8)
+// shapes (1024, 8), (1024, 4), (512, 8) and (512, 16)
 const void *serve_kernel(int block, int R);
 size_t batch_smem_bytes(int m);
 // the (block, rows per thread) shapes instantiated for the batched kernel

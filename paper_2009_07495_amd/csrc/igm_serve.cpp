@@ -438,8 +438,8 @@ igm_status igm_server_create(const igm_server_config *cfg, igm_server **out) {
     c = *cfg;
   }
   if (c.block == 0 && c.rows_per_thread == 0) {  // 8192 rows per workgroup: 1M rows fit in 128
-    c.block = 1024;
-    c.rows_per_thread = 8;
+    c.block = 512;
+    c.rows_per_thread = 16;
   }
   if (!serve_kernel(c.block, c.rows_per_thread)) return IGM_ERR_UNSUPPORTED;
   if (c.max_slots == 0) c.max_slots = 256;

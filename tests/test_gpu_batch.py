@@ -14,7 +14,7 @@ from paper_2009_07495_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(1024, 8), (1024, 4), (512, 8), (256, 8), (256, 16)]
+SHAPES = [(1024, 8), (1024, 4), (512, 8), (512, 16), (256, 8), (256, 16)]
 
 
 @pytest.fixture(scope="module")
