@@ -90,7 +90,20 @@ typedef struct {
   double tol;           /* stop when ||bhat - Ahat x|| / ||bhat|| < tol (Sec. III) */
   int32_t grid_blocks;  /* launch tuning: workgroups of the cycle kernel; 0 = automatic */
   int32_t phase_clock;  /* 1 = record where int-GMRES calls spend their time (igm_stats.phase_us); costs a few % */
-  int32_t reserved_[6];
+  /* Overflow-driven shift retries allowed per solve, 0..64 (0 = none, the
+   * paper's setting; the single-system solver only). The paper reports that an
+   * auto-tuning of the operand shift was tried for the solver without
+   * preconditioner (Sec. VII-D) but gives no rule; the rule here: when an
+   * int-GMRES call overflows, the stage of its first event (see the event
+   * code) picks one shift: lines 7, 8, 10, 13, 15 raise b_dot, b_axpy,
+   * b_norm, b_rot, b_tmp by 4 (at most df); lines 11 and 16 lower b_div_num
+   * (or b_cs_num) by 4 (not below 0), or the denominator's exponent once the
+   * numerator's is 0. The call is then repeated from the same v1. Overflow
+   * in lines 5, 5' or 17, or with the shift at its limit, ends the solve with
+   * IGM_ERR_OVERFLOW as without retries. Adjusted shifts stay in the system's
+   * policy (igm_get_policy) for later solves. */
+  int32_t shift_retry;
+  int32_t reserved_[5];
 } igm_policy;
 
 /* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,
@@ -150,7 +163,7 @@ typedef struct {
   int32_t levels_bwd;      /* ILU backward level sets */
   int64_t device_bytes;    /* device memory held by the system */
   int32_t last_error_line; /* source line of the last HIP error, 0 if none */
-  int32_t reserved0_;
+  int32_t shift_retries;   /* int-GMRES calls of the last solve repeated with adjusted shifts */
   double time_kernel_ms;   /* GPU time of the kernels of the last kernel-level call (igm_spmv ...) */
   /* Where the last int-GMRES call spent its time, seen by workgroup 0 (us;
    * recorded only with igm_policy.phase_clock = 1, zeros otherwise):
@@ -163,6 +176,10 @@ typedef struct {
 
 /* Copy the statistics of the system's last setup and solve. */
 igm_status igm_get_stats(const igm_system *s, igm_stats *out);
+
+/* Copy the system's current policy: the one it was built with, with the
+ * shifts that overflow retries adjusted (igm_policy.shift_retry). */
+igm_status igm_get_policy(const igm_system *s, igm_policy *out);
 
 /* Per-refinement history of the last solve: entry k (0-based) holds the
  * values at the top of refinement k+1: relres of the original and scaled

@@ -40,14 +40,14 @@ def build(force: bool = True) -> str:
 class Policy(C.Structure):
     _fields_ = [(name, C.c_int32) for name in (
         "df", "alpha_a", "s_terms", "m", "precond", "b_dot", "b_axpy", "b_norm", "b_div_num", "b_div_den",
-        "b_rot", "b_tmp", "b_cs_num", "b_cs_den", "max_refine", "pad_")] + [("gtol", C.c_int64), ("tol", C.c_double)]
+        "b_rot", "b_tmp", "b_cs_num", "b_cs_den", "max_refine", "shift_retry")] + [("gtol", C.c_int64), ("tol", C.c_double)]
 
 
 # Shift settings of the paper: Table IV (no preconditioner) and Table VI (ILU),
 # with d_f = 30, WL = 64, s = 0, alpha_a = 16 / 32 (Sec. VII-B, VII-C).
 # "jacobi" is this implementation's extension: the ILU construction on the
 # diagonal-only pattern with the Table VI shifts.
-_BASE = dict(df=30, s_terms=0, m=30, max_refine=2000, gtol=-1, tol=1e-10)
+_BASE = dict(df=30, s_terms=0, m=30, max_refine=2000, shift_retry=0, gtol=-1, tol=1e-10)
 PRESETS = {
     "paper_noprec": dict(_BASE, alpha_a=16, precond=PRE_NONE, b_dot=16, b_axpy=16, b_norm=16, b_div_num=16,
                          b_div_den=14, b_rot=16, b_tmp=16, b_cs_num=16, b_cs_den=14),
@@ -56,6 +56,13 @@ PRESETS = {
     "jacobi": dict(_BASE, alpha_a=32, precond=PRE_JACOBI, b_dot=0, b_axpy=0, b_norm=0, b_div_num=30,
                    b_div_den=0, b_rot=0, b_tmp=0, b_cs_num=30, b_cs_den=0),
 }
+
+
+def shift_retry(pol: dict, code: int):
+    """orc_shift_retry on a copy of `pol`: (changed, new policy dict)."""
+    p = _policy_struct(pol)
+    changed = lib().orc_shift_retry(C.byref(p), code)
+    return bool(changed), {name: getattr(p, name) for name, _ in Policy._fields_}
 
 
 def policy(preset: str = "paper_noprec", **overrides) -> dict:
@@ -81,7 +88,8 @@ class Stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("refinements", C.c_int32), ("iterations", C.c_int32),
                 ("hist_cap", C.c_int32), ("first_ovf", C.c_int64), ("relres_orig", C.c_double),
                 ("relres_scaled", C.c_double), ("hist_relres_orig", C.c_void_p), ("hist_relres_scaled", C.c_void_p),
-                ("hist_gamma", C.c_void_p), ("hist_rho", C.c_void_p), ("hist_jstar", C.c_void_p)]
+                ("hist_gamma", C.c_void_p), ("hist_rho", C.c_void_p), ("hist_jstar", C.c_void_p),
+                ("shift_retries", C.c_int32), ("pad_", C.c_int32)]
 
 
 _lib = None
@@ -124,6 +132,8 @@ def lib():
             "orc_cycle": (C.c_int, [vp, vp, C.POINTER(Trace)]),
             "orc_cycle_update": (None, [vp, C.POINTER(Trace), dbl, vp]),
             "orc_solve": (C.c_int, [vp, vp, C.POINTER(Stats)]),
+            "orc_shift_retry": (C.c_int, [C.POINTER(Policy), i64]),
+            "orc_get_policy": (None, [vp, C.POINTER(Policy)]),
             "orc_residual": (None, [vp, vp, vp, vp]),
             "orc_line1": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl)]),
             "orc_gmres64": (C.c_int, [vp, i32, dbl, i32, vp, C.POINTER(i32)]),
@@ -259,6 +269,12 @@ class OracleSystem:
             lib().orc_destroy(self.h)
             self.h = None
 
+    def policy_now(self) -> dict:
+        """The system's current policy (shifts adjusted by overflow retries included)."""
+        p = Policy()
+        lib().orc_get_policy(self.h, C.byref(p))
+        return {name: getattr(p, name) for name, _ in Policy._fields_}
+
     def scaled(self):
         d, a, b = np.empty(self.n), np.empty(self.nnz), np.empty(self.n)
         lib().orc_get_scaled(self.h, _p(d), _p(a), _p(b))
@@ -342,6 +358,7 @@ class OracleSystem:
         rc = lib().orc_solve(self.h, _p(x), C.byref(st))
         k = st.refinements
         stats = dict(status=rc, refinements=st.refinements, iterations=st.iterations, first_ovf=st.first_ovf,
+                     shift_retries=st.shift_retries,
                      relres_orig=st.relres_orig, relres_scaled=st.relres_scaled,
                      hist_relres_orig=h_ro[: min(k + 1, cap)], hist_relres_scaled=h_rs[: min(k + 1, cap)],
                      hist_gamma=h_g[: min(k + 1, cap)], hist_rho=h_rho[: min(k + 1, cap)],

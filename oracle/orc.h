@@ -71,7 +71,7 @@ typedef struct {
   int32_t b_cs_num;    /* line 16: numerator * 2^beta_1 */
   int32_t b_cs_den;    /* line 16: denominator / 2^beta_2 */
   int32_t max_refine;  /* refinement limit (not given in the paper) */
-  int32_t pad_;
+  int32_t shift_retry; /* overflow-driven shift retries allowed per solve, 0 = none (see orc_shift_retry) */
   int64_t gtol;        /* stop a cycle early when |g_{j+1}| <= gtol; < 0: never */
   double tol;          /* FP64 relative residual target on the original system */
 } orc_policy;
@@ -156,9 +156,26 @@ typedef struct {
   double *hist_gamma;
   double *hist_rho;
   int32_t *hist_jstar;
+  int32_t shift_retries; /* int-GMRES calls repeated with adjusted shifts */
+  int32_t pad_;
 } orc_stats;
 
-int orc_solve(const orc_system *s, double *x, orc_stats *st);
+/* Runs Fig. 1 from x. With pol.shift_retry > 0 an int-GMRES call that
+ * overflows is repeated with the shifts orc_shift_retry chooses, and the
+ * adjusted shifts stay in the system's policy. */
+int orc_solve(orc_system *s, double *x, orc_stats *st);
+/* Overflow-driven shift retry. The paper reports that an auto-tuning of the
+ * operand shift was investigated for the solver without preconditioner
+ * (Sec. VII-D) but gives no rule; this is the reading used here. From the
+ * stage of the first overflow event of a call (ORC_CODE): the right shift
+ * applied before a product grows by 4, capped at df (line 7: b_dot, line 8:
+ * b_axpy, line 10: b_norm, line 13: b_rot, line 15: b_tmp); for a division
+ * (line 11, line 16) the numerator's exponent shrinks by 4 (not below 0),
+ * or the denominator's once the numerator's is 0. Returns 1 if a shift
+ * changed, 0 if none can (lines 5, 5', 17, or shifts at their limits). */
+int orc_shift_retry(orc_policy *p, int64_t code);
+/* The system's current policy (shifts adjusted by retries included). */
+void orc_get_policy(const orc_system *s, orc_policy *out);
 /* Pieces of one refinement, for step-level parity checks. */
 void orc_residual(const orc_system *s, const double *x, double *r, double *rhat);
 int orc_line1(const orc_system *s, const double *r, double *bk, double *r0, int64_t *v1,

@@ -102,10 +102,38 @@ static double relres(double rn, double bn) {
   return rn == 0.0 ? 0.0 : INFINITY;
 }
 
+static int shrink_exponent(int32_t *num, int32_t *den) {
+  int32_t *e = *num > 0 ? num : (*den > 0 ? den : NULL);
+  if (!e) return 0;
+  *e = *e > 4 ? *e - 4 : 0;
+  return 1;
+}
+
+int orc_shift_retry(orc_policy *p, int64_t code) {
+  if (code == ORC_NO_EVENT) return 0;
+  int32_t stage = (int32_t)((code >> 16) & 0xFF);
+  int32_t sub = (int32_t)(code & 0xFFFF);
+  int32_t *b;
+  switch (stage) {
+    case 3: b = (sub % 2 == 0) ? &p->b_dot : &p->b_axpy; break; /* lines 7 / 8 */
+    case 4: b = &p->b_norm; break;                               /* line 10 */
+    case 6: b = &p->b_rot; break;                                /* line 13 */
+    case 7: b = &p->b_tmp; break;                                /* line 15 */
+    case 5: return shrink_exponent(&p->b_div_num, &p->b_div_den); /* line 11 */
+    case 8: return shrink_exponent(&p->b_cs_num, &p->b_cs_den);   /* line 16 */
+    default: return 0;                                             /* lines 5, 5', 17 */
+  }
+  if (*b >= p->df) return 0;
+  *b = *b + 4 > p->df ? p->df : *b + 4;
+  return 1;
+}
+
+void orc_get_policy(const orc_system *s, orc_policy *out) { *out = s->pol; }
+
 /* Fig. 1: refine x until the FP64 relative residual of the original system
  * drops below tol; each refinement solves Abar^(k) x^(k) = b^(k) with one
  * int-GMRES(m) call and adds gamma^(k) x^(k) (eq. (update)). */
-int orc_solve(const orc_system *s, double *x, orc_stats *st) {
+int orc_solve(orc_system *s, double *x, orc_stats *st) {
   int64_t n = s->n;
   int32_t m = s->pol.m;
   double *r = (double *)malloc(sizeof(double) * n);
@@ -126,6 +154,7 @@ int orc_solve(const orc_system *s, double *x, orc_stats *st) {
   st->refinements = 0;
   st->iterations = 0;
   st->first_ovf = ORC_NO_EVENT;
+  st->shift_retries = 0;
   if (!r || !rh || !bk || !r0 || !xk || !v1 || !t.H || !t.c || !t.s || !t.g || !t.V) {
     st->status = ORC_ERR_ARG;
     goto done;
@@ -152,7 +181,13 @@ int orc_solve(const orc_system *s, double *x, orc_stats *st) {
     }
     if (rc != ORC_OK) { st->status = rc; break; }
     if (gamma == 0.0) { st->status = ORC_OK; break; }
-    orc_cycle(s, v1, &t);
+    /* the call, repeated from the same v1 while a retry can adjust a shift */
+    for (;;) {
+      orc_cycle(s, v1, &t);
+      if (t.first_ovf == ORC_NO_EVENT || st->shift_retries >= s->pol.shift_retry) break;
+      if (!orc_shift_retry(&s->pol, t.first_ovf)) break;
+      st->shift_retries += 1;
+    }
     st->refinements += 1;
     st->iterations += t.steps;
     if (k < st->hist_cap && st->hist_jstar) st->hist_jstar[k] = t.jstar;

@@ -22,6 +22,7 @@ static int check_policy(const orc_policy *p) {
   if (bad_shift(p->b_div_num, 62) || bad_shift(p->b_div_den, 62)) return 1;
   if (bad_shift(p->b_cs_num, 62) || bad_shift(p->b_cs_den, 62)) return 1;
   if (p->max_refine < 0) return 1;
+  if (p->shift_retry < 0 || p->shift_retry > 64) return 1;
   if (!(p->tol >= 0.0)) return 1;
   return 0;
 }

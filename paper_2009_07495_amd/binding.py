@@ -30,11 +30,12 @@ _POLICY_INT_FIELDS = ("df", "alpha_a", "s_terms", "m", "precond", "b_dot", "b_ax
 class Policy(C.Structure):
     _fields_ = ([("struct_size", C.c_int32)] + [(f, C.c_int32) for f in _POLICY_INT_FIELDS]
                 + [("gtol", C.c_int64), ("tol", C.c_double), ("grid_blocks", C.c_int32),
-                   ("phase_clock", C.c_int32), ("reserved_", C.c_int32 * 6)])
+                   ("phase_clock", C.c_int32), ("shift_retry", C.c_int32), ("reserved_", C.c_int32 * 5)])
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f in _POLICY_INT_FIELDS}
-        d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks, phase_clock=self.phase_clock)
+        d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks, phase_clock=self.phase_clock,
+                 shift_retry=self.shift_retry)
         return d
 
 
@@ -45,7 +46,7 @@ class Stats(C.Structure):
                 ("time_setup_ms", C.c_double), ("n", C.c_int64), ("nnz", C.c_int64), ("nterms", C.c_int32),
                 ("grid_blocks", C.c_int32), ("rows_per_thread", C.c_int32), ("block_threads", C.c_int32),
                 ("levels_fwd", C.c_int32), ("levels_bwd", C.c_int32), ("device_bytes", C.c_int64),
-                ("last_error_line", C.c_int32), ("reserved0_", C.c_int32), ("time_kernel_ms", C.c_double),
+                ("last_error_line", C.c_int32), ("shift_retries", C.c_int32), ("time_kernel_ms", C.c_double),
                 ("phase_us", C.c_double * 8), ("reserved_", C.c_int32 * 4)]
 
     def as_dict(self) -> dict:
@@ -77,6 +78,7 @@ _SIGS = {
     "igm_solve": [C.c_void_p, C.c_void_p],
     "igm_solve_device": [C.c_void_p, C.c_void_p],
     "igm_get_stats": [C.c_void_p, C.c_void_p],
+    "igm_get_policy": [C.c_void_p, C.c_void_p],
     "igm_get_history": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                         C.c_void_p],
     "igm_int_cycle": [C.c_void_p, C.c_void_p, C.c_void_p],
@@ -249,6 +251,13 @@ class System:
         s.struct_size = C.sizeof(Stats)
         _check(lib().igm_get_stats(self.h, C.byref(s)), "igm_get_stats")
         return s.as_dict()
+
+    def policy(self) -> dict:
+        """The current policy (shifts adjusted by overflow retries included)."""
+        p = Policy()
+        p.struct_size = C.sizeof(Policy)
+        _check(lib().igm_get_policy(self.h, C.byref(p)), "igm_get_policy")
+        return p.as_dict()
 
     def history(self, cap: int = 4096) -> dict:
         ro, rs, g, rho = (np.zeros(cap) for _ in range(4))

@@ -277,6 +277,7 @@ igm_status solve_dev(igm_system *s, double *x) {
   st.iterations = 0;
   st.first_ovf = kNoEvent;
   st.time_cycle_ms = 0.0;
+  st.shift_retries = 0;
   igm_status status = IGM_NOT_CONVERGED;
   CycleArgs a = make_args(s);
   a.update = 1;
@@ -308,16 +309,25 @@ igm_status solve_dev(igm_system *s, double *x) {
     // lines 1'-2, then the int-GMRES call with the fused update
     IGM_TRY(prepare_cycle(s));
     IGM_HIP(launch_line1(s->stream, a, s->d_r, s->d_scal, s->d_lvalf, s->d_uvalf, s->d_bk, s->d_r0, s->d_red));
-    IGM_HIP(hipEventRecord(e0, s->stream));
-    IGM_TRY(launch_cycle(s, a));
-    IGM_HIP(hipEventRecord(e1, s->stream));
     CycleState cs;
-    IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
-    IGM_HIP(hipMemcpyAsync(hp, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
-    IGM_HIP(hipStreamSynchronize(s->stream));
-    float ms = 0.f;
-    IGM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    st.time_cycle_ms += ms;
+    for (;;) {  // the call, repeated from the same v1 while a retry can adjust a shift
+      IGM_HIP(hipEventRecord(e0, s->stream));
+      IGM_TRY(launch_cycle(s, a));
+      IGM_HIP(hipEventRecord(e1, s->stream));
+      IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
+      IGM_HIP(hipMemcpyAsync(hp, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
+      IGM_HIP(hipStreamSynchronize(s->stream));
+      float ms = 0.f;
+      IGM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      st.time_cycle_ms += ms;
+      if (cs.range_err || cs.timeout || cs.first_ovf == kNoEvent || st.shift_retries >= p.shift_retry) break;
+      if (!adjust_shifts(s->pol, cs.first_ovf)) break;
+      st.shift_retries += 1;
+      a = make_args(s);  // the adjusted shifts; v1 (column 0 of V) is untouched by the call
+      a.update = 1;
+      a.x = x;
+      IGM_TRY(prepare_cycle(s));
+    }
     s->hist_rho.push_back(hp[kScalRho]);
     for (int k = 0; k < 8; ++k) st.phase_us[k] = (double)cs.phase[k] * s->wall_us_per_tick;
     if (cs.range_err) { status = IGM_ERR_RANGE; break; }
@@ -474,6 +484,13 @@ igm_status igm_get_stats(const igm_system *s, igm_stats *out) {
   *out = s->stats;
   out->struct_size = sizeof(igm_stats);
   out->last_error_line = s->last_error_line;
+  return IGM_OK;
+}
+
+igm_status igm_get_policy(const igm_system *s, igm_policy *out) {
+  if (!s || !out) return IGM_ERR_ARG;
+  *out = s->pol;
+  out->struct_size = sizeof(igm_policy);
   return IGM_OK;
 }
 

@@ -83,6 +83,9 @@ igm_status host_setup(int64_t n, const hvec<int64_t> &row_ptr, const hvec<int32_
                       const hvec<double> &ahat, const hvec<double> &bhat, const igm_policy &pol,
                       HostSetup &out);
 igm_status check_policy(const igm_policy &p);
+// Overflow-driven shift retry (igm_policy.shift_retry): adjusts the shift that
+// the stage of overflow event `code` names; false if none can change.
+bool adjust_shifts(igm_policy &p, int64_t code);
 // Rows of the largest level set of the ILU sweeps (0 without ILU).
 int32_t max_level_rows(const HostSetup &h);
 // Threads per workgroup that take part in the counter-driven ILU sweeps of a

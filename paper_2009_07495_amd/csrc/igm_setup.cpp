@@ -71,7 +71,35 @@ igm_status check_policy(const igm_policy &p) {
   if (!shift_ok(p.b_cs_num, 62) || !shift_ok(p.b_cs_den, 62)) return IGM_ERR_ARG;
   if (p.max_refine < 0 || !(p.tol >= 0.0) || p.grid_blocks < 0) return IGM_ERR_ARG;
   if (p.phase_clock < 0 || p.phase_clock > 1) return IGM_ERR_ARG;
+  if (p.shift_retry < 0 || p.shift_retry > 64) return IGM_ERR_ARG;
   return IGM_OK;
+}
+
+bool adjust_shifts(igm_policy &p, int64_t code) {
+  if (code == INT64_MAX) return false;
+  const int stage = (int)((code >> 16) & 0xFF);
+  // a right shift applied before a product: more bits dropped, smaller product
+  auto raise = [&](int32_t &b) {
+    if (b >= p.df) return false;
+    b = std::min(b + 4, p.df);
+    return true;
+  };
+  // a division's exponents (numerator first): a smaller quotient
+  auto lower = [](int32_t &num, int32_t &den) {
+    int32_t &e = num > 0 ? num : den;
+    if (e <= 0) return false;
+    e = std::max(e - 4, 0);
+    return true;
+  };
+  switch (stage) {
+    case 3: return (code & 1) == 0 ? raise(p.b_dot) : raise(p.b_axpy);  // line 7 (even sub) / line 8
+    case 4: return raise(p.b_norm);                                      // line 10
+    case 5: return lower(p.b_div_num, p.b_div_den);                      // line 11
+    case 6: return raise(p.b_rot);                                       // line 13
+    case 7: return raise(p.b_tmp);                                       // line 15
+    case 8: return lower(p.b_cs_num, p.b_cs_den);                        // line 16
+    default: return false;                                               // lines 5, 5', 17
+  }
 }
 
 // C cast to int64 with a range check (|y| < 2^63).

@@ -196,6 +196,37 @@ def test_setup_thread_count_does_not_change_bits(torch, monkeypatch):
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
 
 
+ZERO_SHIFTS = dict(b_dot=0, b_axpy=0, b_norm=0, b_rot=0, b_tmp=0)
+SHIFT_KEYS = ("b_dot", "b_axpy", "b_norm", "b_div_num", "b_div_den", "b_rot", "b_tmp", "b_cs_num", "b_cs_den")
+
+
+@pytest.mark.parametrize("retries", [40, 3])
+def test_shift_retry_matches_oracle(orc, torch, retries):
+    """Overflow-driven shift retries (igm_policy.shift_retry): the same
+    retries, the same adjusted shifts, the same status, event code and x bit
+    for bit as the oracle, both when the retries repair the overflow (40) and
+    when the limit ends the solve (3)."""
+    s = W.poisson2d(32)
+    kw = dict(ZERO_SHIFTS, shift_retry=retries)
+    o = orc.OracleSystem.from_system(s, orc.policy("paper_noprec", **kw))
+    xo, so = o.solve()
+    g = B.System.from_system(s, "paper_noprec", **kw)
+    x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    st = g.solve_device(x)
+    gs = g.stats()
+    assert st == so["status"] and gs["shift_retries"] == so["shift_retries"] > 0
+    assert gs["refinements"] == so["refinements"] and gs["first_ovf"] == so["first_ovf"]
+    pol = g.policy()
+    assert all(pol[k] == o.policy_now()[k] for k in SHIFT_KEYS)
+    assert np.array_equal(x.cpu().numpy(), xo)
+
+
+def test_shift_retry_not_in_batches(torch):
+    with pytest.raises(B.IgmError) as e:
+        B.Batch([W.poisson2d(16)], "paper_noprec", m=10, shift_retry=4)
+    assert e.value.status == B.ERR_UNSUPPORTED
+
+
 def _golden():
     path = os.path.join(HERE, "golden", "oracle_runs.json")
     return json.load(open(path)) if os.path.exists(path) else {}

@@ -110,3 +110,82 @@ def test_fp64_comparator_solves(orc):
         x, it, rc = o.gmres64(tol=1e-12)
         assert rc == orc.OK and it % 1 == 0
         assert true_relres(s, x) < 1e-12
+
+
+# ---- overflow-driven shift retry (a reading: the paper names an auto-tuning
+# of the shift for the solver without preconditioner, Sec. VII-D, but gives
+# no rule; the rule is documented at orc_shift_retry) ----
+
+ZERO_SHIFTS = dict(b_dot=0, b_axpy=0, b_norm=0, b_rot=0, b_tmp=0)
+SHIFT_KEYS = ("b_dot", "b_axpy", "b_norm", "b_div_num", "b_div_den", "b_rot", "b_tmp", "b_cs_num", "b_cs_den")
+
+
+def code(j, stage, sub=0):
+    return (j << 24) | (stage << 16) | sub
+
+
+def test_shift_retry_rule_by_stage(orc):
+    base = orc.policy("paper_noprec", **ZERO_SHIFTS)
+    expect = {
+        code(1, 3, 0): ("b_dot", 4), code(2, 3, 3): ("b_axpy", 4), code(1, 4): ("b_norm", 4),
+        code(1, 5): ("b_div_num", 12), code(1, 6, 1): ("b_rot", 4), code(1, 7): ("b_tmp", 4),
+        code(1, 8): ("b_cs_num", 12),
+    }
+    for c, (key, val) in expect.items():
+        changed, p = orc.shift_retry(base, c)
+        assert changed and p[key] == val, (hex(c), key, p[key])
+        assert all(p[k] == base[k] for k in SHIFT_KEYS if k != key)
+    # no shift can prevent an overflow in lines 5, 5' or 17, or without an event
+    for c in (code(1, 1), code(1, 2), code(1, 9), orc.NO_EVENT):
+        assert orc.shift_retry(base, c)[0] is False
+    # limits: raised shifts stop at df; a division's numerator exponent goes
+    # to 0, then its denominator's
+    changed, p = orc.shift_retry(dict(base, b_dot=28), code(1, 3, 0))
+    assert changed and p["b_dot"] == 30
+    assert orc.shift_retry(dict(base, b_dot=30), code(1, 3, 0))[0] is False
+    changed, p = orc.shift_retry(dict(base, b_div_num=0, b_div_den=3), code(1, 5))
+    assert changed and p["b_div_num"] == 0 and p["b_div_den"] == 0
+    assert orc.shift_retry(dict(base, b_div_num=0, b_div_den=0), code(1, 5))[0] is False
+
+
+def test_shift_retry_repairs_overflow_and_equals_a_solve_with_the_final_shifts(orc):
+    """Zero shifts overflow in the first inner product (Q30 x Q30 products of
+    the unpreconditioned Poisson matrix). With retries the solve converges,
+    every retry happens in the first refinement, so the result must equal, bit
+    for bit, a fresh solve that starts from the shifts the retries ended with."""
+    s = W.poisson2d(32)
+    x0, st0 = make(orc, s, "paper_noprec", **ZERO_SHIFTS).solve()
+    assert st0["status"] == orc.ERR_OVERFLOW and (st0["first_ovf"] >> 16) & 0xFF == 3
+    o = make(orc, s, "paper_noprec", shift_retry=40, **ZERO_SHIFTS)
+    x1, st1 = o.solve()
+    assert st1["status"] == orc.OK and st1["relres_orig"] < 1e-10
+    assert 0 < st1["shift_retries"] <= 40
+    final = {k: o.policy_now()[k] for k in SHIFT_KEYS}
+    assert final["b_dot"] > 0 and final["b_norm"] > 0
+    x2, st2 = make(orc, s, "paper_noprec", **dict(ZERO_SHIFTS, **final)).solve()
+    assert st2["status"] == orc.OK and st2["shift_retries"] == 0
+    assert np.array_equal(x1, x2) and st1["refinements"] == st2["refinements"]
+    assert np.abs(x1 - 1.0).max() < 1e-8  # Poisson right-hand side = A * ones
+
+
+def test_shift_retry_limit_and_unretryable_stage(orc):
+    s = W.poisson2d(16)
+    o = make(orc, s, "paper_noprec", shift_retry=3, **ZERO_SHIFTS)
+    x, st = o.solve()
+    # three raises of b_dot (0 -> 12) are not enough: still the line 7 overflow
+    assert st["status"] == orc.ERR_OVERFLOW and st["shift_retries"] == 3
+    assert o.policy_now()["b_dot"] == 12 and (st["first_ovf"] >> 16) & 0xFF == 3
+    assert np.all(x == 0)
+    # an overflow in the SpMV (alpha_a = 62: entries near 2^62 times Q30
+    # vector words) cannot be retried
+    o = make(orc, s, "paper_noprec", alpha_a=62, shift_retry=8)
+    x, st = o.solve()
+    assert st["status"] == orc.ERR_OVERFLOW and st["shift_retries"] == 0
+    assert (st["first_ovf"] >> 16) & 0xFF == 1
+
+
+def test_shift_retry_is_inert_without_overflow(orc):
+    s = W.convdiff3d(10, seed=3)
+    xa, sa = make(orc, s, "jacobi", m=20).solve()
+    xb, sb = make(orc, s, "jacobi", m=20, shift_retry=16).solve()
+    assert sb["shift_retries"] == 0 and np.array_equal(xa, xb) and sa["refinements"] == sb["refinements"]
