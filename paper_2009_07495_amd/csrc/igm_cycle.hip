@@ -20,6 +20,17 @@ namespace igm {
 // thread that runs the scalar Givens work (wavefront 1, lane 0)
 constexpr int kGivens = 64;
 
+// v_{j+1} passes to the other workgroups' SpMV gathers through write-through
+// (device-coherent) stores and a barrier that only waits for them to
+// complete: no cache write-back or invalidation, so cached matrix lines
+// survive the step. Plain loads of v_{j+1} are safe because its cache lines
+// are first touched in a launch by their one owner workgroup's stores (each
+// workgroup owns whole 1024-row blocks), other workgroups first read them
+// after that barrier, and a launch starts with caches coherent with memory.
+#ifndef IGM_COH_V
+#define IGM_COH_V 1
+#endif
+
 template <int BLOCK, int R, int PRE>
 __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   extern __shared__ int64_t smem[];
@@ -245,15 +256,27 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       const int e = df - a.b_div_num - a.b_div_den;
       bool ov = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) vn[gt + k * T] = normalize_elem(w[k], den, a.b_div_num, e, ov);
+      for (int k = 0; k < R; ++k) {
+#if IGM_COH_V
+        st_coh(vn + gt + k * T, normalize_elem(w[k], den, a.b_div_num, e, ov));
+#else
+        vn[gt + k * T] = normalize_elem(w[k], den, a.b_div_num, e, ov);
+#endif
+      }
       if (ov) atomicMin((long long *)first, (long long)ev_code(j, 5, 0));
     }
     IGM_TICK(4)
-    // v_{j+1} and the overflow record become visible to every workgroup; lines
-    // 15-19 (thread kGivens) run while wavefront 0 waits
+    // v_{j+1} becomes visible to every workgroup; lines 15-19 (thread
+    // kGivens) run while wavefront 0 waits
+#if IGM_COH_V
+    grid_barrier_coh(gs, ssh, [&] {
+      if (tid == kGivens) givens(j);
+    });
+#else
     grid_barrier(gs, ssh, [&] {
       if (tid == kGivens) givens(j);
     });
+#endif
     IGM_TICK(6)
     if (sh_stop || ssh.abort) break;
   }

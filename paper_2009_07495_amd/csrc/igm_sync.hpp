@@ -171,7 +171,9 @@ __device__ __forceinline__ void grid_barrier(GridSync &gs, SyncShared &sh) {
 // (ld_coh / st_coh): each wavefront waits for its own stores to complete,
 // then the workgroups meet; no cache write-back or invalidation, so cached
 // read-only data stays cached.
-__device__ __forceinline__ void grid_barrier_coh(GridSync &gs, SyncShared &sh) {
+// Threads of wavefronts 1.. run `side` while wavefront 0 waits.
+template <class Side>
+__device__ __forceinline__ void grid_barrier_coh(GridSync &gs, SyncShared &sh, Side side) {
   const int s = gs.next++;
   wait_vm();
   __syncthreads();
@@ -182,8 +184,14 @@ __device__ __forceinline__ void grid_barrier_coh(GridSync &gs, SyncShared &sh) {
     bool to = false;
     if (!sh.abort) poll_words(gs, s, kSyncGroups, to);
     if (threadIdx.x == 0 && to) record_timeout(gs, sh);
+  } else {
+    side();
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void grid_barrier_coh(GridSync &gs, SyncShared &sh) {
+  grid_barrier_coh(gs, sh, [] {});
 }
 
 // Workgroup sum of one Acc per thread; result valid in thread 0 only.

@@ -133,3 +133,40 @@ def test_bad_requests_and_start_iterate(orc, torch):
     with pytest.raises(B.IgmError):
         sv.wait(12345, 10)
     sv.close(30000)
+
+
+def test_full_size_requests_match_recorded_oracle_runs(orc, torch):
+    """The two largest workloads served at full size, in a mix with small
+    requests on the default server shape: each comes back with the oracle's
+    recorded refinement and iteration counts, final relative residual and
+    solution hash (tests/golden/make_oracle_runs.py); the small ones equal
+    the oracle bit for bit."""
+    import hashlib
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_runs.json")
+    gold = json.load(open(path)) if os.path.exists(path) else {}
+    names = [n for n in ("random27_1m", "convdiff3d_64") if n in gold]
+    if not names:
+        pytest.skip("no recorded oracle runs")
+    small = mix()[:3]
+    refs = [oracle(orc, s, p, m=30) for s, p in small]
+    sv = B.Server()
+    try:
+        big = []
+        for name in names:
+            gen, preset, m = W.WORKLOADS[name]
+            big.append((name, sv.submit(gen(), preset, m=m)))
+        tickets = [sv.submit(s, p, m=30) for s, p in small]
+        for t, ref in zip(tickets, refs):
+            check(*sv.wait(t, 300000), ref)
+        for name, t in big:
+            x, st = sv.wait(t, 300000)
+            g = gold[name]
+            assert st["status"] == B.OK
+            assert st["refinements"] == g["refinements"] and st["iterations"] == g["iterations"]
+            assert st["relres_orig"] == g["relres_orig"]
+            assert hashlib.sha256(x.tobytes()).hexdigest() == g["x_sha256"], name
+    finally:
+        sv.close()
