@@ -166,7 +166,7 @@ igm_status alloc_work(igm_system *s) {
   IGM_TRY(dalloc(s, s->d_sync, (size_t)2 * kSyncGroups * cap));
   IGM_TRY(dalloc(s, s->d_red, kRedWords));
   IGM_TRY(dalloc(s, s->d_scal, kScalWords));
-  IGM_TRY(dalloc(s, s->d_parts, 4096));
+  IGM_TRY(dalloc(s, s->d_parts, kMaxReduceParts + 1));  // partials, then the ticket (zeroed here)
   if (hipHostMalloc((void **)&s->h_pinned, 64 * sizeof(double)) != hipSuccess) return IGM_ERR_OOM;
   return IGM_OK;
 }

@@ -159,8 +159,8 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
         if (PRE == IGM_PRE_JACOBI) z = tdiv_diag(tdiv_diag(z, a.ldiag[row], o2), a.udiag[row], o2);
         w[k] = z;
       }
-      if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
-      if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
+      note_event(o1, first, ev_code(j, 1, 0));
+      note_event(o2, first, ev_code(j, 2, 0));
     } else {
       // z, y and u pass between workgroups through device-coherent stores
       // and loads; the rows of each sweep wait only for the level below
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
         const int64_t row = gt + k * T;
         st_coh(a.zbuf + row, spmv_row(a, row, vj, a.nterms, o1));
       }
-      if (o1) atomicMin((long long *)first, (long long)ev_code(j, 1, 0));
+      note_event(o1, first, ev_code(j, 1, 0));
       grid_barrier_coh(gs, ssh);
       const int64_t pos0 = (int64_t)blockIdx.x * a.sweep_threads + tid;
       const int64_t stride = (int64_t)gridDim.x * a.sweep_threads;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
                            (unsigned)(j - 1), pos0, stride, a.wbuf, a.wbuf, o2, to);
       if (to) __hip_atomic_store(&a.state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       grid_barrier_coh(gs, ssh);
-      if (o2) atomicMin((long long *)first, (long long)ev_code(j, 2, 0));
+      note_event(o2, first, ev_code(j, 2, 0));
 #pragma unroll
       for (int k = 0; k < R; ++k) w[k] = ld_coh(a.wbuf + gt + k * T);  // padded rows hold 0
     }
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       bool o = false;
 #pragma unroll
       for (int k = 0; k < R; ++k) acc.add(mulw(asr(w[k], a.b_dot), vv[k], o));  // line 7: only w is shifted
-      if (o) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1)));
+      note_event(o, first, ev_code(j, 3, 2 * (i - 1)));
       int64_t vnext[R];
       if (i < j) {
         const int64_t *vi1 = a.V + (size_t)i * a.npad;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       bool ou = false;
 #pragma unroll
       for (int k = 0; k < R; ++k) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - a.b_axpy), ou);
-      if (ou) atomicMin((long long *)first, (long long)ev_code(j, 3, 2 * (i - 1) + 1));
+      note_event(ou, first, ev_code(j, 3, 2 * (i - 1) + 1));
       if (i < j) {
 #pragma unroll
         for (int k = 0; k < R; ++k) vv[k] = vnext[k];
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       bool o = false;
 #pragma unroll
       for (int k = 0; k < R; ++k) acc.add(sqrc(asr(w[k], a.b_norm), o));
-      if (o) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
+      note_event(o, first, ev_code(j, 4, 0));
       bool os = false;
       hn = grid_sum<BLOCK>(gs, acc, ssh, fin_norm, [&] {
         if (tid == kGivens && j >= 2) rotate(j, j - 1);
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
         vn[gt + k * T] = normalize_elem(w[k], den, a.b_div_num, e, ov);
 #endif
       }
-      if (ov) atomicMin((long long *)first, (long long)ev_code(j, 5, 0));
+      note_event(ov, first, ev_code(j, 5, 0));
     }
     IGM_TICK(4)
     // v_{j+1} becomes visible to every workgroup; lines 15-19 (thread

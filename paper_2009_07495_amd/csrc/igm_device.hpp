@@ -191,6 +191,15 @@ __device__ __forceinline__ unsigned ld_coh(const unsigned *p) {
 __device__ __forceinline__ void st_coh(unsigned *p, unsigned v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Records overflow event `code` in *first (the smallest code wins) once per
+// wavefront in which any active lane saw an overflow, so a kernel whose rows
+// all overflow does not serialise on one atomic word. `code` must be the same
+// in every lane.
+__device__ __forceinline__ void note_event(bool o, int64_t *first, int64_t code) {
+  const unsigned long long m = __ballot(o);
+  if (m && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicMin((long long *)first, (long long)code);
+}
+
 // Waits until this wavefront's outstanding memory operations have completed
 // (s_waitcnt vmcnt(0); the other counters are left at their maxima).
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }

@@ -213,14 +213,14 @@ __global__ __launch_bounds__(kB) void k_spmv(CycleArgs a, int nterms, const int6
   bool o = false;
   for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
     z[row] = spmv_row(a, row, v, nterms, o);
-  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 1, 0));
+  note_event(o, &a.state->first_ovf, ev_code(1, 1, 0));
 }
 
 __global__ __launch_bounds__(kB) void k_diag_solve(CycleArgs a, const int64_t *__restrict__ z, int64_t *w) {
   bool o = false;
   for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
     w[row] = a.precond == IGM_PRE_NONE ? z[row] : tdiv_diag(tdiv_diag(z[row], a.ldiag[row], o), a.udiag[row], o);
-  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 2, 0));
+  note_event(o, &a.state->first_ovf, ev_code(1, 2, 0));
 }
 
 __global__ __launch_bounds__(kB) void k_lower_level(CycleArgs a, int32_t lo, int32_t hi, const int64_t *__restrict__ z,
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kB) void k_lower_level(CycleArgs a, int32_t lo, int
   bool o = false;
   const int64_t row = a.flev_rows[q];
   y[row] = lower_row(a, row, z[row], y, o);
-  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 2, 0));
+  note_event(o, &a.state->first_ovf, ev_code(1, 2, 0));
 }
 
 __global__ __launch_bounds__(kB) void k_upper_level(CycleArgs a, int32_t lo, int32_t hi, int64_t *u) {
@@ -239,42 +239,67 @@ __global__ __launch_bounds__(kB) void k_upper_level(CycleArgs a, int32_t lo, int
   bool o = false;
   const int64_t row = a.blev_rows[q];
   u[row] = upper_row(a, row, u[row], u, o);
-  if (o) atomicMin((long long *)&a.state->first_ovf, (long long)ev_code(1, 2, 0));
+  note_event(o, &a.state->first_ovf, ev_code(1, 2, 0));
 }
 
-// Partial sums of line 7 (mode 0: asr(w, b) v) or line 10 (mode 1: asr(w, b)^2),
-// one exact Acc per workgroup.
-__global__ __launch_bounds__(kB) void k_reduce_part(int64_t n, const int64_t *__restrict__ w,
-                                                    const int64_t *__restrict__ v, int b, int mode, Acc *parts,
-                                                    CycleState *st, int64_t code) {
-  __shared__ Acc sh_wave[kB / 64];
+// Line 7 (mode 0: h = asr(sum asr(w, b) v, df - b)) or line 10 (mode 1:
+// h = shl(isqrt(sum asr(w, b)^2), b)) in one launch: each workgroup adds its
+// rows into an exact Acc and stores it with device-coherent stores; the last
+// workgroup to take a ticket adds all of them and finishes. The ticket word
+// is zero before the launch and the last workgroup sets it back to zero.
+constexpr int kRB = 512;     // threads per workgroup of the standalone reductions
+constexpr int kRUnroll = 8;  // elements in flight per thread
+
+__global__ __launch_bounds__(kRB) void k_reduce(int64_t n, const int64_t *__restrict__ w,
+                                               const int64_t *__restrict__ v, int b, int df, int mode, Acc *parts,
+                                               unsigned *ticket, int64_t *out, CycleState *st, int64_t code) {
+  __shared__ Acc sh_wave[kRB / 64];
+  __shared__ int last;
   Acc acc;
   acc.zero();
   bool o = false;
-  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
-    const int64_t t = asr(w[i], b);
-    acc.add(mulc(t, mode == 0 ? v[i] : t, o));
+  const int64_t stride = (int64_t)gridDim.x * kRB;
+  for (int64_t i0 = (int64_t)blockIdx.x * kRB + threadIdx.x; i0 < n; i0 += stride * kRUnroll) {
+    int64_t wv[kRUnroll], vv[kRUnroll];
+#pragma unroll
+    for (int u = 0; u < kRUnroll; ++u) {
+      const int64_t i = i0 + u * stride;
+      wv[u] = i < n ? w[i] : 0;
+      vv[u] = (mode == 0 && i < n) ? v[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRUnroll; ++u) {
+      const int64_t t = asr(wv[u], b);
+      acc.add(mode == 0 ? mulw(t, vv[u], o) : sqrc(t, o));
+    }
   }
-  if (o) atomicMin((long long *)&st->first_ovf, (long long)code);
-  Acc p = block_sum<kB>(acc, sh_wave);
-  if (threadIdx.x == 0) parts[blockIdx.x] = p;
-}
-
-// Finish line 7 (mode 0): asr(S, df - b); line 10 (mode 1): shl(isqrt(S), b).
-__global__ __launch_bounds__(kB) void k_reduce_fin(int nparts, const Acc *parts, int b, int df, int mode,
-                                                   int64_t *out, CycleState *st, int64_t code) {
-  __shared__ Acc sh_wave[kB / 64];
-  Acc acc;
-  acc.zero();
-  for (int k = threadIdx.x; k < nparts; k += kB) acc.add(parts[k]);
-  acc.normalize();
-  Acc t = block_sum<kB>(acc, sh_wave);
+  note_event(o, &st->first_ovf, code);
+  const Acc p = block_sum<kRB>(acc, sh_wave);
   if (threadIdx.x == 0) {
-    bool o = false;
-    const int64_t S = t.value(o);
-    const int64_t r = mode == 0 ? asr(S, df - b) : shl(isqrt64(S), b, o);
-    if (o) atomicMin((long long *)&st->first_ovf, (long long)code);
+    st_coh(&parts[blockIdx.x].lo, p.lo);
+    st_coh(&parts[blockIdx.x].hi, p.hi);
+    wait_vm();
+    last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  Acc tot;
+  tot.zero();
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += kRB) {
+    Acc q;
+    q.lo = ld_coh(&parts[k].lo);
+    q.hi = ld_coh(&parts[k].hi);
+    q.normalize();
+    tot.add(q);
+  }
+  const Acc t = block_sum<kRB>(tot, sh_wave);
+  if (threadIdx.x == 0) {
+    bool of = false;
+    const int64_t S = t.value(of);
+    const int64_t r = mode == 0 ? asr(S, df - b) : shl(isqrt64(S), b, of);
+    if (of) atomicMin((long long *)&st->first_ovf, (long long)code);
     *out = r;
+    *ticket = 0u;
   }
 }
 
@@ -284,7 +309,7 @@ __global__ __launch_bounds__(kB) void k_axpy(int64_t n, int64_t h, int b, int df
   const int64_t hs = asr(h, b);
   for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
     w[i] = subc(w[i], asr(mulc(hs, v[i], o), df - b), o);
-  if (o) atomicMin((long long *)&st->first_ovf, (long long)ev_code(1, 3, 1));
+  note_event(o, &st->first_ovf, ev_code(1, 3, 1));
 }
 
 __global__ __launch_bounds__(kB) void k_normalize(int64_t n, const int64_t *__restrict__ w, int64_t den, int b1,
@@ -292,7 +317,7 @@ __global__ __launch_bounds__(kB) void k_normalize(int64_t n, const int64_t *__re
   bool o = false;
   for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
     v[i] = normalize_elem(w[i], den, b1, e, o);
-  if (o) atomicMin((long long *)&st->first_ovf, (long long)ev_code(1, 5, 0));
+  note_event(o, &st->first_ovf, ev_code(1, 5, 0));
 }
 
 // ---- host launchers --------------------------------------------------------
@@ -400,9 +425,12 @@ hipError_t launch_precond(hipStream_t st, const CycleArgs &a, const int64_t *z, 
 hipError_t launch_reduce(hipStream_t st, int64_t n, const int64_t *w, const int64_t *v, int b, int df, int mode,
                          AccWords *parts, int64_t *out, CycleState *state, int64_t code) {
   static_assert(sizeof(AccWords) == sizeof(Acc), "partial-sum layout");
-  unsigned nb = grid_stride_blocks(n);
-  hipLaunchKernelGGL(k_reduce_part, dim3(nb), dim3(kB), 0, st, n, w, v, b, mode, (Acc *)parts, state, code);
-  hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kB), 0, st, (int)nb, (const Acc *)parts, b, df, mode, out, state,
+  // enough workgroups for every compute unit, each thread kRUnroll elements
+  // per pass; parts holds kMaxReduceParts partials and then the ticket word
+  const int64_t want = (n + (int64_t)kRB * kRUnroll - 1) / ((int64_t)kRB * kRUnroll);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kMaxReduceParts));
+  unsigned *ticket = (unsigned *)(parts + kMaxReduceParts);
+  hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(kRB), 0, st, n, w, v, b, df, mode, (Acc *)parts, ticket, out, state,
                      code);
   return hipGetLastError();
 }

@@ -6,6 +6,10 @@
 
 namespace igm {
 
+// Workgroup partials of the standalone reductions (igm_dot, igm_norm); the
+// partial buffer holds this many plus one word for the completion ticket.
+constexpr int kMaxReduceParts = 2048;
+
 // Scratch words of the FP64 reductions (d_red): maxima as double bit patterns,
 // exact norm sums as three 40-bit limbs.
 enum : int {
