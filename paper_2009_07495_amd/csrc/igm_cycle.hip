@@ -24,8 +24,9 @@ constexpr int kGivens = 64;
 // (device-coherent) stores and a barrier that only waits for them to
 // complete: no cache write-back or invalidation, so cached matrix lines
 // survive the step. Plain loads of v_{j+1} are safe because its cache lines
-// are first touched in a launch by their one owner workgroup's stores (each
-// workgroup owns whole 1024-row blocks), other workgroups first read them
+// are first touched in a launch by their one owner workgroup's stores (a
+// workgroup owns whole blocks of BLOCK consecutive rows, BLOCK a multiple of
+// the 16 words of a cache line), other workgroups first read them
 // after that barrier, and a launch starts with caches coherent with memory.
 #ifndef IGM_COH_V
 #define IGM_COH_V 1
