@@ -227,6 +227,38 @@ def test_shift_retry_not_in_batches(torch):
     assert e.value.status == B.ERR_UNSUPPORTED
 
 
+def test_abi_error_statuses_match_oracle(orc, torch):
+    """The failure statuses of the C ABI, forced from the host, equal the
+    oracle's: an all-zero row, a NaN entry, unsorted columns, a structurally
+    zero ILU pivot, a bad policy; and non-convergence (one refinement at
+    tol 1e-14) returns the oracle's best iterate bit for bit."""
+    s = W.random_dd(10, 0.3, 15)
+    cases = []
+    val = s.val.copy()
+    val[s.row_ptr[3]:s.row_ptr[4]] = 0.0
+    cases.append((W.System("zero row", s.n, s.row_ptr, s.col, val, s.b), "paper_noprec", {}))
+    val = s.val.copy()
+    val[0] = np.nan
+    cases.append((W.System("nan", s.n, s.row_ptr, s.col, val, s.b), "paper_noprec", {}))
+    col = s.col.copy()
+    col[s.row_ptr[2]], col[s.row_ptr[2] + 1] = col[s.row_ptr[2] + 1], col[s.row_ptr[2]]
+    cases.append((W.System("unsorted", s.n, s.row_ptr, col, s.val, s.b), "paper_noprec", {}))
+    cases.append((W.from_dense(np.array([[0.0, 1.0], [1.0, 1.0]]), np.ones(2)), "paper_ilu", {}))
+    cases.append((s, "paper_noprec", dict(df=70)))
+    for sysm, preset, kw in cases:
+        with pytest.raises(orc.OracleError) as eo:
+            orc.OracleSystem.from_system(sysm, orc.policy(preset, **kw))
+        with pytest.raises(B.IgmError) as eg:
+            B.System.from_system(sysm, preset, **kw)
+        assert eg.value.status == eo.value.status, (sysm.name, eg.value.status, eo.value.status)
+    big = W.convdiff3d(12, seed=9)
+    xo, so = orc.OracleSystem.from_system(big, orc.policy("jacobi", m=10, max_refine=1, tol=1e-14)).solve()
+    g = B.System.from_system(big, "jacobi", m=10, max_refine=1, tol=1e-14)
+    x, st = g.solve()
+    assert st == so["status"] == B.NOT_CONVERGED
+    assert np.array_equal(x, xo) and g.stats()["relres_orig"] == so["relres_orig"]
+
+
 def _golden():
     path = os.path.join(HERE, "golden", "oracle_runs.json")
     return json.load(open(path)) if os.path.exists(path) else {}
@@ -250,4 +282,6 @@ def test_full_size_workload_matches_recorded_oracle_run(torch, name):
     assert gs["refinements"] == gold["refinements"] and gs["iterations"] == gold["iterations"]
     h = g.history()
     assert [float(v) for v in h["relres_orig"]] == gold["hist_relres_orig"]
+    if name == "random27_1m":  # level sets of the ILU(0) factors of this matrix
+        assert gs["levels_fwd"] == 634 and gs["levels_bwd"] == 634
     assert hashlib.sha256(x.tobytes()).hexdigest() == gold["x_sha256"]
