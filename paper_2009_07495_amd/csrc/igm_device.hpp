@@ -92,17 +92,17 @@ __device__ __forceinline__ int64_t tdiv_diag(int64_t a, int64_t d, bool &ovf) {
   return tdiv(a, d, ovf);
 }
 
-// floor(sqrt(x)) by the bitwise (digit-by-digit) method, integers only;
-// x <= 0 gives 0.
+// floor(sqrt(x)); x <= 0 gives 0. A double-precision estimate (within one of
+// the root, which is below 2^31.5) corrected with exact integer squares,
+// which fit in 64 bits; the correction makes the result exact whatever the
+// estimate.
 __device__ __forceinline__ int64_t isqrt64(int64_t xs) {
   if (xs <= 0) return 0;
-  uint64_t x = (uint64_t)xs, r = 0, bit = 1ull << 62;
-  while (bit > x) bit >>= 2;
-  while (bit) {
-    if (x >= r + bit) { x -= r + bit; r = (r >> 1) + bit; }
-    else r >>= 1;
-    bit >>= 2;
-  }
+  const uint64_t x = (uint64_t)xs;
+  uint64_t r = (uint64_t)sqrt((double)x);
+  if (r > 3037000499ull) r = 3037000499ull;  // floor(sqrt(2^63 - 1))
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
   return (int64_t)r;
 }
 
