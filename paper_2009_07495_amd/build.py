@@ -43,7 +43,8 @@ def build(verbose: bool = False) -> str:
         if verbose and out.strip():
             print(out)
     tmp = LIB + ".tmp"
-    rc, out = _run([HIPCC, *FLAGS, "-shared", *objs, "-o", tmp])
+    # roctx: host trace ranges of the solvers
+    rc, out = _run([HIPCC, *FLAGS, "-shared", *objs, "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-o", tmp])
     if rc != 0:
         raise RuntimeError(f"link failed ({rc}):\n{out}")
     os.replace(tmp, LIB)

@@ -10,6 +10,7 @@
 
 #include "igm_launch.hpp"
 #include "igm_par.hpp"
+#include "igm_trace.hpp"
 
 using namespace igm;
 
@@ -269,6 +270,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 // Fig. 1 on the device; x is a device vector of n doubles.
 igm_status solve_dev(igm_system *s, double *x) {
+  TraceRange trace_solve("igm solve");
   auto t0 = std::chrono::steady_clock::now();
   const igm_policy &p = s->pol;
   s->hist_ro.clear(); s->hist_rs.clear(); s->hist_gamma.clear(); s->hist_rho.clear(); s->hist_jstar.clear();
@@ -287,6 +289,7 @@ igm_status solve_dev(igm_system *s, double *x) {
   IGM_HIP(hipEventCreate(&e1));
   double *hp = s->h_pinned;
   for (int k = 0;; ++k) {
+    TraceRange trace_refinement("igm refinement");
     // top of refinement k+1: residuals, relres, gamma
     IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
     IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
@@ -312,7 +315,10 @@ igm_status solve_dev(igm_system *s, double *x) {
     CycleState cs;
     for (;;) {  // the call, repeated from the same v1 while a retry can adjust a shift
       IGM_HIP(hipEventRecord(e0, s->stream));
-      IGM_TRY(launch_cycle(s, a));
+      {
+        TraceRange trace_call("igm int-GMRES call");
+        IGM_TRY(launch_cycle(s, a));
+      }
       IGM_HIP(hipEventRecord(e1, s->stream));
       IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
       IGM_HIP(hipMemcpyAsync(hp, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));

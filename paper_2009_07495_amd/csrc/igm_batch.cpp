@@ -16,6 +16,7 @@
 
 #include "igm_batch.hpp"
 #include "igm_par.hpp"
+#include "igm_trace.hpp"
 #include "igm_team.hpp"
 
 using namespace igm;
@@ -377,6 +378,7 @@ igm_status apply_shape(igm_batch *bt, int block, int rows) {
 }
 
 igm_status run(igm_batch *bt, double *x_dev) {
+  TraceRange trace_run("igm batch solve");
   auto t0 = std::chrono::steady_clock::now();
   if (bt->x_bound != x_dev) {  // point the records at this solution vector
     for (int32_t s = 0; s < bt->nsys; ++s) bt->sys[s].x = x_dev + bt->x_off[s];

@@ -37,6 +37,7 @@
 
 #include "igm_batch.hpp"
 #include "igm_par.hpp"
+#include "igm_trace.hpp"
 #include "igm_team.hpp"
 
 using namespace igm;
@@ -188,6 +189,7 @@ void setup_worker(igm_server *sv) {
       r = sv->to_prepare.front();
       sv->to_prepare.pop_front();
     }
+    TraceRange trace_setup("igm request setup");
     HostSystem hs;
     igm_status st = prepare_system(r->n, r->rp.data(), r->col.data(), r->val.data(), r->b.data(), r->pol, hs);
     hvec<int64_t>().swap(r->rp);
