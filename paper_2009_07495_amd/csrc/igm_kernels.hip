@@ -246,7 +246,8 @@ __global__ __launch_bounds__(kB) void k_upper_level(CycleArgs a, int32_t lo, int
 // h = shl(isqrt(sum asr(w, b)^2), b)) in one launch: each workgroup adds its
 // rows into an exact Acc and stores it with device-coherent stores; the last
 // workgroup to take a ticket adds all of them and finishes. The ticket word
-// is zero before the launch and the last workgroup sets it back to zero.
+// is zero before the launch (the launcher clears it) and the last workgroup
+// sets it back to zero.
 constexpr int kRB = 512;     // threads per workgroup of the standalone reductions
 constexpr int kRUnroll = 8;  // elements in flight per thread
 
@@ -430,6 +431,10 @@ hipError_t launch_reduce(hipStream_t st, int64_t n, const int64_t *w, const int6
   const int64_t want = (n + (int64_t)kRB * kRUnroll - 1) / ((int64_t)kRB * kRUnroll);
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kMaxReduceParts));
   unsigned *ticket = (unsigned *)(parts + kMaxReduceParts);
+  // the kernel leaves the ticket at zero; clearing it here as well keeps a
+  // launch that never finished from spoiling the next one
+  hipError_t e = hipMemsetAsync(ticket, 0, sizeof(unsigned), st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(kRB), 0, st, n, w, v, b, df, mode, (Acc *)parts, ticket, out, state,
                      code);
   return hipGetLastError();
