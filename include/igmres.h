@@ -103,7 +103,14 @@ typedef struct {
    * IGM_ERR_OVERFLOW as without retries. Adjusted shifts stay in the system's
    * policy (igm_get_policy) for later solves. */
   int32_t shift_retry;
-  int32_t reserved_[5];
+  /* 0: scaling of eq. (eq1) (rows by Dhat, the paper's setting); 1: eq. (eq2)
+   * with D1 = D2 = Dhat^(1/2) (the paper leaves D1, D2 open; this choice keeps
+   * a symmetric matrix symmetric): A = D1^-1 Ahat D2^-1, b = D1^-1 bhat,
+   * computed as a_ij = ahat_ij / (s_i s_j), s = sqrt(dhat); the scaled
+   * residual of Fig. 1 is D1^-1 (bhat - Ahat xhat) and each correction
+   * returns through D2^-1. Single-system solver only. */
+  int32_t two_sided;
+  int32_t reserved_[4];
 } igm_policy;
 
 /* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,

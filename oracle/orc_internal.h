@@ -14,8 +14,8 @@ struct orc_system {
   int32_t *col;
   int64_t *diag_pos; /* position of the diagonal entry in each row, -1 if absent */
   double *ahat, *bhat;
-  /* initial scaling, eqs. (eq1), (eq3) */
-  double *dhat, *a, *b;
+  /* initial scaling, eqs. (eq1)/(eq2), (eq3); cscale = sqrt(dhat) for eq. (eq2), else NULL */
+  double *dhat, *a, *b, *cscale;
   /* integer matrices A_0..A_p on the input pattern, eq. (A) */
   int32_t nterms; /* p + 1 */
   int32_t alpha[ORC_MAX_TERMS + 1];

@@ -45,7 +45,8 @@ void orc_residual(const orc_system *s, const double *x, double *r, double *rhat)
       acc = acc + s->a[e] * x[s->col[e]];
       acch = acch + s->ahat[e] * x[s->col[e]];
     }
-    if (r) r[i] = s->b[i] - acc;
+    /* eq. (eq2): x holds xhat; the scaled residual is D1^-1 (bhat - Ahat xhat) */
+    if (r) r[i] = s->cscale ? (s->bhat[i] - acch) / s->cscale[i] : s->b[i] - acc;
     if (rhat) rhat[i] = s->bhat[i] - acch;
   }
 }
@@ -198,7 +199,8 @@ int orc_solve(orc_system *s, double *x, orc_stats *st) {
     }
     if (t.jstar == 0) { st->status = ORC_ERR_BREAKDOWN; break; }
     orc_cycle_update(s, &t, rho, xk);
-    for (int64_t l = 0; l < n; ++l) x[l] = x[l] + gamma * xk[l];
+    /* eq. (update); with eq. (eq2) the correction returns to xhat = D2^-1 x */
+    for (int64_t l = 0; l < n; ++l) x[l] = x[l] + gamma * (s->cscale ? xk[l] / s->cscale[l] : xk[l]);
   }
 done:
   free(r); free(rh); free(bk); free(r0); free(xk); free(v1);

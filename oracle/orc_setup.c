@@ -23,6 +23,7 @@ static int check_policy(const orc_policy *p) {
   if (bad_shift(p->b_cs_num, 62) || bad_shift(p->b_cs_den, 62)) return 1;
   if (p->max_refine < 0) return 1;
   if (p->shift_retry < 0 || p->shift_retry > 64) return 1;
+  if (p->two_sided < 0 || p->two_sided > 1) return 1;
   if (!(p->tol >= 0.0)) return 1;
   return 0;
 }
@@ -30,14 +31,17 @@ static int check_policy(const orc_policy *p) {
 void orc_destroy(orc_system *s) {
   if (!s) return;
   free(s->row_ptr); free(s->col); free(s->diag_pos); free(s->ahat); free(s->bhat);
-  free(s->dhat); free(s->a); free(s->b);
+  free(s->dhat); free(s->a); free(s->b); free(s->cscale);
   for (int l = 0; l <= ORC_MAX_TERMS; ++l) free(s->abar[l]);
   free(s->lu); free(s->fac); free(s->ldiag); free(s->udiag);
   free(s);
 }
 
 /* Eq. (eq3): dhat_i = max_j |ahat_ij| / 2^alpha_a; eq. (eq1): A = Dhat^-1 Ahat,
- * b = Dhat^-1 bhat, each entry obtained by one FP64 division. */
+ * b = Dhat^-1 bhat, each entry obtained by one FP64 division.
+ * Eq. (eq2) (two_sided; the paper leaves D1 and D2 open, this reading takes
+ * D1 = D2 = Dhat^(1/2) so a symmetric Ahat stays symmetric): s_i = sqrt(dhat_i),
+ * a_ij = ahat_ij / (s_i * s_j), b_i = bhat_i / s_i, x = D2 xhat. */
 static int scale(orc_system *s) {
   for (int64_t i = 0; i < s->n; ++i) {
     double mu = 0.0;
@@ -47,8 +51,19 @@ static int scale(orc_system *s) {
     double d = ldexp(mu, -s->pol.alpha_a);
     if (d == 0.0 || !isfinite(d)) return ORC_ERR_RANGE;
     s->dhat[i] = d;
-    for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) s->a[e] = s->ahat[e] / d;
-    s->b[i] = s->bhat[i] / d;
+    if (!s->cscale) {
+      for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) s->a[e] = s->ahat[e] / d;
+      s->b[i] = s->bhat[i] / d;
+    } else {
+      s->cscale[i] = sqrt(d);
+    }
+  }
+  if (s->cscale) {
+    for (int64_t i = 0; i < s->n; ++i) {
+      for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e)
+        s->a[e] = s->ahat[e] / (s->cscale[i] * s->cscale[s->col[e]]);
+      s->b[i] = s->bhat[i] / s->cscale[i];
+    }
   }
   return ORC_OK;
 }
@@ -210,7 +225,9 @@ int orc_create(int64_t n, const int64_t *row_ptr, const int32_t *col, const doub
   s->dhat = (double *)malloc(sizeof(double) * n);
   s->a = (double *)malloc(sizeof(double) * nz);
   s->b = (double *)malloc(sizeof(double) * n);
-  if (!s->row_ptr || !s->col || !s->diag_pos || !s->ahat || !s->bhat || !s->dhat || !s->a || !s->b) {
+  if (pol->two_sided) s->cscale = (double *)malloc(sizeof(double) * n);
+  if (!s->row_ptr || !s->col || !s->diag_pos || !s->ahat || !s->bhat || !s->dhat || !s->a || !s->b ||
+      (pol->two_sided && !s->cscale)) {
     orc_destroy(s);
     return ORC_ERR_ARG;
   }

@@ -101,6 +101,7 @@ CycleArgs make_args(igm_system *s) {
   a.phase_clock = p.phase_clock;
   a.x = nullptr;
   a.scal = s->d_scal;
+  a.cscale = s->d_cscale;
   return a;
 }
 
@@ -207,6 +208,8 @@ igm_status build(igm_system *s) {
   IGM_TRY(upload(s, s->d_ahat, s->ahat));
   IGM_TRY(upload(s, s->d_b, h.b));
   IGM_TRY(upload(s, s->d_bhat, s->bhat));
+  s->d_cscale = nullptr;
+  if (s->pol.two_sided) IGM_TRY(upload(s, s->d_cscale, h.cscale));
   IGM_TRY(upload(s, s->d_sell_off, h.sell_off));
   IGM_TRY(upload(s, s->d_sell_w, h.sell_w));
   IGM_TRY(upload(s, s->d_sell_col, h.sell_col));
@@ -268,6 +271,18 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Two timing events, destroyed with the object.
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair &) = delete;
+  EventPair &operator=(const EventPair &) = delete;
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 // Fig. 1 on the device; x is a device vector of n doubles.
 igm_status solve_dev(igm_system *s, double *x) {
   TraceRange trace_solve("igm solve");
@@ -284,16 +299,17 @@ igm_status solve_dev(igm_system *s, double *x) {
   CycleArgs a = make_args(s);
   a.update = 1;
   a.x = x;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  IGM_HIP(hipEventCreate(&e0));
-  IGM_HIP(hipEventCreate(&e1));
+  EventPair ev;  // destroyed on every return path
+  IGM_HIP(hipEventCreate(&ev.e0));
+  IGM_HIP(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   double *hp = s->h_pinned;
   for (int k = 0;; ++k) {
     TraceRange trace_refinement("igm refinement");
     // top of refinement k+1: residuals, relres, gamma
     IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
     IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
-                            s->d_r, s->d_rhat, s->d_red));
+                            s->d_cscale, s->d_r, s->d_rhat, s->d_red));
     IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_r, s->d_red + kRedMuR, s->d_red + kRedSumR));
     IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_rhat, s->d_red + kRedMuRhat, s->d_red + kRedSumRhat));
     IGM_HIP(launch_fin_residual(s->stream, s->d_red, s->d_scal + kScalNormB, s->d_scal));
@@ -344,8 +360,6 @@ igm_status solve_dev(igm_system *s, double *x) {
     if (cs.first_ovf != kNoEvent) { st.first_ovf = cs.first_ovf; status = IGM_ERR_OVERFLOW; break; }
     if (cs.jstar == 0) { status = IGM_ERR_BREAKDOWN; break; }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   st.status = status;
   st.time_solve_ms = ms_since(t0);
   return status;
@@ -632,8 +646,8 @@ igm_status igm_normalize(igm_system *s, const int64_t *w, int64_t h, int64_t *v,
 igm_status igm_residual(igm_system *s, const double *x, double *r, double *rhat) {
   if (!s || !x || !r || !rhat) return IGM_ERR_ARG;
   IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
-  IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x, r, rhat,
-                          s->d_red));
+  IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
+                          s->d_cscale, r, rhat, s->d_red));
   IGM_HIP(hipStreamSynchronize(s->stream));
   return IGM_OK;
 }

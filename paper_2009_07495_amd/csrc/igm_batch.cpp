@@ -121,7 +121,7 @@ igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col,
   igm_status st = check_policy(pol);
   if (st != IGM_OK) return st;
   if (pol.m > kMaxBatchM) return IGM_ERR_UNSUPPORTED;
-  if (pol.shift_retry != 0) return IGM_ERR_UNSUPPORTED;  // retries: single-system solver only
+  if (pol.shift_retry != 0 || pol.two_sided != 0) return IGM_ERR_UNSUPPORTED;  // single-system solver only
   st = validate_csr(n, row_ptr, col, val, b);
   if (st != IGM_OK) return st;
   out.n = n;

@@ -319,7 +319,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     if (row < a.n) {
       double acc = 0.0;
       for (int i = 0; i < js; ++i) acc = acc + sy[i] * ldexp((double)a.V[(size_t)i * a.npad + row], -df);
-      a.x[row] = a.x[row] + gamma * acc;
+      a.x[row] = a.x[row] + gamma * (a.cscale ? acc / a.cscale[row] : acc);
     }
   }
 }

@@ -58,7 +58,8 @@ struct CycleState {
 
 // Host-side setup products (all derived from the FP64 input).
 struct HostSetup {
-  hvec<double> dhat, a, b;                     // eq. (eq1), (eq3)
+  hvec<double> dhat, a, b;                     // eq. (eq1)/(eq2), (eq3)
+  hvec<double> cscale;                         // eq. (eq2): sqrt(dhat); empty for eq. (eq1)
   int nterms = 0;
   int32_t alpha[kMaxTerms] = {0};
   std::vector<hvec<int64_t>> abar;             // eq. (A), on the input pattern
@@ -143,6 +144,7 @@ struct CycleArgs {
   int32_t phase_clock;       // record the phase clocks of workgroup 0
   double *x;
   const double *scal;        // device: {gamma, rho}
+  const double *cscale;      // eq. (eq2): the update adds gamma (x^(k)_i / s_i); null for eq. (eq1)
 };
 
 const void *cycle_kernel(int block, int R, int pre);
@@ -165,6 +167,7 @@ struct igm_system {
   int64_t *d_row_ptr = nullptr;
   int32_t *d_col = nullptr;
   double *d_a = nullptr, *d_ahat = nullptr, *d_b = nullptr, *d_bhat = nullptr;
+  double *d_cscale = nullptr;  // eq. (eq2) only
   int64_t *d_sell_off = nullptr;
   int32_t *d_sell_w = nullptr, *d_sell_col = nullptr;
   int64_t *d_sell_val[igm::kMaxTerms] = {nullptr};

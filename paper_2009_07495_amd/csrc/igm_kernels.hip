@@ -44,12 +44,15 @@ __global__ __launch_bounds__(kB) void k_residual(int64_t n, const int64_t *__res
                                                  const int32_t *__restrict__ col, const double *__restrict__ a,
                                                  const double *__restrict__ ahat, const double *__restrict__ b,
                                                  const double *__restrict__ bhat, const double *__restrict__ x,
-                                                 double *r, double *rhat, unsigned long long *red) {
+                                                 const double *__restrict__ cscale, double *r, double *rhat,
+                                                 unsigned long long *red) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   unsigned long long m0 = 0, m1 = 0;
   if (i < n) {
     double ri, rhi;
     residual_row(rp[i], rp[i + 1], col, a, ahat, x, b[i], bhat[i], ri, rhi);
+    // eq. (eq2): x holds xhat and the scaled residual is D1^-1 (bhat - Ahat xhat)
+    if (cscale) ri = rhi / cscale[i];
     r[i] = ri;
     rhat[i] = rhi;
     m0 = dbits(fabs(ri));
@@ -330,10 +333,11 @@ static inline unsigned grid_stride_blocks(int64_t n) {
 }
 
 hipError_t launch_residual(hipStream_t st, int64_t n, const int64_t *rp, const int32_t *col, const double *a,
-                           const double *ahat, const double *b, const double *bhat, const double *x, double *r,
-                           double *rhat, unsigned long long *red) {
+                           const double *ahat, const double *b, const double *bhat, const double *x,
+                           const double *cscale, double *r, double *rhat, unsigned long long *red) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x, r, rhat, red);
+  hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x, cscale, r,
+                     rhat, red);
   return hipGetLastError();
 }
 

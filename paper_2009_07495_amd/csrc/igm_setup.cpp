@@ -72,6 +72,7 @@ igm_status check_policy(const igm_policy &p) {
   if (p.max_refine < 0 || !(p.tol >= 0.0) || p.grid_blocks < 0) return IGM_ERR_ARG;
   if (p.phase_clock < 0 || p.phase_clock > 1) return IGM_ERR_ARG;
   if (p.shift_retry < 0 || p.shift_retry > 64) return IGM_ERR_ARG;
+  if (p.two_sided < 0 || p.two_sided > 1) return IGM_ERR_ARG;
   return IGM_OK;
 }
 
@@ -113,11 +114,15 @@ static inline int64_t cast_i64(double y, bool &bad) {
 
 // eq. (eq3): dhat_i = max_j |ahat_ij| / 2^alpha_a; eq. (eq1): A = Dhat^-1 Ahat,
 // b = Dhat^-1 bhat, one division per entry.
-static igm_status scale_rows(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<double> &ahat,
-                             const hvec<double> &bhat, int alpha, HostSetup &h) {
+// Two-sided (eq. (eq2), D1 = D2 = Dhat^(1/2)): s_i = sqrt(dhat_i), a_ij =
+// ahat_ij / (s_i s_j), b_i = bhat_i / s_i; s is kept in h.cscale.
+static igm_status scale_rows(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
+                             const hvec<double> &ahat, const hvec<double> &bhat, int alpha, bool two_sided,
+                             HostSetup &h) {
   h.dhat.resize(n);
   h.a.resize(ahat.size());
   h.b.resize(n);
+  if (two_sided) h.cscale.resize(n);
   FirstError fe(nt);
   par_ranges(nt, n, [&](int c, int64_t lo, int64_t hi) {
     for (int64_t i = lo; i < hi; ++i) {
@@ -127,11 +132,23 @@ static igm_status scale_rows(int nt, int64_t n, const hvec<int64_t> &rp, const h
       double d = ldexp(mu, -alpha);
       if (d == 0.0 || !isfinite(d)) return fe.set(c, i, IGM_ERR_RANGE);
       h.dhat[i] = d;
+      if (two_sided) {
+        h.cscale[i] = sqrt(d);
+        continue;
+      }
       for (int64_t e = rp[i]; e < rp[i + 1]; ++e) h.a[e] = ahat[e] / d;
       h.b[i] = bhat[i] / d;
     }
   });
-  return fe.first();
+  const igm_status st = fe.first();
+  if (st != IGM_OK || !two_sided) return st;
+  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) h.a[e] = ahat[e] / (h.cscale[i] * h.cscale[col[e]]);
+      h.b[i] = bhat[i] / h.cscale[i];
+    }
+  });
+  return IGM_OK;
 }
 
 // Sec. IV-B: A_0 = trunc(A); remainders R_l give alpha_l = alpha_a -
@@ -403,7 +420,7 @@ igm_status host_setup(int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &c
   SetupRegion region;
   const int nt = setup_thread_count();
   h = HostSetup();
-  igm_status st = scale_rows(nt, n, rp, ahat, bhat, pol.alpha_a, h);
+  igm_status st = scale_rows(nt, n, rp, col, ahat, bhat, pol.alpha_a, pol.two_sided != 0, h);
   if (st != IGM_OK) return st;
   st = split_terms(nt, pol, h);
   if (st != IGM_OK) return st;

@@ -227,6 +227,27 @@ def test_shift_retry_not_in_batches(torch):
     assert e.value.status == B.ERR_UNSUPPORTED
 
 
+@pytest.mark.parametrize("preset,gen", [("paper_noprec", lambda: W.poisson2d(37, 29)),
+                                        ("jacobi", lambda: W.convdiff3d(14, 13, 12, seed=33)),
+                                        ("paper_ilu", lambda: W.random27(12, 11, 10, seed=34))])
+def test_two_sided_scaling_matches_oracle(orc, torch, preset, gen):
+    """Eq. (eq2) with D1 = D2 = Dhat^(1/2) (igm_policy.two_sided): whole solves
+    bit for bit against the oracle, residual history included."""
+    s = gen()
+    xo, so = orc.OracleSystem.from_system(s, orc.policy(preset, two_sided=1)).solve()
+    g = B.System.from_system(s, preset, two_sided=1)
+    x, st = g.solve()
+    assert st == so["status"] == B.OK
+    assert g.stats()["refinements"] == so["refinements"]
+    h = g.history()
+    assert np.array_equal(h["relres_orig"], so["hist_relres_orig"])
+    assert np.array_equal(h["relres_scaled"], so["hist_relres_scaled"])
+    assert np.array_equal(x, xo)
+    with pytest.raises(B.IgmError) as e:
+        B.Batch([s], preset, two_sided=1)
+    assert e.value.status == B.ERR_UNSUPPORTED
+
+
 def test_abi_error_statuses_match_oracle(orc, torch):
     """The failure statuses of the C ABI, forced from the host, equal the
     oracle's: an all-zero row, a NaN entry, unsorted columns, a structurally

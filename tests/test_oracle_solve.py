@@ -189,3 +189,45 @@ def test_shift_retry_is_inert_without_overflow(orc):
     xa, sa = make(orc, s, "jacobi", m=20).solve()
     xb, sb = make(orc, s, "jacobi", m=20, shift_retry=16).solve()
     assert sb["shift_retries"] == 0 and np.array_equal(xa, xb) and sa["refinements"] == sb["refinements"]
+
+
+# ---- two-sided scaling, eq. (eq2): a reading (the paper leaves D1 and D2
+# open); D1 = D2 = Dhat^(1/2) with Dhat from eq. (eq3), see orc_setup.c ----
+
+def test_two_sided_scaling_keeps_symmetry(orc):
+    import scipy.sparse as sp
+
+    s = W.poisson2d(9, 7)
+    o = make(orc, s, "paper_noprec", two_sided=1)
+    d, a, b = o.scaled()
+    A = sp.csr_matrix((a, s.col, s.row_ptr), shape=(s.n, s.n))
+    assert (A != A.T).nnz == 0  # bit for bit
+    # b = D1^-1 bhat, and A = D1^-1 Ahat D2^-1 with D1 = D2 = diag(sqrt(dhat))
+    sq = np.sqrt(d)
+    assert np.array_equal(b, s.b / sq)
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    assert np.array_equal(a, s.val / (sq[rows] * sq[s.col]))
+
+
+@pytest.mark.parametrize("preset,gen", [("paper_noprec", lambda: W.poisson2d(20)),
+                                        ("jacobi", lambda: W.convdiff3d(8, seed=1)),
+                                        ("paper_ilu", lambda: W.random27(5, 4, 3, seed=65))])
+def test_two_sided_scaling_solves(orc, preset, gen):
+    s = gen()
+    x, st = make(orc, s, preset, two_sided=1).solve()
+    assert st["status"] == orc.OK and st["relres_orig"] < 1e-10
+    xd = np.linalg.solve(s.dense(), s.b)
+    assert np.abs(x - xd).max() <= 1e-9 * np.abs(xd).max()
+
+
+def test_two_sided_equals_row_scaling_when_every_dhat_is_one(orc):
+    """Row maxima equal to 2^alpha_a give Dhat = I: both scalings are then the
+    identity and the two solves must agree bit for bit (x, refinements,
+    residual history)."""
+    s = W.poisson2d(10)
+    sc = W.System("poisson_2^14", s.n, s.row_ptr, s.col, s.val * 2.0 ** 14, s.b * 2.0 ** 14)
+    x1, s1 = make(orc, sc, "paper_noprec").solve()
+    x2, s2 = make(orc, sc, "paper_noprec", two_sided=1).solve()
+    assert np.array_equal(x1, x2) and s1["refinements"] == s2["refinements"]
+    assert np.array_equal(s1["hist_relres_orig"], s2["hist_relres_orig"])
+    assert np.array_equal(s1["hist_relres_scaled"], s2["hist_relres_scaled"])
