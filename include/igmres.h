@@ -110,7 +110,14 @@ typedef struct {
    * residual of Fig. 1 is D1^-1 (bhat - Ahat xhat) and each correction
    * returns through D2^-1. Single-system solver only. */
   int32_t two_sided;
-  int32_t reserved_[4];
+  /* With precond = IGM_PRE_ILU0 only: 1 = build the factors from the
+   * Gauss-Seidel splitting M = D + L_A instead of ILU(0) (the paper reports a
+   * Gauss-Seidel preconditioner, Sec. VII-D, without its construction; here M
+   * is written as L D U with L = I + L_A D^-1 and U = I and split as in
+   * Sec. VI, so Lbar carries (a_ij / a_jj)|a_jj|^(1/2) below the diagonal and
+   * Ubar is diagonal). Every solver supports it. */
+  int32_t gauss_seidel;
+  int32_t reserved_[3];
 } igm_policy;
 
 /* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,

@@ -41,14 +41,15 @@ class Policy(C.Structure):
     _fields_ = [(name, C.c_int32) for name in (
         "df", "alpha_a", "s_terms", "m", "precond", "b_dot", "b_axpy", "b_norm", "b_div_num", "b_div_den",
         "b_rot", "b_tmp", "b_cs_num", "b_cs_den", "max_refine", "shift_retry")] + [("gtol", C.c_int64), ("tol", C.c_double),
-                                                                            ("two_sided", C.c_int32), ("pad_", C.c_int32)]
+                                                                            ("two_sided", C.c_int32), ("gauss_seidel", C.c_int32)]
 
 
 # Shift settings of the paper: Table IV (no preconditioner) and Table VI (ILU),
 # with d_f = 30, WL = 64, s = 0, alpha_a = 16 / 32 (Sec. VII-B, VII-C).
 # "jacobi" is this implementation's extension: the ILU construction on the
 # diagonal-only pattern with the Table VI shifts.
-_BASE = dict(df=30, s_terms=0, m=30, max_refine=2000, shift_retry=0, gtol=-1, tol=1e-10, two_sided=0)
+_BASE = dict(df=30, s_terms=0, m=30, max_refine=2000, shift_retry=0, gtol=-1, tol=1e-10, two_sided=0,
+             gauss_seidel=0)
 PRESETS = {
     "paper_noprec": dict(_BASE, alpha_a=16, precond=PRE_NONE, b_dot=16, b_axpy=16, b_norm=16, b_div_num=16,
                          b_div_den=14, b_rot=16, b_tmp=16, b_cs_num=16, b_cs_den=14),

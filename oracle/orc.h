@@ -75,7 +75,7 @@ typedef struct {
   int64_t gtol;        /* stop a cycle early when |g_{j+1}| <= gtol; < 0: never */
   double tol;          /* FP64 relative residual target on the original system */
   int32_t two_sided;   /* 0: eq. (eq1); 1: eq. (eq2) with D1 = D2 = Dhat^(1/2) (see orc_setup.c) */
-  int32_t pad_;
+  int32_t gauss_seidel; /* with ORC_PRE_ILU0: the Gauss-Seidel splitting instead of ILU(0) (orc_setup.c) */
 } orc_policy;
 
 /* Overflow event code: (step j, stage, sub-index), ordered as executed.

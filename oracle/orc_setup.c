@@ -24,6 +24,8 @@ static int check_policy(const orc_policy *p) {
   if (p->max_refine < 0) return 1;
   if (p->shift_retry < 0 || p->shift_retry > 64) return 1;
   if (p->two_sided < 0 || p->two_sided > 1) return 1;
+  if (p->gauss_seidel < 0 || p->gauss_seidel > 1) return 1;
+  if (p->gauss_seidel && p->precond != ORC_PRE_ILU0) return 1;
   if (!(p->tol >= 0.0)) return 1;
   return 0;
 }
@@ -137,6 +139,31 @@ static int ilu0(orc_system *s) {
   return rc;
 }
 
+/* Gauss-Seidel splitting (policy gauss_seidel; a reading: the paper reports
+ * a Gauss-Seidel preconditioner, Sec. VII-D, without its construction):
+ * M = D + L_A (the diagonal and the strict lower part of A) written as
+ * L D U with L = I + L_A D^-1 and U = I. The multipliers below the diagonal
+ * are a_ik / a_kk, nothing is eliminated and no entry remains above the
+ * diagonal; the split of eqs. (dl)-(u1) then gives Lbar and a diagonal Ubar. */
+static int gs_split(orc_system *s) {
+  double *lu = s->lu;
+  memcpy(lu, s->a, sizeof(double) * s->nnz);
+  for (int64_t i = 0; i < s->n; ++i) {
+    for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
+      int64_t k = s->col[e];
+      if (k < i) {
+        double piv = s->a[s->diag_pos[k]];
+        if (piv == 0.0) return ORC_ERR_ZERO_PIVOT;
+        lu[e] = s->a[e] / piv;
+      } else if (k > i) {
+        lu[e] = 0.0;
+      }
+    }
+    if (lu[s->diag_pos[i]] == 0.0) return ORC_ERR_ZERO_PIVOT;
+  }
+  return ORC_OK;
+}
+
 /* Eqs. (dl), (dl2), (l1), (u1): D_l = |d|^1/2, D_u = sgn(d)|d|^1/2,
  * Ltilde = L D_l, Utilde = D_u U (U with unit diagonal, i.e. the stored upper
  * entries divided by d_i), then each entry cast to int64. */
@@ -181,7 +208,7 @@ static int build_precond(orc_system *s) {
   if (s->pol.precond == ORC_PRE_ILU0) {
     s->lu = (double *)malloc(sizeof(double) * (s->nnz ? s->nnz : 1));
     if (!s->lu) { free(dv); return ORC_ERR_ARG; }
-    rc = ilu0(s);
+    rc = s->pol.gauss_seidel ? gs_split(s) : ilu0(s);
     if (rc == ORC_OK) {
       for (int64_t i = 0; i < n; ++i) dv[i] = s->lu[s->diag_pos[i]];
       rc = cast_factors(s, dv, 1);

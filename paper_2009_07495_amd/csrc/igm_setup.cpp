@@ -73,6 +73,8 @@ igm_status check_policy(const igm_policy &p) {
   if (p.phase_clock < 0 || p.phase_clock > 1) return IGM_ERR_ARG;
   if (p.shift_retry < 0 || p.shift_retry > 64) return IGM_ERR_ARG;
   if (p.two_sided < 0 || p.two_sided > 1) return IGM_ERR_ARG;
+  if (p.gauss_seidel < 0 || p.gauss_seidel > 1) return IGM_ERR_ARG;
+  if (p.gauss_seidel && p.precond != IGM_PRE_ILU0) return IGM_ERR_ARG;
   return IGM_OK;
 }
 
@@ -278,10 +280,35 @@ static igm_status ilu0_fp(int nt, int64_t n, const hvec<int64_t> &rp, const hvec
   return zero_level.load() != INT32_MAX ? IGM_ERR_ZERO_PIVOT : IGM_OK;
 }
 
+// Gauss-Seidel splitting (policy gauss_seidel): M = D + L_A as L D U with
+// L = I + L_A D^-1, U = I: below the diagonal a_ik / a_kk, nothing
+// eliminated, nothing above; every row is independent.
+static igm_status gs_split_fp(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
+                              HostSetup &h) {
+  h.lu.resize(rp[n]);
+  std::atomic<bool> zero{false};
+  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int64_t k = col[e];
+        if (k < i) {
+          const double piv = h.a[h.diag_pos[k]];
+          if (piv == 0.0) zero = true;
+          h.lu[e] = h.a[e] / piv;
+        } else {
+          h.lu[e] = k == i ? h.a[e] : 0.0;
+        }
+      }
+      if (h.a[h.diag_pos[i]] == 0.0) zero = true;
+    }
+  });
+  return zero ? IGM_ERR_ZERO_PIVOT : IGM_OK;
+}
+
 // eqs. (dl), (dl2), (l1), (u1): Lbar = trunc(L |D|^1/2), Ubar = trunc(sgn(D)
 // |D|^1/2 U) with U unit upper (stored entries divided by the pivot).
 static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
-                               const hvec<double> &piv, bool offdiag, HostSetup &h) {
+                               const hvec<double> &piv, bool offdiag, bool upper, HostSetup &h) {
   h.ldiag.resize(n);
   h.udiag.resize(n);
   hvec<double> sq(n);
@@ -302,7 +329,7 @@ static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const
         int64_t nl = 0, nu = 0;
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
           nl += col[e] < i;
-          nu += col[e] > i;
+          nu += upper && col[e] > i;
         }
         h.lptr[i + 1] = nl;
         h.uptr[i + 1] = nu;
@@ -333,7 +360,7 @@ static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const
           if (j < i) {
             h.lcol[pl] = j;
             h.lval[pl++] = cast_i64(h.lu[e] * sq[j], bad);
-          } else if (j > i) {
+          } else if (upper && j > i) {
             h.ucol[pu] = j;
             h.uval[pu++] = cast_i64(su * (h.lu[e] / piv[i]), bad);
           }
@@ -435,13 +462,13 @@ igm_status host_setup(int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &c
       if (h.diag_pos[i] < 0) return IGM_ERR_ZERO_PIVOT;
     hvec<double> piv(n);
     if (pol.precond == IGM_PRE_ILU0) {
-      st = ilu0_fp(nt, n, rp, col, h);
+      st = pol.gauss_seidel ? gs_split_fp(nt, n, rp, col, h) : ilu0_fp(nt, n, rp, col, h);
       if (st != IGM_OK) return st;
       for (int64_t i = 0; i < n; ++i) piv[i] = h.lu[h.diag_pos[i]];
     } else {
       for (int64_t i = 0; i < n; ++i) piv[i] = h.a[h.diag_pos[i]];
     }
-    st = cast_factors(nt, n, rp, col, piv, pol.precond == IGM_PRE_ILU0, h);
+    st = cast_factors(nt, n, rp, col, piv, pol.precond == IGM_PRE_ILU0, !pol.gauss_seidel, h);
     if (st != IGM_OK) return st;
     level_sets(n, h);
   }

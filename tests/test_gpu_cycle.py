@@ -248,6 +248,25 @@ def test_two_sided_scaling_matches_oracle(orc, torch, preset, gen):
     assert e.value.status == B.ERR_UNSUPPORTED
 
 
+@pytest.mark.parametrize("gen", [lambda: W.convdiff2d(91, 77, seed=41), lambda: W.random27(20, 20, 12, seed=42),
+                                 lambda: W.random27(40, 40, 40, seed=43)])
+def test_gauss_seidel_matches_oracle(orc, torch, gen):
+    """The Gauss-Seidel splitting (igm_policy.gauss_seidel) through the
+    single-system and the batched solver: whole solves bit for bit against the
+    oracle (the last case, 64,000 rows, builds its factors on several host
+    threads and sweeps with the level counters)."""
+    s = gen()
+    xo, so = orc.OracleSystem.from_system(s, orc.policy("paper_ilu", gauss_seidel=1)).solve()
+    g = B.System.from_system(s, "paper_ilu", gauss_seidel=1)
+    x, st = g.solve()
+    assert st == so["status"] == B.OK and g.stats()["refinements"] == so["refinements"]
+    assert g.stats()["levels_bwd"] == 1  # Ubar is diagonal
+    assert np.array_equal(x, xo)
+    bt = B.Batch([s], "paper_ilu", gauss_seidel=1)
+    xb, stb = bt.solve()
+    assert stb == B.OK and np.array_equal(xb, xo)
+
+
 def test_abi_error_statuses_match_oracle(orc, torch):
     """The failure statuses of the C ABI, forced from the host, equal the
     oracle's: an all-zero row, a NaN entry, unsorted columns, a structurally

@@ -198,3 +198,59 @@ def test_presets_match_paper_tables(orc):
         assert orc.PRESETS[preset][key] == int(val), (preset, key)
         n += 1
     assert n == 24
+
+
+# ---- Gauss-Seidel splitting (a reading: the paper reports a Gauss-Seidel
+# preconditioner, Sec. VII-D, without its construction; see orc_setup.c) ----
+
+def test_gauss_seidel_factors_reproduce_the_splitting(orc):
+    """Lbar Ubar approximates M = D + L_A (diagonal and strict lower part of
+    the scaled A) within the truncation of the two casts, with nothing above
+    the diagonal; Ubar is diagonal."""
+    s = W.convdiff2d(9, 7, seed=5)
+    o = orc.OracleSystem.from_system(s, orc.policy("paper_ilu", gauss_seidel=1))
+    fac, ld, ud = o.precond()
+    _, a, _ = o.scaled()
+    n = s.n
+    rows = np.repeat(np.arange(n), np.diff(s.row_ptr))
+    upper = s.col > rows
+    assert np.all(fac[upper] == 0)
+    L = np.zeros((n, n))
+    L[rows[~upper & (s.col != rows)], s.col[~upper & (s.col != rows)]] = fac[~upper & (s.col != rows)]
+    L[np.arange(n), np.arange(n)] = ld
+    M = L @ np.diag(ud.astype(float))
+    Aful = np.zeros((n, n))
+    Aful[rows, s.col] = a
+    target = np.tril(Aful)
+    # each factor entry is truncated once (error < 1) and Ubar is diagonal
+    bound = np.abs(L) + np.abs(ud)[None, :] + 1.0
+    assert np.all(np.abs(M - target) <= bound)
+
+
+def test_gauss_seidel_equals_ilu0_on_a_lower_triangular_matrix(orc):
+    """ILU(0) of a lower-triangular matrix eliminates nothing and has U = I,
+    which is the Gauss-Seidel splitting: both must give the same solve bit for
+    bit. On a general matrix they differ."""
+    rng = np.random.default_rng(3)
+    n = 40
+    A = np.tril(rng.normal(size=(n, n)) * (rng.random((n, n)) < 0.2), -1)
+    A += np.diag(np.abs(A).sum(1) * 1.1 + 1.0)
+    s = W.from_dense(A, rng.uniform(-1, 1, n))
+    x1, s1 = orc.OracleSystem.from_system(s, orc.policy("paper_ilu")).solve()
+    x2, s2 = orc.OracleSystem.from_system(s, orc.policy("paper_ilu", gauss_seidel=1)).solve()
+    assert s1["status"] == s2["status"] == orc.OK and np.array_equal(x1, x2)
+    g = W.convdiff2d(12, 10, seed=6)
+    f1 = orc.OracleSystem.from_system(g, orc.policy("paper_ilu")).precond()[0]
+    f2 = orc.OracleSystem.from_system(g, orc.policy("paper_ilu", gauss_seidel=1)).precond()[0]
+    assert not np.array_equal(f1, f2)
+
+
+@pytest.mark.parametrize("gen", [lambda: W.convdiff2d(30, 20, seed=3), lambda: W.random27(5, 4, 3, seed=65)])
+def test_gauss_seidel_solves(orc, gen):
+    s = gen()
+    x, st = orc.OracleSystem.from_system(s, orc.policy("paper_ilu", gauss_seidel=1)).solve()
+    assert st["status"] == orc.OK and st["relres_orig"] < 1e-10
+    xd = np.linalg.solve(s.dense(), s.b)
+    assert np.abs(x - xd).max() <= 1e-9 * np.abs(xd).max()
+    with pytest.raises(orc.OracleError):  # only as a variant of the ILU(0) preconditioner
+        orc.OracleSystem.from_system(s, orc.policy("jacobi", gauss_seidel=1))
