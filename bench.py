@@ -65,7 +65,8 @@ def cycle_bytes(n: int, nnz: int, m_steps: int, precond: int, nnz_l: int, nnz_u:
     per Arnoldi step j the matrix stream (8 B value per term + 4 B column per
     nonzero) and one read of v_j, the preconditioner operands, j reads of the
     basis for modified Gram-Schmidt (w stays in registers), one write of
-    v_{j+1}; then lines 21-23 read the basis once and update x."""
+    v_{j+1}; then the closing least-squares step reads the basis once and
+    updates x."""
     per_step = nnz * (8 * nterms + 4) + 8 * n + 8 * n  # matrix, v_j gather, v_{j+1} write
     if precond == 1:
         per_step += 16 * n  # two integer diagonals
@@ -223,7 +224,7 @@ def batch_bytes(n: int, nnz: int, m: int, refinements: int) -> float:
     """Algorithmic HBM bytes of one system's solve in the batched kernel
     (Jacobi, one term): per refinement the int-GMRES call (see cycle_bytes)
     plus the FP64 residual (20 B per nonzero, row pointers, b, bhat, x, 48 B
-    per row) and line 1'/2 (x, diagonals, v1)."""
+    per row) and the start step with the cast of v1 (x, diagonals, v1)."""
     return refinements * (cycle_bytes(n, nnz, m, 1, 0, 0, 1) + 20 * nnz + 48 * n + 40 * n)
 
 
@@ -364,7 +365,7 @@ def served(B, W, count: int, distinct: int, rate: float = 2000.0) -> dict:
 
 
 def kernel_rates(torch, B, W) -> dict:
-    """Standalone SpMV (line 5) and inner-product (line 7) kernels on the
+    """Standalone SpMV and Gram-Schmidt inner-product kernels (Fig. 2) on the
     27-point 1M-row matrix, timed with HIP events around the kernels."""
     sysm = W.random27(128, 128, 64, seed=3)
     g = B.System.from_system(sysm, "jacobi", m=2)

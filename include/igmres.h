@@ -62,10 +62,13 @@ enum { IGM_PRESET_PAPER_NOPREC = 0, IGM_PRESET_PAPER_ILU = 1, IGM_PRESET_JACOBI 
 
 /* Overflow event code (igm_stats.first_ovf, igm_cycle_trace.first_ovf):
  *   (step j << 24) | (stage << 16) | sub
- * stage 1 = line 5 SpMV, 2 = line 5' preconditioner, 3 = lines 7/8 (sub =
- * 2(i-1) for the inner product with v_i, 2(i-1)+1 for the update), 4 = line
- * 10, 5 = line 11, 6 = line 13 (sub = i), 7 = line 15, 8 = line 16, 9 = line
- * 17. The smallest code of a cycle is reported. IGM_NO_EVENT if none. */
+ * stages follow the steps of Fig. 2 and Sec. VI: 1 = integer SpMV w = A v_j,
+ * 2 = preconditioner apply M^-1 w, 3 = modified Gram-Schmidt (sub = 2(i-1)
+ * for the inner product with v_i, 2(i-1)+1 for the update of w), 4 = norm
+ * h_{j+1,j} = ||w||, 5 = normalisation v_{j+1} = w / h_{j+1,j}, 6 = earlier
+ * Givens rotations applied to column j (sub = i), 7 = rotation radius
+ * t_mp = sqrt(h_jj^2 + h_{j+1,j}^2), 8 = new rotation c_j, s_j, 9 = rotation
+ * of g. The smallest code of a cycle is reported. IGM_NO_EVENT if none. */
 #define IGM_NO_EVENT INT64_MAX
 
 /* Solver parameters (Table I arguments, Table II operand shifts). */
@@ -76,15 +79,15 @@ typedef struct {
   int32_t s_terms;      /* s of eq. (AA): correction matrices used, 0..8 (paper: 0) */
   int32_t m;            /* int-GMRES iterations per refinement, 1..1024 */
   int32_t precond;      /* IGM_PRE_* (Sec. VI) */
-  int32_t b_dot;        /* line 7 shift of w */
-  int32_t b_axpy;       /* line 8 shift of h */
-  int32_t b_norm;       /* line 10 shift of both operands */
-  int32_t b_div_num;    /* line 11 numerator * 2^b */
-  int32_t b_div_den;    /* line 11 denominator / 2^b */
-  int32_t b_rot;        /* line 13 shift of the h entries */
-  int32_t b_tmp;        /* line 15 shift of both operands */
-  int32_t b_cs_num;     /* line 16 numerator * 2^b */
-  int32_t b_cs_den;     /* line 16 denominator / 2^b */
+  int32_t b_dot;        /* Gram-Schmidt inner product: shift of w */
+  int32_t b_axpy;       /* Gram-Schmidt update: shift of h */
+  int32_t b_norm;       /* norm of w: shift of both operands */
+  int32_t b_div_num;    /* normalisation: numerator * 2^b */
+  int32_t b_div_den;    /* normalisation: denominator / 2^b */
+  int32_t b_rot;        /* earlier rotations on column j: shift of the h entries */
+  int32_t b_tmp;        /* rotation radius: shift of both operands */
+  int32_t b_cs_num;     /* new rotation c_j, s_j: numerator * 2^b */
+  int32_t b_cs_den;     /* new rotation c_j, s_j: denominator / 2^b */
   int32_t max_refine;   /* refinement limit (the paper gives none) */
   int64_t gtol;         /* end a cycle early when |g_{j+1}| <= gtol (Sec. V-A); < 0 = never */
   double tol;           /* stop when ||bhat - Ahat x|| / ||bhat|| < tol (Sec. III) */
@@ -95,11 +98,13 @@ typedef struct {
    * auto-tuning of the operand shift was tried for the solver without
    * preconditioner (Sec. VII-D) but gives no rule; the rule here: when an
    * int-GMRES call overflows, the stage of its first event (see the event
-   * code) picks one shift: lines 7, 8, 10, 13, 15 raise b_dot, b_axpy,
-   * b_norm, b_rot, b_tmp by 4 (at most df); lines 11 and 16 lower b_div_num
-   * (or b_cs_num) by 4 (not below 0), or the denominator's exponent once the
-   * numerator's is 0. The call is then repeated from the same v1. Overflow
-   * in lines 5, 5' or 17, or with the shift at its limit, ends the solve with
+   * code) picks one shift: the Gram-Schmidt inner product and update, the
+   * norm, the earlier rotations and the rotation radius raise b_dot, b_axpy,
+   * b_norm, b_rot, b_tmp by 4 (at most df); the normalisation and the new
+   * rotation lower b_div_num (or b_cs_num) by 4 (not below 0), or the
+   * denominator's exponent once the numerator's is 0. The call is then
+   * repeated from the same v1. Overflow in the SpMV, the preconditioner apply
+   * or the rotation of g, or with the shift at its limit, ends the solve with
    * IGM_ERR_OVERFLOW as without retries. Adjusted shifts stay in the system's
    * policy (igm_get_policy) for later solves. */
   int32_t shift_retry;
@@ -197,22 +202,23 @@ igm_status igm_get_policy(const igm_system *s, igm_policy *out);
 
 /* Per-refinement history of the last solve: entry k (0-based) holds the
  * values at the top of refinement k+1: relres of the original and scaled
- * system, gamma^(k) (eq. (gammak)), rho = ||r0|| (line 1'), and the number of
+ * system, gamma^(k) (eq. (gammak)), rho = ||r0|| (the FP64 start step of Fig. 2 and Sec. VI), and the number of
  * columns used (j*). Any pointer may be NULL. Returns the number of entries
  * written (<= cap) in *count. */
 igm_status igm_get_history(const igm_system *s, int32_t cap, double *relres_orig, double *relres_scaled,
                            double *gamma, double *rho, int32_t *jstar, int32_t *count);
 
-/* One int-GMRES(m) call, lines 3-20 of Fig. 2, from the integer start vector
- * v1 (host, n int64 words: the output of line 2), with the system's policy.
+/* One int-GMRES(m) call, the integer loop of Fig. 2 (Arnoldi steps with
+ * Givens rotations), from the integer start vector v1 (host, n int64 words:
+ * v1 cast to Q.df as in Fig. 2), with the system's policy.
  * Outputs (caller-allocated host arrays; V may be NULL):
  *   H[(m+1)*m] row-major (H[i*m + j], 0-based) after the rotations,
  *   c[m], s[m], g[m+1], V[(m+1)*n] (basis vector j at V + j*n).
  * m is taken from trace->m, which must equal the policy's m. */
 typedef struct {
   int32_t m;          /* in */
-  int32_t jstar;      /* out: columns usable by lines 21-23 */
-  int32_t breakdown;  /* out: 0 none, 1 line 11 zero denominator, 2 line 16 zero denominator */
+  int32_t jstar;      /* out: columns usable by the closing FP64 least-squares step */
+  int32_t breakdown;  /* out: 0 none, 1 zero denominator in the normalisation, 2 in the new rotation */
   int32_t steps;      /* out: Arnoldi steps executed */
   int64_t first_ovf;  /* out: overflow event code or IGM_NO_EVENT */
   int64_t *H, *c, *s, *g, *V;
@@ -225,25 +231,25 @@ igm_status igm_int_cycle(igm_system *s, const int64_t *v1, igm_cycle_trace *trac
  * All vectors are device pointers of length n unless stated otherwise;
  * *first_ovf receives the overflow event code with step j = 1. */
 
-/* Line 5 (Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_{l=1..nterms-1}
+/* Integer SpMV w = A v (Fig. 2; Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_{l=1..nterms-1}
  * asr(A_l v, alpha_l) over the system's integer matrices (nterms clamped to
  * the number built). */
 igm_status igm_spmv(igm_system *s, int32_t nterms, const int64_t *v, int64_t *z, int64_t *first_ovf);
 
-/* Line 5' (Sec. VI-A): w = Mbar^-1 z by integer forward/backward substitution
+/* Preconditioner apply (Sec. VI, VI-A): w = Mbar^-1 z by integer forward/backward substitution
  * (truncating division), level-scheduled; w = z without a preconditioner. */
 igm_status igm_precond(igm_system *s, const int64_t *z, int64_t *w, int64_t *first_ovf);
 
-/* Line 7 (Sec. V-C.1, Table II): *h = asr(sum_l asr(w_l, b_dot) v_l, df - b_dot). */
+/* Gram-Schmidt inner product (Fig. 2; Sec. V-C.1, Table II): *h = asr(sum_l asr(w_l, b_dot) v_l, df - b_dot). */
 igm_status igm_dot(igm_system *s, const int64_t *w, const int64_t *v, int64_t *h, int64_t *first_ovf);
 
-/* Line 8: w_l -= asr(asr(h, b_axpy) v_l, df - b_axpy), in place. */
+/* Gram-Schmidt update (Fig. 2): w_l -= asr(asr(h, b_axpy) v_l, df - b_axpy), in place. */
 igm_status igm_axpy(igm_system *s, int64_t h, int64_t *w, const int64_t *v, int64_t *first_ovf);
 
-/* Line 10 (Sec. V-C.2): *h = shl(isqrt(sum_l asr(w_l, b_norm)^2), b_norm). */
+/* Norm of w (Fig. 2; Sec. V-C.2): *h = shl(isqrt(sum_l asr(w_l, b_norm)^2), b_norm). */
 igm_status igm_norm(igm_system *s, const int64_t *w, int64_t *h, int64_t *first_ovf);
 
-/* Line 11 (Sec. V-B.3): v_l = sc(tdiv(shl(w_l, b_div_num), asr(h, b_div_den)),
+/* Normalisation v = w / h (Fig. 2; Sec. V-B.3): v_l = sc(tdiv(shl(w_l, b_div_num), asr(h, b_div_den)),
  * df - b_div_num - b_div_den). IGM_ERR_BREAKDOWN if the shifted denominator is 0. */
 igm_status igm_normalize(igm_system *s, const int64_t *w, int64_t h, int64_t *v, int64_t *first_ovf);
 
@@ -255,12 +261,13 @@ igm_status igm_residual(igm_system *s, const double *x, double *r, double *rhat)
  * (mu = max|x_i|, exact integer sum of floor(2^96 (x_i/mu)^2), one rounding). */
 igm_status igm_fp_norm(igm_system *s, const double *x, int64_t len, double *norm);
 
-/* Eqs. (gammak), (scale) and lines 1'-2: gamma = max|r|, bk = r / gamma,
+/* Start vector: eqs. (gammak), (scale), the FP64 start step of Sec. VI and the
+ * cast of Fig. 2: gamma = max|r|, bk = r / gamma,
  * r0 = Mbar^-1 bk (FP64 substitution with the integer factors), rho =
  * ||r0||, v1 = trunc(2^df r0 / rho). IGM_ERR_RANGE if a cast is out of range.
  * *gamma = 0 means r = 0 (nothing written to v1). */
-igm_status igm_line1(igm_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
-                     double *rho);
+igm_status igm_start_vector(igm_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
+                            double *rho);
 
 /* Release all device and host memory of the system. NULL is a no-op. */
 void igm_destroy(igm_system *s);

@@ -24,7 +24,7 @@ NO_EVENT = (1 << 63) - 1
 
 
 def code(j: int, stage: int, sub: int = 0) -> int:
-    """Overflow event code: step j, stage (1 SpMV .. 9 line 17), sub-index."""
+    """Overflow event code: step j, stage (1 SpMV .. 9 rotation of g), sub-index."""
     return (j << 24) | (stage << 16) | sub
 
 
@@ -137,7 +137,7 @@ def lib():
             "orc_shift_retry": (C.c_int, [C.POINTER(Policy), i64]),
             "orc_get_policy": (None, [vp, C.POINTER(Policy)]),
             "orc_residual": (None, [vp, vp, vp, vp]),
-            "orc_line1": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl)]),
+            "orc_start_vector": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl)]),
             "orc_gmres64": (C.c_int, [vp, i32, dbl, i32, vp, C.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
@@ -341,12 +341,12 @@ class OracleSystem:
         lib().orc_residual(self.h, _p(x), _p(r), _p(rh))
         return r, rh
 
-    def line1(self, r):
+    def start_vector(self, r):
         r = _f64(r)
         bk, r0 = np.empty(self.n), np.empty(self.n)
         v1 = np.empty(self.n, dtype=np.int64)
         g, rho = C.c_double(0), C.c_double(0)
-        rc = lib().orc_line1(self.h, _p(r), _p(bk), _p(r0), _p(v1), C.byref(g), C.byref(rho))
+        rc = lib().orc_start_vector(self.h, _p(r), _p(bk), _p(r0), _p(v1), C.byref(g), C.byref(rho))
         return dict(status=rc, bk=bk, r0=r0, v1=v1, gamma=g.value, rho=rho.value)
 
     def solve(self, x0=None, hist_cap: int | None = None):

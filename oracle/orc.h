@@ -32,7 +32,7 @@
  * Parity status: the primitives, setup, FP64 steps and whole solves are pinned
  * by tests against definitions, closed forms, textbook special cases, dense
  * solves and the invariants the paper states. The exact bits of the integer
- * cycle (lines 2-20 of the algorithm in Fig. 2) have no worked example in the
+ * cycle (the cast of v1 and the integer loop of Fig. 2) have no worked example in the
  * paper; they are pinned only through those properties.
  */
 #ifndef ORC_H
@@ -61,15 +61,15 @@ typedef struct {
   int32_t s_terms;     /* s: number of correction matrices A_1..A_s used, eq. (AA) */
   int32_t m;           /* iterations per int-GMRES call (= per refinement) */
   int32_t precond;     /* ORC_PRE_* */
-  int32_t b_dot;       /* line 7:  beta_1 on w */
-  int32_t b_axpy;      /* line 8:  beta_1 on h */
-  int32_t b_norm;      /* line 10: beta_1 = beta_2 */
-  int32_t b_div_num;   /* line 11: numerator * 2^beta_1 */
-  int32_t b_div_den;   /* line 11: denominator / 2^beta_2 */
-  int32_t b_rot;       /* line 13: beta_2 on the h entries */
-  int32_t b_tmp;       /* line 15: beta_1 = beta_2 */
-  int32_t b_cs_num;    /* line 16: numerator * 2^beta_1 */
-  int32_t b_cs_den;    /* line 16: denominator / 2^beta_2 */
+  int32_t b_dot;       /* Gram-Schmidt inner product: beta_1 on w */
+  int32_t b_axpy;      /* Gram-Schmidt update: beta_1 on h */
+  int32_t b_norm;      /* norm of w: beta_1 = beta_2 */
+  int32_t b_div_num;   /* normalisation: numerator * 2^beta_1 */
+  int32_t b_div_den;   /* normalisation: denominator / 2^beta_2 */
+  int32_t b_rot;       /* earlier rotations on column j: beta_2 on the h entries */
+  int32_t b_tmp;       /* rotation radius t_mp: beta_1 = beta_2 */
+  int32_t b_cs_num;    /* new rotation c_j, s_j: numerator * 2^beta_1 */
+  int32_t b_cs_den;    /* new rotation c_j, s_j: denominator / 2^beta_2 */
   int32_t max_refine;  /* refinement limit (not given in the paper) */
   int32_t shift_retry; /* overflow-driven shift retries allowed per solve, 0 = none (see orc_shift_retry) */
   int64_t gtol;        /* stop a cycle early when |g_{j+1}| <= gtol; < 0: never */
@@ -79,8 +79,10 @@ typedef struct {
 } orc_policy;
 
 /* Overflow event code: (step j, stage, sub-index), ordered as executed.
- * stage 1 l.5 SpMV, 2 l.5' preconditioner, 3 l.7/8 (sub = 2(i-1) + {0 dot,
- * 1 update}), 4 l.10, 5 l.11, 6 l.13 (sub = i), 7 l.15, 8 l.16, 9 l.17. */
+ * Stages, as the steps of Fig. 2 and Sec. VI: 1 SpMV, 2 preconditioner apply,
+ * 3 Gram-Schmidt (sub = 2(i-1) + {0 inner product, 1 update}), 4 norm of w,
+ * 5 normalisation, 6 earlier rotations (sub = i), 7 rotation radius, 8 new
+ * rotation, 9 rotation of g. */
 #define ORC_CODE(j, stage, sub) (((int64_t)(j) << 24) | ((int64_t)(stage) << 16) | (int64_t)(sub))
 #define ORC_NO_EVENT INT64_MAX
 
@@ -130,8 +132,8 @@ void orc_precond_apply(const orc_system *s, const int64_t *z, int64_t *w, int32_
 
 typedef struct {
   int32_t m;          /* in: columns allocated */
-  int32_t jstar;      /* out: columns usable for the update (lines 21-23) */
-  int32_t breakdown;  /* out: 0 none, 1 line 11 denominator 0, 2 line 16 denominator 0 */
+  int32_t jstar;      /* out: columns usable for the closing least-squares step */
+  int32_t breakdown;  /* out: 0 none, 1 normalisation denominator 0, 2 new-rotation denominator 0 */
   int32_t steps;      /* out: Arnoldi steps executed */
   int64_t first_ovf;  /* out: smallest overflow event code, ORC_NO_EVENT if none */
   int64_t *H;         /* (m+1) x m, row-major: H[i*m + j], 0-based */
@@ -140,9 +142,9 @@ typedef struct {
   int64_t *V;         /* n x (m+1), column j at V + j*n */
 } orc_trace;
 
-/* Lines 3-20 of Fig. 2 starting from the integer v1 (line 2's output). */
+/* The integer loop of Fig. 2 starting from the integer v1 (v1 cast to Q df). */
 int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t);
-/* Lines 21-23: x[n] = sum_i y_i v_i with y = rho * H^-1 g (FP64). */
+/* Closing FP64 step of Fig. 2: x[n] = sum_i y_i v_i with y = rho * H^-1 g (FP64). */
 void orc_cycle_update(const orc_system *s, const orc_trace *t, double rho, double *x);
 
 /* ---- refinement driver (orc_ir.c) ---------------------------------------- */
@@ -170,18 +172,19 @@ int orc_solve(orc_system *s, double *x, orc_stats *st);
  * operand shift was investigated for the solver without preconditioner
  * (Sec. VII-D) but gives no rule; this is the reading used here. From the
  * stage of the first overflow event of a call (ORC_CODE): the right shift
- * applied before a product grows by 4, capped at df (line 7: b_dot, line 8:
- * b_axpy, line 10: b_norm, line 13: b_rot, line 15: b_tmp); for a division
- * (line 11, line 16) the numerator's exponent shrinks by 4 (not below 0),
- * or the denominator's once the numerator's is 0. Returns 1 if a shift
- * changed, 0 if none can (lines 5, 5', 17, or shifts at their limits). */
+ * applied before a product grows by 4, capped at df (inner product: b_dot,
+ * update: b_axpy, norm: b_norm, earlier rotations: b_rot, rotation radius:
+ * b_tmp); for a division (normalisation, new rotation) the numerator's
+ * exponent shrinks by 4 (not below 0), or the denominator's once the
+ * numerator's is 0. Returns 1 if a shift changed, 0 if none can (SpMV,
+ * preconditioner apply, rotation of g, or shifts at their limits). */
 int orc_shift_retry(orc_policy *p, int64_t code);
 /* The system's current policy (shifts adjusted by retries included). */
 void orc_get_policy(const orc_system *s, orc_policy *out);
 /* Pieces of one refinement, for step-level parity checks. */
 void orc_residual(const orc_system *s, const double *x, double *r, double *rhat);
-int orc_line1(const orc_system *s, const double *r, double *bk, double *r0, int64_t *v1,
-              double *gamma, double *rho);
+int orc_start_vector(const orc_system *s, const double *r, double *bk, double *r0, int64_t *v1,
+                     double *gamma, double *rho);
 
 /* ---- FP64 GMRES(m) comparator (orc_gmres64.c) ---------------------------- */
 int orc_gmres64(const orc_system *s, int32_t m, double tol, int32_t max_restart, double *x,

@@ -4,12 +4,15 @@
  *
  * Readings of the paper taken here (each one also listed in the design notes):
  *  - right shifts are arithmetic (floor), divisions truncate toward zero;
- *  - line 7 shifts only w (beta_2 = 0), line 8 shifts only h, line 13 shifts
- *    only the h entries (Sec. V-D.2, V-D.3);
- *  - the minus signs of lines 13 and 17 are applied to the operand s before
- *    the multiplication; line 17 uses the old g_j for both updates;
- *  - a zero (shifted) denominator in line 11 ends the call after the Givens
- *    update of column j; in line 16 it ends the call without column j.
+ *  - the Gram-Schmidt inner product shifts only w (beta_2 = 0), its update
+ *    shifts only h, the earlier rotations shift only the h entries
+ *    (Sec. V-D.2, V-D.3);
+ *  - the minus signs of the rotations (of H and of g) are applied to the
+ *    operand s before the multiplication; the rotation of g uses the old g_j
+ *    for both updates;
+ *  - a zero (shifted) denominator in the normalisation ends the call after
+ *    the Givens update of column j; in the new rotation it ends the call
+ *    without column j.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -32,7 +35,7 @@ static int64_t pmul(int64_t a, int64_t b, int32_t *ovf) {
   return wrap64(p);
 }
 
-/* Line 5 (Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_{l=1..s} asr(A_l v, alpha_l).
+/* Integer SpMV (Fig. 2; Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_{l=1..s} asr(A_l v, alpha_l).
  * Matrix entries have no fraction bits, v and z are Q df; no shift on A_0 v. */
 void orc_spmv(const orc_system *s, int32_t nterms, const int64_t *v, int64_t *z, int32_t j, int64_t *first) {
   if (nterms > s->nterms) nterms = s->nterms;
@@ -53,7 +56,7 @@ void orc_spmv(const orc_system *s, int32_t nterms, const int64_t *v, int64_t *z,
   }
 }
 
-/* Line 5' (Sec. VI-A): w = Mbar^-1 z with Mbar = Lbar Ubar, by forward then
+/* Preconditioner apply (Sec. VI, VI-A): w = Mbar^-1 z with Mbar = Lbar Ubar, by forward then
  * backward substitution in integers: the FP substitution with the data type
  * changed, so each division is C integer division (truncation). */
 void orc_precond_apply(const orc_system *s, const int64_t *z, int64_t *w, int32_t j, int64_t *first) {
@@ -101,33 +104,33 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
   t->breakdown = 0;
   t->jstar = m;
   t->steps = 0;
-  /* line 3: g = (1, 0, ..., 0) in Q df */
+  /* g = (1, 0, ..., 0) in Q df */
   t->g[0] = (int64_t)1 << f;
   int32_t nterms = p->s_terms + 1;
-  for (int32_t j = 1; j <= m; ++j) { /* line 4 */
+  for (int32_t j = 1; j <= m; ++j) { /* Arnoldi step j */
     int32_t ovf;
     const int64_t *vj = t->V + (size_t)(j - 1) * n;
     t->steps = j;
-    /* lines 5 / 5' */
+    /* SpMV, then the preconditioner apply */
     orc_spmv(s, nterms, vj, z, j, &t->first_ovf);
     orc_precond_apply(s, z, w, j, &t->first_ovf);
-    /* lines 6-9: modified Gram-Schmidt, i in increasing order */
+    /* modified Gram-Schmidt, i in increasing order */
     for (int32_t i = 1; i <= j; ++i) {
       const int64_t *vi = t->V + (size_t)(i - 1) * n;
       ovf = 0;
-      int64_t h = orc_dot(n, w, vi, p->b_dot, f, &ovf); /* line 7 */
+      int64_t h = orc_dot(n, w, vi, p->b_dot, f, &ovf); /* h_ij = (w, v_i) */
       if (ovf) event(&t->first_ovf, ORC_CODE(j, 3, 2 * (i - 1)));
       HH(i - 1, j - 1) = h;
-      ovf = 0; /* line 8 */
+      ovf = 0; /* w -= h_ij v_i */
       orc_axpy(n, w, vi, h, p->b_axpy, f, &ovf);
       if (ovf) event(&t->first_ovf, ORC_CODE(j, 3, 2 * (i - 1) + 1));
     }
-    /* line 10 */
+    /* h_{j+1,j} = ||w|| */
     ovf = 0;
     int64_t hn = orc_norm(n, w, p->b_norm, f, &ovf);
     if (ovf) event(&t->first_ovf, ORC_CODE(j, 4, 0));
     HH(j, j - 1) = hn;
-    /* line 11: v_{j+1} = w / h_{j+1,j} (division of Sec. V-B.3) */
+    /* normalisation: v_{j+1} = w / h_{j+1,j} (division of Sec. V-B.3) */
     int64_t den = orc_asr(hn, p->b_div_den);
     int lucky = den == 0;
     if (!lucky) {
@@ -135,7 +138,7 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
       orc_normalize(n, w, den, p->b_div_num, p->b_div_den, f, t->V + (size_t)j * n, &ovf);
       if (ovf) event(&t->first_ovf, ORC_CODE(j, 5, 0));
     }
-    /* lines 12-14: apply the previous rotations to column j */
+    /* apply the previous rotations to column j */
     for (int32_t i = 1; i <= j - 1; ++i) {
       int64_t a = orc_asr(HH(i - 1, j - 1), p->b_rot);
       int64_t b = orc_asr(HH(i, j - 1), p->b_rot);
@@ -150,12 +153,12 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
       HH(i, j - 1) = orc_asr(wrap64(bot), f - p->b_rot);
       if (ovf) event(&t->first_ovf, ORC_CODE(j, 6, i));
     }
-    /* line 15: tmp = sqrt(h_jj^2 + h_{j+1,j}^2), a 2-element norm */
+    /* rotation radius: tmp = sqrt(h_jj^2 + h_{j+1,j}^2), a 2-element norm */
     ovf = 0;
     int64_t pair[2] = {HH(j - 1, j - 1), HH(j, j - 1)};
     int64_t tmp = orc_norm(2, pair, p->b_tmp, f, &ovf);
     if (ovf) event(&t->first_ovf, ORC_CODE(j, 7, 0));
-    /* line 16 */
+    /* new rotation: c_j = h_jj / tmp, s_j = h_{j+1,j} / tmp */
     ovf = 0;
     int32_t zero = 0;
     int64_t cj = orc_div(pair[0], tmp, p->b_cs_num, p->b_cs_den, f, &ovf, &zero);
@@ -168,7 +171,7 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
     if (ovf) event(&t->first_ovf, ORC_CODE(j, 8, 0));
     t->c[j - 1] = cj;
     t->s[j - 1] = sj;
-    /* line 17: products of Q df numbers without operand shifts */
+    /* rotation of g: products of Q df numbers without operand shifts */
     ovf = 0;
     int64_t gj = t->g[j - 1];
     int64_t msj = wrap64(-(i128)sj);
@@ -176,7 +179,7 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
     t->g[j - 1] = orc_asr(pmul(cj, gj, &ovf), f);
     t->g[j] = orc_asr(pmul(msj, gj, &ovf), f);
     if (ovf) event(&t->first_ovf, ORC_CODE(j, 9, 0));
-    /* lines 18-19 */
+    /* h_jj = tmp, h_{j+1,j} = 0 */
     HH(j - 1, j - 1) = tmp;
     HH(j, j - 1) = 0;
     if (lucky) {
@@ -194,7 +197,7 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
   return ORC_OK;
 }
 
-/* Lines 21-23: cast H and g to FP (exact scaling by 2^-df), y = rho H^-1 g by
+/* Closing FP64 step of Fig. 2: cast H and g to FP (exact scaling by 2^-df), y = rho H^-1 g by
  * back substitution (row i: y_i = (g_i - sum_{k>i} H_ik y_k) / H_ii with the
  * sum over k increasing), then x_l = sum_{i} y_i * (v_il 2^-df), i increasing. */
 void orc_cycle_update(const orc_system *s, const orc_trace *t, double rho, double *x) {

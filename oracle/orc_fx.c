@@ -101,7 +101,7 @@ static int64_t finish_sum(i128 s, int32_t *ovf) {
   return wrap64(s);
 }
 
-/* Inner product (Sec. V-C.1, Table II line 7): only the first operand w is
+/* Inner product (Sec. V-C.1, Table II): only the first operand w is
  * shifted (beta_2 = 0), products are summed in Q(2df - b), and the sum is
  * shifted once by df - b to return to Q df. */
 int64_t orc_dot(int64_t n, const int64_t *w, const int64_t *v, int32_t b, int32_t df, int32_t *ovf) {
@@ -110,7 +110,7 @@ int64_t orc_dot(int64_t n, const int64_t *w, const int64_t *v, int32_t b, int32_
   return orc_asr(finish_sum(s, ovf), df - b);
 }
 
-/* Norm (Sec. V-C.2, Table II line 10): sum of asr(w, b)^2 in Q(2df - 2b),
+/* Norm (Sec. V-C.2, Table II): sum of asr(w, b)^2 in Q(2df - 2b),
  * integer square root (Q(df - b)), then times 2^b (= 2^(df - (2df-2b)/2)). */
 int64_t orc_norm(int64_t n, const int64_t *w, int32_t b, int32_t df, int32_t *ovf) {
   (void)df;
@@ -123,7 +123,7 @@ int64_t orc_norm(int64_t n, const int64_t *w, int32_t b, int32_t df, int32_t *ov
   return orc_shl(orc_isqrt(sq), b, ovf);
 }
 
-/* Line 8 (Table II): w_l -= asr(asr(h, b) * v_l, df - b) for every l, in
+/* Gram-Schmidt update (Table II): w_l -= asr(asr(h, b) * v_l, df - b) for every l, in
  * place; only h is shifted (Sec. V-D.2). */
 void orc_axpy(int64_t n, int64_t *w, const int64_t *v, int64_t h, int32_t b, int32_t df, int32_t *ovf) {
   int64_t hs = orc_asr(h, b);
@@ -135,7 +135,7 @@ void orc_axpy(int64_t n, int64_t *w, const int64_t *v, int64_t h, int32_t b, int
   }
 }
 
-/* Line 11 (Sec. V-B.3): v_l = sc(tdiv(shl(w_l, b1), den), df - b1 - b2) with
+/* Normalisation (Sec. V-B.3): v_l = sc(tdiv(shl(w_l, b1), den), df - b1 - b2) with
  * den = asr(h, b2) != 0 (the caller checks for 0). */
 void orc_normalize(int64_t n, const int64_t *w, int64_t den, int32_t b1, int32_t b2, int32_t df, int64_t *v,
                    int32_t *ovf) {

@@ -1,6 +1,7 @@
 /*
  * FP64 iterative refinement around the integer GMRES call (Sec. IV, Fig. 1)
- * and the FP64 statements of Fig. 2 (lines 1/1', 21-23).
+ * and the FP64 steps of Fig. 2 and Sec. VI (start vector, closing least-squares
+ * step).
  * TEST INFRASTRUCTURE ONLY (see orc.h).
  */
 #include <math.h>
@@ -51,7 +52,7 @@ void orc_residual(const orc_system *s, const double *x, double *r, double *rhat)
   }
 }
 
-/* Line 1': r0 = Mbar^-1 bk in FP64 with the integer factors converted to
+/* FP64 start step (Sec. VI): r0 = Mbar^-1 bk in FP64 with the integer factors converted to
  * double: forward rows in increasing order, backward in decreasing order;
  * each row sums its off-diagonal products in CSR order, subtracts, divides. */
 static void precond_fp(const orc_system *s, const double *bk, double *u) {
@@ -75,12 +76,13 @@ static void precond_fp(const orc_system *s, const double *bk, double *u) {
   }
 }
 
-/* Eqs. (gammak), (scale), then Fig. 2 lines 1'-2 with x^(k) = 0:
+/* Eqs. (gammak), (scale), then the start step and cast of Fig. 2 and Sec. VI
+ * with x^(k) = 0:
  * gamma = max|r|, bk = r / gamma, r0 = Mbar^-1 bk, rho = ||r0||,
  * v1 = trunc(2^df * r0 / rho). Returns ORC_ERR_RANGE if a cast fails and
  * ORC_OK otherwise; gamma == 0 means r == 0. */
-int orc_line1(const orc_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
-              double *rho) {
+int orc_start_vector(const orc_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
+                     double *rho) {
   int64_t n = s->n;
   double g = 0.0;
   for (int64_t i = 0; i < n; ++i)
@@ -116,13 +118,13 @@ int orc_shift_retry(orc_policy *p, int64_t code) {
   int32_t sub = (int32_t)(code & 0xFFFF);
   int32_t *b;
   switch (stage) {
-    case 3: b = (sub % 2 == 0) ? &p->b_dot : &p->b_axpy; break; /* lines 7 / 8 */
-    case 4: b = &p->b_norm; break;                               /* line 10 */
-    case 6: b = &p->b_rot; break;                                /* line 13 */
-    case 7: b = &p->b_tmp; break;                                /* line 15 */
-    case 5: return shrink_exponent(&p->b_div_num, &p->b_div_den); /* line 11 */
-    case 8: return shrink_exponent(&p->b_cs_num, &p->b_cs_den);   /* line 16 */
-    default: return 0;                                             /* lines 5, 5', 17 */
+    case 3: b = (sub % 2 == 0) ? &p->b_dot : &p->b_axpy; break; /* inner product / update */
+    case 4: b = &p->b_norm; break;                               /* norm */
+    case 6: b = &p->b_rot; break;                                /* earlier rotations */
+    case 7: b = &p->b_tmp; break;                                /* rotation radius */
+    case 5: return shrink_exponent(&p->b_div_num, &p->b_div_den); /* normalisation */
+    case 8: return shrink_exponent(&p->b_cs_num, &p->b_cs_den);   /* new rotation */
+    default: return 0;                                             /* SpMV, preconditioner, rotation of g */
   }
   if (*b >= p->df) return 0;
   *b = *b + 4 > p->df ? p->df : *b + 4;
@@ -175,7 +177,7 @@ int orc_solve(orc_system *s, double *x, orc_stats *st) {
     if (ro < s->pol.tol) { st->status = ORC_OK; break; }
     if (k >= s->pol.max_refine) { st->status = ORC_NOT_CONVERGED; break; }
     double gamma, rho;
-    int rc = orc_line1(s, r, bk, r0, v1, &gamma, &rho);
+    int rc = orc_start_vector(s, r, bk, r0, v1, &gamma, &rho);
     if (k < st->hist_cap) {
       if (st->hist_gamma) st->hist_gamma[k] = gamma;
       if (st->hist_rho) st->hist_rho[k] = rho;

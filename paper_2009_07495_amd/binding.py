@@ -91,7 +91,7 @@ _SIGS = {
     "igm_normalize": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
     "igm_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "igm_fp_norm": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
-    "igm_line1": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_start_vector": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "igm_destroy": [C.c_void_p],
     "igm_status_str": [C.c_int],
     "igm_batch_create": [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -323,10 +323,10 @@ class System:
         _check(lib().igm_fp_norm(self.h, _ptr(x), ln, C.byref(out)), "igm_fp_norm")
         return out.value
 
-    def line1(self, r, bk, r0, v1):
+    def start_vector(self, r, bk, r0, v1):
         g, rho = C.c_double(0), C.c_double(0)
-        st = lib().igm_line1(self.h, _ptr(r), _ptr(bk), _ptr(r0), _ptr(v1), C.byref(g), C.byref(rho))
-        _check(st, "igm_line1", ok=(OK, ERR_RANGE))
+        st = lib().igm_start_vector(self.h, _ptr(r), _ptr(bk), _ptr(r0), _ptr(v1), C.byref(g), C.byref(rho))
+        _check(st, "igm_start_vector", ok=(OK, ERR_RANGE))
         return st, g.value, rho.value
 
 

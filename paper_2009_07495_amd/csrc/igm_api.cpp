@@ -325,9 +325,9 @@ igm_status solve_dev(igm_system *s, double *x) {
     if (k >= p.max_refine) { status = IGM_NOT_CONVERGED; break; }
     s->hist_gamma.push_back(gamma);
     if (gamma == 0.0) { s->hist_rho.push_back(0.0); status = IGM_OK; break; }
-    // lines 1'-2, then the int-GMRES call with the fused update
+    // FP64 start step and cast of v1, then the int-GMRES call with the fused update
     IGM_TRY(prepare_cycle(s));
-    IGM_HIP(launch_line1(s->stream, a, s->d_r, s->d_scal, s->d_lvalf, s->d_uvalf, s->d_bk, s->d_r0, s->d_red));
+    IGM_HIP(launch_start_vector(s->stream, a, s->d_r, s->d_scal, s->d_lvalf, s->d_uvalf, s->d_bk, s->d_r0, s->d_red));
     CycleState cs;
     for (;;) {  // the call, repeated from the same v1 while a retry can adjust a shift
       IGM_HIP(hipEventRecord(e0, s->stream));
@@ -660,8 +660,8 @@ igm_status igm_fp_norm(igm_system *s, const double *x, int64_t len, double *norm
   return IGM_OK;
 }
 
-igm_status igm_line1(igm_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
-                     double *rho) {
+igm_status igm_start_vector(igm_system *s, const double *r, double *bk, double *r0, int64_t *v1, double *gamma,
+                            double *rho) {
   if (!s || !r || !bk || !r0 || !v1 || !gamma || !rho) return IGM_ERR_ARG;
   IGM_TRY(reset_state(s));
   IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
@@ -675,8 +675,8 @@ igm_status igm_line1(igm_system *s, const double *r, double *bk, double *r0, int
   IGM_HIP(hipMemcpyAsync(s->d_scal + kScalGamma, s->d_red + kRedMuR, sizeof(double), hipMemcpyDeviceToDevice,
                          s->stream));
   CycleArgs a = make_args(s);
-  a.V = v1;  // line 2 writes its output as the first basis vector
-  IGM_HIP(launch_line1(s->stream, a, r, s->d_scal, s->d_lvalf, s->d_uvalf, bk, r0, s->d_red));
+  a.V = v1;  // the cast of v1 writes its output as the first basis vector
+  IGM_HIP(launch_start_vector(s->stream, a, r, s->d_scal, s->d_lvalf, s->d_uvalf, bk, r0, s->d_red));
   CycleState cs;
   IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
   IGM_HIP(hipMemcpyAsync(s->h_pinned, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));

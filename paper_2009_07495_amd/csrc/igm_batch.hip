@@ -1,6 +1,7 @@
 // Batched and served solver: many independent systems, each solved
 // completely (Fig. 1 of the paper: FP64 iterative refinement around
-// int-GMRES(m) calls, Fig. 2 with line 5' of Sec. VI) by a team of workgroups
+// int-GMRES(m) calls, Fig. 2 with the preconditioned product of Sec. VI) by a
+// team of workgroups
 // inside one persistent cooperative launch. Every system carries its own
 // policy (shifts, m, preconditioner: none, Jacobi or ILU(0)).
 //
@@ -29,7 +30,7 @@ constexpr int kBatchSweepPre = 8;
 
 namespace {
 
-constexpr int kGivensThread = 64;  // runs the scalar work of lines 12-19 (wavefront 1, lane 0)
+constexpr int kGivensThread = 64;  // runs the scalar Givens work (wavefront 1, lane 0)
 constexpr double kDblMax = 1.7976931348623157e308;
 
 __device__ __forceinline__ double relres_of(double rn, double bn) {
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
     int64_t *sg = ss + m;                               // g_1..g_{m+1}
     int64_t *col = sg + m + 1;                          // current column h_{1..j+1, j}
     int64_t *sH = col + m + 1;                          // H, (m+1) x m, row-major
-    double *sy = (double *)(sH + (size_t)(m + 1) * m);  // y of lines 21-23
+    double *sy = (double *)(sH + (size_t)(m + 1) * m);  // y of the closing least-squares step
     Team tm{S.words, S.team, member, 0, ba.timeout};
     const int64_t n = S.n, ldv = S.ldv;
     const int64_t TB = (int64_t)S.team * BLOCK;
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       if (kref >= S.max_refine) { status = IGM_NOT_CONVERGED; break; }
       // gamma = max |r| (eq. (gammak)); gamma == 0 means r == 0
       if (gamma == 0.0) { status = IGM_OK; break; }
-      // ---- line 1': b^(k) = r / gamma, r0 = Mbar^-1 b^(k) in FP64
+      // ---- FP64 start step (Sec. VI): b^(k) = r / gamma, r0 = Mbar^-1 b^(k) in FP64
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const int64_t row = g0 + k * TB;
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       const double rho = team_norm1<BLOCK, R>(tm, tsh, r);
       if (tsh.abort) break;
       if (!finite_pos(rho)) { status = IGM_ERR_RANGE; break; }
-      // ---- line 2: v1 = trunc(2^df r0 / rho)
+      // ---- cast of v1 to Q.df: v1 = trunc(2^df r0 / rho)
       {
         unsigned long long rerr[1] = {0};
 #pragma unroll
@@ -379,11 +380,11 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       }
       IGM_TICK(5)
 
-      // ---- lines 3-20: the int-GMRES(m) call
+      // ---- the integer loop of Fig. 2: the int-GMRES(m) call
       if (tid == 0) {
         for (int i = 0; i < m; ++i) { sc[i] = 0; ss[i] = 0; }
         for (int i = 0; i <= m; ++i) { sg[i] = 0; col[i] = 0; }
-        sg[0] = (int64_t)1 << df;  // line 3
+        sg[0] = (int64_t)1 << df;  // g = e_1 in Q.df
         sh_stop = 0; sh_jstar = m; sh_steps = 0;
         sh_ovf = (long long)kNoEvent;
       }
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       int64_t w[R];
       int64_t carry = 0, hn = 0;
       bool lucky = false;
-      // rotation i (1-based) of lines 12-14 on (carry, col[i]); thread kGivensThread only
+      // earlier rotation i (1-based) on (carry, col[i]); thread kGivensThread only
       auto rotate = [&](int j, int i) {
         const int64_t x0 = asr(carry, S.b_rot), x1 = asr(col[i], S.b_rot);
         const int64_t c = sc[i - 1], s = ss[i - 1];
@@ -409,18 +410,18 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
         carry = asr(bot, df - S.b_rot);
         if (o) record(ev_code(j, 6, i));
       };
-      // lines 15-19 for column j on (carry, hn); thread kGivensThread only
+      // radius, new rotation, rotation of g and H update for column j on (carry, hn); thread kGivensThread only
       auto givens = [&](int j) {
         col[j - 1] = carry;
         col[j] = hn;
-        bool o = false;  // line 15
+        bool o = false;  // rotation radius t_mp
         const int64_t p0 = asr(col[j - 1], S.b_tmp), p1 = asr(col[j], S.b_tmp);
         const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
         const int64_t tmp = shl(isqrt64(ssq), S.b_tmp, o);
         if (o) record(ev_code(j, 7, 0));
-        const int64_t den2 = asr(tmp, S.b_cs_den);  // line 16
+        const int64_t den2 = asr(tmp, S.b_cs_den);  // new rotation c_j, s_j
         int stop = 0;
-        if (den2 == 0) {  // line 16 breakdown
+        if (den2 == 0) {  // new rotation: zero denominator
           sh_jstar = j - 1;
           stop = 1;
         } else {
@@ -431,15 +432,15 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           if (oc) record(ev_code(j, 8, 0));
           sc[j - 1] = cj;
           ss[j - 1] = sj;
-          bool og = false;  // line 17, both from the old g_j
+          bool og = false;  // rotation of g, both from the old g_j
           const int64_t gj = sg[j - 1];
           const int64_t msj = subc(0, sj, og);
           sg[j - 1] = asr(mulw(gj, cj, og), df);
           sg[j] = asr(mulw(gj, msj, og), df);
           if (og) record(ev_code(j, 9, 0));
-          col[j - 1] = tmp;  // lines 18-19
+          col[j - 1] = tmp;  // h_jj = t_mp, h_{j+1,j} = 0
           col[j] = 0;
-          if (lucky) {  // line 11 breakdown
+          if (lucky) {  // normalisation: zero denominator
             sh_jstar = j;
             stop = 1;
           } else if (S.gtol >= 0) {
@@ -452,9 +453,9 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
         sh_stop = stop;
       };
 
-      for (int j = 1; j <= m; ++j) {  // line 4
+      for (int j = 1; j <= m; ++j) {  // Arnoldi step j
         const int64_t *__restrict__ vj = S.V + (size_t)(j - 1) * ldv;
-        // ---- line 5 / 5'
+        // ---- integer SpMV, then the preconditioner apply
         {
           bool o1 = false, o2 = false;
 #pragma unroll
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           }
           if (o1) record(ev_code(j, 1, 0));
           if (pre == IGM_PRE_ILU0) {
-            // line 5': integer forward and backward substitution; z, y and u
+            // preconditioner apply: integer forward and backward substitution; z, y and u
             // pass between members through device-coherent stores and loads
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
               if (row < n) st_coh(S.zbuf + row, w[k]);
             }
             team_barrier_coh(tm, tsh);
-            if (S.team == 1) {  // one workgroup, as for line 1'
+            if (S.team == 1) {  // one workgroup, as for the start step
               for (int L = 0; L < S.nflev; ++L) {
                 for (int64_t q = S.flev_ptr[L] + tid; q < S.flev_ptr[L + 1]; q += BLOCK) {
                   const int64_t row = S.flev_rows[q];
@@ -520,9 +521,9 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           if (o2) record(ev_code(j, 2, 0));
         }
         IGM_TICK(0)
-        // ---- lines 6-9: modified Gram-Schmidt, i increasing; v_{i+1} is
+        // ---- modified Gram-Schmidt, i increasing; v_{i+1} is
         // loaded before the reduction of (w, v_i) so its latency overlaps,
-        // and rotation i-2 of lines 12-14 runs inside the wait.
+        // and the earlier rotation i-2 runs inside the wait.
         int64_t vv[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -534,7 +535,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           acc.zero();
           bool o = false;
 #pragma unroll
-          for (int k = 0; k < R; ++k)  // line 7: only w is shifted
+          for (int k = 0; k < R; ++k)  // inner product: only w is shifted
             if (k < nk) acc.add(mulw(asr(w[k], S.b_dot), vv[k], o));
           if (o) record(ev_code(j, 3, 2 * (i - 1)));
           int64_t vnext[R];
@@ -557,7 +558,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
             col[i - 1] = h;
             if (i == 1) carry = h;
           }
-          // line 8: only h is shifted
+          // update of w: only h is shifted
           const int64_t hs = asr(h, S.b_axpy);
           bool ou = false;
 #pragma unroll
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           }
           IGM_TICK(1)
         }
-        // ---- line 10 (the last rotation j-1 runs during this reduction)
+        // ---- norm of w (the last rotation j-1 runs during this reduction)
         {
           Acc acc;
           acc.zero();
@@ -586,7 +587,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           if (os && tid == 0) record(ev_code(j, 4, 0));
         }
         IGM_TICK(3)
-        // ---- line 11
+        // ---- normalisation v_{j+1} = w / h_{j+1,j}
         const int64_t den = asr(hn, S.b_div_den);
         lucky = den == 0;
         if (!lucky) {
@@ -601,7 +602,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           if (ov) record(ev_code(j, 5, 0));
         }
         IGM_TICK(4)
-        // v_{j+1} becomes visible to the team; lines 15-19 run meanwhile
+        // v_{j+1} becomes visible to the team; the new rotation runs meanwhile
         team_barrier(tm, tsh, [&] {
           if (tid == kGivensThread) givens(j);
         });
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       if (ev != kNoEvent) { first_ovf = ev; status = IGM_ERR_OVERFLOW; break; }
       if (js == 0) { status = IGM_ERR_BREAKDOWN; break; }
 
-      // ---- lines 21-23 and x += gamma x^(k) (eq. (update))
+      // ---- closing least-squares step and x += gamma x^(k) (eq. (update))
       if (tid == 0) {
         for (int i = js - 1; i >= 0; --i) {  // back substitution, inner sum k increasing
           double acc = 0.0;

@@ -17,7 +17,7 @@ struct BatchSys {
   int64_t n;       // rows
   int64_t ldv;     // leading dimension of V (n rounded up to 16)
   int32_t team;    // workgroups that share the system
-  int32_t nterms;  // integer matrix terms used by line 5
+  int32_t nterms;  // integer matrix terms used by the SpMV
   int32_t m, df, precond, max_refine;
   int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
   int32_t nflev, nblev;  // ILU level sets
@@ -38,11 +38,11 @@ struct BatchSys {
   const int64_t *lptr, *uptr;    // strict triangles of the integer ILU factors
   const int32_t *lcol, *ucol;
   const int64_t *lval, *uval;
-  const double *lvalf, *uvalf;   // the same values in FP64 (line 1')
+  const double *lvalf, *uvalf;   // the same values in FP64 (start step)
   const int32_t *flev_ptr, *flev_rows, *blev_ptr, *blev_rows;
   int64_t *V;                    // (m+1) x ldv basis
   int64_t *zbuf, *wbuf;          // ILU: SpMV output and preconditioned vector
-  double *fbuf;                  // ILU: FP64 substitution of line 1'
+  double *fbuf;                  // ILU: FP64 substitution of the start step
   unsigned *lev_cnt;             // ILU: level completion counters (cleared by the kernel)
   double *x;                     // solution (in: start, out: result)
   unsigned long long *words;     // team exchange words
@@ -67,7 +67,8 @@ struct BatchResult {
   // wall-clock ticks of the first member's thread 0 per phase: 0 SpMV +
   // preconditioner, 1 inner products and updates (local work), 2 waits for
   // the inner-product sums, 3 norm, 4 normalisation, 5 FP64 refinement steps
-  // (residual, norms, lines 1'-2, lines 21-23), 6 end-of-step barriers
+  // (residual, norms, start step and cast of v1, closing least-squares step),
+  // 6 end-of-step barriers
   uint64_t phase[8];
 };
 
@@ -100,7 +101,7 @@ struct HostSystem {
   hvec<double> ahat, bhat;
   HostSetup h;
   int nterms = 1;
-  hvec<double> lvalf, uvalf;  // FP64 copies of the integer factors (line 1')
+  hvec<double> lvalf, uvalf;  // FP64 copies of the integer factors (start step)
 };
 
 // Largest m of the batched kernel (H lives in LDS).

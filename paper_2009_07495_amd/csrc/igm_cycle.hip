@@ -1,13 +1,14 @@
-// The int-GMRES(m) call of the paper (Fig. 2, lines 3-20, with the
-// preconditioned line 5' of Sec. VI and optionally lines 21-23 plus the
-// refinement update of eq. (update)) as one persistent cooperative kernel.
+// The int-GMRES(m) call of the paper (the integer loop of Fig. 2, with the
+// preconditioned product of Sec. VI, and optionally the closing FP64
+// least-squares step of Fig. 2 plus the refinement update of eq. (update)) as
+// one persistent cooperative kernel.
 //
 // Layout: thread t of workgroup b owns rows r = b*BLOCK + t + k*T (k < R,
 // T = gridDim.x*BLOCK) and keeps w_r in registers for the whole Arnoldi step;
 // consecutive lanes own consecutive rows, so every vector access and the
 // SELL-64 matrix stream are coalesced. Each inner product of the modified
 // Gram-Schmidt loop is one exact grid reduction (igm_sync.hpp). The scalar
-// work of lines 12-19 runs in thread kGivens of every workgroup on identical
+// Givens work (rotations of H and g) runs in thread kGivens of every workgroup on identical
 // data, so all workgroups take the same decisions without extra
 // communication; it is scheduled inside the waits of the grid reductions and
 // barriers. Workgroup 0 stores H, c, s, g for the caller.
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   int64_t *ss = sc + m;           // s_1..s_m
   int64_t *sg = ss + m;           // g_1..g_{m+1}
   int64_t *col = sg + m + 1;      // current column h_{1..j+1, j}
-  double *sy = (double *)(col + m + 1);  // y for lines 21-23
+  double *sy = (double *)(col + m + 1);  // y of the closing least-squares step
   __shared__ SyncShared ssh;
   __shared__ int sh_stop, sh_jstar, sh_breakdown, sh_steps, sh_update;
 
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   if (tid == 0) {
     for (int i = 0; i < m; ++i) { sc[i] = 0; ss[i] = 0; }
     for (int i = 0; i <= m; ++i) { sg[i] = 0; col[i] = 0; }
-    sg[0] = (int64_t)1 << df;  // line 3
+    sg[0] = (int64_t)1 << df;  // g = e_1 in Q.df
     ssh.abort = 0; ssh.flag = 0;
     sh_stop = 0; sh_jstar = m; sh_breakdown = 0; sh_steps = 0;
   }
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   int64_t carry = 0;  // rotated lower entry of the current column (thread kGivens)
   int64_t hn = 0;     // h_{j+1,j}
   bool lucky = false;
-  // rotation i (1-based) of lines 12-14 on (carry, col[i]); thread kGivens only
+  // earlier rotation i (1-based) on (carry, col[i]); thread kGivens only
   auto rotate = [&](int j, int i) {
     const int64_t x0 = asr(carry, a.b_rot), x1 = asr(col[i], a.b_rot);
     const int64_t c = sc[i - 1], s = ss[i - 1];
@@ -97,16 +98,16 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     carry = asr(bot, df - a.b_rot);
     if (o) atomicMin((long long *)first, (long long)ev_code(j, 6, i));
   };
-  // lines 15-19 for column j on (carry, hn); thread kGivens only
+  // radius, new rotation, rotation of g and H update for column j on (carry, hn); thread kGivens only
   auto givens = [&](int j) {
     col[j - 1] = carry;
     col[j] = hn;
-    bool o = false;  // line 15
+    bool o = false;  // rotation radius t_mp
     const int64_t p0 = asr(col[j - 1], a.b_tmp), p1 = asr(col[j], a.b_tmp);
     const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
     const int64_t tmp = shl(isqrt64(ssq), a.b_tmp, o);
     if (o) atomicMin((long long *)first, (long long)ev_code(j, 7, 0));
-    const int64_t den2 = asr(tmp, a.b_cs_den);  // line 16
+    const int64_t den2 = asr(tmp, a.b_cs_den);  // new rotation c_j, s_j
     int stop = 0;
     if (den2 == 0) {
       sh_breakdown = 2;
@@ -120,13 +121,13 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       if (oc) atomicMin((long long *)first, (long long)ev_code(j, 8, 0));
       sc[j - 1] = cj;
       ss[j - 1] = sj;
-      bool og = false;  // line 17, both from the old g_j
+      bool og = false;  // rotation of g, both from the old g_j
       const int64_t gj = sg[j - 1];
       const int64_t msj = subc(0, sj, og);
       sg[j - 1] = asr(mulw(gj, cj, og), df);
       sg[j] = asr(mulw(gj, msj, og), df);
       if (og) atomicMin((long long *)first, (long long)ev_code(j, 9, 0));
-      col[j - 1] = tmp;  // lines 18-19
+      col[j - 1] = tmp;  // h_jj = t_mp, h_{j+1,j} = 0
       col[j] = 0;
       if (lucky) {
         sh_breakdown = 1;
@@ -148,9 +149,9 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     sh_stop = stop;
   };
 
-  for (int j = 1; j <= m; ++j) {  // line 4
+  for (int j = 1; j <= m; ++j) {  // Arnoldi step j
     const int64_t *__restrict__ vj = a.V + (size_t)(j - 1) * a.npad;
-    // ---- line 5 / 5'
+    // ---- integer SpMV, then the preconditioner apply
     if (PRE != IGM_PRE_ILU0) {
       bool o1 = false, o2 = false;
 #pragma unroll
@@ -191,9 +192,9 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       for (int k = 0; k < R; ++k) w[k] = ld_coh(a.wbuf + gt + k * T);  // padded rows hold 0
     }
     IGM_TICK(0)
-    // ---- lines 6-9: modified Gram-Schmidt, i increasing. v_{i+1} is loaded
+    // ---- modified Gram-Schmidt, i increasing. v_{i+1} is loaded
     // before waiting for the grid sum of (w, v_i) so its latency overlaps.
-    // Rotation i of lines 12-14 needs only h_{i+1,j}, so thread kGivens
+    // Earlier rotation i needs only h_{i+1,j}, so thread kGivens
     // applies rotation q-2 while wavefront 0 waits for reduction q.
     int64_t vv[R];
 #pragma unroll
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       acc.zero();
       bool o = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) acc.add(mulw(asr(w[k], a.b_dot), vv[k], o));  // line 7: only w is shifted
+      for (int k = 0; k < R; ++k) acc.add(mulw(asr(w[k], a.b_dot), vv[k], o));  // inner product: only w is shifted
       note_event(o, first, ev_code(j, 3, 2 * (i - 1)));
       int64_t vnext[R];
       if (i < j) {
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
         col[i - 1] = h;
         if (i == 1) carry = h;
       }
-      // line 8: only h is shifted
+      // update of w: only h is shifted
       const int64_t hs = asr(h, a.b_axpy);
       bool ou = false;
 #pragma unroll
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       }
       IGM_TICK(1)
     }
-    // ---- line 10 (the last rotation j-1 runs during this reduction)
+    // ---- norm of w (the last rotation j-1 runs during this reduction)
     {
       Acc acc;
       acc.zero();
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       if (os && tid == 0) atomicMin((long long *)first, (long long)ev_code(j, 4, 0));
     }
     IGM_TICK(3)
-    // ---- line 11
+    // ---- normalisation v_{j+1} = w / h_{j+1,j}
     const int64_t den = asr(hn, a.b_div_den);
     lucky = den == 0;
     if (!lucky) {
@@ -267,8 +268,8 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       note_event(ov, first, ev_code(j, 5, 0));
     }
     IGM_TICK(4)
-    // v_{j+1} becomes visible to every workgroup; lines 15-19 (thread
-    // kGivens) run while wavefront 0 waits
+    // v_{j+1} becomes visible to every workgroup; the new rotation and the
+    // update of g and H (thread kGivens) run while wavefront 0 waits
 #if IGM_COH_V
     grid_barrier_coh(gs, ssh, [&] {
       if (tid == kGivens) givens(j);
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
   }
 #undef IGM_TICK
   if (!a.update || ssh.abort) return;
-  // ---- lines 21-23 and x += gamma x^(k): each thread updates its own rows
+  // ---- closing least-squares step and x += gamma x^(k): each thread updates its own rows
   if (tid == 0) {
     const int64_t ev = __hip_atomic_load(first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     sh_update = (ev == kNoEvent && sh_jstar > 0);

@@ -140,7 +140,7 @@ struct CycleArgs {
   CycleState *state;
   unsigned long long *sync;  // 2 * kSyncGroups * sync_cap words
   int32_t sync_cap;
-  int32_t update;            // apply lines 21-23 and x += gamma x^(k)
+  int32_t update;            // apply the closing least-squares step of Fig. 2 and x += gamma x^(k)
   int32_t phase_clock;       // record the phase clocks of workgroup 0
   double *x;
   const double *scal;        // device: {gamma, rho}

@@ -1,4 +1,5 @@
-// FP64 refinement kernels (Sec. IV, Fig. 1; Fig. 2 lines 1'-2) and the
+// FP64 refinement kernels (Sec. IV, Fig. 1; the start step and cast of Fig. 2
+// and Sec. VI) and the
 // standalone integer kernels behind the kernel-level entry points.
 //
 // FP64 rules: no contraction (built with -ffp-contract=off), each row sums its
@@ -139,7 +140,8 @@ __global__ void k_fin_norm(const unsigned long long *red, double *out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = dnrm_finish(red + kRedSumX, red[kRedMuX]);
 }
 
-// Line 1' for the diagonal or identity preconditioner, fused with eq. (scale):
+// FP64 start step (Sec. VI) for the diagonal or identity preconditioner, fused
+// with eq. (scale):
 // bk = r / gamma, r0 = (bk / Lbar_ii) / Ubar_ii.
 __global__ __launch_bounds__(kB) void k_scale_diag(int64_t n, const double *__restrict__ r, const double *scal,
                                                    const int64_t *__restrict__ ld, const int64_t *__restrict__ ud,
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(kB) void k_scale(int64_t n, const double *__restric
   if (i < n) bk[i] = r[i] / scal[kScalGamma];
 }
 
-// Line 1' with ILU(0): the FP64 substitution with the integer factors
+// FP64 start step (Sec. VI) with ILU(0): the FP64 substitution with the integer factors
 // converted to double, forward y_i = (bk_i - sum L_ij y_j) / Lbar_ii, then
 // backward u_i = (y_i - sum U_ij u_j) / Ubar_ii in place; each row sums in CSR
 // order. One launch per direction; every row waits only for the level below
@@ -195,7 +197,7 @@ __global__ void k_fin_rho(const unsigned long long *red, double *scal, CycleStat
   if (!(rho > 0.0) || !(rho <= 1.7976931348623157e308)) st->range_err = 1;
 }
 
-// Line 2 (Sec. V-D.1): v1 = trunc(2^df r0 / rho), with a range check.
+// Cast of v1 to Q.df (Fig. 2; Sec. V-D.1): v1 = trunc(2^df r0 / rho), with a range check.
 __global__ __launch_bounds__(kB) void k_cast_v1(int64_t n, const double *__restrict__ r0, const double *scal, int df,
                                                 int64_t *v1, CycleState *st) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
@@ -245,7 +247,8 @@ __global__ __launch_bounds__(kB) void k_upper_level(CycleArgs a, int32_t lo, int
   note_event(o, &a.state->first_ovf, ev_code(1, 2, 0));
 }
 
-// Line 7 (mode 0: h = asr(sum asr(w, b) v, df - b)) or line 10 (mode 1:
+// Gram-Schmidt inner product (mode 0: h = asr(sum asr(w, b) v, df - b)) or the
+// norm of w (mode 1:
 // h = shl(isqrt(sum asr(w, b)^2), b)) in one launch: each workgroup adds its
 // rows into an exact Acc and stores it with device-coherent stores; the last
 // workgroup to take a ticket adds all of them and finishes. The ticket word
@@ -362,8 +365,8 @@ hipError_t launch_fin_norm(hipStream_t st, const unsigned long long *red, double
   return hipGetLastError();
 }
 
-hipError_t launch_line1(hipStream_t st, const CycleArgs &a, const double *r, double *scal, const double *lvalf,
-                        const double *uvalf, double *bk, double *r0, unsigned long long *red) {
+hipError_t launch_start_vector(hipStream_t st, const CycleArgs &a, const double *r, double *scal, const double *lvalf,
+                               const double *uvalf, double *bk, double *r0, unsigned long long *red) {
   const int64_t n = a.n;
   if (a.precond != IGM_PRE_ILU0) {
     hipLaunchKernelGGL(k_scale_diag, dim3(blocks_for(n)), dim3(kB), 0, st, n, r, (const double *)scal, a.ldiag,

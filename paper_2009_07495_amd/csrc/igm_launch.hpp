@@ -31,8 +31,8 @@ hipError_t launch_dnrm_sum(hipStream_t st, int64_t n, const double *x, const uns
                            unsigned long long *limbs);
 hipError_t launch_fin_residual(hipStream_t st, const unsigned long long *red, const double *norms, double *scal);
 hipError_t launch_fin_norm(hipStream_t st, const unsigned long long *red, double *out);
-hipError_t launch_line1(hipStream_t st, const CycleArgs &a, const double *r, double *scal, const double *lvalf,
-                        const double *uvalf, double *bk, double *r0, unsigned long long *red);
+hipError_t launch_start_vector(hipStream_t st, const CycleArgs &a, const double *r, double *scal, const double *lvalf,
+                               const double *uvalf, double *bk, double *r0, unsigned long long *red);
 hipError_t launch_spmv(hipStream_t st, const CycleArgs &a, int nterms, const int64_t *v, int64_t *z);
 hipError_t launch_precond(hipStream_t st, const CycleArgs &a, const int64_t *z, int64_t *w);
 hipError_t launch_reduce(hipStream_t st, int64_t n, const int64_t *w, const int64_t *v, int b, int df, int mode,

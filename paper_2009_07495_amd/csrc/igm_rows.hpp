@@ -38,7 +38,7 @@ __device__ __forceinline__ void row_visit(int64_t lo, int64_t hi, const int32_t 
   }
 }
 
-// Line 5 for one row (Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_l
+// Integer SpMV for one row (Fig. 2; Sec. V-C.3, eq. (matvec)): z = A_0 v + sum_l
 // asr(A_l v, alpha_l), the matrices in SELL-64 layout (slice = 64 rows stored
 // column-major, so the 64 lanes of a wavefront read consecutive words). Every
 // sum is exact; `ovf` is set if a product, a term or the total leaves int64.
@@ -79,7 +79,7 @@ __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64
   return tot.value(ovf);
 }
 
-// Line 5' forward substitution for one row: y_i = tdiv(z_i - sum_{j<i}
+// Preconditioner apply (Sec. VI), forward substitution for one row: y_i = tdiv(z_i - sum_{j<i}
 // Lbar_ij y_j, Lbar_ii) (COH: y read with device-coherent loads).
 template <bool COH = false, class A>
 __device__ __forceinline__ int64_t lower_row(const A &a, int64_t row, int64_t zi, const int64_t *y, bool &ovf) {
@@ -91,7 +91,7 @@ __device__ __forceinline__ int64_t lower_row(const A &a, int64_t row, int64_t zi
   return tdiv(acc.value(ovf), a.ldiag[row], ovf);
 }
 
-// Line 5' backward substitution for one row: u_i = tdiv(y_i - sum_{j>i}
+// Preconditioner apply (Sec. VI), backward substitution for one row: u_i = tdiv(y_i - sum_{j>i}
 // Ubar_ij u_j, Ubar_ii).
 template <bool COH = false, class A>
 __device__ __forceinline__ int64_t upper_row(const A &a, int64_t row, int64_t yi, const int64_t *u, bool &ovf) {
@@ -103,7 +103,7 @@ __device__ __forceinline__ int64_t upper_row(const A &a, int64_t row, int64_t yi
   return tdiv(acc.value(ovf), a.udiag[row], ovf);
 }
 
-// FP64 row of the triangular substitution of line 1': (b - sum_e f_e x_col) /
+// FP64 row of the triangular substitution of the start step (Sec. VI): (b - sum_e f_e x_col) /
 // d, the sum in CSR order.
 template <bool COH = false>
 __device__ __forceinline__ double fp_sub_row(int64_t lo, int64_t hi, const int32_t *__restrict__ col,
@@ -144,7 +144,7 @@ __device__ __forceinline__ void residual_row(int64_t lo, int64_t hi, const int32
   rhat = bhat - acch;
 }
 
-// Line 11 for one element: sc(tdiv(shl(w, b1), den), df - b1 - b2).
+// Normalisation v = w / h (Fig. 2) for one element: sc(tdiv(shl(w, b1), den), df - b1 - b2).
 __device__ __forceinline__ int64_t normalize_elem(int64_t w, int64_t den, int b1, int sc_exp, bool &ovf) {
   return scale2(tdiv(shl(w, b1, ovf), den, ovf), sc_exp, ovf);
 }

@@ -95,13 +95,13 @@ bool adjust_shifts(igm_policy &p, int64_t code) {
     return true;
   };
   switch (stage) {
-    case 3: return (code & 1) == 0 ? raise(p.b_dot) : raise(p.b_axpy);  // line 7 (even sub) / line 8
-    case 4: return raise(p.b_norm);                                      // line 10
-    case 5: return lower(p.b_div_num, p.b_div_den);                      // line 11
-    case 6: return raise(p.b_rot);                                       // line 13
-    case 7: return raise(p.b_tmp);                                       // line 15
-    case 8: return lower(p.b_cs_num, p.b_cs_den);                        // line 16
-    default: return false;                                               // lines 5, 5', 17
+    case 3: return (code & 1) == 0 ? raise(p.b_dot) : raise(p.b_axpy);  // inner product (even sub) / update
+    case 4: return raise(p.b_norm);                                      // norm of w
+    case 5: return lower(p.b_div_num, p.b_div_den);                      // normalisation
+    case 6: return raise(p.b_rot);                                       // earlier rotations
+    case 7: return raise(p.b_tmp);                                       // rotation radius
+    case 8: return lower(p.b_cs_num, p.b_cs_den);                        // new rotation
+    default: return false;                                               // SpMV, preconditioner, rotation of g
   }
 }
 

@@ -1,5 +1,5 @@
 // Level-scheduled triangular sweeps of the integer ILU(0) preconditioner
-// (line 5' of Sec. VI) without a barrier per level.
+// (the preconditioner apply of Sec. VI) without a barrier per level.
 //
 // The rows of a triangular factor are grouped into level sets (every row
 // depends only on rows of lower levels) and stored level by level, so the
@@ -41,7 +41,7 @@ constexpr int kSweepPre = IGM_SWEEP_PRE;
 
 // One sweep. Integer (FP = false): y = tdiv(src - Lbar_strict y, Lbar_ii)
 // (LOWER, src = z) or u = tdiv(src - Ubar_strict u, Ubar_ii), the sums exact.
-// FP64 (FP = true, line 1'): the same substitution with the factors' values
+// FP64 (FP = true, the start step of Sec. VI): the same substitution with the factors' values
 // in FP64, each row summed in CSR order and then divided by its diagonal.
 // src == dst is allowed (in place): row i reads src only at i and dst only at
 // its neighbours, which precede it in the order. `a` is any record with the

@@ -83,7 +83,7 @@ int main(void) {
   csr a = poisson(12);
   for (int w = 0; w < 3; ++w) bad += solve(&a, preset(w), ORC_OK, NULL);
   orc_policy z = preset(0);
-  z.b_dot = z.b_axpy = z.b_norm = z.b_rot = z.b_tmp = 0; /* overflows in line 7 */
+  z.b_dot = z.b_axpy = z.b_norm = z.b_rot = z.b_tmp = 0; /* overflows in the inner product */
   bad += solve(&a, z, ORC_ERR_OVERFLOW, NULL);
   int32_t r = 0;
   z.shift_retry = 40;

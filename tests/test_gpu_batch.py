@@ -91,7 +91,7 @@ def test_batch_teams_of_many_workgroups(orc, torch):
 @pytest.mark.parametrize("block,rows", [(1024, 4), (256, 8)])
 def test_batch_ilu_bit_exact(orc, torch, block, rows):
     """ILU(0) preconditioned systems (Sec. VI): level-scheduled integer sweeps
-    and the FP64 substitution of line 1' inside a team, including teams of
+    and the FP64 substitution of the start step inside a team, including teams of
     several workgroups (the 4800- and 7007-row systems at 2048 rows each)."""
     systems = [W.random27(9, 8, 6, seed=61), W.random_dd(300, 0.05, 62), W.random27(20, 20, 12, seed=63),
                W.convdiff2d(91, 77, seed=64), W.random27(5, 4, 3, seed=65)]

@@ -43,7 +43,7 @@ def torch():
 
 def first_v1(o, n):
     r, _ = o.residual(np.zeros(n))
-    return o.line1(r)["v1"]
+    return o.start_vector(r)["v1"]
 
 
 def assert_trace_equal(tg, to, n):

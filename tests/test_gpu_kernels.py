@@ -112,7 +112,7 @@ def test_dot_norm_axpy_normalize_bit_exact(orc, torch, name):
 
 def test_normalize_zero_denominator_is_breakdown(orc, torch):
     s = W.poisson2d(9, 7)
-    g = B.System.from_system(s, "paper_noprec")  # line 11 divides by asr(h, 14)
+    g = B.System.from_system(s, "paper_noprec")  # the normalisation divides by asr(h, 14)
     w = dev(torch, np.ones(s.n, dtype=np.int64))
     v = torch.zeros(s.n, dtype=torch.int64, device="cuda")
     with pytest.raises(B.IgmError) as e:
@@ -131,7 +131,7 @@ def test_reduction_overflow_flags(orc, torch):
 
 
 @pytest.mark.parametrize("name", [s[0] for s in SYSTEMS])
-def test_residual_and_line1_bit_exact(orc, torch, name):
+def test_residual_and_start_vector_bit_exact(orc, torch, name):
     s, o, g = pair(orc, name)
     rng = np.random.default_rng(4)
     for x in (np.zeros(s.n), rng.standard_normal(s.n)):
@@ -141,10 +141,10 @@ def test_residual_and_line1_bit_exact(orc, torch, name):
         g.residual(dev(torch, x), r, rh)
         assert np.array_equal(r.cpu().numpy(), r_o)
         assert np.array_equal(rh.cpu().numpy(), rh_o)
-        l1 = o.line1(r_o)
+        l1 = o.start_vector(r_o)
         bk, r0 = torch.zeros_like(r), torch.zeros_like(r)
         v1 = torch.zeros(s.n, dtype=torch.int64, device="cuda")
-        st, gamma, rho = g.line1(r, bk, r0, v1)
+        st, gamma, rho = g.start_vector(r, bk, r0, v1)
         assert st == B.OK and gamma == l1["gamma"] and rho == l1["rho"]
         assert np.array_equal(bk.cpu().numpy(), l1["bk"])
         assert np.array_equal(r0.cpu().numpy(), l1["r0"])

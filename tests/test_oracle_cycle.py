@@ -6,8 +6,8 @@ wrong sign, a wrong index or a swapped operand would break:
   * SpMV = exact integer matrix-vector product (eq. (matvec));
   * integer sweeps satisfy the truncated-division residual property;
   * after the rotations H is upper triangular, |g| is non-increasing (Sec.
-    V-D.3, line 17), c^2 + s^2 = 1, the basis is normalised with its upper
-    bits zero (Sec. V-D.2, line 7);
+    V-D.3, rotation of g), c^2 + s^2 = 1, the basis is normalised with its
+    upper bits zero (Sec. V-D.2, inner product);
   * the GMRES residual identity rho |g_{j+1}| = ||Mbar^-1 (b - Abar x_j)||;
   * each rotated column matches one FP64 MGS step on the oracle's own basis;
   * A = c I breaks down at j = 1.
@@ -105,7 +105,7 @@ def test_precond_truncated_substitution(orc, preset):
 
 
 def residual_sequence(tr):
-    """|g_{j+1}| right after step j (line 17), before step j+1 rotates it:
+    """|g_{j+1}| right after step j (rotation of g), before step j+1 rotates it:
     G_0 = 2^df, G_{j+1} = floor(-s_j G_j / 2^df); also checks that the stored
     g_j equals floor(c_j G_j / 2^df)."""
     G = [1 << 30]
@@ -120,7 +120,7 @@ def residual_sequence(tr):
 def run_cycle(orc, sysm, preset, m, **kw):
     o = make(orc, sysm, preset, m=m, **kw)
     r, _ = o.residual(np.zeros(sysm.n))
-    l1 = o.line1(r)
+    l1 = o.start_vector(r)
     assert l1["status"] == orc.OK
     tr = o.cycle(l1["v1"])
     return o, l1, tr
@@ -144,12 +144,12 @@ def test_cycle_invariants(orc, name, gen, preset, m):
     pol = o.pol
     G = residual_sequence(tr)
     for j in range(js):
-        assert H[j + 1, j] == 0  # line 19
+        assert H[j + 1, j] == 0  # set to zero after the new rotation
         assert np.all(H[j + 2:, j] == 0)  # upper triangular after the rotations
         assert H[j, j] > 0
         cs = float(c[j]) ** 2 + float(sn[j]) ** 2
-        # rotation is orthonormal up to the truncation of t (line 15) and of the
-        # shifted denominator (line 16), both relative to t
+        # rotation is orthonormal up to the truncation of t (rotation radius) and
+        # of the shifted denominator (new rotation), both relative to t
         tol_cs = 4.0 * ((1 << pol["b_cs_den"]) + (1 << pol["b_tmp"])) / float(H[j, j]) + 2.0 ** -26
         assert abs(cs / 2.0 ** 60 - 1.0) < tol_cs
         assert abs(G[j + 1]) <= abs(G[j]) * (1 + 2.0 ** -12) + 2  # residual non-increasing
@@ -179,7 +179,7 @@ def dense_mbar_inv(o, sysm):
 @pytest.mark.parametrize("name,gen,preset,m", CASES)
 def test_gmres_residual_identity(orc, name, gen, preset, m):
     """rho |g_{j+1}| 2^-df equals the preconditioned residual norm of the
-    iterate built from the first j columns (lines 21-23), up to the fixed-point
+    iterate built from the first j columns (closing least-squares step), up to the fixed-point
     rounding of the basis."""
     s = gen()
     o, l1, tr = run_cycle(orc, s, preset, m)
@@ -208,7 +208,7 @@ def test_columns_match_fp64_mgs_step(orc, name, gen, preset, m):
     integers), do one FP64 Arnoldi/MGS step for column j, apply the oracle's
     rotations c_i, s_i (i < j) in FP64, and compare with the stored rotated
     column, t = H_jj and (c_j, s_j) = (h_jj, h_j+1,j) / t. A wrong index, a
-    dropped term or a sign error in lines 5-19 breaks this at the first column
+    dropped term or a sign error in the Arnoldi step or its rotations breaks this at the first column
     where it acts; fixed-point rounding only costs ~2^-30 (or 2^-14 with the
     16-bit shifts)."""
     s = gen()
@@ -239,9 +239,10 @@ def test_columns_match_fp64_mgs_step(orc, name, gen, preset, m):
 
 
 def test_scalar_matrix_breaks_down_at_step_one(orc):
-    """A = 3 I, b = -2 e_5 with the Jacobi preset: v1 = 2^30 e_5 exactly, line 8
-    leaves w = 0, so line 11 meets a zero denominator at j = 1 and the single
-    column gives the exact solution x = b / 3."""
+    """A = 3 I, b = -2 e_5 with the Jacobi preset: v1 = 2^30 e_5 exactly, the
+    Gram-Schmidt update leaves w = 0, so the normalisation meets a zero
+    denominator at j = 1 and the single column gives the exact solution
+    x = b / 3."""
     n = 20
     b = np.zeros(n)
     b[5] = -2.0
@@ -256,8 +257,9 @@ def test_scalar_matrix_breaks_down_at_step_one(orc):
 
 
 def test_singular_direction_gives_no_column(orc):
-    """A v1 = 0: lines 10 and 15 both give 0, line 16 has a zero denominator and
-    no column is usable; the refinement driver reports the breakdown."""
+    """A v1 = 0: the norm and the rotation radius both give 0, the new
+    rotation has a zero denominator and no column is usable; the refinement
+    driver reports the breakdown."""
     a = np.array([[1.0, 1.0], [1.0, 1.0]])
     s = W.from_dense(a, np.array([1.0, -1.0]))
     o, l1, tr = run_cycle(orc, s, "paper_noprec", 5)

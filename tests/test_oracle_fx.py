@@ -212,7 +212,7 @@ def test_dnrm_matches_textbook_norm_and_is_order_free(orc):
 
 
 def test_dot_shifts_first_operand_only(orc):
-    """Table II line 7: w (first operand) is divided by 2^beta, v is not. With
+    """Table II, inner product: w (first operand) is divided by 2^beta, v is not. With
     v = 1.0 in Q30 (2^30) the result is sum_l floor(w_l / 2^b) 2^b, i.e. w with
     its low b bits dropped; shifting v instead would keep them."""
     rng = np.random.default_rng(30)

@@ -71,7 +71,7 @@ def test_multiterm_matrix_solve(orc):
 
 def test_overflow_is_reported_with_its_position(orc):
     """The no-preconditioner shifts (beta = 16) with alpha_a = 40 overflow the
-    line 11 numerator shift (|w| 2^(30+16) >= 2^63) in the first step."""
+    normalisation's numerator shift (|w| 2^(30+16) >= 2^63) in the first step."""
     s = W.poisson2d(16)
     o = make(orc, s, "paper_noprec", alpha_a=40)
     x, st = o.solve()
@@ -135,7 +135,8 @@ def test_shift_retry_rule_by_stage(orc):
         changed, p = orc.shift_retry(base, c)
         assert changed and p[key] == val, (hex(c), key, p[key])
         assert all(p[k] == base[k] for k in SHIFT_KEYS if k != key)
-    # no shift can prevent an overflow in lines 5, 5' or 17, or without an event
+    # no shift can prevent an overflow in the SpMV, the preconditioner apply or
+    # the rotation of g, or without an event
     for c in (code(1, 1), code(1, 2), code(1, 9), orc.NO_EVENT):
         assert orc.shift_retry(base, c)[0] is False
     # limits: raised shifts stop at df; a division's numerator exponent goes
@@ -172,7 +173,7 @@ def test_shift_retry_limit_and_unretryable_stage(orc):
     s = W.poisson2d(16)
     o = make(orc, s, "paper_noprec", shift_retry=3, **ZERO_SHIFTS)
     x, st = o.solve()
-    # three raises of b_dot (0 -> 12) are not enough: still the line 7 overflow
+    # three raises of b_dot (0 -> 12) are not enough: still the inner-product overflow
     assert st["status"] == orc.ERR_OVERFLOW and st["shift_retries"] == 3
     assert o.policy_now()["b_dot"] == 12 and (st["first_ovf"] >> 16) & 0xFF == 3
     assert np.all(x == 0)
