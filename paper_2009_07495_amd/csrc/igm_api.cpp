@@ -166,7 +166,7 @@ igm_status alloc_work(igm_system *s) {
   IGM_TRY(dalloc(s, s->d_g, m + 1));
   IGM_TRY(dalloc(s, s->d_state, 1));
   IGM_TRY(dalloc(s, s->d_sync, (size_t)2 * kSyncGroups * cap));
-  IGM_TRY(dalloc(s, s->d_red, kRedWords));
+  IGM_TRY(dalloc(s, s->d_red, kRedTotal));
   IGM_TRY(dalloc(s, s->d_scal, kScalWords));
   IGM_TRY(dalloc(s, s->d_parts, kMaxReduceParts + 1));  // partials, then the ticket (zeroed here)
   if (hipHostMalloc((void **)&s->h_pinned, 64 * sizeof(double)) != hipSuccess) return IGM_ERR_OOM;
@@ -174,7 +174,7 @@ igm_status alloc_work(igm_system *s) {
 }
 
 igm_status device_norm(igm_system *s, const double *x, int64_t len, double *out_dev) {
-  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
   IGM_HIP(launch_absmax(s->stream, len, x, s->d_red + kRedMuX));
   IGM_HIP(launch_dnrm_sum(s->stream, len, x, s->d_red + kRedMuX, s->d_red + kRedSumX));
   IGM_HIP(launch_fin_norm(s->stream, s->d_red, out_dev));
@@ -307,7 +307,7 @@ igm_status solve_dev(igm_system *s, double *x) {
   for (int k = 0;; ++k) {
     TraceRange trace_refinement("igm refinement");
     // top of refinement k+1: residuals, relres, gamma
-    IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+    IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
     IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
                             s->d_cscale, s->d_r, s->d_rhat, s->d_red));
     IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_r, s->d_red + kRedMuR, s->d_red + kRedSumR));
@@ -645,7 +645,7 @@ igm_status igm_normalize(igm_system *s, const int64_t *w, int64_t h, int64_t *v,
 
 igm_status igm_residual(igm_system *s, const double *x, double *r, double *rhat) {
   if (!s || !x || !r || !rhat) return IGM_ERR_ARG;
-  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
   IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
                           s->d_cscale, r, rhat, s->d_red));
   IGM_HIP(hipStreamSynchronize(s->stream));
@@ -664,16 +664,15 @@ igm_status igm_start_vector(igm_system *s, const double *r, double *bk, double *
                             double *rho) {
   if (!s || !r || !bk || !r0 || !v1 || !gamma || !rho) return IGM_ERR_ARG;
   IGM_TRY(reset_state(s));
-  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedWords, s->stream));
+  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
   IGM_HIP(launch_absmax(s->stream, s->n, r, s->d_red + kRedMuR));
-  IGM_HIP(hipMemcpyAsync(s->h_pinned, s->d_red + kRedMuR, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  IGM_HIP(launch_fin_max(s->stream, s->d_red + kRedMuR, s->d_scal + kScalGamma));
+  IGM_HIP(hipMemcpyAsync(s->h_pinned, s->d_scal + kScalGamma, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   IGM_HIP(hipStreamSynchronize(s->stream));
   const double g = s->h_pinned[0];
   *gamma = g;
   *rho = 0.0;
   if (g == 0.0) return IGM_OK;
-  IGM_HIP(hipMemcpyAsync(s->d_scal + kScalGamma, s->d_red + kRedMuR, sizeof(double), hipMemcpyDeviceToDevice,
-                         s->stream));
   CycleArgs a = make_args(s);
   a.V = v1;  // the cast of v1 writes its output as the first basis vector
   IGM_HIP(launch_start_vector(s->stream, a, r, s->d_scal, s->d_lvalf, s->d_uvalf, bk, r0, s->d_red));

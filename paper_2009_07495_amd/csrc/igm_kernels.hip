@@ -26,6 +26,19 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
+// The copy of reduction word w that this workgroup adds into.
+__device__ __forceinline__ unsigned long long *red_copy(unsigned long long *w) {
+  return w + (blockIdx.x % kRedCopies) * kRedWords;
+}
+
+// Maximum over the copies of reduction word w.
+__device__ __forceinline__ unsigned long long red_max(const unsigned long long *w) {
+  unsigned long long m = 0;
+#pragma unroll
+  for (int c = 0; c < kRedCopies; ++c) m = w[c * kRedWords] > m ? w[c * kRedWords] : m;
+  return m;
+}
+
 // Max of non-negative doubles through their bit patterns (monotone for
 // non-negative values; NaN patterns sort above infinity).
 __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long *dst) {
@@ -36,7 +49,7 @@ __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long
   if (threadIdx.x == 0) {
     unsigned long long m = 0;
     for (int k = 0; k < kB / 64; ++k) m = sh[k] > m ? sh[k] : m;
-    if (m) atomicMax(dst, m);
+    if (m) atomicMax(red_copy(dst), m);
   }
 }
 
@@ -76,7 +89,7 @@ __global__ __launch_bounds__(kB) void k_absmax(int64_t n, const double *__restri
 // Exact sum of floor(2^96 (x_i / mu)^2) as three 40-bit limbs.
 __global__ __launch_bounds__(kB) void k_dnrm_sum(int64_t n, const double *__restrict__ x,
                                                  const unsigned long long *mu_bits, unsigned long long *limbs) {
-  const double mu = __longlong_as_double((long long)*mu_bits);
+  const double mu = __longlong_as_double((long long)red_max(mu_bits));
   unsigned long long l0 = 0, l1 = 0, l2 = 0;
   if (mu > 0.0 && mu <= 1.7976931348623157e308) {
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
@@ -107,18 +120,23 @@ __global__ __launch_bounds__(kB) void k_dnrm_sum(int64_t n, const double *__rest
     s0 &= kLimbMask;
     s2 += s1 >> 40;
     s1 &= kLimbMask;
-    if (s0) atomicAdd(limbs + 0, s0);
-    if (s1) atomicAdd(limbs + 1, s1);
-    if (s2) atomicAdd(limbs + 2, s2);
+    unsigned long long *dst = red_copy(limbs);
+    if (s0) atomicAdd(dst + 0, s0);
+    if (s1) atomicAdd(dst + 1, s1);
+    if (s2) atomicAdd(dst + 2, s2);
   }
 }
 
-// ||x|| = mu * sqrt(rn(S)) * 2^-48 with S the exact limb sum.
-__device__ double dnrm_finish(const unsigned long long *limbs, unsigned long long mu_bits) {
-  const double mu = __longlong_as_double((long long)mu_bits);
+// ||x|| = mu * sqrt(rn(S)) * 2^-48 with S the exact limb sum (all copies;
+// S <= n 2^96 < 2^128, and every partial sum is at most S).
+__device__ double dnrm_finish(const unsigned long long *limbs, const unsigned long long *mu_word) {
+  const double mu = __longlong_as_double((long long)red_max(mu_word));
   if (!(mu > 0.0) || !(mu <= 1.7976931348623157e308)) return mu;
-  unsigned __int128 S = ((unsigned __int128)limbs[2] << 80) + ((unsigned __int128)limbs[1] << 40) +
-                        (unsigned __int128)limbs[0];
+  unsigned __int128 S = 0;
+  for (int c = 0; c < kRedCopies; ++c) {
+    const unsigned long long *l = limbs + c * kRedWords;
+    S += ((unsigned __int128)l[2] << 80) + ((unsigned __int128)l[1] << 40) + (unsigned __int128)l[0];
+  }
   return mu * ldexp(sqrt(u128_to_double_rn(S)), -48);
 }
 
@@ -129,15 +147,19 @@ __device__ __forceinline__ double relres(double rn, double bn) {
 
 __global__ void k_fin_residual(const unsigned long long *red, const double *norms, double *scal) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double rn = dnrm_finish(red + kRedSumR, red[kRedMuR]);
-  const double rhn = dnrm_finish(red + kRedSumRhat, red[kRedMuRhat]);
-  scal[kScalGamma] = __longlong_as_double((long long)red[kRedMuR]);
+  const double rn = dnrm_finish(red + kRedSumR, red + kRedMuR);
+  const double rhn = dnrm_finish(red + kRedSumRhat, red + kRedMuRhat);
+  scal[kScalGamma] = __longlong_as_double((long long)red_max(red + kRedMuR));
   scal[kScalRelresOrig] = relres(rhn, norms[1]);
   scal[kScalRelresScaled] = relres(rn, norms[0]);
 }
 
 __global__ void k_fin_norm(const unsigned long long *red, double *out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *out = dnrm_finish(red + kRedSumX, red[kRedMuX]);
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = dnrm_finish(red + kRedSumX, red + kRedMuX);
+}
+
+__global__ void k_fin_max(const unsigned long long *w, double *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = __longlong_as_double((long long)red_max(w));
 }
 
 // FP64 start step (Sec. VI) for the diagonal or identity preconditioner, fused
@@ -192,7 +214,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_fp_sweep(FpFactors f, const int
 
 __global__ void k_fin_rho(const unsigned long long *red, double *scal, CycleState *st) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double rho = dnrm_finish(red + kRedSumR0, red[kRedMuR0]);
+  const double rho = dnrm_finish(red + kRedSumR0, red + kRedMuR0);
   scal[kScalRho] = rho;
   if (!(rho > 0.0) || !(rho <= 1.7976931348623157e308)) st->range_err = 1;
 }
@@ -252,7 +274,7 @@ __global__ __launch_bounds__(kB) void k_upper_level(CycleArgs a, int32_t lo, int
 // h = shl(isqrt(sum asr(w, b)^2), b)) in one launch: each workgroup adds its
 // rows into an exact Acc and stores it with device-coherent stores; the last
 // workgroup to take a ticket adds all of them and finishes. The ticket word
-// is zero before the launch (the launcher clears it) and the last workgroup
+// is zero when the buffer is allocated and the last workgroup of every launch
 // sets it back to zero.
 constexpr int kRB = 512;     // threads per workgroup of the standalone reductions
 constexpr int kRUnroll = 8;  // elements in flight per thread
@@ -330,9 +352,11 @@ __global__ __launch_bounds__(kB) void k_normalize(int64_t n, const int64_t *__re
 // ---- host launchers --------------------------------------------------------
 
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+// Grid-stride kernels: at most four workgroups per compute unit, so each
+// reduction copy takes at most 64 workgroup atomics.
 static inline unsigned grid_stride_blocks(int64_t n) {
   int64_t b = (n + kB - 1) / kB;
-  return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+  return (unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024);
 }
 
 hipError_t launch_residual(hipStream_t st, int64_t n, const int64_t *rp, const int32_t *col, const double *a,
@@ -362,6 +386,11 @@ hipError_t launch_fin_residual(hipStream_t st, const unsigned long long *red, co
 
 hipError_t launch_fin_norm(hipStream_t st, const unsigned long long *red, double *out) {
   hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(64), 0, st, red, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_max(hipStream_t st, const unsigned long long *w, double *out) {
+  hipLaunchKernelGGL(k_fin_max, dim3(1), dim3(64), 0, st, w, out);
   return hipGetLastError();
 }
 
@@ -437,11 +466,7 @@ hipError_t launch_reduce(hipStream_t st, int64_t n, const int64_t *w, const int6
   // per pass; parts holds kMaxReduceParts partials and then the ticket word
   const int64_t want = (n + (int64_t)kRB * kRUnroll - 1) / ((int64_t)kRB * kRUnroll);
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kMaxReduceParts));
-  unsigned *ticket = (unsigned *)(parts + kMaxReduceParts);
-  // the kernel leaves the ticket at zero; clearing it here as well keeps a
-  // launch that never finished from spoiling the next one
-  hipError_t e = hipMemsetAsync(ticket, 0, sizeof(unsigned), st);
-  if (e != hipSuccess) return e;
+  unsigned *ticket = (unsigned *)(parts + kMaxReduceParts);  // zero between launches
   hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(kRB), 0, st, n, w, v, b, df, mode, (Acc *)parts, ticket, out, state,
                      code);
   return hipGetLastError();

@@ -11,11 +11,15 @@ namespace igm {
 constexpr int kMaxReduceParts = 2048;
 
 // Scratch words of the FP64 reductions (d_red): maxima as double bit patterns,
-// exact norm sums as three 40-bit limbs.
+// exact norm sums as three 40-bit limbs. The block of kRedWords words is held
+// kRedCopies times, 256 bytes apart: workgroup b adds into copy b % kRedCopies,
+// so atomics to one word from many workgroups do not all queue on one cache
+// line; readers combine the copies (max of maxima, sum of limbs, both
+// order-free).
 enum : int {
   kRedMuR = 0, kRedMuRhat = 1, kRedMuR0 = 2, kRedMuX = 3,
   kRedSumR = 4, kRedSumRhat = 8, kRedSumR0 = 12, kRedSumX = 16,
-  kRedWords = 32
+  kRedWords = 32, kRedCopies = 16, kRedTotal = kRedWords * kRedCopies
 };
 // Device scalars (d_scal).
 enum : int {
@@ -31,6 +35,8 @@ hipError_t launch_dnrm_sum(hipStream_t st, int64_t n, const double *x, const uns
                            unsigned long long *limbs);
 hipError_t launch_fin_residual(hipStream_t st, const unsigned long long *red, const double *norms, double *scal);
 hipError_t launch_fin_norm(hipStream_t st, const unsigned long long *red, double *out);
+// *out = the maximum recorded in word w of the reduction block, as a double
+hipError_t launch_fin_max(hipStream_t st, const unsigned long long *w, double *out);
 hipError_t launch_start_vector(hipStream_t st, const CycleArgs &a, const double *r, double *scal, const double *lvalf,
                                const double *uvalf, double *bk, double *r0, unsigned long long *red);
 hipError_t launch_spmv(hipStream_t st, const CycleArgs &a, int nterms, const int64_t *v, int64_t *z);
