@@ -73,6 +73,20 @@ def test_cycle_trace_bit_exact_for_every_launch_shape(orc, torch, name, gen, pre
     assert_trace_equal(tg2, to, s.n)
 
 
+def test_cycle_trace_at_the_largest_m(orc, torch):
+    """m = 1024, the policy's maximum: all 1024 Arnoldi steps run (no
+    breakdown, no overflow) on a ragged 1100-row system, so the kernel's
+    per-call arrays (H column, rotations, g, one synchronisation slot per
+    grid sum) are exercised at their largest size."""
+    s = W.random_dd(1100, 0.005, 77)
+    o = orc.OracleSystem.from_system(s, orc.policy("jacobi", m=1024))
+    v1 = first_v1(o, s.n)
+    to = o.cycle(v1)
+    assert to["steps"] == 1024 and to["breakdown"] == 0
+    g = B.System.from_system(s, "jacobi", m=1024)
+    assert_trace_equal(g.int_cycle(v1), to, s.n)
+
+
 def test_cycle_breakdown_cases(orc, torch):
     n = 20
     b = np.zeros(n)

@@ -160,6 +160,13 @@ def test_fp_norm_bit_exact(orc, torch):
             x = rng.standard_normal(n) * scale
             x[rng.integers(0, n)] = 0.0
             assert g.fp_norm(dev(torch, x), n) == orc.dnrm(x), (n, scale)
+    # more elements than one pass of the capped grid-stride launch, with the
+    # largest entry first or last (the maxima land in different copies of
+    # the reduction words)
+    for pos in (0, -1):
+        x = rng.uniform(-1.0, 1.0, 300001)
+        x[pos] = -7.5
+        assert g.fp_norm(dev(torch, x), x.size) == orc.dnrm(x), pos
     x = np.array([3.0, 4.0])
     assert g.fp_norm(dev(torch, x), 2) == 5.0
     assert g.fp_norm(dev(torch, np.zeros(10)), 10) == 0.0
