@@ -31,6 +31,13 @@ namespace {
     if (st_ != IGM_OK) return st_;     \
   } while (0)
 
+// Layout of the system's pinned host area (doubles): device scalars after the
+// latest residual step and after the latest int-GMRES call, the call's state,
+// and the constant initial state that every call starts from.
+constexpr int kPinResidual = 0, kPinCall = 8, kPinState = 16, kPinInit = 32, kPinDoubles = 64;
+static_assert(kScalWords <= 8, "scalar blocks");
+static_assert(sizeof(CycleState) <= 16 * sizeof(double), "state blocks");
+
 template <class T>
 igm_status dalloc(igm_system *s, T *&p, size_t count) {
   size_t bytes = sizeof(T) * (count ? count : 1);
@@ -169,7 +176,10 @@ igm_status alloc_work(igm_system *s) {
   IGM_TRY(dalloc(s, s->d_red, kRedTotal));
   IGM_TRY(dalloc(s, s->d_scal, kScalWords));
   IGM_TRY(dalloc(s, s->d_parts, kMaxReduceParts + 1));  // partials, then the ticket (zeroed here)
-  if (hipHostMalloc((void **)&s->h_pinned, 64 * sizeof(double)) != hipSuccess) return IGM_ERR_OOM;
+  if (hipHostMalloc((void **)&s->h_pinned, kPinDoubles * sizeof(double)) != hipSuccess) return IGM_ERR_OOM;
+  memset(s->h_pinned, 0, kPinDoubles * sizeof(double));
+  CycleState *init = (CycleState *)(s->h_pinned + kPinInit);  // constant from here on
+  init->first_ovf = kNoEvent;
   return IGM_OK;
 }
 
@@ -260,10 +270,22 @@ igm_status launch_cycle(igm_system *s, const CycleArgs &a) {
 igm_status prepare_cycle(igm_system *s) {
   IGM_HIP(hipMemsetAsync(s->d_sync, 0, sizeof(unsigned long long) * 2 * kSyncGroups * (size_t)s->sync_cap,
                          s->stream));
-  CycleState init;
-  memset(&init, 0, sizeof(init));
-  init.first_ovf = kNoEvent;
-  IGM_HIP(hipMemcpyAsync(s->d_state, &init, sizeof(init), hipMemcpyHostToDevice, s->stream));
+  IGM_HIP(hipMemcpyAsync(s->d_state, s->h_pinned + kPinInit, sizeof(CycleState), hipMemcpyHostToDevice,
+                         s->stream));
+  return IGM_OK;
+}
+
+// The FP64 residual step of a refinement (eq. (b), both norms, relres and
+// gamma of eq. (gammak)) for the iterate x, its scalars copied to dst (pinned
+// host memory) at the end; everything is enqueued on the system's stream.
+igm_status enqueue_residual(igm_system *s, const double *x, double *dst) {
+  IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
+  IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
+                          s->d_cscale, s->d_r, s->d_rhat, s->d_red));
+  IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_r, s->d_red + kRedMuR, s->d_red + kRedSumR));
+  IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_rhat, s->d_red + kRedMuRhat, s->d_red + kRedSumRhat));
+  IGM_HIP(launch_fin_residual(s->stream, s->d_red, s->d_scal + kScalNormB, s->d_scal));
+  IGM_HIP(hipMemcpyAsync(dst, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
   return IGM_OK;
 }
 
@@ -303,19 +325,19 @@ igm_status solve_dev(igm_system *s, double *x) {
   IGM_HIP(hipEventCreate(&ev.e0));
   IGM_HIP(hipEventCreate(&ev.e1));
   hipEvent_t e0 = ev.e0, e1 = ev.e1;
-  double *hp = s->h_pinned;
+  double *res = s->h_pinned + kPinResidual;   // scalars of the latest residual step
+  double *after = s->h_pinned + kPinCall;     // scalars after the latest call (rho)
+  CycleState *hcs = (CycleState *)(s->h_pinned + kPinState);
+  // The first residual step; every later one is enqueued right behind the
+  // int-GMRES call that produced its iterate, so a refinement waits for the
+  // device once. A call that fails leaves x unchanged, and the residual step
+  // behind it then repeats the previous one bit for bit.
+  IGM_TRY(enqueue_residual(s, x, res));
+  IGM_HIP(hipStreamSynchronize(s->stream));
   for (int k = 0;; ++k) {
     TraceRange trace_refinement("igm refinement");
     // top of refinement k+1: residuals, relres, gamma
-    IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
-    IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
-                            s->d_cscale, s->d_r, s->d_rhat, s->d_red));
-    IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_r, s->d_red + kRedMuR, s->d_red + kRedSumR));
-    IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_rhat, s->d_red + kRedMuRhat, s->d_red + kRedSumRhat));
-    IGM_HIP(launch_fin_residual(s->stream, s->d_red, s->d_scal + kScalNormB, s->d_scal));
-    IGM_HIP(hipMemcpyAsync(hp, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
-    IGM_HIP(hipStreamSynchronize(s->stream));
-    const double gamma = hp[kScalGamma], ro = hp[kScalRelresOrig], rs = hp[kScalRelresScaled];
+    const double gamma = res[kScalGamma], ro = res[kScalRelresOrig], rs = res[kScalRelresScaled];
     s->hist_ro.push_back(ro);
     s->hist_rs.push_back(rs);
     st.relres_orig = ro;
@@ -336,9 +358,11 @@ igm_status solve_dev(igm_system *s, double *x) {
         IGM_TRY(launch_cycle(s, a));
       }
       IGM_HIP(hipEventRecord(e1, s->stream));
-      IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));
-      IGM_HIP(hipMemcpyAsync(hp, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
+      IGM_HIP(hipMemcpyAsync(hcs, s->d_state, sizeof(CycleState), hipMemcpyDeviceToHost, s->stream));
+      IGM_HIP(hipMemcpyAsync(after, s->d_scal, sizeof(double) * kScalWords, hipMemcpyDeviceToHost, s->stream));
+      IGM_TRY(enqueue_residual(s, x, res));  // the next refinement's residual step
       IGM_HIP(hipStreamSynchronize(s->stream));
+      cs = *hcs;
       float ms = 0.f;
       IGM_HIP(hipEventElapsedTime(&ms, e0, e1));
       st.time_cycle_ms += ms;
@@ -350,7 +374,7 @@ igm_status solve_dev(igm_system *s, double *x) {
       a.x = x;
       IGM_TRY(prepare_cycle(s));
     }
-    s->hist_rho.push_back(hp[kScalRho]);
+    s->hist_rho.push_back(after[kScalRho]);
     for (int k = 0; k < 8; ++k) st.phase_us[k] = (double)cs.phase[k] * s->wall_us_per_tick;
     if (cs.range_err) { status = IGM_ERR_RANGE; break; }
     if (cs.timeout) { status = IGM_ERR_DEVICE; s->last_error_line = __LINE__; break; }
