@@ -51,7 +51,7 @@ typedef enum {
   IGM_ERR_OOM = -6,           /* device or host allocation failed */
   IGM_ERR_DEVICE = -7,        /* HIP error, or a device-side wait that timed out */
   IGM_ERR_BREAKDOWN = -8,     /* a cycle produced no usable Krylov column */
-  IGM_ERR_UNSUPPORTED = -9    /* size outside what this build supports */
+  IGM_ERR_UNSUPPORTED = -9    /* a size or option the library does not support */
 } igm_status;
 
 enum { IGM_PRE_NONE = 0, IGM_PRE_JACOBI = 1, IGM_PRE_ILU0 = 2 };
