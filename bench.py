@@ -134,9 +134,14 @@ def main():
     candidates = [args.grid_blocks] if args.grid_blocks else [64, 128, 256]
     best = None
     x = torch.zeros(sysm.n, dtype=torch.float64, device="cuda")
-    g = B.System.from_system(sysm, preset, m=m, grid_blocks=candidates[0])
+    g = B.System.from_system(sysm, preset, m=m)
     for gb in candidates:
-        g.set_policy(B.make_policy(preset, m=m, grid_blocks=gb))
+        try:
+            g.set_policy(B.make_policy(preset, m=m, grid_blocks=gb))
+        except B.IgmError as e:  # too few workgroups for this many rows
+            if e.status != B.ERR_UNSUPPORTED:
+                raise
+            continue
         x.zero_()
         assert g.solve_device(x) == B.OK
         x.zero_()
