@@ -380,7 +380,11 @@ igm_status igm_server_create(const igm_server_config *cfg, igm_server **out);
  * call. *ticket receives the request's number. Errors found while preparing
  * the request (IGM_ERR_ARG, IGM_ERR_SINGULAR_ROW, ...) and requests that can
  * never fit (IGM_ERR_UNSUPPORTED: m > 64, footprint above the pool, more than
- * 256 or than all resident workgroups) are reported as the request's status. */
+ * 256 or than all resident workgroups) are reported as the request's status.
+ * The persistent kernel waits for work for as long as the server exists (it
+ * stops only in igm_server_destroy); if it has ended through a device failure,
+ * the call returns IGM_ERR_DEVICE and requests not yet admitted finish with
+ * that status. */
 igm_status igm_server_submit(igm_server *sv, int64_t n, const int64_t *row_ptr, const int32_t *col,
                              const double *val, const double *b, const double *x0, const igm_policy *pol,
                              int64_t *ticket);

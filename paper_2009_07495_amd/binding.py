@@ -8,8 +8,11 @@ torch CUDA tensors); PyTorch is never imported here.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -69,6 +72,17 @@ class IgmError(RuntimeError):
 
 
 _lib = None
+
+# Objects still open at interpreter exit are closed by an atexit hook, while
+# the HIP runtime (and any profiler attached to it) is certainly alive; their
+# __del__ does nothing once the interpreter is finalising.
+_open = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_objects():
+    for obj in list(_open):
+        obj.close()
 
 _SIGS = {
     "igm_policy_preset": [C.c_int32, C.c_void_p],
@@ -208,6 +222,7 @@ class System:
         self.h = h
         self.n = int(n)
         self.pol = _policy_struct(pol)
+        _open.add(self)
 
     @classmethod
     def from_system(cls, sysm, pol="paper_noprec", **overrides):
@@ -218,7 +233,9 @@ class System:
             _lib.igm_destroy(self.h)
         self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if not sys.is_finalizing():  # see _open
+            self.close()
 
     def set_policy(self, pol):
         ps = _policy_struct(pol)
@@ -357,13 +374,16 @@ class Batch:
             raise IgmError(st, f"igm_batch_create (system {failed.value})")
         self.h = h
         self.nsys = ns
+        _open.add(self)
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.igm_batch_destroy(self.h)
         self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if not sys.is_finalizing():  # see System.__del__
+            self.close()
 
     def set_stream(self, stream):
         handle = getattr(stream, "cuda_stream", stream)
@@ -439,6 +459,7 @@ class Server:
         _check(lib().igm_server_create(C.byref(cfg), C.byref(h)), "igm_server_create")
         self.h = h
         self._n = {}
+        _open.add(self)
 
     def close(self, timeout_ms: float = 60000.0):
         if getattr(self, "h", None) and _lib is not None:
@@ -446,7 +467,8 @@ class Server:
         self.h = None
 
     def __del__(self):
-        self.close(10000.0)
+        if not sys.is_finalizing():  # see System.__del__
+            self.close(10000.0)
 
     def submit(self, sysm, pol="jacobi", x0=None, **overrides) -> int:
         if isinstance(pol, str):

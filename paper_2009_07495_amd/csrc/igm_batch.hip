@@ -148,15 +148,18 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           member = ba.jobs[2 * c + 1];
         }
       } else {
-        // served mode: wait (bounded) until the host has published job c;
-        // the pause between polls of host memory grows to ~16 x 8k clocks
+        // served mode: wait until the host has published job c, or has
+        // asked the kernel to stop (it does so only once every request it
+        // admitted has finished, so no published job is ever left behind);
+        // a workgroup never leaves on its own, since the host may publish
+        // into the ticket it holds at any time. The pause between polls of
+        // host memory grows to ~16 x 8k clocks.
         for (int64_t idle = 0;; ++idle) {
           if (c < __hip_atomic_load(ba.host_published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
             job = c;
             break;
           }
-          if (__hip_atomic_load(ba.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) || idle >= ba.idle_polls)
-            break;
+          if (__hip_atomic_load(ba.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
           const int pauses = idle < 64 ? 1 : 16;
           for (int k = 0; k < pauses; ++k) __builtin_amdgcn_s_sleep(127);
         }

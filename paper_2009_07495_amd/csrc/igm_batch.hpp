@@ -86,7 +86,6 @@ struct BatchArgs {
   int32_t *host_done;             // per slot: seq of the last completed request
   int32_t ring;                   // capacity of host_jobs in pairs (0 = batch mode)
   int32_t pad_;
-  int64_t idle_polls;             // served mode: exit after this many polls without work
 };
 
 // ---- host side, shared by the batched and the served solver ----

@@ -29,9 +29,6 @@ constexpr int kGivens = 64;
 // workgroup owns whole blocks of BLOCK consecutive rows, BLOCK a multiple of
 // the 16 words of a cache line), other workgroups first read them
 // after that barrier, and a launch starts with caches coherent with memory.
-#ifndef IGM_COH_V
-#define IGM_COH_V 1
-#endif
 
 template <int BLOCK, int R, int PRE>
 __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
@@ -258,27 +255,15 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       const int e = df - a.b_div_num - a.b_div_den;
       bool ov = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-#if IGM_COH_V
-        st_coh(vn + gt + k * T, normalize_elem(w[k], den, a.b_div_num, e, ov));
-#else
-        vn[gt + k * T] = normalize_elem(w[k], den, a.b_div_num, e, ov);
-#endif
-      }
+      for (int k = 0; k < R; ++k) st_coh(vn + gt + k * T, normalize_elem(w[k], den, a.b_div_num, e, ov));
       note_event(ov, first, ev_code(j, 5, 0));
     }
     IGM_TICK(4)
     // v_{j+1} becomes visible to every workgroup; the new rotation and the
     // update of g and H (thread kGivens) run while wavefront 0 waits
-#if IGM_COH_V
     grid_barrier_coh(gs, ssh, [&] {
       if (tid == kGivens) givens(j);
     });
-#else
-    grid_barrier(gs, ssh, [&] {
-      if (tid == kGivens) givens(j);
-    });
-#endif
     IGM_TICK(6)
     if (sh_stop || ssh.abort) break;
   }

@@ -47,7 +47,6 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 constexpr int32_t kRing = 1 << 20;       // job ring capacity (pairs)
-constexpr int64_t kIdlePolls = 10000000;  // the kernel leaves after this many empty polls (~9 minutes)
 constexpr size_t kRegionAlign = 4096;
 // records are first built against this made-up base, then moved to the region
 constexpr uintptr_t kFakeBase = (uintptr_t)1 << 44;
@@ -343,15 +342,23 @@ void driver_loop(igm_server *sv) {
       const bool running = hipStreamQuery(sv->kstream) == hipErrorNotReady;
       std::lock_guard<std::mutex> lk(sv->mu);
       if (sv->kernel_alive && !running) {
-        sv->kernel_alive = false;  // it ended (idle limit or a failure): fail what it held
+        sv->kernel_alive = false;  // it ended before the host stopped it (a failure): fail what it held
         for (int32_t slot = 0; slot < sv->max_slots; ++slot) {
           Request *r = sv->slot_req[slot];
           if (!r) continue;
           sv->slot_req[slot] = nullptr;
           finish(sv, r, IGM_ERR_DEVICE);
         }
+      }
+    }
+    {
+      // without the kernel nothing prepared can run: fail it as it arrives
+      // (setup threads may still hand over requests submitted before the end)
+      std::lock_guard<std::mutex> lk(sv->mu);
+      if (!sv->kernel_alive && !sv->prepared.empty()) {
         for (Request *r : sv->prepared) finish(sv, r, IGM_ERR_DEVICE);
         sv->prepared.clear();
+        progress = true;
       }
     }
     {
@@ -374,7 +381,6 @@ igm_status launch(igm_server *sv) {
   a.host_stop = sv->dh_stop;
   a.host_done = sv->dh_done;
   a.ring = kRing;
-  a.idle_polls = kIdlePolls;
   void *args[] = {(void *)&a};
   const void *k = serve_kernel(sv->block, sv->rows);
   // an ordinary launch: the grid fits on the device at once, and admission
@@ -529,6 +535,7 @@ igm_status igm_server_submit(igm_server *sv, int64_t n, const int64_t *row_ptr, 
   if (x0) r->x0.assign(x0, x0 + n);
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->stopping) return IGM_ERR_ARG;
+  if (!sv->kernel_alive) return IGM_ERR_DEVICE;  // the persistent kernel has ended
   r->ticket = sv->next_ticket++;
   *ticket = r->ticket;
   sv->to_prepare.push_back(r.get());

@@ -163,25 +163,32 @@ def convdiff2d(nx: int = 64, ny: int | None = None, seed: int = 2) -> System:
     return _convdiff((nx, ny), np.random.default_rng(seed), f"convdiff2d_{nx}x{ny}_s{seed}")
 
 
+def _batch_member(i: int, child, n_lo: int, n_hi: int) -> System:
+    rng = np.random.default_rng(child)
+    nt = int(round(float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))))
+    if rng.random() < 0.5:
+        nx = max(1, int(round(np.sqrt(nt))))
+        ny = max(1, int(round(nt / nx)))
+        return _convdiff((nx, ny), rng, f"b{i}_convdiff2d_{nx}x{ny}")
+    nx = max(1, int(round(nt ** (1.0 / 3.0))))
+    nz = max(1, int(round(nt / (nx * nx))))
+    return _convdiff((nx, nx, nz), rng, f"b{i}_convdiff3d_{nx}x{nx}x{nz}")
+
+
 def batch_systems(count: int = 512, seed: int = 4, n_lo: int = 1024, n_hi: int = 65536) -> list:
     """Independent systems for the batched solver: sizes log-uniform on
     [n_lo, n_hi], each a 2D 5-point or a 3D 7-point convection-diffusion
     system (probability 1/2 each) with the coefficient law above. System i
     draws everything from child i of SeedSequence(seed): target size, family,
     then its coefficients and right-hand side."""
-    out = []
-    for i, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
-        rng = np.random.default_rng(child)
-        nt = int(round(float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))))
-        if rng.random() < 0.5:
-            nx = max(1, int(round(np.sqrt(nt))))
-            ny = max(1, int(round(nt / nx)))
-            out.append(_convdiff((nx, ny), rng, f"b{i}_convdiff2d_{nx}x{ny}"))
-        else:
-            nx = max(1, int(round(nt ** (1.0 / 3.0))))
-            nz = max(1, int(round(nt / (nx * nx))))
-            out.append(_convdiff((nx, nx, nz), rng, f"b{i}_convdiff3d_{nx}x{nx}x{nz}"))
-    return out
+    return [_batch_member(i, child, n_lo, n_hi)
+            for i, child in enumerate(np.random.SeedSequence(seed).spawn(count))]
+
+
+def batch_system(i: int, seed: int = 4, n_lo: int = 1024, n_hi: int = 65536) -> System:
+    """System i of batch_systems(count, seed) for any count > i (children of a
+    SeedSequence do not depend on how many are spawned)."""
+    return _batch_member(i, np.random.SeedSequence(seed).spawn(i + 1)[i], n_lo, n_hi)
 
 
 def random27(nx: int = 128, ny: int | None = None, nz: int = 64, seed: int = 3) -> System:

@@ -1,6 +1,7 @@
 """Write tests/golden/oracle_runs.json: whole-solve results of the oracle on
 the three named workloads (refinements, iterations, final relative residuals,
-per-refinement history and a SHA-256 of the solution bytes).
+per-refinement history and a SHA-256 of the solution bytes), and the
+iteration count of the oracle's FP64 GMRES(m) comparator on each.
 
 Calls only the oracle (oracle/) and the seeded input generators; run it from
 the repository root: python tests/golden/make_oracle_runs.py
@@ -26,7 +27,11 @@ def run(name):
     t0 = time.time()
     x, st = osys.solve()
     dt = time.time() - t0
+    # the paper's comparator ("Double"): FP64 GMRES(m) with the FP64 form of
+    # the same preconditioner, relres checked once per restart
+    _, fp_it, fp_rc = osys.gmres64(m=m)
     return dict(workload=name, preset=preset, m=m, n=sysm.n, nnz=sysm.nnz, status=st["status"],
+                fp64_gmres_iterations=fp_it, fp64_gmres_restarts=-(-fp_it // m), fp64_gmres_status=fp_rc,
                 refinements=st["refinements"], iterations=st["iterations"], relres_orig=st["relres_orig"],
                 relres_scaled=st["relres_scaled"], hist_relres_orig=[float(v) for v in st["hist_relres_orig"]],
                 hist_gamma=[float(v) for v in st["hist_gamma"]], hist_rho=[float(v) for v in st["hist_rho"]],

@@ -170,3 +170,42 @@ def test_fp_norm_bit_exact(orc, torch):
     x = np.array([3.0, 4.0])
     assert g.fp_norm(dev(torch, x), 2) == 5.0
     assert g.fp_norm(dev(torch, np.zeros(10)), 10) == 0.0
+
+
+def _diag_system(n: int, preset: str):
+    """An n-row diagonal system: a cheap carrier for the vector kernels at
+    sizes that need many workgroups."""
+    rp = np.arange(n + 1, dtype=np.int64)
+    return B.System(n, rp, np.arange(n, dtype=np.int32), np.full(n, 2.0), np.ones(n), preset)
+
+
+@pytest.mark.parametrize("n", [1_048_576, 300_001])
+@pytest.mark.parametrize("preset", ["paper_noprec", "paper_ilu"])
+def test_dot_norm_many_workgroups(orc, torch, n, preset):
+    """The standalone inner product and norm (Fig. 2; Table II) over enough
+    elements that 73 to 256 workgroups each add an exact partial and the last
+    one to take the completion ticket finishes the sum: in-range operands,
+    products that overflow, and sums that overflow although no product does.
+    Two calls in a row check that the ticket resets."""
+    g = _diag_system(n, preset)
+    p = g.policy()
+    rng = np.random.default_rng(n + p["b_dot"])
+    wr = 1 << (33 if p["b_dot"] else 21)  # no overflow in the products, the sums or the squares
+    cases = [
+        (rng.integers(-wr, wr, n), rng.integers(-(1 << 30), 1 << 30, n)),  # in range
+        (np.full(n, 1 << 40, dtype=np.int64), np.full(n, 1 << 30, dtype=np.int64)),  # products overflow
+        (np.full(n, (1 << 37) + 12345, dtype=np.int64), np.full(n, (1 << 30) - 7, dtype=np.int64)),
+    ]
+    w3 = rng.integers(1 << 20, 1 << 22, n)
+    w3[-1] = -(1 << 45)  # the last element alone (the ragged tail) decides the sign
+    cases.append((w3, rng.integers(1 << 28, 1 << 30, n)))
+    for w, v in cases:
+        wd, vd = dev(torch, w), dev(torch, v)
+        h_o, ovf = orc.dot(w, v, p["b_dot"])
+        n_o, novf = orc.norm(w, p["b_norm"])
+        for _ in range(2):
+            h_g, ev = g.dot(wd, vd)
+            assert h_g == h_o and (ev != B.NO_EVENT) == ovf, (n, preset, h_g, h_o, ev, ovf)
+            n_g, ev = g.norm(wd)
+            assert n_g == n_o and (ev != B.NO_EVENT) == novf, (n, preset, n_g, n_o, ev, novf)
+    g.close()

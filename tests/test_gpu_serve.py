@@ -170,3 +170,24 @@ def test_full_size_requests_match_recorded_oracle_runs(orc, torch):
             assert hashlib.sha256(x.tobytes()).hexdigest() == g["x_sha256"], name
     finally:
         sv.close()
+
+
+def test_requests_after_quiet_spells(orc, torch):
+    """Every workgroup of the persistent kernel holds a claimed ticket while
+    it waits; none may leave on its own, since the host can publish into any
+    held ticket later. Requests spaced by quiet spells, and small enough that
+    each one lands in a different workgroup's ticket, all complete (bounded
+    waits) and the kernel stays alive throughout."""
+    reqs = [(W.convdiff2d(23 + k, 19, seed=90 + k), "jacobi") for k in range(5)]
+    refs = [oracle(orc, s, p, m=30) for s, p in reqs]
+    sv = B.Server()
+    for k, ((s, p), ref) in enumerate(zip(reqs, refs)):
+        if k:
+            time.sleep(0.7)
+        t = sv.submit(s, p, m=30)
+        x, st = sv.wait(t, 20000)
+        check(x, st, ref)
+        assert sv.stats()["kernel_alive"] == 1
+    stats = sv.stats()
+    assert stats["submitted"] == stats["completed"] == len(reqs)
+    sv.close(30000)
