@@ -122,7 +122,14 @@ typedef struct {
    * Sec. VI, so Lbar carries (a_ij / a_jj)|a_jj|^(1/2) below the diagonal and
    * Ubar is diagonal). Every solver supports it. */
   int32_t gauss_seidel;
-  int32_t reserved_[3];
+  /* Launch tuning of the ILU(0) sweeps of the single-system solver (the bits
+   * do not depend on either): rows per block of the blocked sweeps, a multiple
+   * of 64 (0 = automatic: as many as the workgroup's LDS holds, at most
+   * 16384), and lanes per row of the integer sweeps, 1, 2, 4, 8 or 16
+   * (0 = automatic, 8). */
+  int32_t sweep_rows;
+  int32_t sweep_lanes;
+  int32_t reserved_[1];
 } igm_policy;
 
 /* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,

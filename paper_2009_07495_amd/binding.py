@@ -34,12 +34,14 @@ class Policy(C.Structure):
     _fields_ = ([("struct_size", C.c_int32)] + [(f, C.c_int32) for f in _POLICY_INT_FIELDS]
                 + [("gtol", C.c_int64), ("tol", C.c_double), ("grid_blocks", C.c_int32),
                    ("phase_clock", C.c_int32), ("shift_retry", C.c_int32), ("two_sided", C.c_int32),
-                   ("gauss_seidel", C.c_int32), ("reserved_", C.c_int32 * 3)])
+                   ("gauss_seidel", C.c_int32), ("sweep_rows", C.c_int32), ("sweep_lanes", C.c_int32),
+                   ("reserved_", C.c_int32 * 1)])
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f in _POLICY_INT_FIELDS}
         d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks, phase_clock=self.phase_clock,
-                 shift_retry=self.shift_retry, two_sided=self.two_sided, gauss_seidel=self.gauss_seidel)
+                 shift_retry=self.shift_retry, two_sided=self.two_sided, gauss_seidel=self.gauss_seidel,
+                 sweep_rows=self.sweep_rows, sweep_lanes=self.sweep_lanes)
         return d
 
 

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libigmres.so")
-SOURCES = ["igm_setup.cpp", "igm_api.cpp", "igm_batch.cpp", "igm_serve.cpp", "igm_kernels.hip", "igm_cycle.hip",
+SOURCES = ["igm_setup.cpp", "igm_bsched.cpp", "igm_api.cpp", "igm_batch.cpp", "igm_serve.cpp", "igm_kernels.hip", "igm_cycle.hip",
            "igm_batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

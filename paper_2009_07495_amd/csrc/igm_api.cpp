@@ -57,6 +57,32 @@ igm_status upload(igm_system *s, T *&p, const std::vector<T, A> &v) {
   return IGM_OK;
 }
 
+// Device copy of a blocked sweep schedule (the progress words are set by
+// alloc_work).
+igm_status upload_schedule(igm_system *s, const BlockSchedule &h, BlockSweepArgs &d) {
+  d = BlockSweepArgs{};
+  d.S = h.S;
+  d.nb = h.nb;
+  d.narrow = h.narrow ? 1 : 0;
+  int32_t *prow = nullptr, *ecode = nullptr, *lvbase = nullptr, *lvoff = nullptr, *wbase = nullptr;
+  int64_t *eoff = nullptr, *eval = nullptr, *pdiag = nullptr;
+  double *evalf = nullptr;
+  WaitRec *wrec = nullptr;
+  IGM_TRY(upload(s, prow, h.prow));
+  IGM_TRY(upload(s, eoff, h.eoff));
+  IGM_TRY(upload(s, ecode, h.ecode));
+  IGM_TRY(upload(s, eval, h.eval));
+  IGM_TRY(upload(s, evalf, h.evalf));
+  IGM_TRY(upload(s, pdiag, h.pdiag));
+  IGM_TRY(upload(s, lvbase, h.lvbase));
+  IGM_TRY(upload(s, lvoff, h.lvoff));
+  IGM_TRY(upload(s, wbase, h.wbase));
+  IGM_TRY(upload(s, wrec, h.wrec));
+  d.prow = prow; d.eoff = eoff; d.ecode = ecode; d.eval = eval; d.evalf = evalf; d.pdiag = pdiag;
+  d.lvbase = lvbase; d.lvoff = lvoff; d.wbase = wbase; d.wrec = wrec;
+  return IGM_OK;
+}
+
 void free_device(igm_system *s) {
   for (auto &b : s->bufs) (void)hipFree(b.p);
   s->bufs.clear();
@@ -100,6 +126,10 @@ CycleArgs make_args(igm_system *s) {
   a.wbuf = s->d_w;
   a.lev_cnt = s->d_levcnt;
   a.sweep_threads = sweep_threads(s->block, s->grid, a.max_level);
+  a.bsf = s->bsf;
+  a.bsb = s->bsb;
+  a.sweep_lanes = s->sweep_lanes;
+  a.sweep_lds_off = (int32_t)s->sweep_lds_off;
   a.H = s->d_H; a.c = s->d_c; a.s = s->d_s; a.g = s->d_g;
   a.state = s->d_state;
   a.sync = s->d_sync;
@@ -125,7 +155,7 @@ igm_status choose_launch(igm_system *s) {
   s->wall_us_per_tick = wall_khz > 0 ? 1000.0 / wall_khz : 0.0;
   int target = s->pol.grid_blocks > 0 ? s->pol.grid_blocks : 256;
   target = std::min(target, 1023);
-  const size_t smem = cycle_smem_bytes(s->pol.m);
+  const size_t smem = s->cycle_lds;
   // ILU(0): the sweeps hold a row's structure in registers while they wait,
   // which the 512-thread shapes (256 registers per thread) keep without spills
   static const int kShapes[][2] = {{1024, 1}, {1024, 2}, {1024, 4}, {512, 8}, {512, 16}};
@@ -160,8 +190,14 @@ igm_status alloc_work(igm_system *s) {
   IGM_TRY(dalloc(s, s->d_z, np));
   IGM_TRY(dalloc(s, s->d_w, np));
   s->d_levcnt = nullptr;
-  if (s->pol.precond == IGM_PRE_ILU0)
+  s->d_prog = nullptr;
+  if (s->pol.precond == IGM_PRE_ILU0) {
     IGM_TRY(dalloc(s, s->d_levcnt, ((s->hs.flev_ptr.size() - 1) + (s->hs.blev_ptr.size() - 1)) * kLevStride));
+    // the backward schedule's progress words follow the forward ones
+    IGM_TRY(dalloc(s, s->d_prog, ((size_t)s->bsf.nb + s->bsb.nb) * kLevStride));
+    s->bsf.prog = s->d_prog;
+    s->bsb.prog = s->d_prog + (size_t)s->bsf.nb * kLevStride;
+  }
   IGM_TRY(dalloc(s, s->d_r, np));
   IGM_TRY(dalloc(s, s->d_rhat, np));
   IGM_TRY(dalloc(s, s->d_bk, np));
@@ -196,6 +232,29 @@ igm_status build(igm_system *s) {
   free_device(s);
   IGM_TRY(host_setup(s->n, s->row_ptr, s->col, s->ahat, s->bhat, s->pol, s->hs));
   HostSetup &h = s->hs;
+  // ILU(0): the blocked schedules of the two sweeps, sized by the LDS a
+  // workgroup of the cycle kernel has left for the block's values
+  BlockSchedule sf, sb;
+  s->cycle_lds = cycle_smem_bytes(s->pol.m);
+  s->bsf = s->bsb = BlockSweepArgs{};
+  s->sweep_lanes = 0;
+  s->sweep_lds_off = 0;
+  if (s->pol.precond == IGM_PRE_ILU0) {
+    hipDeviceProp_t prop;
+    IGM_HIP(hipGetDeviceProperties(&prop, s->device));
+    s->sweep_lds_off = (s->cycle_lds + 255) / 256 * 256;
+    const int64_t room = (int64_t)prop.sharedMemPerBlock - (int64_t)s->sweep_lds_off - kCycleStaticLds -
+                         (int64_t)sizeof(unsigned) * kSeenSlots;
+    const int64_t cap = room / (int64_t)sizeof(int64_t) / 64 * 64;
+    if (cap < 64) return IGM_ERR_UNSUPPORTED;
+    int64_t S = s->pol.sweep_rows > 0 ? s->pol.sweep_rows : kSweepRowsAuto;
+    S = std::min<int64_t>({S, cap, (s->n + 63) / 64 * 64});
+    block_schedule(s->n, true, (int32_t)S, h.lptr, h.lcol, h.lval, h.ldiag, sf);
+    block_schedule(s->n, false, (int32_t)S, h.uptr, h.ucol, h.uval, h.udiag, sb);
+    if (sf.wrec.size() >= ((size_t)1 << 31) || sb.wrec.size() >= ((size_t)1 << 31)) return IGM_ERR_UNSUPPORTED;
+    s->cycle_lds = s->sweep_lds_off + sizeof(int64_t) * (size_t)S + sizeof(unsigned) * kSeenSlots;
+    s->sweep_lanes = s->pol.sweep_lanes > 0 ? s->pol.sweep_lanes : kSweepLanesAuto;
+  }
   // Rows touched by the cycle kernel: every row r < grid * BLOCK * R. The basis,
   // the SELL slices (zero width) and the diagonals (value 1) are padded to that
   // many rows so the kernel needs no per-row bounds test; padded rows stay 0.
@@ -243,6 +302,8 @@ igm_status build(igm_system *s) {
     IGM_TRY(upload(s, s->d_flev_rows, h.flev_rows));
     IGM_TRY(upload(s, s->d_blev_ptr, h.blev_ptr));
     IGM_TRY(upload(s, s->d_blev_rows, h.blev_rows));
+    IGM_TRY(upload_schedule(s, sf, s->bsf));
+    IGM_TRY(upload_schedule(s, sb, s->bsb));
   } else {
     s->d_ldiag = s->d_udiag = s->d_lptr = s->d_uptr = s->d_lval = s->d_uval = nullptr;
     s->d_lcol = s->d_ucol = nullptr;
@@ -262,8 +323,7 @@ igm_status build(igm_system *s) {
 igm_status launch_cycle(igm_system *s, const CycleArgs &a) {
   const void *k = cycle_kernel(s->block, s->rows_per_thread, s->pol.precond);
   void *args[] = {(void *)&a};
-  IGM_HIP(hipLaunchCooperativeKernel(k, dim3(s->grid), dim3(s->block), args, cycle_smem_bytes(s->pol.m),
-                                     s->stream));
+  IGM_HIP(hipLaunchCooperativeKernel(k, dim3(s->grid), dim3(s->block), args, s->cycle_lds, s->stream));
   return IGM_OK;
 }
 

@@ -12,8 +12,8 @@
 // data, so all workgroups take the same decisions without extra
 // communication; it is scheduled inside the waits of the grid reductions and
 // barriers. Workgroup 0 stores H, c, s, g for the caller.
+#include "igm_bsweep.hpp"
 #include "igm_rows.hpp"
-#include "igm_sweep.hpp"
 #include "igm_sync.hpp"
 
 namespace igm {
@@ -29,6 +29,20 @@ constexpr int kGivens = 64;
 // workgroup owns whole blocks of BLOCK consecutive rows, BLOCK a multiple of
 // the 16 words of a cache line), other workgroups first read them
 // after that barrier, and a launch starts with caches coherent with memory.
+
+// One integer sweep of the ILU(0) preconditioner apply with G lanes per row
+// (a runtime choice: the bits do not depend on it).
+template <int BLOCK>
+__device__ __forceinline__ void ilu_sweep(int G, const BlockSweepArgs &b, const int64_t *src, int64_t *dst,
+                                          int64_t *vals, unsigned *seen, bool &ovf, bool &to) {
+  switch (G) {
+    case 1: block_sweep<BLOCK, 1, false>(b, src, dst, vals, seen, ovf, to); break;
+    case 2: block_sweep<BLOCK, 2, false>(b, src, dst, vals, seen, ovf, to); break;
+    case 4: block_sweep<BLOCK, 4, false>(b, src, dst, vals, seen, ovf, to); break;
+    case 8: block_sweep<BLOCK, 8, false>(b, src, dst, vals, seen, ovf, to); break;
+    default: block_sweep<BLOCK, 16, false>(b, src, dst, vals, seen, ovf, to); break;
+  }
+}
 
 template <int BLOCK, int R, int PRE>
 __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
@@ -67,10 +81,6 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     ssh.abort = 0; ssh.flag = 0;
     sh_stop = 0; sh_jstar = m; sh_breakdown = 0; sh_steps = 0;
   }
-  // level counters of the ILU sweeps start from zero in every launch (the
-  // grid barrier before the first sweep orders these stores)
-  if (PRE == IGM_PRE_ILU0)
-    for (int64_t i = gt; i < (int64_t)a.nflev + a.nblev; i += T) st_coh(a.lev_cnt + i * kLevStride, 0u);
   __syncthreads();
 
   // reduction finishers (run once per workgroup, in wavefront 0)
@@ -162,26 +172,25 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       note_event(o2, first, ev_code(j, 2, 0));
     } else {
       // z, y and u pass between workgroups through device-coherent stores
-      // and loads; the rows of each sweep wait only for the level below
-      // them (igm_sweep.hpp), and three grid barriers per step separate the
-      // SpMV, the two sweeps and the read-back of u
+      // and loads; the two sweeps run block by block (igm_bsweep.hpp), and
+      // three grid barriers per step separate the SpMV, the two sweeps and
+      // the read-back of u. The blocks' progress words restart from zero in
+      // every step (cleared before the barrier that follows the SpMV; the
+      // previous step's sweeps ended at an earlier barrier).
       bool o1 = false, o2 = false, to = false;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const int64_t row = gt + k * T;
         st_coh(a.zbuf + row, spmv_row(a, row, vj, a.nterms, o1));
       }
+      for (int64_t i = gt; i < (int64_t)a.bsf.nb + a.bsb.nb; i += T) st_coh(a.bsf.prog + i * kLevStride, 0u);
       note_event(o1, first, ev_code(j, 1, 0));
       grid_barrier_coh(gs, ssh);
-      const int64_t pos0 = (int64_t)blockIdx.x * a.sweep_threads + tid;
-      const int64_t stride = (int64_t)gridDim.x * a.sweep_threads;
-      if (tid < a.sweep_threads && !ssh.abort)
-        level_sweep<true, false>(a, a.flev_ptr, a.flev_rows, a.nflev, a.lev_cnt, (unsigned)(j - 1), pos0, stride,
-                          a.zbuf, a.wbuf, o2, to);
+      int64_t *svals = (int64_t *)((char *)smem + a.sweep_lds_off);
+      unsigned *seen = (unsigned *)(svals + a.bsf.S);
+      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsf, (const int64_t *)a.zbuf, a.wbuf, svals, seen, o2, to);
       grid_barrier_coh(gs, ssh);
-      if (tid < a.sweep_threads && !ssh.abort)
-        level_sweep<false, false>(a, a.blev_ptr, a.blev_rows, a.nblev, a.lev_cnt + (int64_t)a.nflev * kLevStride,
-                           (unsigned)(j - 1), pos0, stride, a.wbuf, a.wbuf, o2, to);
+      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsb, (const int64_t *)a.wbuf, a.wbuf, svals, seen, o2, to);
       if (to) __hip_atomic_store(&a.state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       grid_barrier_coh(gs, ssh);
       note_event(o2, first, ev_code(j, 2, 0));

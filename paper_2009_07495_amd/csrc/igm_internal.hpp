@@ -56,6 +56,67 @@ struct CycleState {
   uint64_t phase[8];
 };
 
+// One dependency wait of the blocked triangular sweep (igm_bsweep.hpp):
+// before local level `level`, block `dep` must have finished `need` of its
+// local levels; `slot` indexes the waiting block's cache of what it last saw
+// of that block.
+struct alignas(16) WaitRec {
+  int32_t level, slot, need, dep;
+};
+
+// Blocked schedule of one triangular sweep of the integer ILU(0) factors
+// (forward on the strict lower factor in increasing rows, backward on the
+// strict upper factor in decreasing rows). Positions number the rows in
+// processing order; block q holds positions [q S, (q + 1) S), and inside a
+// block the rows are sorted by local level (a row's level counts only the
+// dependencies inside its block). Every dependency outside the block is in an
+// earlier block and becomes a wait on that block's progress.
+struct BlockSchedule {
+  int32_t S = 0, nb = 0;     // rows per block, blocks
+  int32_t max_slots = 0;     // most dependency blocks of one block
+  int32_t max_levels = 0;    // most local levels of one block
+  bool narrow = false;       // every factor value fits in int32
+  hvec<int32_t> prow;        // n: row of each sorted position
+  hvec<int64_t> eoff;        // n + 1: entries of each sorted position, in CSR order of its row
+  hvec<int32_t> ecode;       // >= 0: sorted position inside the block of an in-block dependency; < 0: -(row + 1)
+  hvec<int64_t> eval;        // the factor's value of each entry
+  hvec<double> evalf;        // the same values as doubles (FP64 start step)
+  hvec<int64_t> pdiag;       // n: the factor's diagonal of each sorted position's row
+  hvec<int32_t> lvbase;      // nb + 1: where each block's level offsets start in lvoff
+  hvec<int32_t> lvoff;       // per block, nl + 1 offsets of its levels (positions inside the block)
+  hvec<int32_t> wbase;       // nb + 1: where each block's wait records start in wrec
+  hvec<WaitRec> wrec;        // per block, sorted by level
+};
+
+// Device view of one BlockSchedule.
+struct BlockSweepArgs {
+  int32_t S, nb;
+  int32_t narrow;  // every factor value fits in int32
+  const int32_t *prow;
+  const int64_t *eoff;
+  const int32_t *ecode;
+  const int64_t *eval;
+  const double *evalf;
+  const int64_t *pdiag;
+  const int32_t *lvbase, *lvoff, *wbase;
+  const WaitRec *wrec;
+  unsigned *prog;  // nb progress words kLevStride apart, zero at the start of the sweep
+};
+
+// Dependency blocks per block whose progress a sweep caches in LDS.
+constexpr int kSeenSlots = 256;
+// Rows per block and lanes per row of the blocked sweeps when the policy
+// leaves them open, and the static LDS the cycle kernel keeps besides its
+// dynamic part (reduction scratch and flags; an upper bound).
+constexpr int kSweepRowsAuto = 16384;
+constexpr int kSweepLanesAuto = 8;
+constexpr int kCycleStaticLds = 4096;
+
+// Builds the schedule of one sweep from a strict triangular factor in CSR
+// (ptr, col, val), its diagonal, and S rows per block (a multiple of 64).
+void block_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> &ptr, const hvec<int32_t> &col,
+                    const hvec<int64_t> &val, const hvec<int64_t> &diag, BlockSchedule &out);
+
 // Host-side setup products (all derived from the FP64 input).
 struct HostSetup {
   hvec<double> dhat, a, b;                     // eq. (eq1)/(eq2), (eq3)
@@ -136,6 +197,9 @@ struct CycleArgs {
   int64_t *wbuf;   // npad (preconditioner path)
   unsigned *lev_cnt;      // ILU: completion counters (igm_sweep.hpp), nflev forward then nblev backward
   int32_t sweep_threads;  // ILU: threads per workgroup taking part in the sweeps (multiple of 64)
+  BlockSweepArgs bsf, bsb;  // ILU: blocked schedules of the forward and backward sweeps (igm_bsweep.hpp)
+  int32_t sweep_lanes;      // ILU: lanes per row in the integer sweeps (1, 2, 4, 8 or 16)
+  int32_t sweep_lds_off;    // ILU: byte offset of the sweeps' LDS (S values, then the seen cache)
   int64_t *H, *c, *s, *g;
   CycleState *state;
   unsigned long long *sync;  // 2 * kSyncGroups * sync_cap words
@@ -192,6 +256,12 @@ struct igm_system {
   int m_alloc = 0;
   // launch configuration of the cycle kernel
   int grid = 0, block = 0, rows_per_thread = 0, max_coresident = 0;
+  // ILU(0): blocked schedules of the two sweeps (device copies), their
+  // progress words, and the cycle kernel's dynamic LDS (cycle part + sweeps)
+  igm::BlockSweepArgs bsf{}, bsb{};
+  unsigned *d_prog = nullptr;
+  int32_t sweep_lanes = 0;
+  size_t cycle_lds = 0, sweep_lds_off = 0;
   // statistics
   igm_stats stats{};
   std::vector<double> hist_ro, hist_rs, hist_gamma, hist_rho;

@@ -8,6 +8,7 @@
 // launch shape.
 #include <algorithm>
 
+#include "igm_bsweep.hpp"
 #include "igm_launch.hpp"
 #include "igm_rows.hpp"
 #include "igm_sweep.hpp"
@@ -190,25 +191,16 @@ __global__ __launch_bounds__(kB) void k_scale(int64_t n, const double *__restric
 // FP64 start step (Sec. VI) with ILU(0): the FP64 substitution with the integer factors
 // converted to double, forward y_i = (bk_i - sum L_ij y_j) / Lbar_ii, then
 // backward u_i = (y_i - sum U_ij u_j) / Ubar_ii in place; each row sums in CSR
-// order. One launch per direction; every row waits only for the level below
-// it (igm_sweep.hpp), so the launch must be co-resident (cooperative).
-struct FpFactors {
-  const int64_t *lptr, *uptr;
-  const int32_t *lcol, *ucol;
-  const double *lvalf, *uvalf;
-  const int64_t *ldiag, *udiag;
-};
+// order. One launch per direction, run block by block on the schedules of
+// the integer sweeps (igm_bsweep.hpp); a block waits for the blocks it reads,
+// so the launch must be co-resident (cooperative).
+constexpr int kSweepBlock = 64;  // one wavefront per workgroup: a level of a block rarely has more rows
 
-constexpr int kSweepBlock = 64;  // one wavefront per workgroup
-
-template <bool LOWER>
-__global__ __launch_bounds__(kSweepBlock) void k_fp_sweep(FpFactors f, const int32_t *__restrict__ lev_ptr,
-                                                          const int32_t *__restrict__ lev_rows, int nlev,
-                                                          unsigned *cnt, const double *src, double *dst,
-                                                          CycleState *state) {
+__global__ __launch_bounds__(kSweepBlock) void k_fp_bsweep(BlockSweepArgs b, const double *src, double *dst,
+                                                           CycleState *state) {
+  extern __shared__ double fsm[];
   bool ovf = false, to = false;
-  level_sweep<LOWER, true>(f, lev_ptr, lev_rows, nlev, cnt, 0u, (int64_t)blockIdx.x * kSweepBlock + threadIdx.x,
-                           (int64_t)gridDim.x * kSweepBlock, src, dst, ovf, to);
+  block_sweep<kSweepBlock, 1, true>(b, src, dst, fsm, (unsigned *)(fsm + b.S), ovf, to);
   if (to) __hip_atomic_store(&state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -402,30 +394,28 @@ hipError_t launch_start_vector(hipStream_t st, const CycleArgs &a, const double 
                        a.udiag, a.precond, bk, r0, red);
   } else {
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kB), 0, st, n, r, (const double *)scal, bk);
-    // the level counters of the integer sweeps serve here too (k_cycle
-    // clears them again at its own start)
-    hipError_t e = hipMemsetAsync(a.lev_cnt, 0, sizeof(unsigned) * ((size_t)a.nflev + a.nblev) * kLevStride, st);
+    // the progress words of the blocked sweeps serve here too (k_cycle
+    // clears them again in every Arnoldi step)
+    hipError_t e = hipMemsetAsync(a.bsf.prog, 0, sizeof(unsigned) * ((size_t)a.bsf.nb + a.bsb.nb) * kLevStride, st);
     if (e != hipSuccess) return e;
-    FpFactors f{a.lptr, a.uptr, a.lcol, a.ucol, lvalf, uvalf, a.ldiag, a.udiag};
-    // about four times the widest level in flight, at most the co-resident limit
+    const size_t lds = sizeof(double) * (size_t)a.bsf.S + sizeof(unsigned) * kSeenSlots;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fp_sweep<true>, kSweepBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fp_bsweep, kSweepBlock, lds);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    const int64_t want = (4 * (int64_t)a.max_level + kSweepBlock - 1) / kSweepBlock;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)std::max(per_cu, 1) * cus));
-    const double *cbk = bk;
-    const double *cr0 = r0;
-    unsigned *cf = a.lev_cnt, *cb = a.lev_cnt + (size_t)a.nflev * kLevStride;
-    int nf = a.nflev, nbl = a.nblev;
+    const int cap = std::max(per_cu, 1) * cus;
     CycleState *state = a.state;
-    void *argf[] = {&f, (void *)&a.flev_ptr, (void *)&a.flev_rows, &nf, &cf, &cbk, &r0, &state};
-    e = hipLaunchCooperativeKernel((const void *)k_fp_sweep<true>, dim3(grid), dim3(kSweepBlock), argf, 0, st);
+    const double *cbk = bk, *cr0 = r0;
+    BlockSweepArgs bf = a.bsf, bb = a.bsb;
+    void *argf[] = {&bf, &cbk, &r0, &state};
+    e = hipLaunchCooperativeKernel((const void *)k_fp_bsweep, dim3(std::min(bf.nb, cap)), dim3(kSweepBlock), argf,
+                                   lds, st);
     if (e != hipSuccess) return e;
-    void *argb[] = {&f, (void *)&a.blev_ptr, (void *)&a.blev_rows, &nbl, &cb, &cr0, &r0, &state};
-    e = hipLaunchCooperativeKernel((const void *)k_fp_sweep<false>, dim3(grid), dim3(kSweepBlock), argb, 0, st);
+    void *argb[] = {&bb, &cr0, &r0, &state};
+    e = hipLaunchCooperativeKernel((const void *)k_fp_bsweep, dim3(std::min(bb.nb, cap)), dim3(kSweepBlock), argb,
+                                   lds, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_absmax, dim3(grid_stride_blocks(n)), dim3(kB), 0, st, n, (const double *)r0,
                        red + kRedMuR0);

@@ -97,6 +97,101 @@ static uint64_t setup_hash(const Csr &a, const igm_policy &p, igm_status &st) {
   return H;
 }
 
+// The blocked sweep schedule of a strict triangular factor (igm_bsched.cpp):
+// every row appears once; an in-block dependency sits at a lower local level
+// of the same block; a dependency on another block is covered by a wait
+// record at or before the row's level asking for at least the dependency's
+// level + 1 (blocks only wait on earlier blocks); and a serial replay of the
+// schedule (exact integer sums, truncating division) equals plain
+// substitution in processing order. Returns the number of violations.
+static int check_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> &ptr, const hvec<int32_t> &col,
+                          const hvec<int64_t> &val, const hvec<int64_t> &diag, uint64_t &hash) {
+  igm::BlockSchedule b;
+  igm::block_schedule(n, lower, S, ptr, col, val, diag, b);
+  int bad = 0;
+  auto pos_of = [&](int64_t r) { return lower ? r : n - 1 - r; };
+  std::vector<int32_t> where(n, -1), level(n, -1);  // sorted position and local level of each row
+  for (int32_t q = 0; q < b.nb; ++q) {
+    const int32_t *lo = b.lvoff.data() + b.lvbase[q];
+    const int32_t nl = b.lvbase[q + 1] - b.lvbase[q] - 1;
+    for (int32_t L = 0; L < nl; ++L)
+      for (int32_t k = lo[L]; k < lo[L + 1]; ++k) {
+        const int64_t r = b.prow[(int64_t)q * S + k];
+        if (where[r] >= 0 || pos_of(r) / S != q) ++bad;
+        where[r] = (int32_t)((int64_t)q * S + k);
+        level[r] = L;
+      }
+  }
+  for (int64_t r = 0; r < n; ++r)
+    if (where[r] < 0) ++bad;
+  if (bad) return bad;
+  // dependencies against the levels and the wait records
+  for (int32_t q = 0; q < b.nb; ++q) {
+    std::vector<int32_t> req(b.nb, 0);
+    int32_t w = b.wbase[q];
+    const int32_t *lo = b.lvoff.data() + b.lvbase[q];
+    const int32_t nl = b.lvbase[q + 1] - b.lvbase[q] - 1;
+    for (int32_t L = 0; L < nl; ++L) {
+      for (; w < b.wbase[q + 1] && b.wrec[w].level <= L; ++w) {
+        if (b.wrec[w].level != L || b.wrec[w].dep >= q) ++bad;
+        req[b.wrec[w].dep] = std::max(req[b.wrec[w].dep], b.wrec[w].need);
+      }
+      for (int32_t k = lo[L]; k < lo[L + 1]; ++k) {
+        const int64_t pk = (int64_t)q * S + k;
+        for (int64_t e = b.eoff[pk]; e < b.eoff[pk + 1]; ++e) {
+          const int32_t c = b.ecode[e];
+          if (c >= 0) {
+            if (c >= S || level[b.prow[(int64_t)q * S + c]] >= L) ++bad;
+          } else {
+            const int64_t dr = -(int64_t)c - 1;
+            const int32_t dq = (int32_t)(pos_of(dr) / S);
+            if (dq >= q || req[dq] < level[dr] + 1) ++bad;
+          }
+        }
+      }
+    }
+    if (w != b.wbase[q + 1]) ++bad;
+  }
+  // replay against plain substitution (rhs z_i = 2^40 + 12345 i, varying signs)
+  std::vector<int64_t> z(n), ref(n), got(n);
+  for (int64_t i = 0; i < n; ++i) z[i] = (i % 3 == 1 ? -1 : 1) * (((int64_t)1 << 40) + 12345 * i);
+  auto tdiv = [](__int128 a, int64_t d) { return (int64_t)(a / d); };
+  for (int64_t p = 0; p < n; ++p) {
+    const int64_t r = lower ? p : n - 1 - p;
+    __int128 acc = z[r];
+    for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) acc -= (__int128)val[e] * ref[col[e]];
+    ref[r] = tdiv(acc, diag[r]);
+  }
+  for (int32_t q = 0; q < b.nb; ++q) {
+    const int32_t *lo = b.lvoff.data() + b.lvbase[q];
+    const int32_t nl = b.lvbase[q + 1] - b.lvbase[q] - 1;
+    for (int32_t L = 0; L < nl; ++L)
+      for (int32_t k = lo[L]; k < lo[L + 1]; ++k) {
+        const int64_t pk = (int64_t)q * S + k;
+        const int64_t r = b.prow[pk];
+        __int128 acc = z[r];
+        for (int64_t e = b.eoff[pk]; e < b.eoff[pk + 1]; ++e) {
+          const int32_t c = b.ecode[e];
+          const int64_t x = c >= 0 ? got[b.prow[(int64_t)q * S + c]] : got[-(int64_t)c - 1];
+          acc -= (__int128)b.eval[e] * x;
+          if ((double)b.eval[e] != b.evalf[e]) ++bad;
+        }
+        if (b.pdiag[pk] != diag[r]) ++bad;
+        got[r] = tdiv(acc, b.pdiag[pk]);
+      }
+  }
+  for (int64_t r = 0; r < n; ++r)
+    if (got[r] != ref[r]) ++bad;
+  H = 1469598103934665603ull;
+  mix(b.prow); mix(b.eoff); mix(b.ecode); mix(b.eval); mix(b.pdiag); mix(b.lvbase); mix(b.lvoff); mix(b.wbase);
+  for (const auto &w : b.wrec) {
+    const int32_t f[4] = {w.level, w.slot, w.need, w.dep};
+    for (int32_t x : f) H = (H ^ (uint32_t)x) * 1099511628211ull;
+  }
+  hash = H;
+  return bad;
+}
+
 int main() {
   int bad = 0;
   const Csr a = stencil(40, 40, 24, 7);  // 38,400 rows
@@ -112,6 +207,28 @@ int main() {
     printf("preconditioner %d: status %d / %d, hash %016llx / %016llx\n", preset, (int)s1, (int)s4, (unsigned long long)h1,
            (unsigned long long)h4);
     if (s1 != IGM_OK || s4 != IGM_OK || h1 != h4) ++bad;
+  }
+  // blocked sweep schedules of the ILU(0) factors: invariants, replay, and
+  // the same schedule for one and four setup threads
+  {
+    igm_policy p = preset_policy(IGM_PRE_ILU0);
+    igm::HostSetup h;
+    igm_status st = igm::host_setup(a.n, a.rp, a.col, a.val, a.b, p, h);
+    if (st != IGM_OK) ++bad;
+    for (int32_t S : {64, 640, 4096, 65536}) {
+      for (int lower = 0; lower < 2; ++lower) {
+        uint64_t h1 = 0, h4 = 0;
+        setenv("IGM_SETUP_THREADS", "1", 1);
+        int v1 = lower ? check_schedule(a.n, true, S, h.lptr, h.lcol, h.lval, h.ldiag, h1)
+                       : check_schedule(a.n, false, S, h.uptr, h.ucol, h.uval, h.udiag, h1);
+        setenv("IGM_SETUP_THREADS", "4", 1);
+        int v4 = lower ? check_schedule(a.n, true, S, h.lptr, h.lcol, h.lval, h.ldiag, h4)
+                       : check_schedule(a.n, false, S, h.uptr, h.ucol, h.uval, h.udiag, h4);
+        printf("blocked schedule S=%d %s: %d / %d violations, hash %016llx / %016llx\n", S,
+               lower ? "forward" : "backward", v1, v4, (unsigned long long)h1, (unsigned long long)h4);
+        if (v1 || v4 || h1 != h4) ++bad;
+      }
+    }
   }
   // error paths: an all-zero row, a zero ILU pivot
   Csr z = a;

@@ -339,3 +339,32 @@ def test_full_size_workload_matches_recorded_oracle_run(torch, name):
     if name == "random27_1m":  # level sets of the ILU(0) factors of this matrix
         assert gs["levels_fwd"] == 634 and gs["levels_bwd"] == 634
     assert hashlib.sha256(x.tobytes()).hexdigest() == gold["x_sha256"]
+
+
+ILU_SWEEP_CASES = [
+    ("r27_11x9x8", lambda: W.random27(11, 9, 8, seed=31), dict(m=12)),
+    ("dd_301_ragged", lambda: W.random_dd(301, 0.04, 32), dict(m=10)),
+    ("cd_13x12x7_ilu", lambda: W.convdiff3d(13, 12, 7, seed=33), dict(m=12)),
+]
+
+
+@pytest.mark.parametrize("name,gen,kw", ILU_SWEEP_CASES)
+@pytest.mark.parametrize("rows,lanes", [(64, 1), (64, 16), (128, 2), (192, 4), (320, 8), (0, 0)])
+def test_ilu_blocked_sweeps_any_block_size(orc, torch, name, gen, kw, rows, lanes):
+    """The ILU(0) preconditioner apply runs block by block (Sec. VI; blocks of
+    `rows` consecutive rows, `lanes` lanes per row): small blocks force many
+    blocks, waits on earlier blocks' progress across workgroups and, with
+    fewer workgroups than blocks, workgroups that run several blocks in turn.
+    The cycle trace (whole basis included) and a whole solve (whose FP64
+    start step runs the same schedules) equal the oracle's bit for bit."""
+    s = gen()
+    o = orc.OracleSystem.from_system(s, orc.policy("paper_ilu", **kw))
+    v1 = first_v1(o, s.n)
+    to = o.cycle(v1)
+    for grid in (0, 2):
+        g = B.System.from_system(s, "paper_ilu", grid_blocks=grid, sweep_rows=rows, sweep_lanes=lanes, **kw)
+        assert_trace_equal(g.int_cycle(v1), to, s.n)
+        x, st = g.solve()
+        xo, so = o.solve()
+        assert st == so["status"] and np.array_equal(x, xo), (name, rows, lanes, grid)
+        g.close()

@@ -1,6 +1,6 @@
 """Host code under sanitizers (CPU only): the oracle, and the library's host
 setup (validation, scaling, integer terms, FP64 ILU(0), factor casts, level
-sets, SELL-64 layout), each built with g++ and AddressSanitizer +
+sets, SELL-64 layout, blocked sweep schedules), each built with g++ and AddressSanitizer +
 UndefinedBehaviorSanitizer, the threaded setup also with ThreadSanitizer.
 The drivers (tests/san/) check statuses and, for the setup, that one and four
 threads give the same products bit for bit. GPU code is not built here."""
@@ -42,7 +42,8 @@ def test_oracle_under_asan_ubsan(tmp_path):
 
 HOST_FLAGS = ["-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 HOST_SOURCES = [os.path.join(HERE, "san", "setup_driver.cpp"),
-                os.path.join(ROOT, "paper_2009_07495_amd", "csrc", "igm_setup.cpp"), "-lpthread"]
+                os.path.join(ROOT, "paper_2009_07495_amd", "csrc", "igm_setup.cpp"),
+                os.path.join(ROOT, "paper_2009_07495_amd", "csrc", "igm_bsched.cpp"), "-lpthread"]
 
 
 def test_host_setup_under_asan_ubsan(tmp_path):
