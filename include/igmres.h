@@ -129,7 +129,12 @@ typedef struct {
    * (0 = automatic, 8). */
   int32_t sweep_rows;
   int32_t sweep_lanes;
-  int32_t reserved_[1];
+  /* s(k) of eq. (AA), the correction matrices used by the int-GMRES call of
+   * refinement k = 1, 2, ... (the paper makes s(k) a solver parameter bounded
+   * by S, Fig. 1, without a rule): 0 = s(k) = S = s_terms in every refinement
+   * (the paper's experiments, S = 0); 1 = s(k) = min(S, k - 1), Abar_0 alone in
+   * the first refinement and one more term in each later one. */
+  int32_t s_rule;
 } igm_policy;
 
 /* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,
@@ -217,7 +222,8 @@ igm_status igm_get_history(const igm_system *s, int32_t cap, double *relres_orig
 
 /* One int-GMRES(m) call, the integer loop of Fig. 2 (Arnoldi steps with
  * Givens rotations), from the integer start vector v1 (host, n int64 words:
- * v1 cast to Q.df as in Fig. 2), with the system's policy.
+ * v1 cast to Q.df as in Fig. 2), with the system's policy, as the call of
+ * refinement k >= 1 (its matrix is Abar^(k) of eq. (AA); k < 1 is IGM_ERR_ARG).
  * Outputs (caller-allocated host arrays; V may be NULL):
  *   H[(m+1)*m] row-major (H[i*m + j], 0-based) after the rotations,
  *   c[m], s[m], g[m+1], V[(m+1)*n] (basis vector j at V + j*n).
@@ -231,7 +237,7 @@ typedef struct {
   int64_t *H, *c, *s, *g, *V;
 } igm_cycle_trace;
 
-igm_status igm_int_cycle(igm_system *s, const int64_t *v1, igm_cycle_trace *trace);
+igm_status igm_int_cycle(igm_system *s, const int64_t *v1, int32_t k, igm_cycle_trace *trace);
 
 /* Kernel-level entry points (each runs one GPU kernel family on device
  * buffers, for checking a single step of the method and for timing it).

@@ -41,7 +41,8 @@ class Policy(C.Structure):
     _fields_ = [(name, C.c_int32) for name in (
         "df", "alpha_a", "s_terms", "m", "precond", "b_dot", "b_axpy", "b_norm", "b_div_num", "b_div_den",
         "b_rot", "b_tmp", "b_cs_num", "b_cs_den", "max_refine", "shift_retry")] + [("gtol", C.c_int64), ("tol", C.c_double),
-                                                                            ("two_sided", C.c_int32), ("gauss_seidel", C.c_int32)]
+                                                                            ("two_sided", C.c_int32), ("gauss_seidel", C.c_int32),
+                                                                            ("s_rule", C.c_int32)]
 
 
 # Shift settings of the paper: Table IV (no preconditioner) and Table VI (ILU),
@@ -49,7 +50,7 @@ class Policy(C.Structure):
 # "jacobi" is this implementation's extension: the ILU construction on the
 # diagonal-only pattern with the Table VI shifts.
 _BASE = dict(df=30, s_terms=0, m=30, max_refine=2000, shift_retry=0, gtol=-1, tol=1e-10, two_sided=0,
-             gauss_seidel=0)
+             gauss_seidel=0, s_rule=0)
 PRESETS = {
     "paper_noprec": dict(_BASE, alpha_a=16, precond=PRE_NONE, b_dot=16, b_axpy=16, b_norm=16, b_div_num=16,
                          b_div_den=14, b_rot=16, b_tmp=16, b_cs_num=16, b_cs_den=14),
@@ -131,7 +132,7 @@ def lib():
             "orc_get_ilu_fp": (C.c_int, [vp, vp]),
             "orc_spmv": (None, [vp, i32, vp, vp, i32, C.POINTER(i64)]),
             "orc_precond_apply": (None, [vp, vp, vp, i32, C.POINTER(i64)]),
-            "orc_cycle": (C.c_int, [vp, vp, C.POINTER(Trace)]),
+            "orc_cycle": (C.c_int, [vp, vp, i32, C.POINTER(Trace)]),
             "orc_cycle_update": (None, [vp, C.POINTER(Trace), dbl, vp]),
             "orc_solve": (C.c_int, [vp, vp, C.POINTER(Stats)]),
             "orc_shift_retry": (C.c_int, [C.POINTER(Policy), i64]),
@@ -313,7 +314,8 @@ class OracleSystem:
         lib().orc_precond_apply(self.h, _p(z), _p(w), j, C.byref(first))
         return w, first.value
 
-    def cycle(self, v1, m=None):
+    def cycle(self, v1, m=None, k: int = 1):
+        """The int-GMRES call of refinement k (its matrix per eq. (AA))."""
         m = self.pol["m"] if m is None else m
         v1 = _i64(v1)
         H = np.zeros((m + 1) * m, dtype=np.int64)
@@ -321,7 +323,7 @@ class OracleSystem:
         g = np.zeros(m + 1, dtype=np.int64)
         V = np.zeros(self.n * (m + 1), dtype=np.int64)
         t = Trace(m, 0, 0, 0, 0, _p(H).value, _p(c).value, _p(s).value, _p(g).value, _p(V).value)
-        rc = lib().orc_cycle(self.h, _p(v1), C.byref(t))
+        rc = lib().orc_cycle(self.h, _p(v1), int(k), C.byref(t))
         if rc != OK:
             raise OracleError(rc)
         out = dict(m=m, jstar=t.jstar, breakdown=t.breakdown, steps=t.steps, first_ovf=t.first_ovf,

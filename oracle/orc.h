@@ -76,6 +76,7 @@ typedef struct {
   double tol;          /* FP64 relative residual target on the original system */
   int32_t two_sided;   /* 0: eq. (eq1); 1: eq. (eq2) with D1 = D2 = Dhat^(1/2) (see orc_setup.c) */
   int32_t gauss_seidel; /* with ORC_PRE_ILU0: the Gauss-Seidel splitting instead of ILU(0) (orc_setup.c) */
+  int32_t s_rule;      /* s(k) of eq. (AA), S = s_terms: 0 s(k) = S; 1 s(k) = min(S, k - 1) (orc_s_of_k) */
 } orc_policy;
 
 /* Overflow event code: (step j, stage, sub-index), ordered as executed.
@@ -142,8 +143,12 @@ typedef struct {
   int64_t *V;         /* n x (m+1), column j at V + j*n */
 } orc_trace;
 
-/* The integer loop of Fig. 2 starting from the integer v1 (v1 cast to Q df). */
-int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t);
+/* s(k) of eq. (AA) for refinement k = 1, 2, ...: the correction matrices
+ * A_1..A_s(k) the k-th int-GMRES call uses. */
+int32_t orc_s_of_k(const orc_policy *p, int32_t k);
+/* The integer loop of Fig. 2 of refinement k starting from the integer v1
+ * (v1 cast to Q df); its matrix is Abar^(k) of eq. (AA). */
+int orc_cycle(const orc_system *s, const int64_t *v1, int32_t k, orc_trace *t);
 /* Closing FP64 step of Fig. 2: x[n] = sum_i y_i v_i with y = rho * H^-1 g (FP64). */
 void orc_cycle_update(const orc_system *s, const orc_trace *t, double rho, double *x);
 

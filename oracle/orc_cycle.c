@@ -88,7 +88,16 @@ void orc_precond_apply(const orc_system *s, const int64_t *z, int64_t *w, int32_
 
 #define HH(i, k) t->H[(size_t)(i) * m + (k)]
 
-int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
+/* The paper makes s(k) a solver parameter bounded by S (Fig. 1) without a
+ * rule; reading: either the same S in every refinement (the paper's
+ * experiments, S = 0), or one more correction term per refinement, starting
+ * from Abar_0 alone, until S is reached. */
+int32_t orc_s_of_k(const orc_policy *p, int32_t k) {
+  if (p->s_rule == 0) return p->s_terms;
+  return k - 1 < p->s_terms ? k - 1 : p->s_terms;
+}
+
+int orc_cycle(const orc_system *s, const int64_t *v1, int32_t k, orc_trace *t) {
   const orc_policy *p = &s->pol;
   int64_t n = s->n;
   int32_t m = t->m, f = p->df;
@@ -106,7 +115,7 @@ int orc_cycle(const orc_system *s, const int64_t *v1, orc_trace *t) {
   t->steps = 0;
   /* g = (1, 0, ..., 0) in Q df */
   t->g[0] = (int64_t)1 << f;
-  int32_t nterms = p->s_terms + 1;
+  int32_t nterms = orc_s_of_k(p, k) + 1;
   for (int32_t j = 1; j <= m; ++j) { /* Arnoldi step j */
     int32_t ovf;
     const int64_t *vj = t->V + (size_t)(j - 1) * n;

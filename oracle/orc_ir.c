@@ -186,7 +186,7 @@ int orc_solve(orc_system *s, double *x, orc_stats *st) {
     if (gamma == 0.0) { st->status = ORC_OK; break; }
     /* the call, repeated from the same v1 while a retry can adjust a shift */
     for (;;) {
-      orc_cycle(s, v1, &t);
+      orc_cycle(s, v1, k + 1, &t);
       if (t.first_ovf == ORC_NO_EVENT || st->shift_retries >= s->pol.shift_retry) break;
       if (!orc_shift_retry(&s->pol, t.first_ovf)) break;
       st->shift_retries += 1;

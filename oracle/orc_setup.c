@@ -26,6 +26,7 @@ static int check_policy(const orc_policy *p) {
   if (p->two_sided < 0 || p->two_sided > 1) return 1;
   if (p->gauss_seidel < 0 || p->gauss_seidel > 1) return 1;
   if (p->gauss_seidel && p->precond != ORC_PRE_ILU0) return 1;
+  if (p->s_rule < 0 || p->s_rule > 1) return 1;
   if (!(p->tol >= 0.0)) return 1;
   return 0;
 }

@@ -35,13 +35,13 @@ class Policy(C.Structure):
                 + [("gtol", C.c_int64), ("tol", C.c_double), ("grid_blocks", C.c_int32),
                    ("phase_clock", C.c_int32), ("shift_retry", C.c_int32), ("two_sided", C.c_int32),
                    ("gauss_seidel", C.c_int32), ("sweep_rows", C.c_int32), ("sweep_lanes", C.c_int32),
-                   ("reserved_", C.c_int32 * 1)])
+                   ("s_rule", C.c_int32)])
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f in _POLICY_INT_FIELDS}
         d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks, phase_clock=self.phase_clock,
                  shift_retry=self.shift_retry, two_sided=self.two_sided, gauss_seidel=self.gauss_seidel,
-                 sweep_rows=self.sweep_rows, sweep_lanes=self.sweep_lanes)
+                 sweep_rows=self.sweep_rows, sweep_lanes=self.sweep_lanes, s_rule=self.s_rule)
         return d
 
 
@@ -98,7 +98,7 @@ _SIGS = {
     "igm_get_policy": [C.c_void_p, C.c_void_p],
     "igm_get_history": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                         C.c_void_p],
-    "igm_int_cycle": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_int_cycle": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "igm_spmv": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "igm_precond": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "igm_dot": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
@@ -288,7 +288,9 @@ class System:
         k = cnt.value
         return dict(relres_orig=ro[:k], relres_scaled=rs[:k], gamma=g[:k], rho=rho[:k], jstar=js[:k])
 
-    def int_cycle(self, v1, with_basis: bool = True) -> dict:
+    def int_cycle(self, v1, with_basis: bool = True, k: int = 1) -> dict:
+        """The int-GMRES call of refinement k (lines 3-20 of Fig. 2; the
+        matrix Abar^(k) of eq. (AA)) from the integer v1."""
         m = self.pol.m
         v1 = np.ascontiguousarray(v1, dtype=np.int64)
         H = np.zeros((m + 1) * m, dtype=np.int64)
@@ -297,7 +299,7 @@ class System:
         V = np.zeros((m + 1) * self.n, dtype=np.int64) if with_basis else None
         t = CycleTrace(m, 0, 0, 0, 0, H.ctypes.data, c.ctypes.data, s.ctypes.data, g.ctypes.data,
                        V.ctypes.data if V is not None else None)
-        _check(lib().igm_int_cycle(self.h, v1.ctypes.data, C.byref(t)), "igm_int_cycle")
+        _check(lib().igm_int_cycle(self.h, v1.ctypes.data, int(k), C.byref(t)), "igm_int_cycle")
         return dict(m=m, jstar=t.jstar, breakdown=t.breakdown, steps=t.steps, first_ovf=t.first_ovf,
                     H=H.reshape(m + 1, m), c=c, s=s, g=g, V=None if V is None else V.reshape(m + 1, self.n))
 

@@ -90,6 +90,14 @@ void free_device(igm_system *s) {
   if (s->h_pinned) { (void)hipHostFree(s->h_pinned); s->h_pinned = nullptr; }
 }
 
+// Integer matrix terms of refinement k (1, 2, ...): Abar^(k) of eq. (AA)
+// holds Abar_0 and the first s(k) correction matrices, s(k) = S = s_terms
+// (s_rule 0) or min(S, k - 1) (s_rule 1), at most what the setup built.
+int32_t terms_for(const igm_policy &p, int32_t k, int32_t built) {
+  const int32_t sk = p.s_rule == 0 ? p.s_terms : std::min(p.s_terms, k - 1);
+  return std::min(sk + 1, built);
+}
+
 CycleArgs make_args(igm_system *s) {
   CycleArgs a;
   memset(&a, 0, sizeof(a));
@@ -98,7 +106,7 @@ CycleArgs make_args(igm_system *s) {
   a.npad = s->npad;
   a.m = p.m;
   a.df = p.df;
-  a.nterms = std::min(p.s_terms + 1, s->hs.nterms);
+  a.nterms = terms_for(p, 1, s->hs.nterms);
   a.precond = p.precond;
   a.b_dot = p.b_dot; a.b_axpy = p.b_axpy; a.b_norm = p.b_norm;
   a.b_div_num = p.b_div_num; a.b_div_den = p.b_div_den; a.b_rot = p.b_rot; a.b_tmp = p.b_tmp;
@@ -408,6 +416,7 @@ igm_status solve_dev(igm_system *s, double *x) {
     s->hist_gamma.push_back(gamma);
     if (gamma == 0.0) { s->hist_rho.push_back(0.0); status = IGM_OK; break; }
     // FP64 start step and cast of v1, then the int-GMRES call with the fused update
+    a.nterms = terms_for(p, k + 1, s->hs.nterms);
     IGM_TRY(prepare_cycle(s));
     IGM_HIP(launch_start_vector(s->stream, a, s->d_r, s->d_scal, s->d_lvalf, s->d_uvalf, s->d_bk, s->d_r0, s->d_red));
     CycleState cs;
@@ -432,6 +441,7 @@ igm_status solve_dev(igm_system *s, double *x) {
       a = make_args(s);  // the adjusted shifts; v1 (column 0 of V) is untouched by the call
       a.update = 1;
       a.x = x;
+      a.nterms = terms_for(p, k + 1, s->hs.nterms);
       IGM_TRY(prepare_cycle(s));
     }
     s->hist_rho.push_back(after[kScalRho]);
@@ -613,8 +623,8 @@ igm_status igm_get_history(const igm_system *s, int32_t cap, double *relres_orig
   return IGM_OK;
 }
 
-igm_status igm_int_cycle(igm_system *s, const int64_t *v1, igm_cycle_trace *t) {
-  if (!s || !v1 || !t || t->m != s->pol.m || !t->H || !t->c || !t->s || !t->g) return IGM_ERR_ARG;
+igm_status igm_int_cycle(igm_system *s, const int64_t *v1, int32_t k, igm_cycle_trace *t) {
+  if (!s || !v1 || !t || k < 1 || t->m != s->pol.m || !t->H || !t->c || !t->s || !t->g) return IGM_ERR_ARG;
   const int m = s->pol.m;
   IGM_HIP(hipMemsetAsync(s->d_V, 0, sizeof(int64_t) * (size_t)(m + 1) * s->npad, s->stream));
   IGM_HIP(hipMemsetAsync(s->d_H, 0, sizeof(int64_t) * (size_t)(m + 1) * m, s->stream));
@@ -624,6 +634,7 @@ igm_status igm_int_cycle(igm_system *s, const int64_t *v1, igm_cycle_trace *t) {
   IGM_HIP(hipMemcpyAsync(s->d_V, v1, sizeof(int64_t) * s->n, hipMemcpyHostToDevice, s->stream));
   IGM_TRY(prepare_cycle(s));
   CycleArgs a = make_args(s);
+  a.nterms = terms_for(s->pol, k, s->hs.nterms);
   IGM_TRY(launch_cycle(s, a));
   CycleState cs;
   IGM_HIP(hipMemcpyAsync(&cs, s->d_state, sizeof(cs), hipMemcpyDeviceToHost, s->stream));

@@ -155,6 +155,7 @@ void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
   S.ldv = (hs.n + 15) / 16 * 16;
   S.team = 1;
   S.nterms = hs.nterms;
+  S.s_rule = p.s_rule;
   S.m = p.m; S.df = p.df; S.precond = p.precond; S.max_refine = p.max_refine;
   S.b_dot = p.b_dot; S.b_axpy = p.b_axpy; S.b_norm = p.b_norm;
   S.b_div_num = p.b_div_num; S.b_div_den = p.b_div_den; S.b_rot = p.b_rot; S.b_tmp = p.b_tmp;

@@ -277,6 +277,8 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
     double ro = 0.0, rs = 0.0;
     for (int kref = 0;; ++kref) {
       if (tsh.abort) break;
+      // integer matrix terms of this refinement (k = kref + 1): Abar_0 and s(k) corrections, eq. (AA)
+      const int nterms_k = S.s_rule ? (S.nterms < kref + 1 ? S.nterms : kref + 1) : S.nterms;
       // ---- eq. (b): r = b - A x and rhat = bhat - Ahat x, rows in CSR order
       double r[R], rh[R];
 #pragma unroll
@@ -466,7 +468,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
             const int64_t row = g0 + k * TB;
             int64_t z = 0;
             if (row < n) {
-              z = spmv_row(S, row, vj, S.nterms, o1);
+              z = spmv_row(S, row, vj, nterms_k, o1);
               if (pre == IGM_PRE_JACOBI) z = tdiv_diag(tdiv_diag(z, S.ldiag[row], o2), S.udiag[row], o2);
             }
             w[k] = z;

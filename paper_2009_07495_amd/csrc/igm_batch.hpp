@@ -17,7 +17,8 @@ struct BatchSys {
   int64_t n;       // rows
   int64_t ldv;     // leading dimension of V (n rounded up to 16)
   int32_t team;    // workgroups that share the system
-  int32_t nterms;  // integer matrix terms used by the SpMV
+  int32_t nterms;  // integer matrix terms used by the SpMV (at most; see s_rule)
+  int32_t s_rule;  // s(k) of eq. (AA): 0 = nterms in every refinement, 1 = min(nterms, k) in refinement k
   int32_t m, df, precond, max_refine;
   int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
   int32_t nflev, nblev;  // ILU level sets

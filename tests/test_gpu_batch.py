@@ -114,6 +114,20 @@ def test_batch_paper_noprec_preset(orc, torch):
     assert np.abs(x - 1.0).max() < 1e-8
 
 
+@pytest.mark.parametrize("rule", [0, 1])
+def test_batch_s_schedule(orc, torch, rule):
+    """s(k) of eq. (AA) in the batched kernel: each system's call of
+    refinement k uses Abar_0 and s(k) correction matrices (rule 1:
+    min(S, k - 1)); every system equals the oracle bit for bit."""
+    systems = [W.convdiff3d(9, 8, 7, seed=10), W.convdiff2d(31, 27, seed=11), W.convdiff3d(12, 10, 6, seed=12)]
+    kw = dict(m=15, alpha_a=24, s_terms=2, s_rule=rule)
+    refs = [oracle_solve(orc, s, "jacobi", **kw) for s in systems]
+    bt = B.Batch(systems, "jacobi", **kw)
+    x, st = bt.solve()
+    assert st == B.OK
+    check_against_oracle(bt, x, systems, refs)
+
+
 def test_batch_matches_single_system_solver(torch):
     systems = [W.convdiff3d(14, 13, 12, seed=31), W.convdiff2d(70, 61, seed=32)]
     bt = B.Batch(systems, "jacobi", m=25)

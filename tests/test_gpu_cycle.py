@@ -368,3 +368,21 @@ def test_ilu_blocked_sweeps_any_block_size(orc, torch, name, gen, kw, rows, lane
         xo, so = o.solve()
         assert st == so["status"] and np.array_equal(x, xo), (name, rows, lanes, grid)
         g.close()
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_s_schedule_matches_oracle(orc, torch, rule):
+    """s(k) of eq. (AA): the call of refinement k uses Abar_0 and s(k)
+    correction matrices (rule 1: s(k) = min(S, k - 1)). The cycle traces of
+    refinements 1 to 3 and a whole solve equal the oracle's bit for bit."""
+    s = W.convdiff3d(9, 8, 7, seed=10)
+    kw = dict(m=15, alpha_a=24, s_terms=2, s_rule=rule)
+    o = orc.OracleSystem.from_system(s, orc.policy("jacobi", **kw))
+    g = B.System.from_system(s, "jacobi", **kw)
+    v1 = first_v1(o, s.n)
+    for k in (1, 2, 3):
+        assert_trace_equal(g.int_cycle(v1, k=k), o.cycle(v1, k=k), s.n)
+    x, st = g.solve()
+    xo, so = o.solve()
+    assert st == so["status"] == B.OK and np.array_equal(x, xo)
+    assert g.stats()["refinements"] == so["refinements"]

@@ -232,3 +232,39 @@ def test_two_sided_equals_row_scaling_when_every_dhat_is_one(orc):
     assert np.array_equal(x1, x2) and s1["refinements"] == s2["refinements"]
     assert np.array_equal(s1["hist_relres_orig"], s2["hist_relres_orig"])
     assert np.array_equal(s1["hist_relres_scaled"], s2["hist_relres_scaled"])
+
+
+def test_s_schedule_ramp(orc):
+    """s(k) of eq. (AA) under the ramp reading (s_rule 1: s(k) = min(S, k - 1)).
+    Pins: with S = 0 it is the constant rule bit for bit; refinement k of the
+    ramp equals one refinement with the constant rule at s = min(S, k - 1)
+    resumed from the ramp's previous iterate (checked for k = 1, 2, 3, so an
+    off-by-one in k or in the term count fails); the first call's cycle
+    trace uses A_0 alone; and the ramp solves to tolerance."""
+    s = W.convdiff3d(9, 8, 7, seed=10)
+    kw = dict(m=15, alpha_a=24)
+
+    def solve(x0=None, **p):
+        return orc.OracleSystem.from_system(s, orc.policy("jacobi", **kw, **p)).solve(x0)
+
+    x0, st0 = solve(s_terms=0)
+    xr0, str0 = solve(s_terms=0, s_rule=1)
+    assert np.array_equal(x0, xr0) and st0["refinements"] == str0["refinements"]
+    xk = None
+    for k in (1, 2, 3):
+        x_step, _ = solve(x0=xk, s_terms=min(2, k - 1), max_refine=1)
+        x_ramp, st = solve(s_terms=2, s_rule=1, max_refine=k)
+        assert st["refinements"] == k
+        assert np.array_equal(x_step, x_ramp), k
+        xk = x_ramp
+    # the integer loop of refinement k follows s(k): k = 1 is A_0 alone
+    o_ramp = orc.OracleSystem.from_system(s, orc.policy("jacobi", **kw, s_terms=2, s_rule=1))
+    o_one = orc.OracleSystem.from_system(s, orc.policy("jacobi", **kw, s_terms=0))
+    o_two = orc.OracleSystem.from_system(s, orc.policy("jacobi", **kw, s_terms=1))
+    r, _ = o_one.residual(np.zeros(s.n))
+    v1 = o_one.start_vector(r)["v1"]
+    assert np.array_equal(o_ramp.cycle(v1, k=1)["V"], o_one.cycle(v1)["V"])
+    assert np.array_equal(o_ramp.cycle(v1, k=2)["V"], o_two.cycle(v1)["V"])
+    assert not np.array_equal(o_ramp.cycle(v1, k=2)["V"], o_one.cycle(v1)["V"])
+    x, st = solve(s_terms=2, s_rule=1)
+    assert st["status"] == 0 and st["relres_orig"] < 1e-10
