@@ -176,6 +176,7 @@ def status_str(st: int) -> str:
 igm_status_str = status_str
 
 
+
 def igm_policy_preset(preset) -> Policy:
     p = Policy()
     code = PRESET[preset] if isinstance(preset, str) else int(preset)
@@ -235,8 +236,8 @@ class System:
             _lib.igm_destroy(self.h)
         self.h = None
 
-    def __del__(self):
-        if not sys.is_finalizing():  # see _open
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():  # see _open
             self.close()
 
     def set_policy(self, pol):
@@ -385,8 +386,8 @@ class Batch:
             _lib.igm_batch_destroy(self.h)
         self.h = None
 
-    def __del__(self):
-        if not sys.is_finalizing():  # see System.__del__
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():  # see _open
             self.close()
 
     def set_stream(self, stream):
@@ -470,8 +471,8 @@ class Server:
             _lib.igm_server_destroy(self.h, float(timeout_ms))
         self.h = None
 
-    def __del__(self):
-        if not sys.is_finalizing():  # see System.__del__
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():  # see _open
             self.close(10000.0)
 
     def submit(self, sysm, pol="jacobi", x0=None, **overrides) -> int:

@@ -64,22 +64,29 @@ igm_status upload_schedule(igm_system *s, const BlockSchedule &h, BlockSweepArgs
   d.S = h.S;
   d.nb = h.nb;
   d.narrow = h.narrow ? 1 : 0;
-  int32_t *prow = nullptr, *ecode = nullptr, *lvbase = nullptr, *lvoff = nullptr, *wbase = nullptr;
-  int64_t *eoff = nullptr, *eval = nullptr, *pdiag = nullptr;
+  d.max_levels = h.max_levels;
+  int32_t *prow = nullptr, *plen = nullptr, *ecode = nullptr, *lvbase = nullptr, *lvoff = nullptr, *wbase = nullptr;
+  int64_t *levent = nullptr, *eval = nullptr, *pdiag = nullptr;
+  uint64_t *pmag = nullptr;
+  int32_t *pshift = nullptr;
   double *evalf = nullptr;
   WaitRec *wrec = nullptr;
   IGM_TRY(upload(s, prow, h.prow));
-  IGM_TRY(upload(s, eoff, h.eoff));
+  IGM_TRY(upload(s, plen, h.plen));
+  IGM_TRY(upload(s, levent, h.levent));
   IGM_TRY(upload(s, ecode, h.ecode));
   IGM_TRY(upload(s, eval, h.eval));
   IGM_TRY(upload(s, evalf, h.evalf));
   IGM_TRY(upload(s, pdiag, h.pdiag));
+  IGM_TRY(upload(s, pmag, h.pmag));
+  IGM_TRY(upload(s, pshift, h.pshift));
   IGM_TRY(upload(s, lvbase, h.lvbase));
   IGM_TRY(upload(s, lvoff, h.lvoff));
   IGM_TRY(upload(s, wbase, h.wbase));
   IGM_TRY(upload(s, wrec, h.wrec));
-  d.prow = prow; d.eoff = eoff; d.ecode = ecode; d.eval = eval; d.evalf = evalf; d.pdiag = pdiag;
-  d.lvbase = lvbase; d.lvoff = lvoff; d.wbase = wbase; d.wrec = wrec;
+  d.prow = prow; d.plen = plen; d.ecode = ecode; d.eval = eval; d.evalf = evalf; d.pdiag = pdiag;
+  d.lvbase = lvbase; d.lvoff = lvoff; d.levent = levent; d.wbase = wbase; d.wrec = wrec;
+  d.pmag = pmag; d.pshift = pshift;
   return IGM_OK;
 }
 
@@ -251,16 +258,23 @@ igm_status build(igm_system *s) {
     hipDeviceProp_t prop;
     IGM_HIP(hipGetDeviceProperties(&prop, s->device));
     s->sweep_lds_off = (s->cycle_lds + 255) / 256 * 256;
-    const int64_t room = (int64_t)prop.sharedMemPerBlock - (int64_t)s->sweep_lds_off - kCycleStaticLds -
-                         (int64_t)sizeof(unsigned) * kSeenSlots;
-    const int64_t cap = room / (int64_t)sizeof(int64_t) / 64 * 64;
-    if (cap < 64) return IGM_ERR_UNSUPPORTED;
+    const int64_t room = (int64_t)prop.sharedMemPerBlock - (int64_t)s->sweep_lds_off - kCycleStaticLds;
     int64_t S = s->pol.sweep_rows > 0 ? s->pol.sweep_rows : kSweepRowsAuto;
-    S = std::min<int64_t>({S, cap, (s->n + 63) / 64 * 64});
-    block_schedule(s->n, true, (int32_t)S, h.lptr, h.lcol, h.lval, h.ldiag, sf);
-    block_schedule(s->n, false, (int32_t)S, h.uptr, h.ucol, h.uval, h.udiag, sb);
+    S = std::min<int64_t>(S, (s->n + 63) / 64 * 64);
+    // the largest S (halving from the request) whose values and level tables fit
+    for (;;) {
+      if (S < 64 || room < (int64_t)sweep_lds_bytes(64, 64)) return IGM_ERR_UNSUPPORTED;
+      if ((int64_t)sweep_lds_bytes(S, 0) <= room) {
+        block_schedule(s->n, true, (int32_t)S, h.lptr, h.lcol, h.lval, h.ldiag, sf);
+        block_schedule(s->n, false, (int32_t)S, h.uptr, h.ucol, h.uval, h.udiag, sb);
+        if ((int64_t)sweep_lds_bytes(S, std::max(sf.max_levels, sb.max_levels)) <= room) break;
+      }
+      S = S / 2 / 64 * 64;
+    }
     if (sf.wrec.size() >= ((size_t)1 << 31) || sb.wrec.size() >= ((size_t)1 << 31)) return IGM_ERR_UNSUPPORTED;
-    s->cycle_lds = s->sweep_lds_off + sizeof(int64_t) * (size_t)S + sizeof(unsigned) * kSeenSlots;
+    const int32_t ml = std::max(sf.max_levels, sb.max_levels);
+    sf.max_levels = sb.max_levels = ml;
+    s->cycle_lds = s->sweep_lds_off + sweep_lds_bytes(S, ml);
     s->sweep_lanes = s->pol.sweep_lanes > 0 ? s->pol.sweep_lanes : kSweepLanesAuto;
   }
   // Rows touched by the cycle kernel: every row r < grid * BLOCK * R. The basis,

@@ -57,11 +57,11 @@ void block_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> &ptr, 
   const int32_t nb = o.nb;
   auto row_of = [&](int64_t p) { return lower ? p : n - 1 - p; };  // also maps rows to positions
   hvec<int32_t> lv(n), sorted(n);  // local level of each position; sorted index inside its block
-  std::vector<int32_t> nl(nb), ecount(nb);
+  std::vector<int32_t> nl(nb);
+  std::vector<int64_t> eslots(nb);  // entry slots of each block (levels padded to their longest row)
   for_blocks(nb, [&](int32_t q) {
     const int64_t p0 = (int64_t)q * S, p1 = std::min<int64_t>(n, p0 + S);
     int32_t top = 0;
-    int64_t ents = 0;
     for (int64_t p = p0; p < p1; ++p) {
       const int64_t r = row_of(p);
       int32_t l = 0;
@@ -71,68 +71,87 @@ void block_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> &ptr, 
       }
       lv[p] = l;
       top = std::max(top, l + 1);
-      ents += ptr[r + 1] - ptr[r];
     }
-    // counting sort by level, stable in position
+    // counting sort by level, stable in position; widest row of each level
     std::vector<int32_t> fill(top + 1, 0);
-    for (int64_t p = p0; p < p1; ++p) fill[lv[p] + 1]++;
+    std::vector<int64_t> width(top, 0);
+    for (int64_t p = p0; p < p1; ++p) {
+      fill[lv[p] + 1]++;
+      const int64_t r = row_of(p);
+      width[lv[p]] = std::max<int64_t>(width[lv[p]], ptr[r + 1] - ptr[r]);
+    }
+    int64_t slots = 0;
+    for (int32_t l = 0; l < top; ++l) slots += width[l] * fill[l + 1];
     for (int32_t l = 0; l < top; ++l) fill[l + 1] += fill[l];
     for (int64_t p = p0; p < p1; ++p) sorted[p] = fill[lv[p]]++;
     nl[q] = top;
-    ecount[q] = (int32_t)ents;
+    eslots[q] = slots;
   });
   o.lvbase.assign(nb + 1, 0);
   std::vector<int64_t> ebase(nb + 1, 0);
   for (int32_t q = 0; q < nb; ++q) {
     o.lvbase[q + 1] = o.lvbase[q] + nl[q] + 1;
-    ebase[q + 1] = ebase[q] + ecount[q];
+    ebase[q + 1] = ebase[q] + eslots[q];
     o.max_levels = std::max(o.max_levels, nl[q]);
   }
-  const int64_t nnz = ebase[nb];
+  const int64_t nslots = ebase[nb];
   o.prow.resize(n);
+  o.plen.resize(n);
   o.pdiag.resize(n);
-  o.eoff.resize(n + 1);
-  o.ecode.resize(nnz);
-  o.eval.resize(nnz);
-  o.evalf.resize(nnz);
+  o.pmag.resize(n);
+  o.pshift.resize(n);
+  o.ecode.resize(nslots);
+  o.eval.resize(nslots);
+  o.evalf.resize(nslots);
   o.lvoff.resize(o.lvbase[nb]);
-  o.eoff[n] = nnz;
+  o.levent.resize(o.lvbase[nb]);
   std::vector<std::vector<WaitRec>> recs(nb);
   std::vector<int32_t> slots(nb), narrow(nb, 1);
   for_blocks(nb, [&](int32_t q) {
     const int64_t p0 = (int64_t)q * S, p1 = std::min<int64_t>(n, p0 + S);
     int32_t *lo = o.lvoff.data() + o.lvbase[q];
+    int64_t *le = o.levent.data() + o.lvbase[q];
     for (int32_t l = 0; l <= nl[q]; ++l) lo[l] = 0;
     for (int64_t p = p0; p < p1; ++p) lo[lv[p] + 1]++;
     for (int32_t l = 0; l < nl[q]; ++l) lo[l + 1] += lo[l];
-    // entry counts of the sorted positions, then their offsets
     for (int64_t p = p0; p < p1; ++p) {
       const int64_t r = row_of(p);
       o.prow[p0 + sorted[p]] = (int32_t)r;
+      o.plen[p0 + sorted[p]] = (int32_t)(ptr[r + 1] - ptr[r]);
       o.pdiag[p0 + sorted[p]] = diag[r];
+      if (diag[r] != 0) div_magic(diag[r], o.pmag[p0 + sorted[p]], o.pshift[p0 + sorted[p]]);
+      else o.pmag[p0 + sorted[p]] = 0, o.pshift[p0 + sorted[p]] = 512;  // the device divides the slow way
     }
-    int64_t e_at = ebase[q];
-    for (int64_t k = p0; k < p1; ++k) {
-      o.eoff[k] = e_at;
-      const int64_t r = o.prow[k];
-      e_at += ptr[r + 1] - ptr[r];
+    // level L's slots: its row count times its widest row
+    le[0] = ebase[q];
+    for (int32_t l = 0; l < nl[q]; ++l) {
+      int64_t w = 0;
+      for (int32_t k = lo[l]; k < lo[l + 1]; ++k) w = std::max<int64_t>(w, o.plen[p0 + k]);
+      le[l + 1] = le[l] + w * (lo[l + 1] - lo[l]);
     }
+    std::fill(o.ecode.begin() + ebase[q], o.ecode.begin() + ebase[q + 1], 0);  // padding: never read
+    std::fill(o.eval.begin() + ebase[q], o.eval.begin() + ebase[q + 1], 0);
+    std::fill(o.evalf.begin() + ebase[q], o.evalf.begin() + ebase[q + 1], 0.0);
     std::vector<CrossDep> cross;
-    for (int64_t k = p0; k < p1; ++k) {
-      const int64_t r = o.prow[k];
-      const int64_t p = row_of(r);
-      int64_t out = o.eoff[k];
-      for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e, ++out) {
-        const int64_t c = col[e];
-        const int64_t pc = row_of(c);
-        o.eval[out] = val[e];
-        o.evalf[out] = (double)val[e];
-        if (val[e] < INT32_MIN || val[e] > INT32_MAX) narrow[q] = 0;
-        if (pc >= p0) {
-          o.ecode[out] = sorted[pc];
-        } else {
-          o.ecode[out] = (int32_t)(-(c + 1));
-          cross.push_back({(int32_t)(pc / S), lv[p], lv[pc] + 1});
+    for (int32_t l = 0; l < nl[q]; ++l) {
+      const int64_t c = lo[l + 1] - lo[l];
+      for (int32_t k = lo[l]; k < lo[l + 1]; ++k) {
+        const int64_t r = o.prow[p0 + k];
+        const int64_t p = row_of(r);
+        int64_t kk = 0;
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e, ++kk) {
+          const int64_t at = le[l] + kk * c + (k - lo[l]);
+          const int64_t cl = col[e];
+          const int64_t pc = row_of(cl);
+          o.eval[at] = val[e];
+          o.evalf[at] = (double)val[e];
+          if (val[e] < INT32_MIN || val[e] > INT32_MAX) narrow[q] = 0;
+          if (pc >= p0) {
+            o.ecode[at] = sorted[pc];
+          } else {
+            o.ecode[at] = (int32_t)(-(cl + 1));
+            cross.push_back({(int32_t)(pc / S), lv[p], lv[pc] + 1});
+          }
         }
       }
     }

@@ -26,6 +26,8 @@
 // order does not matter); the FP64 sweep sums each row in CSR order (G = 1).
 #pragma once
 
+#include <type_traits>
+
 #include "igm_rows.hpp"
 #include "igm_sync.hpp"
 
@@ -45,6 +47,21 @@ __device__ __forceinline__ int64_t mul_w32(int64_t a, int32_t b, bool &ovf) {
   return (int64_t)(((uint64_t)hi << 32) + (uint64_t)lo);
 }
 
+// tdiv(a, d) (truncation toward zero, the flag for INT64_MIN / -1) through
+// the multiplier and shift that div_magic made for d (shift 512: d == 0, the
+// general division flags it).
+__device__ __forceinline__ int64_t tdiv_magic(int64_t a, int64_t d, uint64_t m, int32_t sh, bool &ovf) {
+  if (sh & 512) return tdiv(a, d, ovf);
+  const int l = sh & 255;
+  const bool neg_a = a < 0;
+  const uint64_t u = neg_a ? 0ull - (uint64_t)a : (uint64_t)a;
+  const uint64_t t = __umul64hi(m, u);
+  const uint64_t q = (t + ((u - t) >> (l < 1 ? l : 1))) >> (l > 1 ? l - 1 : 0);
+  const bool neg = neg_a != ((sh & 256) != 0);
+  if (!neg && q > (uint64_t)INT64_MAX) ovf = true;
+  return neg ? (int64_t)(0ull - q) : (int64_t)q;
+}
+
 // Sum of an int64 over each group of G consecutive lanes (G = 1, 2, 4, 8, 16),
 // returned to every lane of the group; every lane of the wavefront active.
 template <int G>
@@ -56,105 +73,259 @@ __device__ __forceinline__ int64_t group_sum64(int64_t v) {
   return v;
 }
 
+// The first-pass row of one level held in registers by a lane: stage 1
+// (issued two levels ahead: everything addressed by the position alone) and
+// stage 2 (one level ahead: the right-hand side and, when the waits of the
+// level are already known to be met, the values of other blocks).
+template <int PRE, class VT, class TX>
+struct SweepRow {
+  bool act;
+  int lp;       // position inside the block
+  int len;      // entries
+  int64_t e0;   // slot of entry 0; entry k at e0 + k * cnt
+  int32_t cnt;  // rows of the level
+  int32_t row;
+  int64_t dg;   // the diagonal (as a divisor: mag, sh)
+  uint64_t mag;
+  int32_t sh;
+  TX rhs;
+  bool xok;     // x holds the values of the entries from other blocks
+  int32_t c[PRE];
+  VT v[PRE];
+  TX x[PRE];
+};
+
 // One sweep by the whole grid. FP = false: integer values (TX = int64_t),
 // dst = tdiv(src - strict part, diagonal); FP = true: doubles, G must be 1.
-// `vals` is LDS for S values, `seen` LDS for kSeenSlots words. Must be called
-// by every thread of every workgroup (BLOCK threads each).
+// `lds` holds sweep_lds_bytes(S, max_levels) bytes: the block's values, its
+// level table (entry starts, offsets), a window of its wait records, the
+// cache of what each dependency block was seen to have finished, and two
+// flags. The level table and the records are copied there when a block
+// starts, so nothing on the path from one level to the next reads global
+// memory except the values other blocks computed. Must be called by every
+// thread of every workgroup (BLOCK threads each).
+//
+// Per level L of a block: compute L from the registers; publish level L - 1
+// (this wavefront's stores of it have had a whole level to complete, so the
+// wait is short); issue stage 2 of L + 1 and stage 1 of L + 2; store L (LDS
+// and global); wavefront 0 takes the waits of L + 1 and checks from the cache
+// whether those of L + 2 are already met; one workgroup barrier. Only the
+// in-block values come from LDS on the critical path; rows of a level beyond
+// the first pass of BLOCK / G rows are loaded when computed.
 template <int BLOCK, int G, bool FP, class TX>
-__device__ __forceinline__ void block_sweep(const BlockSweepArgs &b, const TX *src, TX *dst, TX *vals,
-                                            unsigned *seen, bool &ovf, bool &to) {
+__device__ __forceinline__ void block_sweep(const BlockSweepArgs &b, const TX *src, TX *dst, char *lds, bool &ovf,
+                                            bool &to) {
   static_assert(BLOCK % 64 == 0 && G >= 1 && G <= 16 && (G & (G - 1)) == 0, "lanes per row");
   static_assert(!FP || G == 1, "the FP64 substitution sums each row in CSR order");
-  constexpr int RPP = BLOCK / G;  // rows per pass
+  constexpr int RPP = BLOCK / G;      // rows per pass
+  constexpr int NW = BLOCK / 64;      // wavefronts: each adds one to the progress word per level
+  constexpr int PRE = G >= 16 ? 1 : 16 / G;  // entries per lane held in registers
+  using VT = typename std::conditional<FP, double, int64_t>::type;
+  using Row = SweepRow<PRE, VT, TX>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int rs = tid / G, gl = tid % G;
+  const int klv = b.max_levels + 1;
+  TX *vals = (TX *)lds;
+  int64_t *levent = (int64_t *)(lds + 8 * (size_t)b.S);
+  int32_t *lvoff = (int32_t *)(levent + klv);
+  WaitRec *recs = (WaitRec *)((char *)lvoff + (4 * (size_t)klv + 15) / 16 * 16);
+  unsigned *seen = (unsigned *)(recs + kRecWindow);
+  int *ready = (int *)(seen + kSeenSlots);
+
   for (int q = blockIdx.x; q < b.nb; q += gridDim.x) {
     const int64_t q0 = (int64_t)q * b.S;
     const int lb = b.lvbase[q];
     const int nl = b.lvbase[q + 1] - lb - 1;
-    int wr = b.wbase[q];
+    unsigned *prog = b.prog + (int64_t)q * kLevStride;
+    // wavefront 0: the next wait record, and the records held in `recs`
+    int wr = b.wbase[q], win_lo = wr, win_hi = wr;
     const int we = b.wbase[q + 1];
+    for (int i = tid; i <= nl; i += BLOCK) {
+      lvoff[i] = b.lvoff[lb + i];
+      levent[i] = b.levent[lb + i];
+    }
+
+    // stage 1 of pass `pass` of level L for this lane
+    auto stage1 = [&](int L, int pass, Row &r) {
+      const int p0 = lvoff[L], p1 = lvoff[L + 1];
+      r.cnt = p1 - p0;
+      const int i = pass * RPP + rs;
+      r.act = p0 + i < p1;
+      r.lp = p0 + i;
+      r.xok = false;
+      r.len = 0;
+      if (!r.act) return;
+      const int64_t lev0 = levent[L];
+      const int width = (int)((levent[L + 1] - lev0) / r.cnt);
+      const int64_t pos = q0 + r.lp;
+      r.row = b.prow[pos];
+      r.len = b.plen[pos];
+      r.dg = b.pdiag[pos];
+      if constexpr (!FP) {
+        r.mag = b.pmag[pos];
+        r.sh = b.pshift[pos];
+      }
+      r.e0 = lev0 + i;
+#pragma unroll
+      for (int j = 0; j < PRE; ++j) {
+        const int k = gl + j * G;
+        if (k < width) {  // slots past the row's length are padding of the level: readable
+          const int64_t e = r.e0 + (int64_t)k * r.cnt;
+          r.c[j] = b.ecode[e];
+          if constexpr (FP) r.v[j] = b.evalf[e];
+          else r.v[j] = b.eval[e];
+        }
+      }
+    };
+    // stage 2: the right-hand side, and the values of other blocks if the
+    // level's waits are met (`met`)
+    auto stage2 = [&](Row &r, bool met) {
+      if (!r.act) return;
+      r.rhs = ld_coh(src + r.row);
+      if (!met) return;
+#pragma unroll
+      for (int j = 0; j < PRE; ++j) {
+        const int k = gl + j * G;
+        if (k < r.len && r.c[j] < 0) r.x[j] = ld_coh(dst + (-(int64_t)r.c[j] - 1));
+      }
+      r.xok = true;
+    };
+    // the row's value: in-block values from LDS, others from registers or memory
+    auto compute = [&](const Row &r) {
+      Acc acc;
+      acc.zero();
+      double facc = 0.0;
+      if (r.act) {
+        auto term = [&](int32_t c, VT v, TX xr) {
+          const TX xv = c >= 0 ? vals[c] : xr;
+          if constexpr (FP) {
+            facc = facc + v * xv;
+          } else {
+            acc.sub(b.narrow ? mul_w32(xv, (int32_t)v, ovf) : mulw(xv, v, ovf));
+          }
+        };
+#pragma unroll
+        for (int j = 0; j < PRE; ++j) {
+          const int k = gl + j * G;
+          if (k < r.len) {
+            const int32_t c = r.c[j];
+            const TX xr = (c >= 0 || r.xok) ? r.x[j] : ld_coh(dst + (-(int64_t)c - 1));
+            term(c, r.v[j], xr);
+          }
+        }
+        for (int k = gl + PRE * G; k < r.len; k += G) {  // entries beyond the registers, in order
+          const int64_t e = r.e0 + (int64_t)k * r.cnt;
+          const int32_t c = b.ecode[e];
+          VT v;
+          if constexpr (FP) v = b.evalf[e];
+          else v = b.eval[e];
+          term(c, v, c >= 0 ? (TX)0 : ld_coh(dst + (-(int64_t)c - 1)));
+        }
+      }
+      if constexpr (!FP && G > 1) {
+        acc.lo = group_sum64<G>(acc.lo);
+        acc.hi = group_sum64<G>(acc.hi);
+      }
+      TX y = 0;
+      if (r.act && gl == 0) {
+        if constexpr (FP) {
+          y = (r.rhs - facc) / (double)r.dg;
+        } else {
+          acc.add(r.rhs);
+          y = tdiv_magic(acc.value(ovf), r.dg, r.mag, r.sh, ovf);
+        }
+      }
+      return y;
+    };
+    auto store = [&](const Row &r, TX y) {
+      if (r.act && gl == 0) {
+        vals[r.lp] = y;
+        st_coh(dst + r.row, y);
+      }
+    };
+    // wavefront 0: take the waits of level L (blocking); then report whether
+    // the records of level L + 1 are already met by what was seen
+    auto waits = [&](int L) {
+      if (tid >= 64) return;
+      for (;;) {
+        if (wr + 64 > win_hi && win_hi < we) {  // refill the window from the next record on
+          const int cnt = we - wr < kRecWindow ? we - wr : kRecWindow;
+          for (int i = lane; i < cnt; i += 64) recs[i] = b.wrec[wr + i];
+          win_lo = wr;
+          win_hi = wr + cnt;
+        }
+        const int r = wr + lane;
+        WaitRec rec{0, 0, 0, 0};
+        if (r < win_hi) rec = recs[r - win_lo];
+        const bool mine = r < win_hi && rec.level == L;
+        const unsigned long long got = __ballot(mine);
+        if (mine) {
+          const unsigned target = (unsigned)rec.need * NW;
+          const bool cached = rec.slot < kSeenSlots;
+          unsigned v = cached ? seen[rec.slot] : 0u;
+          for (int spin = 0; v < target; ++spin) {
+            v = ld_coh(b.prog + (int64_t)rec.dep * kLevStride);
+            if (v >= target) break;
+            if (spin >= kSpinLimit || to) {
+              to = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
+          }
+          if (cached) seen[rec.slot] = v;
+        }
+        const int cnt = __popcll(got);  // the records of a level are consecutive
+        wr += cnt;
+        if (cnt < 64) break;
+      }
+      // level L + 1: met if every record of it is below the cached progress
+      // (records beyond the window count as not met)
+      const int r = wr + lane;
+      WaitRec rec{0, 0, 0, 0};
+      if (r < win_hi) rec = recs[r - win_lo];
+      const bool mine = r < win_hi && rec.level == L + 1;
+      const bool ok = (r >= win_hi && r < we) ? false
+                      : !mine || (rec.slot < kSeenSlots && seen[rec.slot] >= (unsigned)rec.need * NW);
+      const unsigned long long all = __ballot(mine);
+      const bool met = __all(ok) && __popcll(all) < 64;
+      if (lane == 0) ready[(L + 1) & 1] = met ? 1 : 0;
+    };
+    auto publish = [&]() {
+      wait_vm();
+      if (lane == 0) __hip_atomic_fetch_add(prog, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+
     for (int s = tid; s < kSeenSlots; s += BLOCK) seen[s] = 0;
     __syncthreads();
+    waits(0);
+    __syncthreads();
+    Row A, B;
+    stage1(0, 0, A);
+    stage2(A, true);
+    if (nl > 1) stage1(1, 0, B);
     for (int L = 0; L < nl; ++L) {
-      // ---- the waits of level L (wavefront 0, one record per lane)
-      if (tid < 64) {
-        for (;;) {
-          const int r = wr + lane;
-          WaitRec rec{0, 0, 0, 0};
-          if (r < we) rec = b.wrec[r];
-          const bool mine = r < we && rec.level == L;
-          const unsigned long long got = __ballot(mine);
-          if (mine) {
-            const bool cached = rec.slot < kSeenSlots;
-            unsigned v = cached ? seen[rec.slot] : 0u;
-            for (int spin = 0; v < (unsigned)rec.need; ++spin) {
-              v = ld_coh(b.prog + (int64_t)rec.dep * kLevStride);
-              if (v >= (unsigned)rec.need) break;
-              if (spin >= kSpinLimit || to) {
-                to = true;
-                break;
-              }
-              __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
-            }
-            if (cached) seen[rec.slot] = v;
-          }
-          const int cnt = __popcll(got);  // the records of a level are consecutive
-          wr += cnt;
-          if (cnt < 64) break;
-        }
+      const TX y = compute(A);
+      if (L > 0) publish();
+      Row C;
+      if (L + 1 < nl) stage2(B, ready[(L + 1) & 1] != 0);
+      if (L + 2 < nl) stage1(L + 2, 0, C);
+      store(A, y);
+      // passes after the first (levels wider than BLOCK / G rows)
+      const int cnt = A.cnt;
+      for (int pass = 1; pass * RPP < cnt; ++pass) {
+        Row P;
+        stage1(L, pass, P);
+        stage2(P, true);
+        const TX yp = compute(P);
+        store(P, yp);
       }
+      waits(L + 1);
       __syncthreads();
-      // ---- the rows of level L
-      const int p0 = b.lvoff[lb + L], p1 = b.lvoff[lb + L + 1];
-      for (int base = p0; base < p1; base += RPP) {
-        const int lp = base + rs;
-        const bool act = lp < p1;
-        Acc acc;
-        acc.zero();
-        double facc = 0.0;
-        int64_t row = 0;
-        if (act) {
-          const int64_t pos = q0 + lp;
-          row = b.prow[pos];
-          const int64_t e1 = b.eoff[pos + 1];
-          for (int64_t e = b.eoff[pos] + gl; e < e1; e += G) {
-            const int32_t c = b.ecode[e];
-            const TX xv = c >= 0 ? vals[c] : ld_coh(dst + (-(int64_t)c - 1));
-            if constexpr (FP) {
-              facc = facc + b.evalf[e] * xv;
-            } else {
-              const int64_t v = b.eval[e];
-              acc.sub(b.narrow ? mul_w32(xv, (int32_t)v, ovf) : mulw(xv, v, ovf));
-            }
-          }
-        }
-        if constexpr (!FP && G > 1) {
-          acc.lo = group_sum64<G>(acc.lo);
-          acc.hi = group_sum64<G>(acc.hi);
-        }
-        if (act && gl == 0) {
-          const TX rhs = ld_coh(src + row);
-          const int64_t dg = b.pdiag[q0 + lp];
-          TX y;
-          if constexpr (FP) {
-            y = (rhs - facc) / (double)dg;
-          } else {
-            acc.add(rhs);
-            y = tdiv(acc.value(ovf), dg, ovf);
-          }
-          vals[lp] = y;
-          st_coh(dst + row, y);
-        }
-      }
-      // publish level L once this workgroup's stores of it have completed
-      wait_vm();
-      __syncthreads();
-      if (tid == 0)
-        __hip_atomic_store(b.prog + (int64_t)q * kLevStride, (unsigned)(L + 1), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      A = B;
+      B = C;
     }
+    publish();
   }
 }
 

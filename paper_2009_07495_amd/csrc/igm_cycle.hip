@@ -30,18 +30,15 @@ constexpr int kGivens = 64;
 // the 16 words of a cache line), other workgroups first read them
 // after that barrier, and a launch starts with caches coherent with memory.
 
-// One integer sweep of the ILU(0) preconditioner apply with G lanes per row
-// (a runtime choice: the bits do not depend on it).
+// One integer sweep of the ILU(0) preconditioner apply with G = 8 or 16 lanes
+// per row (a runtime choice: the bits do not depend on it; fewer lanes per
+// row hold more entries per lane in registers than the cycle kernel has to
+// spare, and it would spill).
 template <int BLOCK>
 __device__ __forceinline__ void ilu_sweep(int G, const BlockSweepArgs &b, const int64_t *src, int64_t *dst,
-                                          int64_t *vals, unsigned *seen, bool &ovf, bool &to) {
-  switch (G) {
-    case 1: block_sweep<BLOCK, 1, false>(b, src, dst, vals, seen, ovf, to); break;
-    case 2: block_sweep<BLOCK, 2, false>(b, src, dst, vals, seen, ovf, to); break;
-    case 4: block_sweep<BLOCK, 4, false>(b, src, dst, vals, seen, ovf, to); break;
-    case 8: block_sweep<BLOCK, 8, false>(b, src, dst, vals, seen, ovf, to); break;
-    default: block_sweep<BLOCK, 16, false>(b, src, dst, vals, seen, ovf, to); break;
-  }
+                                          char *lds, bool &ovf, bool &to) {
+  if (G == 16) block_sweep<BLOCK, 16, false>(b, src, dst, lds, ovf, to);
+  else block_sweep<BLOCK, 8, false>(b, src, dst, lds, ovf, to);
 }
 
 template <int BLOCK, int R, int PRE>
@@ -186,11 +183,10 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       for (int64_t i = gt; i < (int64_t)a.bsf.nb + a.bsb.nb; i += T) st_coh(a.bsf.prog + i * kLevStride, 0u);
       note_event(o1, first, ev_code(j, 1, 0));
       grid_barrier_coh(gs, ssh);
-      int64_t *svals = (int64_t *)((char *)smem + a.sweep_lds_off);
-      unsigned *seen = (unsigned *)(svals + a.bsf.S);
-      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsf, (const int64_t *)a.zbuf, a.wbuf, svals, seen, o2, to);
+      char *slds = (char *)smem + a.sweep_lds_off;
+      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsf, (const int64_t *)a.zbuf, a.wbuf, slds, o2, to);
       grid_barrier_coh(gs, ssh);
-      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsb, (const int64_t *)a.wbuf, a.wbuf, svals, seen, o2, to);
+      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsb, (const int64_t *)a.wbuf, a.wbuf, slds, o2, to);
       if (to) __hip_atomic_store(&a.state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       grid_barrier_coh(gs, ssh);
       note_event(o2, first, ev_code(j, 2, 0));

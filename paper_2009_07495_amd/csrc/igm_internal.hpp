@@ -77,13 +77,22 @@ struct BlockSchedule {
   int32_t max_levels = 0;    // most local levels of one block
   bool narrow = false;       // every factor value fits in int32
   hvec<int32_t> prow;        // n: row of each sorted position
-  hvec<int64_t> eoff;        // n + 1: entries of each sorted position, in CSR order of its row
+  hvec<int32_t> plen;        // n: entries of each sorted position's row
   hvec<int32_t> ecode;       // >= 0: sorted position inside the block of an in-block dependency; < 0: -(row + 1)
   hvec<int64_t> eval;        // the factor's value of each entry
   hvec<double> evalf;        // the same values as doubles (FP64 start step)
   hvec<int64_t> pdiag;       // n: the factor's diagonal of each sorted position's row
-  hvec<int32_t> lvbase;      // nb + 1: where each block's level offsets start in lvoff
+  // n: the diagonal as an invariant divisor (see div_magic): multiplier, and
+  // the shift l = ceil(log2 |d|) with bit 8 set for a negative divisor
+  hvec<uint64_t> pmag;
+  hvec<int32_t> pshift;
+  hvec<int32_t> lvbase;      // nb + 1: where each block's level offsets start in lvoff and levent
   hvec<int32_t> lvoff;       // per block, nl + 1 offsets of its levels (positions inside the block)
+  // per block, nl + 1: where each level's entries start. Inside a level of c
+  // rows the entries are column-major: entry k (CSR order) of the level's
+  // i-th row is at levent[L] + k c + i, so a row's entries are addressed from
+  // its position alone; slots past a row's length are padding.
+  hvec<int64_t> levent;
   hvec<int32_t> wbase;       // nb + 1: where each block's wait records start in wrec
   hvec<WaitRec> wrec;        // per block, sorted by level
 };
@@ -91,26 +100,52 @@ struct BlockSchedule {
 // Device view of one BlockSchedule.
 struct BlockSweepArgs {
   int32_t S, nb;
-  int32_t narrow;  // every factor value fits in int32
-  const int32_t *prow;
-  const int64_t *eoff;
+  int32_t narrow;      // every factor value fits in int32
+  int32_t max_levels;  // most local levels of one block (sizes the LDS copy of a block's level table)
+  const int32_t *prow, *plen;
   const int32_t *ecode;
   const int64_t *eval;
   const double *evalf;
   const int64_t *pdiag;
+  const uint64_t *pmag;
+  const int32_t *pshift;
   const int32_t *lvbase, *lvoff, *wbase;
+  const int64_t *levent;
   const WaitRec *wrec;
-  unsigned *prog;  // nb progress words kLevStride apart, zero at the start of the sweep
+  // nb progress words kLevStride apart, zero at the start of the sweep: every
+  // wavefront of the block's workgroup adds one per finished level
+  unsigned *prog;
 };
 
-// Dependency blocks per block whose progress a sweep caches in LDS.
+// Dependency blocks per block whose progress a sweep caches in LDS, wait
+// records held in LDS at a time, and the LDS a sweep needs: the block's S
+// values, its level table (offsets and entry starts of max_levels + 1
+// levels), the record window, that cache and two flags.
 constexpr int kSeenSlots = 256;
+constexpr int kRecWindow = 256;
+inline size_t sweep_lds_bytes(int64_t S, int32_t max_levels) {
+  const size_t lv = (size_t)max_levels + 1;
+  return 8 * (size_t)S + 8 * lv + (4 * lv + 15) / 16 * 16 + 16 * (size_t)kRecWindow + 4 * (size_t)kSeenSlots + 16;
+}
 // Rows per block and lanes per row of the blocked sweeps when the policy
 // leaves them open, and the static LDS the cycle kernel keeps besides its
 // dynamic part (reduction scratch and flags; an upper bound).
 constexpr int kSweepRowsAuto = 16384;
 constexpr int kSweepLanesAuto = 8;
 constexpr int kCycleStaticLds = 4096;
+
+// Truncating division by an invariant nonzero divisor d through one
+// multiply-high (Granlund and Montgomery, "Division by invariant integers
+// using multiplication", 1994, unsigned form): with l = ceil(log2 |d|) and
+// m = floor(2^64 (2^l - |d|) / |d|) + 1, floor(u / |d|) = (t + ((u - t) >> min(l, 1))) >> max(l - 1, 0)
+// for every u < 2^64, t = floor(m u / 2^64). The sign follows C division.
+inline void div_magic(int64_t d, uint64_t &m, int32_t &shift) {
+  const uint64_t a = d < 0 ? 0ull - (uint64_t)d : (uint64_t)d;
+  int32_t l = 0;
+  while (l < 64 && (((unsigned __int128)1) << l) < a) ++l;
+  m = (uint64_t)((((unsigned __int128)((((unsigned __int128)1) << l) - a)) << 64) / a) + 1;
+  shift = l | (d < 0 ? 256 : 0);
+}
 
 // Builds the schedule of one sweep from a strict triangular factor in CSR
 // (ptr, col, val), its diagonal, and S rows per block (a multiple of 64).

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_fp_bsweep(BlockSweepArgs b, con
                                                            CycleState *state) {
   extern __shared__ double fsm[];
   bool ovf = false, to = false;
-  block_sweep<kSweepBlock, 1, true>(b, src, dst, fsm, (unsigned *)(fsm + b.S), ovf, to);
+  block_sweep<kSweepBlock, 1, true>(b, src, dst, (char *)fsm, ovf, to);
   if (to) __hip_atomic_store(&state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -273,7 +273,7 @@ constexpr int kRUnroll = 8;  // elements in flight per thread
 
 __global__ __launch_bounds__(kRB) void k_reduce(int64_t n, const int64_t *__restrict__ w,
                                                const int64_t *__restrict__ v, int b, int df, int mode, Acc *parts,
-                                               unsigned *ticket, int64_t *out, CycleState *st, int64_t code) {
+                                               unsigned *ticket, int64_t *out, int64_t *first, int64_t code) {
   __shared__ Acc sh_wave[kRB / 64];
   __shared__ int last;
   Acc acc;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kRB) void k_reduce(int64_t n, const int64_t *__rest
       acc.add(mode == 0 ? mulw(t, vv[u], o) : sqrc(t, o));
     }
   }
-  note_event(o, &st->first_ovf, code);
+  note_event(o, first, code);
   const Acc p = block_sum<kRB>(acc, sh_wave);
   if (threadIdx.x == 0) {
     st_coh(&parts[blockIdx.x].lo, p.lo);
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kRB) void k_reduce(int64_t n, const int64_t *__rest
     bool of = false;
     const int64_t S = t.value(of);
     const int64_t r = mode == 0 ? asr(S, df - b) : shl(isqrt64(S), b, of);
-    if (of) atomicMin((long long *)&st->first_ovf, (long long)code);
+    if (of) atomicMin((long long *)first, (long long)code);
     *out = r;
     *ticket = 0u;
   }
@@ -398,7 +398,7 @@ hipError_t launch_start_vector(hipStream_t st, const CycleArgs &a, const double 
     // clears them again in every Arnoldi step)
     hipError_t e = hipMemsetAsync(a.bsf.prog, 0, sizeof(unsigned) * ((size_t)a.bsf.nb + a.bsb.nb) * kLevStride, st);
     if (e != hipSuccess) return e;
-    const size_t lds = sizeof(double) * (size_t)a.bsf.S + sizeof(unsigned) * kSeenSlots;
+    const size_t lds = sweep_lds_bytes(a.bsf.S, a.bsf.max_levels);
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fp_bsweep, kSweepBlock, lds);
     if (e != hipSuccess) return e;
@@ -457,8 +457,8 @@ hipError_t launch_reduce(hipStream_t st, int64_t n, const int64_t *w, const int6
   const int64_t want = (n + (int64_t)kRB * kRUnroll - 1) / ((int64_t)kRB * kRUnroll);
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kMaxReduceParts));
   unsigned *ticket = (unsigned *)(parts + kMaxReduceParts);  // zero between launches
-  hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(kRB), 0, st, n, w, v, b, df, mode, (Acc *)parts, ticket, out, state,
-                     code);
+  hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(kRB), 0, st, n, w, v, b, df, mode, (Acc *)parts, ticket, out,
+                     &state->first_ovf, code);
   return hipGetLastError();
 }
 

@@ -97,6 +97,13 @@ static uint64_t setup_hash(const Csr &a, const igm_policy &p, igm_status &st) {
   return H;
 }
 
+// Slot of entry kk (CSR order) of the row at sorted position k of block q,
+// level L: levels are stored column-major.
+static int64_t entry_at(const igm::BlockSchedule &b, int32_t q, int32_t L, int32_t k, int64_t kk) {
+  const int32_t *lo = b.lvoff.data() + b.lvbase[q];
+  return b.levent[b.lvbase[q] + L] + kk * (lo[L + 1] - lo[L]) + (k - lo[L]);
+}
+
 // The blocked sweep schedule of a strict triangular factor (igm_bsched.cpp):
 // every row appears once; an in-block dependency sits at a lower local level
 // of the same block; a dependency on another block is covered by a wait
@@ -138,7 +145,10 @@ static int check_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> 
       }
       for (int32_t k = lo[L]; k < lo[L + 1]; ++k) {
         const int64_t pk = (int64_t)q * S + k;
-        for (int64_t e = b.eoff[pk]; e < b.eoff[pk + 1]; ++e) {
+        if (b.plen[pk] != ptr[b.prow[pk] + 1] - ptr[b.prow[pk]]) ++bad;
+        for (int64_t kk = 0; kk < b.plen[pk]; ++kk) {
+          const int64_t e = entry_at(b, q, L, k, kk);
+          if (e < b.levent[b.lvbase[q] + L] || e >= b.levent[b.lvbase[q] + L + 1]) ++bad;
           const int32_t c = b.ecode[e];
           if (c >= 0) {
             if (c >= S || level[b.prow[(int64_t)q * S + c]] >= L) ++bad;
@@ -170,7 +180,10 @@ static int check_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> 
         const int64_t pk = (int64_t)q * S + k;
         const int64_t r = b.prow[pk];
         __int128 acc = z[r];
-        for (int64_t e = b.eoff[pk]; e < b.eoff[pk + 1]; ++e) {
+        for (int64_t kk = 0; kk < b.plen[pk]; ++kk) {
+          const int64_t e = entry_at(b, q, L, k, kk);
+          const int64_t want = col[ptr[r] + kk];  // CSR order kept
+          if (b.ecode[e] >= 0 ? b.prow[(int64_t)q * S + b.ecode[e]] != want : -(int64_t)b.ecode[e] - 1 != want) ++bad;
           const int32_t c = b.ecode[e];
           const int64_t x = c >= 0 ? got[b.prow[(int64_t)q * S + c]] : got[-(int64_t)c - 1];
           acc -= (__int128)b.eval[e] * x;
@@ -183,7 +196,8 @@ static int check_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> 
   for (int64_t r = 0; r < n; ++r)
     if (got[r] != ref[r]) ++bad;
   H = 1469598103934665603ull;
-  mix(b.prow); mix(b.eoff); mix(b.ecode); mix(b.eval); mix(b.pdiag); mix(b.lvbase); mix(b.lvoff); mix(b.wbase);
+  mix(b.prow); mix(b.plen); mix(b.levent); mix(b.ecode); mix(b.eval); mix(b.pdiag); mix(b.lvbase); mix(b.lvoff);
+  mix(b.wbase);
   for (const auto &w : b.wrec) {
     const int32_t f[4] = {w.level, w.slot, w.need, w.dep};
     for (int32_t x : f) H = (H ^ (uint32_t)x) * 1099511628211ull;
