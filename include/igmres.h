@@ -262,6 +262,24 @@ igm_status igm_axpy(igm_system *s, int64_t h, int64_t *w, const int64_t *v, int6
 /* Norm of w (Fig. 2; Sec. V-C.2): *h = shl(isqrt(sum_l asr(w_l, b_norm)^2), b_norm). */
 igm_status igm_norm(igm_system *s, const int64_t *w, int64_t *h, int64_t *first_ovf);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the inner
+ * product of igm_dot (mode 0) or the norm of igm_norm (mode 1) over n words
+ * of the caller's device vectors w (and v for mode 0), with shift b and d_f =
+ * df given directly instead of by a system. Nothing is allocated and nothing
+ * is waited for: the kernels are enqueued on `stream` (a hipStream_t; NULL =
+ * null stream), and out_dev (device, 2 words) receives the result in
+ * out_dev[0] and the overflow event code (step 1, stage 3 or 4) or
+ * IGM_NO_EVENT in out_dev[1]. The kernels' scratch (256 per-workgroup partial
+ * sums and a completion ticket, 4.3 KB) is a fixed array of the library on
+ * each device, cleared by the call itself; it keeps the last call's contents.
+ * Calls that overlap on one device (other streams, other threads) race on it
+ * and must be serialised by the caller. Errors: IGM_ERR_ARG (mode, n outside
+ * 1..2^48, null pointers, df outside 1..62, b outside 0..df), IGM_ERR_DEVICE,
+ * IGM_ERR_UNSUPPORTED (device index above 63). */
+igm_status igm_reduce_noalloc(int32_t mode, int64_t n, const int64_t *w, const int64_t *v, int32_t b, int32_t df,
+                              int64_t *out_dev, void *stream);
+
 /* Normalisation v = w / h (Fig. 2; Sec. V-B.3): v_l = sc(tdiv(shl(w_l, b_div_num), asr(h, b_div_den)),
  * df - b_div_num - b_div_den). IGM_ERR_BREAKDOWN if the shifted denominator is 0. */
 igm_status igm_normalize(igm_system *s, const int64_t *w, int64_t h, int64_t *v, int64_t *first_ovf);

@@ -108,6 +108,8 @@ _SIGS = {
     "igm_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "igm_fp_norm": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
     "igm_start_vector": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "igm_reduce_noalloc": [C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                           C.c_void_p],
     "igm_destroy": [C.c_void_p],
     "igm_status_str": [C.c_int],
     "igm_batch_create": [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -175,6 +177,13 @@ def status_str(st: int) -> str:
 
 igm_status_str = status_str
 
+
+def igm_reduce_noalloc(mode: int, n: int, w, v, b: int, df: int, out_dev, stream=None) -> int:
+    """Inner product (mode 0) or norm (mode 1) into out_dev[0..1] (device),
+    enqueued on `stream` without any allocation; returns the status."""
+    handle = getattr(stream, "cuda_stream", stream)
+    return lib().igm_reduce_noalloc(int(mode), int(n), _ptr(w), _ptr(v), int(b), int(df), _ptr(out_dev),
+                                    C.c_void_p(handle or 0))
 
 
 def igm_policy_preset(preset) -> Policy:

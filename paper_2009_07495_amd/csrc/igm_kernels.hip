@@ -7,6 +7,7 @@
 // order-free construction of dnrm_finish, so results do not depend on the
 // launch shape.
 #include <algorithm>
+#include <mutex>
 
 #include "igm_bsweep.hpp"
 #include "igm_launch.hpp"
@@ -474,4 +475,62 @@ hipError_t launch_normalize(hipStream_t st, int64_t n, const int64_t *w, int64_t
   return hipGetLastError();
 }
 
+// ---- The standalone inner product and norm without allocation -------------
+//
+// The same k_reduce as igm_dot / igm_norm, with its scratch (per-workgroup
+// partial sums, then the completion ticket) in this fixed device array
+// instead of a system's buffers, and at most kNoAllocParts workgroups (one per
+// compute unit of the device is plenty for a streaming reduction). Each
+// device holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device, looked up once per device.
+constexpr int kNoAllocParts = 256;
+constexpr size_t kNoAllocScratchBytes = sizeof(Acc) * kNoAllocParts + 256;  // partials, then the ticket
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kNoAllocDevices] = {nullptr};
+
+// clears the ticket and the caller's event word before a reduction
+__global__ void k_noalloc_init(unsigned *ticket, int64_t *event) {
+  *ticket = 0u;
+  *event = kNoEvent;
+}
+
+}  // namespace
+
 }  // namespace igm
+
+extern "C" igm_status igm_reduce_noalloc(int32_t mode, int64_t n, const int64_t *w, const int64_t *v, int32_t b,
+                                         int32_t df, int64_t *out_dev, void *stream) {
+  using namespace igm;
+  if ((mode != 0 && mode != 1) || n < 1 || n > kNoAllocMaxN || !w || (mode == 0 && !v) || !out_dev || df < 1 ||
+      df > 62 || b < 0 || b > df)
+    return IGM_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return IGM_ERR_DEVICE;
+  if (dev < 0 || dev >= kNoAllocDevices) return IGM_ERR_UNSUPPORTED;
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {  // first call on this device: its copy's address
+      void *p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IGM_ERR_DEVICE;
+      g_scratch_dev[dev] = p;
+    }
+    base = g_scratch_dev[dev];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Acc *parts = (Acc *)base;
+  unsigned *ticket = (unsigned *)((char *)base + sizeof(Acc) * kNoAllocParts);
+  const int64_t want = (n + (int64_t)kRB * kRUnroll - 1) / ((int64_t)kRB * kRUnroll);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kNoAllocParts));
+  hipLaunchKernelGGL(k_noalloc_init, dim3(1), dim3(1), 0, st, ticket, out_dev + 1);
+  // event codes as in igm_dot / igm_norm: step 1, stage 3 (inner product) or 4 (norm)
+  const int64_t code = ((int64_t)1 << 24) | ((int64_t)(mode == 0 ? 3 : 4) << 16);
+  hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(kRB), 0, st, n, w, mode == 0 ? v : w, b, df, mode, parts, ticket,
+                     out_dev, out_dev + 1, code);
+  return hipGetLastError() == hipSuccess ? IGM_OK : IGM_ERR_DEVICE;
+}

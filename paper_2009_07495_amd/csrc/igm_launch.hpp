@@ -9,6 +9,9 @@ namespace igm {
 // Workgroup partials of the standalone reductions (igm_dot, igm_norm); the
 // partial buffer holds this many plus one word for the completion ticket.
 constexpr int kMaxReduceParts = 2048;
+// Largest length igm_reduce_noalloc accepts (its grid strides over any length;
+// the bound only keeps index arithmetic far from overflow).
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 48;
 
 // Scratch words of the FP64 reductions (d_red): maxima as double bit patterns,
 // exact norm sums as three 40-bit limbs. The block of kRedWords words is held
