@@ -492,29 +492,53 @@ def served(B, W, count: int, distinct: int, rate: float = 2000.0, plain_sample: 
 
 
 def kernel_rates(torch, B, W) -> dict:
-    """Standalone SpMV and Gram-Schmidt inner-product kernels (Fig. 2) on the
-    27-point 1M-row matrix, timed with HIP events around the kernels."""
-    sysm = W.random27(128, 128, 64, seed=3)
-    g = B.System.from_system(sysm, "jacobi", m=2)
-    n, nnz = sysm.n, sysm.nnz
-    rng = np.random.default_rng(0)
-    v = torch.from_numpy(rng.integers(-(1 << 30), 1 << 30, n)).cuda()
-    z = torch.zeros(n, dtype=torch.int64, device="cuda")
-    res = {}
-    for name, fn, byts in (("spmv", lambda: g.spmv(v, z), 12 * nnz + 16 * n + 4 * (n + 1)),
-                           ("dot", lambda: g.dot(v, v), 16 * n)):  # Q30 words: no product overflows
+    """Standalone SpMV and Gram-Schmidt inner-product kernels (Fig. 2), timed
+    with HIP events around the kernels: the SpMV with each row-to-lane mapping
+    (one thread per row over SELL-64; 4, 16, 64 lanes per row over CSR) on the
+    27-point 1M-row matrix, the 7-point 64^3 matrix and a heavy-tailed 1M-row
+    matrix, with the mapping the automatic rule and the setup-time measurement
+    pick; the inner product on the 27-point matrix's vector length."""
+
+    def med_ms(g, fn):
         for _ in range(3):
             fn()
         ts = []
         for _ in range(20):
             fn()
             ts.append(g.stats()["time_kernel_ms"])
-        t = float(np.median(ts)) / 1000.0
-        res[name] = {"gb_s": byts / t / 1e9, "frac": byts / t / 1e9 / HBM_PEAK_GBS, "ms": t * 1000.0,
-                     "bytes": byts, "workload": f"random27 n={n} nnz={nnz}"}
-    g.close()
-    return res
+        return float(np.median(ts))
 
+    res = {"spmv_mappings": {}}
+    rng = np.random.default_rng(0)
+    for wl, gen in (("random27_1m", lambda: W.random27(128, 128, 64, seed=3)),
+                    ("convdiff3d_64", lambda: W.convdiff3d(64)),
+                    ("skewed_1m", lambda: W.skewed(1 << 20, seed=6))):
+        sysm = gen()
+        n, nnz = sysm.n, sysm.nnz
+        byts = 12 * nnz + 16 * n + 4 * (n + 1)
+        v = torch.from_numpy(rng.integers(-(1 << 30), 1 << 30, n)).cuda()
+        z = torch.zeros(n, dtype=torch.int64, device="cuda")
+        row = {"n": n, "nnz": nnz, "bytes": byts, "lanes": {}}
+        for lanes in (1, 4, 16, 64):
+            g = B.System.from_system(sysm, "jacobi", m=2, spmv_lanes=lanes)
+            ms = med_ms(g, lambda: g.spmv(v, z))
+            row["lanes"][str(lanes)] = {"ms": ms, "gb_s": byts / ms / 1e6, "frac": byts / ms / 1e6 / HBM_PEAK_GBS}
+            if wl == "random27_1m" and lanes == 1:
+                res["spmv"] = dict(row["lanes"]["1"], bytes=byts, workload=f"random27 n={n} nnz={nnz}")
+                dms = med_ms(g, lambda: g.dot(v, v))  # Q30 words: no product overflows
+                res["dot"] = {"ms": dms, "gb_s": 16 * n / dms / 1e6, "frac": 16 * n / dms / 1e6 / HBM_PEAK_GBS,
+                              "bytes": 16 * n, "workload": f"random27 n={n}"}
+            g.close()
+        for key, lanes in (("auto", 0), ("measured", -1)):
+            g = B.System.from_system(sysm, "jacobi", m=2, spmv_lanes=lanes)
+            row[key] = g.stats()["spmv_lanes"]
+            g.close()
+        best = min(row["lanes"], key=lambda k: row["lanes"][k]["ms"])
+        row["fastest"] = int(best)
+        res["spmv_mappings"][wl] = row
+        progress(f"spmv mappings {wl}: " + ", ".join(f"{k}: {r['gb_s']:.0f} GB/s" for k, r in row["lanes"].items())
+            + f"; auto {row['auto']}, measured {row['measured']}")
+    return res
 
 if __name__ == "__main__":
     main()

@@ -135,6 +135,17 @@ typedef struct {
    * (the paper's experiments, S = 0); 1 = s(k) = min(S, k - 1), Abar_0 alone in
    * the first refinement and one more term in each later one. */
   int32_t s_rule;
+  /* Launch tuning of the single-system solver's integer SpMV and FP64
+   * residual (the bits do not depend on it): lanes per row. 1 = one thread per
+   * row over the SELL-64 layout (rows of similar length); 4, 16 or 64 = that
+   * many lanes of a wavefront per row over the CSR layout (rows of very
+   * different or large lengths; 64 = a wavefront per row); 0 = automatic from
+   * the row lengths: 1 unless SELL-64 would more than double the entries
+   * loaded, then 16; -1 = measured: at setup each of 1, 4, 16, 64 runs the standalone
+   * SpMV a few times and the fastest is kept. With 4, 16, 64 or -1 the system
+   * also holds the integer matrices in CSR order (8 bytes per entry and term). */
+  int32_t spmv_lanes;
+  int32_t reserved_[3];
 } igm_policy;
 
 /* Fill *out with a preset (IGM_PRESET_*): df = 30, s = 0, m = 30, tol = 1e-10,
@@ -202,7 +213,9 @@ typedef struct {
    * 2 waits for the grid-wide inner-product sums, 3 norm, 4 normalisation,
    * 5 Givens rotations, 6 end-of-step barriers, 7 the whole call. */
   double phase_us[8];
-  int32_t reserved_[4];
+  int32_t spmv_lanes;      /* lanes per row of the integer SpMV and FP64 residual (1 = SELL-64) */
+  int32_t sweep_rows;      /* ILU(0): rows per block of the blocked sweeps */
+  int32_t reserved_[2];
 } igm_stats;
 
 /* Copy the statistics of the system's last setup and solve. */

@@ -35,13 +35,14 @@ class Policy(C.Structure):
                 + [("gtol", C.c_int64), ("tol", C.c_double), ("grid_blocks", C.c_int32),
                    ("phase_clock", C.c_int32), ("shift_retry", C.c_int32), ("two_sided", C.c_int32),
                    ("gauss_seidel", C.c_int32), ("sweep_rows", C.c_int32), ("sweep_lanes", C.c_int32),
-                   ("s_rule", C.c_int32)])
+                   ("s_rule", C.c_int32), ("spmv_lanes", C.c_int32), ("reserved_", C.c_int32 * 3)])
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f in _POLICY_INT_FIELDS}
         d.update(gtol=self.gtol, tol=self.tol, grid_blocks=self.grid_blocks, phase_clock=self.phase_clock,
                  shift_retry=self.shift_retry, two_sided=self.two_sided, gauss_seidel=self.gauss_seidel,
-                 sweep_rows=self.sweep_rows, sweep_lanes=self.sweep_lanes, s_rule=self.s_rule)
+                 sweep_rows=self.sweep_rows, sweep_lanes=self.sweep_lanes, s_rule=self.s_rule,
+                 spmv_lanes=self.spmv_lanes)
         return d
 
 
@@ -53,7 +54,8 @@ class Stats(C.Structure):
                 ("grid_blocks", C.c_int32), ("rows_per_thread", C.c_int32), ("block_threads", C.c_int32),
                 ("levels_fwd", C.c_int32), ("levels_bwd", C.c_int32), ("device_bytes", C.c_int64),
                 ("last_error_line", C.c_int32), ("shift_retries", C.c_int32), ("time_kernel_ms", C.c_double),
-                ("phase_us", C.c_double * 8), ("reserved_", C.c_int32 * 4)]
+                ("phase_us", C.c_double * 8), ("spmv_lanes", C.c_int32), ("sweep_rows", C.c_int32),
+                ("reserved_", C.c_int32 * 2)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if not f.endswith("_")}

@@ -145,6 +145,11 @@ CycleArgs make_args(igm_system *s) {
   a.bsb = s->bsb;
   a.sweep_lanes = s->sweep_lanes;
   a.sweep_lds_off = (int32_t)s->sweep_lds_off;
+  a.spmv_lanes = s->spmv_lanes;
+  a.spmv_lds_off = (int32_t)s->spmv_lds_off;
+  a.crp = s->d_row_ptr;
+  a.ccol = s->d_col;
+  for (int l = 0; l < kMaxTerms; ++l) a.cval[l] = s->d_cval[l];
   a.H = s->d_H; a.c = s->d_c; a.s = s->d_s; a.g = s->d_g;
   a.state = s->d_state;
   a.sync = s->d_sync;
@@ -242,15 +247,45 @@ igm_status device_norm(igm_system *s, const double *x, int64_t len, double *out_
   return IGM_OK;
 }
 
+// Lanes per row of the integer SpMV and the FP64 residual when the policy
+// leaves it open. SELL-64 (one lane per row) loads every slice padded to its
+// longest row and walks a row's entries one after another; a group of G lanes
+// per row loads no padding and cuts the walk G-fold, but reduces across the
+// group and leaves lanes idle on short rows. Measured on stencils (mean row
+// lengths 7 and 27, SELL-64 fill above 0.95) one lane per row is fastest by
+// 1.5x or more; on heavy-tailed rows (fill 0.08) 16 lanes are fastest, 5x
+// ahead of SELL-64. The rule follows the fill.
+int32_t auto_spmv_lanes(int64_t n, const int64_t *row_ptr) {
+  if (n <= 0) return 1;
+  const int64_t nnz = row_ptr[n];
+  int64_t padded = 0;
+  for (int64_t q = 0; q < n; q += kSlice) {
+    int64_t w = 0;
+    const int64_t e = std::min<int64_t>(n, q + kSlice);
+    for (int64_t i = q; i < e; ++i) w = std::max<int64_t>(w, row_ptr[i + 1] - row_ptr[i]);
+    padded += w * kSlice;
+  }
+  return 2 * nnz >= padded ? 1 : 16;
+}
+
+igm_status tune_spmv_lanes(igm_system *s);
+
 // Everything that depends on the policy or the right-hand side.
 igm_status build(igm_system *s) {
   free_device(s);
   IGM_TRY(host_setup(s->n, s->row_ptr, s->col, s->ahat, s->bhat, s->pol, s->hs));
   HostSetup &h = s->hs;
+  const bool tune = s->pol.spmv_lanes < 0;
+  s->spmv_lanes = s->pol.spmv_lanes > 0 ? s->pol.spmv_lanes : tune ? 4 : auto_spmv_lanes(s->n, s->row_ptr.data());
   // ILU(0): the blocked schedules of the two sweeps, sized by the LDS a
   // workgroup of the cycle kernel has left for the block's values
   BlockSchedule sf, sb;
   s->cycle_lds = cycle_smem_bytes(s->pol.m);
+  s->spmv_lds_off = 0;
+  if (s->spmv_lanes > 1) {  // one int64 per thread of the largest workgroup (any lanes when measured)
+    s->spmv_lds_off = (s->cycle_lds + 255) / 256 * 256;
+    s->cycle_lds = s->spmv_lds_off + (size_t)1024 * sizeof(int64_t);
+  }
   s->bsf = s->bsb = BlockSweepArgs{};
   s->sweep_lanes = 0;
   s->sweep_lds_off = 0;
@@ -304,8 +339,10 @@ igm_status build(igm_system *s) {
   IGM_TRY(upload(s, s->d_sell_off, h.sell_off));
   IGM_TRY(upload(s, s->d_sell_w, h.sell_w));
   IGM_TRY(upload(s, s->d_sell_col, h.sell_col));
-  for (int l = 0; l < kMaxTerms; ++l) s->d_sell_val[l] = nullptr;
+  for (int l = 0; l < kMaxTerms; ++l) s->d_sell_val[l] = s->d_cval[l] = nullptr;
   for (int l = 0; l < h.nterms; ++l) IGM_TRY(upload(s, s->d_sell_val[l], h.sell_val[l]));
+  if (s->spmv_lanes > 1)  // the same matrices in CSR order, for the lane groups
+    for (int l = 0; l < h.nterms; ++l) IGM_TRY(upload(s, s->d_cval[l], h.abar[l]));
   if (s->pol.precond != IGM_PRE_NONE) {
     IGM_TRY(upload(s, s->d_ldiag, h.ldiag));
     IGM_TRY(upload(s, s->d_udiag, h.udiag));
@@ -335,6 +372,7 @@ igm_status build(igm_system *s) {
     h.blev_ptr.clear();
   }
   IGM_TRY(alloc_work(s));
+  if (tune) IGM_TRY(tune_spmv_lanes(s));
   // norms of the scaled and original right-hand sides (denominators of relres)
   IGM_TRY(device_norm(s, s->d_b, s->n, s->d_scal + kScalNormB));
   IGM_TRY(device_norm(s, s->d_bhat, s->n, s->d_scal + kScalNormBhat));
@@ -363,7 +401,7 @@ igm_status prepare_cycle(igm_system *s) {
 igm_status enqueue_residual(igm_system *s, const double *x, double *dst) {
   IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
   IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
-                          s->d_cscale, s->d_r, s->d_rhat, s->d_red));
+                          s->d_cscale, s->d_r, s->d_rhat, s->d_red, s->spmv_lanes));
   IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_r, s->d_red + kRedMuR, s->d_red + kRedSumR));
   IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_rhat, s->d_red + kRedMuRhat, s->d_red + kRedSumRhat));
   IGM_HIP(launch_fin_residual(s->stream, s->d_red, s->d_scal + kScalNormB, s->d_scal));
@@ -386,6 +424,32 @@ struct EventPair {
     if (e1) (void)hipEventDestroy(e1);
   }
 };
+
+// igm_policy.spmv_lanes = -1: time the standalone SpMV (all terms, a zero
+// vector: the traffic does not depend on the values) with each mapping and keep
+// the fastest. The cycle kernel's SpMV reads the same arrays in the same way.
+igm_status tune_spmv_lanes(igm_system *s) {
+  IGM_HIP(hipMemsetAsync(s->d_V, 0, sizeof(int64_t) * (size_t)s->npad, s->stream));
+  EventPair ev;
+  IGM_HIP(hipEventCreate(&ev.e0));
+  IGM_HIP(hipEventCreate(&ev.e1));
+  float best = 0.0f;
+  int32_t pick = 1;
+  for (int32_t g : {1, 4, 16, 64}) {
+    s->spmv_lanes = g;
+    const CycleArgs a = make_args(s);
+    IGM_HIP(launch_spmv(s->stream, a, s->hs.nterms, s->d_V, s->d_z));
+    IGM_HIP(hipEventRecord(ev.e0, s->stream));
+    for (int r = 0; r < 5; ++r) IGM_HIP(launch_spmv(s->stream, a, s->hs.nterms, s->d_V, s->d_z));
+    IGM_HIP(hipEventRecord(ev.e1, s->stream));
+    IGM_HIP(hipEventSynchronize(ev.e1));
+    float ms = 0.0f;
+    IGM_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    if (g == 1 || ms < best) best = ms, pick = g;
+  }
+  s->spmv_lanes = pick;
+  return IGM_OK;
+}
 
 // Fig. 1 on the device; x is a device vector of n doubles.
 igm_status solve_dev(igm_system *s, double *x) {
@@ -485,6 +549,8 @@ void fill_stats_static(igm_system *s) {
   st.levels_fwd = s->hs.flev_ptr.empty() ? 0 : (int32_t)s->hs.flev_ptr.size() - 1;
   st.levels_bwd = s->hs.blev_ptr.empty() ? 0 : (int32_t)s->hs.blev_ptr.size() - 1;
   st.device_bytes = s->device_bytes;
+  st.spmv_lanes = s->spmv_lanes;
+  st.sweep_rows = s->bsf.S;
 }
 
 }  // namespace
@@ -756,7 +822,7 @@ igm_status igm_residual(igm_system *s, const double *x, double *r, double *rhat)
   if (!s || !x || !r || !rhat) return IGM_ERR_ARG;
   IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
   IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
-                          s->d_cscale, r, rhat, s->d_red));
+                          s->d_cscale, r, rhat, s->d_red, s->spmv_lanes));
   IGM_HIP(hipStreamSynchronize(s->stream));
   return IGM_OK;
 }

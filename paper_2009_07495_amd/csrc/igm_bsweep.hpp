@@ -62,17 +62,6 @@ __device__ __forceinline__ int64_t tdiv_magic(int64_t a, int64_t d, uint64_t m, 
   return neg ? (int64_t)(0ull - q) : (int64_t)q;
 }
 
-// Sum of an int64 over each group of G consecutive lanes (G = 1, 2, 4, 8, 16),
-// returned to every lane of the group; every lane of the wavefront active.
-template <int G>
-__device__ __forceinline__ int64_t group_sum64(int64_t v) {
-  if constexpr (G >= 2) v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
-  if constexpr (G >= 4) v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
-  if constexpr (G >= 8) v += dpp64<0x141>(v);  // row_half_mirror
-  if constexpr (G >= 16) v += dpp64<0x140>(v); // row_mirror
-  return v;
-}
-
 // The first-pass row of one level held in registers by a lane: stage 1
 // (issued two levels ahead: everything addressed by the position alone) and
 // stage 2 (one level ahead: the right-hand side and, when the waits of the
@@ -197,6 +186,7 @@ __device__ __forceinline__ void block_sweep(const BlockSweepArgs &b, const TX *s
       acc.zero();
       double facc = 0.0;
       if (r.act) {
+        // c >= 0: the value is the block's own, in LDS; otherwise xr
         auto term = [&](int32_t c, VT v, TX xr) {
           const TX xv = c >= 0 ? vals[c] : xr;
           if constexpr (FP) {
@@ -210,8 +200,11 @@ __device__ __forceinline__ void block_sweep(const BlockSweepArgs &b, const TX *s
           const int k = gl + j * G;
           if (k < r.len) {
             const int32_t c = r.c[j];
-            const TX xr = (c >= 0 || r.xok) ? r.x[j] : ld_coh(dst + (-(int64_t)c - 1));
-            term(c, r.v[j], xr);
+            TX xv;  // the block's own values from LDS: no wait on the prefetched registers
+            if (c >= 0) xv = vals[c];
+            else if (r.xok) xv = r.x[j];
+            else xv = ld_coh(dst + (-(int64_t)c - 1));
+            term(-1, r.v[j], xv);
           }
         }
         for (int k = gl + PRE * G; k < r.len; k += G) {  // entries beyond the registers, in order

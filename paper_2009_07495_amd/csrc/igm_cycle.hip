@@ -159,9 +159,18 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
     if (PRE != IGM_PRE_ILU0) {
       bool o1 = false, o2 = false;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {  // padded rows: empty slices, unit diagonals
+      for (int k = 0; k < R; ++k) {  // padded rows: empty slices (or rows), unit diagonals
         const int64_t row = gt + k * T;
-        int64_t z = spmv_row(a, row, vj, a.nterms, o1);
+        int64_t z;
+        if (a.spmv_lanes > 1) {  // the workgroup's chunk of rows, several lanes per row, through LDS
+          int64_t *zl = (int64_t *)((char *)smem + a.spmv_lds_off);
+          spmv_chunk_lanes<BLOCK>(a, (int64_t)blockIdx.x * BLOCK + k * T, vj, a.nterms, a.spmv_lanes, zl, o1);
+          __syncthreads();
+          z = zl[tid];
+          __syncthreads();
+        } else {
+          z = spmv_row(a, row, vj, a.nterms, o1);
+        }
         if (PRE == IGM_PRE_JACOBI) z = tdiv_diag(tdiv_diag(z, a.ldiag[row], o2), a.udiag[row], o2);
         w[k] = z;
       }
@@ -178,7 +187,17 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const int64_t row = gt + k * T;
-        st_coh(a.zbuf + row, spmv_row(a, row, vj, a.nterms, o1));
+        int64_t z;
+        if (a.spmv_lanes > 1) {
+          int64_t *zl = (int64_t *)((char *)smem + a.spmv_lds_off);
+          spmv_chunk_lanes<BLOCK>(a, (int64_t)blockIdx.x * BLOCK + k * T, vj, a.nterms, a.spmv_lanes, zl, o1);
+          __syncthreads();
+          z = zl[tid];
+          __syncthreads();
+        } else {
+          z = spmv_row(a, row, vj, a.nterms, o1);
+        }
+        st_coh(a.zbuf + row, z);
       }
       for (int64_t i = gt; i < (int64_t)a.bsf.nb + a.bsb.nb; i += T) st_coh(a.bsf.prog + i * kLevStride, 0u);
       note_event(o1, first, ev_code(j, 1, 0));

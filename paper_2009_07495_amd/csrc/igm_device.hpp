@@ -160,6 +160,19 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
   return readlane64(v, 0) + readlane64(v, 16) + readlane64(v, 32) + readlane64(v, 48);
 }
 
+// Sum of an int64 over each group of G consecutive lanes (G = 1, 2, 4, 8, 16,
+// 64), returned to every lane of the group; every lane of the wavefront active.
+template <int G>
+__device__ __forceinline__ int64_t group_sum64(int64_t v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 64, "lane groups");
+  if constexpr (G == 64) return wave_sum64(v);
+  if constexpr (G >= 2) v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp64<0x141>(v);  // row_half_mirror
+  if constexpr (G >= 16) v += dpp64<0x140>(v); // row_mirror
+  return v;
+}
+
 __device__ __forceinline__ Acc wave_sum(Acc a) {
   a.lo = wave_sum64(a.lo);
   a.hi = wave_sum64(a.hi);

@@ -232,6 +232,14 @@ struct CycleArgs {
   int64_t *wbuf;   // npad (preconditioner path)
   unsigned *lev_cnt;      // ILU: completion counters (igm_sweep.hpp), nflev forward then nblev backward
   int32_t sweep_threads;  // ILU: threads per workgroup taking part in the sweeps (multiple of 64)
+  // integer SpMV with several lanes per row (spmv_lanes 4, 16, 64; 1 = SELL-64):
+  // the integer matrices in CSR order, and the byte offset of the LDS that
+  // passes each chunk's row sums to their owners
+  int32_t spmv_lanes;
+  int32_t spmv_lds_off;
+  const int64_t *crp;
+  const int32_t *ccol;
+  const int64_t *cval[kMaxTerms];
   BlockSweepArgs bsf, bsb;  // ILU: blocked schedules of the forward and backward sweeps (igm_bsweep.hpp)
   int32_t sweep_lanes;      // ILU: lanes per row in the integer sweeps (1, 2, 4, 8 or 16)
   int32_t sweep_lds_off;    // ILU: byte offset of the sweeps' LDS (S values, then the seen cache)
@@ -295,6 +303,10 @@ struct igm_system {
   // progress words, and the cycle kernel's dynamic LDS (cycle part + sweeps)
   igm::BlockSweepArgs bsf{}, bsb{};
   unsigned *d_prog = nullptr;
+  // integer matrices in CSR order (spmv_lanes > 1) and the chosen lanes per row
+  int64_t *d_cval[igm::kMaxTerms] = {nullptr};
+  int32_t spmv_lanes = 1;
+  size_t spmv_lds_off = 0;
   int32_t sweep_lanes = 0;
   size_t cycle_lds = 0, sweep_lds_off = 0;
   // statistics

@@ -56,6 +56,54 @@ __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long
 }
 
 // eq. (b): r = b - A x (scaled) and rhat = bhat - Ahat x (original).
+// eq. (b) with G lanes per row (G = 4, 16, 64): the lanes of a group form the
+// products of G consecutive entries at once, then every lane of the group adds
+// them one after another in entry order, so r and rhat round exactly as the
+// sums in CSR order of residual_row.
+template <int G>
+__global__ __launch_bounds__(kB) void k_residual_lanes(int64_t n, const int64_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col, const double *__restrict__ a,
+                                                       const double *__restrict__ ahat, const double *__restrict__ b,
+                                                       const double *__restrict__ bhat, const double *__restrict__ x,
+                                                       const double *__restrict__ cscale, double *r, double *rhat,
+                                                       unsigned long long *red) {
+  const int gl = (int)(threadIdx.x % G);
+  const int lead = (int)(threadIdx.x & 63) - gl;  // the group's first lane in the wavefront
+  const int64_t i = (int64_t)blockIdx.x * (kB / G) + threadIdx.x / G;
+  unsigned long long m0 = 0, m1 = 0;
+  if (i < n) {
+    const int64_t lo = rp[i], hi = rp[i + 1];
+    double acc = 0.0, acch = 0.0;
+    for (int64_t e0 = lo; e0 < hi; e0 += G) {  // the same trip count in every lane of the group
+      double p = 0.0, ph = 0.0;
+      if (e0 + gl < hi) {
+        const double xv = x[col[e0 + gl]];
+        p = a[e0 + gl] * xv;
+        ph = ahat[e0 + gl] * xv;
+      }
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const double pj = __shfl(p, lead + j, 64), phj = __shfl(ph, lead + j, 64);
+        if (e0 + j < hi) {
+          acc = acc + pj;
+          acch = acch + phj;
+        }
+      }
+    }
+    double ri = b[i] - acc, rhi = bhat[i] - acch;
+    if (cscale) ri = rhi / cscale[i];  // eq. (eq2), as in k_residual
+    if (gl == 0) {
+      r[i] = ri;
+      rhat[i] = rhi;
+      m0 = dbits(fabs(ri));
+      m1 = dbits(fabs(rhi));
+    }
+  }
+  block_max_to(m0, red + kRedMuR);
+  __syncthreads();
+  block_max_to(m1, red + kRedMuRhat);
+}
+
 __global__ __launch_bounds__(kB) void k_residual(int64_t n, const int64_t *__restrict__ rp,
                                                  const int32_t *__restrict__ col, const double *__restrict__ a,
                                                  const double *__restrict__ ahat, const double *__restrict__ b,
@@ -236,6 +284,22 @@ __global__ __launch_bounds__(kB) void k_spmv(CycleArgs a, int nterms, const int6
   note_event(o, &a.state->first_ovf, ev_code(1, 1, 0));
 }
 
+// The standalone SpMV with G lanes per row (igm_rows.hpp): kB / G rows per
+// workgroup pass; every lane runs the same number of passes.
+template <int G>
+__global__ __launch_bounds__(kB) void k_spmv_lanes(CycleArgs a, int nterms, const int64_t *__restrict__ v,
+                                                   int64_t *z) {
+  bool o = false;
+  constexpr int RPW = kB / G;
+  const int gl = (int)(threadIdx.x % G);
+  for (int64_t r0 = (int64_t)blockIdx.x * RPW; r0 < a.n; r0 += (int64_t)gridDim.x * RPW) {
+    const int64_t row = r0 + threadIdx.x / G;
+    const int64_t zr = spmv_row_lanes(a, row, row < a.n, v, nterms, G, o);
+    if (row < a.n && gl == 0) z[row] = zr;
+  }
+  note_event(o, &a.state->first_ovf, ev_code(1, 1, 0));
+}
+
 __global__ __launch_bounds__(kB) void k_diag_solve(CycleArgs a, const int64_t *__restrict__ z, int64_t *w) {
   bool o = false;
   for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
@@ -354,10 +418,21 @@ static inline unsigned grid_stride_blocks(int64_t n) {
 
 hipError_t launch_residual(hipStream_t st, int64_t n, const int64_t *rp, const int32_t *col, const double *a,
                            const double *ahat, const double *b, const double *bhat, const double *x,
-                           const double *cscale, double *r, double *rhat, unsigned long long *red) {
+                           const double *cscale, double *r, double *rhat, unsigned long long *red, int lanes) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x, cscale, r,
-                     rhat, red);
+  const unsigned rows_blocks = (unsigned)((n + kB / std::max(lanes, 1) - 1) / (kB / std::max(lanes, 1)));
+  if (lanes == 4)
+    hipLaunchKernelGGL(k_residual_lanes<4>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
+                       cscale, r, rhat, red);
+  else if (lanes == 16)
+    hipLaunchKernelGGL(k_residual_lanes<16>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
+                       cscale, r, rhat, red);
+  else if (lanes == 64)
+    hipLaunchKernelGGL(k_residual_lanes<64>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
+                       cscale, r, rhat, red);
+  else
+    hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x, cscale,
+                       r, rhat, red);
   return hipGetLastError();
 }
 
@@ -430,7 +505,11 @@ hipError_t launch_start_vector(hipStream_t st, const CycleArgs &a, const double 
 }
 
 hipError_t launch_spmv(hipStream_t st, const CycleArgs &a, int nterms, const int64_t *v, int64_t *z) {
-  hipLaunchKernelGGL(k_spmv, dim3(grid_stride_blocks(a.n)), dim3(kB), 0, st, a, nterms, v, z);
+  const unsigned g = grid_stride_blocks(a.n);
+  if (a.spmv_lanes == 4) hipLaunchKernelGGL(k_spmv_lanes<4>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  else if (a.spmv_lanes == 16) hipLaunchKernelGGL(k_spmv_lanes<16>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  else if (a.spmv_lanes == 64) hipLaunchKernelGGL(k_spmv_lanes<64>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  else hipLaunchKernelGGL(k_spmv, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ enum : int {
 
 hipError_t launch_residual(hipStream_t st, int64_t n, const int64_t *rp, const int32_t *col, const double *a,
                            const double *ahat, const double *b, const double *bhat, const double *x,
-                           const double *cscale, double *r, double *rhat, unsigned long long *red);
+                           const double *cscale, double *r, double *rhat, unsigned long long *red, int lanes);
 hipError_t launch_absmax(hipStream_t st, int64_t n, const double *x, unsigned long long *dst);
 hipError_t launch_dnrm_sum(hipStream_t st, int64_t n, const double *x, const unsigned long long *mu,
                            unsigned long long *limbs);

@@ -79,6 +79,71 @@ __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64
   return tot.value(ovf);
 }
 
+// The same SpMV row by g lanes (g = 4, 16 or 64, the same in every lane:
+// aligned groups of consecutive lanes of one wavefront) over the CSR layout of
+// the integer matrices (crp, ccol, cval): lane l of the group takes entries l,
+// l + g, ...; the exact partial sums are combined over the group, so every
+// lane of the group returns the row's z and sets the overflow flag exactly
+// when spmv_row would. Rows with act == false give 0. Every lane of the
+// wavefront must call it (the combination reads all lanes).
+constexpr int kLaneChunk = 2;
+
+__device__ __forceinline__ int64_t group_sum64_rt(int64_t v, int g) {
+  for (int off = 1; off < g; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <class A>
+__device__ __forceinline__ int64_t spmv_row_lanes(const A &a, int64_t row, bool act, const int64_t *__restrict__ v,
+                                                  int nterms, int g, bool &ovf) {
+  const int gl = (int)(threadIdx.x & (g - 1));
+  const int64_t lo = act ? a.crp[row] : 0, hi = act ? a.crp[row + 1] : 0;
+  Acc tot;
+  tot.zero();
+  for (int l = 0; l < nterms; ++l) {
+    const int64_t *__restrict__ val = a.cval[l];
+    Acc acc;
+    acc.zero();
+    for (int64_t e0 = lo + gl; e0 < hi; e0 += (int64_t)g * kLaneChunk) {
+      int32_t c[kLaneChunk];
+      int64_t vv[kLaneChunk], xv[kLaneChunk];
+#pragma unroll
+      for (int k = 0; k < kLaneChunk; ++k)
+        if (e0 + k * g < hi) {
+          c[k] = a.ccol[e0 + k * g];
+          vv[k] = val[e0 + k * g];
+        }
+#pragma unroll
+      for (int k = 0; k < kLaneChunk; ++k)
+        if (e0 + k * g < hi) xv[k] = v[c[k]];
+#pragma unroll
+      for (int k = 0; k < kLaneChunk; ++k)
+        if (e0 + k * g < hi) acc.add(mulw(vv[k], xv[k], ovf));
+    }
+    acc.lo = group_sum64_rt(acc.lo, g);
+    acc.hi = group_sum64_rt(acc.hi, g);
+    int64_t t = acc.value(ovf);
+    if (l > 0) t = asr(t, a.alpha[l]);
+    tot.add(t);
+  }
+  return tot.value(ovf);
+}
+
+// The SpMV of BLOCK consecutive rows row0 .. row0 + BLOCK - 1 (rows >= a.n
+// give 0) by one workgroup with g lanes per row; row row0 + i's z is left in
+// zl[i] (LDS). Called by every thread of the workgroup.
+template <int BLOCK, class A>
+__device__ __forceinline__ void spmv_chunk_lanes(const A &a, int64_t row0, const int64_t *__restrict__ v, int nterms,
+                                                 int g, int64_t *zl, bool &ovf) {
+  const int sh = __builtin_ctz((unsigned)g);
+  const int rs = (int)(threadIdx.x >> sh), gl = (int)(threadIdx.x & (g - 1));
+  for (int p = 0; p < g; ++p) {
+    const int i = (p << (__builtin_ctz((unsigned)BLOCK) - sh)) + rs;
+    const int64_t z = spmv_row_lanes(a, row0 + i, row0 + i < a.n, v, nterms, g, ovf);
+    if (gl == 0) zl[i] = z;
+  }
+}
+
 // Preconditioner apply (Sec. VI), forward substitution for one row: y_i = tdiv(z_i - sum_{j<i}
 // Lbar_ij y_j, Lbar_ii) (COH: y read with device-coherent loads).
 template <bool COH = false, class A>

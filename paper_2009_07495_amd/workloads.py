@@ -227,6 +227,36 @@ def random_dd(n: int, density: float = 0.1, seed: int = 0, dominance: float = 1.
     return System(f"random_dd_{n}_s{seed}", n, row_ptr, c.astype(np.int32), vals[r, c].astype(np.float64), b)
 
 
+def skewed(n: int, mean_len: float = 8.0, shape: float = 1.5, max_len: int = 4096, seed: int = 6) -> System:
+    """Unstructured nonsymmetric sparse matrix with heavy-tailed row lengths,
+    the kind that one-lane-per-row layouts pad badly: each row holds its
+    diagonal and about k off-diagonal entries, k drawn from a Pareto law of the
+    given shape with mean mean_len - 1, capped at min(max_len, n - 1);
+    off-diagonal columns uniform over the other rows (repeats merged),
+    off-diagonal values N(0, 1), diagonal 1.1 times the row's absolute sum (1
+    for a row without off-diagonal entries)."""
+    rng = np.random.default_rng(seed)
+    cap = max(0, min(max_len, n - 1))
+    scale = (mean_len - 1.0) * (shape - 1.0) / shape  # Pareto minimum giving that mean
+    k = np.minimum(np.floor(scale * (1.0 + rng.pareto(shape, size=n))), cap).astype(np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), k)
+    u = rng.integers(0, max(n - 1, 1), size=len(rows), dtype=np.int64)
+    cols = u + (u >= rows)  # skip the diagonal
+    key = np.unique(rows * n + cols)
+    rows, cols = key // n, key % n
+    off = rng.standard_normal(len(rows))
+    absum = np.bincount(rows, weights=np.abs(off), minlength=n)
+    diag = np.where(absum > 0, 1.1 * absum, 1.0)
+    r_all = np.concatenate([rows, np.arange(n, dtype=np.int64)])
+    c_all = np.concatenate([cols, np.arange(n, dtype=np.int64)])
+    v_all = np.concatenate([off, diag])
+    order = np.lexsort((c_all, r_all))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r_all, minlength=n), out=row_ptr[1:])
+    b = rng.uniform(-1.0, 1.0, size=n)
+    return System(f"skewed_{n}_m{mean_len:g}_s{seed}", n, row_ptr, c_all[order].astype(np.int32), v_all[order], b)
+
+
 def served_requests(count: int = 20000, seed: int = 5, n_lo: int = 4096, n_hi: int = 1 << 20):
     """Request stream for the served solver, one (system, preset) at a time:
     sizes log-uniform on [n_lo, n_hi], family uniform over 2D 5-point

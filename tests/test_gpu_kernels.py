@@ -21,7 +21,12 @@ SYSTEMS = [
     # Jacobi with diagonals that are not the row maximum and of both signs:
     # cast diagonals that are not powers of two (general division path)
     ("dd_weakdiag_jacobi", lambda: W.random_dd(257, 0.05, 7, dominance=0.1, nonneg_diag=False), "jacobi", {}),
+    # heavy-tailed row lengths (rows up to 548 entries), two terms
+    ("skewed_4099_multiterm", lambda: W.skewed(4099, seed=11), "jacobi", dict(s_terms=1)),
 ]
+# lanes per row of the SpMV and the residual: SELL-64, then 4, 16 and 64 lanes
+# per row over CSR (every mapping must give the same bits)
+LANES = [1, 4, 16, 64]
 
 
 @pytest.fixture(scope="module")
@@ -36,18 +41,20 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def pair(orc, name):
+def pair(orc, name, **lib_kw):
     for nm, gen, preset, kw in SYSTEMS:
         if nm == name:
             s = gen()
             return s, orc.OracleSystem.from_system(s, orc.policy(preset, **kw)), B.System.from_system(
-                s, preset, **kw)
+                s, preset, **kw, **lib_kw)
     raise KeyError(name)
 
 
 @pytest.mark.parametrize("name", [s[0] for s in SYSTEMS])
-def test_spmv_bit_exact(orc, torch, name):
-    s, o, g = pair(orc, name)
+@pytest.mark.parametrize("lanes", LANES)
+def test_spmv_bit_exact(orc, torch, name, lanes):
+    s, o, g = pair(orc, name, spmv_lanes=lanes)
+    assert g.stats()["spmv_lanes"] == lanes
     rng = np.random.default_rng(1)
     for trial in range(3):
         v = rng.integers(-(1 << 30), 1 << 30, s.n)
@@ -131,8 +138,9 @@ def test_reduction_overflow_flags(orc, torch):
 
 
 @pytest.mark.parametrize("name", [s[0] for s in SYSTEMS])
-def test_residual_and_start_vector_bit_exact(orc, torch, name):
-    s, o, g = pair(orc, name)
+@pytest.mark.parametrize("lanes", LANES)
+def test_residual_and_start_vector_bit_exact(orc, torch, name, lanes):
+    s, o, g = pair(orc, name, spmv_lanes=lanes)
     rng = np.random.default_rng(4)
     for x in (np.zeros(s.n), rng.standard_normal(s.n)):
         r_o, rh_o = o.residual(x)

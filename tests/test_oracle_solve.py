@@ -60,6 +60,29 @@ def test_ilu_and_jacobi_workload_shapes_converge(orc):
         assert st["refinements"] <= np.ceil(it64 / m) * 1.25 + 1
 
 
+def test_skewed_generator_shape_and_solve(orc):
+    """The heavy-tailed family: CSR well formed (sorted distinct columns, one
+    diagonal per row), strictly diagonally dominant, row lengths heavy-tailed
+    (median well below the mean's tail, longest row tens of times the mean),
+    the same matrix for the same seed; the oracle solves it to 1e-10."""
+    s = W.skewed(4099, seed=11)
+    rp, col, val = s.row_ptr, s.col, s.val
+    lens = np.diff(rp)
+    assert rp[0] == 0 and rp[-1] == len(col) == len(val) and np.all(lens >= 1)
+    rows = np.repeat(np.arange(s.n), lens)
+    assert np.all((np.diff(col) > 0) | (np.diff(rows) > 0))  # sorted, distinct within a row
+    diag = col == rows
+    assert np.array_equal(np.bincount(rows[diag], minlength=s.n), np.ones(s.n))
+    offsum = np.bincount(rows[~diag], weights=np.abs(val[~diag]), minlength=s.n)
+    assert np.all(val[diag] > offsum)
+    assert lens.max() > 30 * lens.mean() and np.median(lens) < lens.mean()
+    t = W.skewed(4099, seed=11)
+    assert np.array_equal(t.col, col) and np.array_equal(t.val, val) and np.array_equal(t.b, s.b)
+    o = make(orc, s, "jacobi", m=20)
+    x, st = o.solve()
+    assert st["status"] == orc.OK and true_relres(s, x) < 1e-10
+
+
 def test_multiterm_matrix_solve(orc):
     """s = 2 correction matrices (eq. (AA)) with a coarse alpha_a still solves."""
     s = W.convdiff3d(6, seed=9)
