@@ -15,6 +15,7 @@ SpMV and inner-product kernels and a device copy (measured bandwidth peak).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import re
@@ -494,7 +495,8 @@ def served(B, W, count: int, distinct: int, rate: float = 2000.0, plain_sample: 
 def kernel_rates(torch, B, W) -> dict:
     """Standalone SpMV and Gram-Schmidt inner-product kernels (Fig. 2), timed
     with HIP events around the kernels: the SpMV with each row-to-lane mapping
-    (one thread per row over SELL-64; 4, 16, 64 lanes per row over CSR) on the
+    (1: one thread per row over SELL-64; 2: each workgroup's rows split evenly
+    by entries; 4, 16, 64 lanes per row over CSR) on the
     27-point 1M-row matrix, the 7-point 64^3 matrix and a heavy-tailed 1M-row
     matrix, with the mapping the automatic rule and the setup-time measurement
     pick; the inner product on the 27-point matrix's vector length."""
@@ -519,10 +521,17 @@ def kernel_rates(torch, B, W) -> dict:
         v = torch.from_numpy(rng.integers(-(1 << 30), 1 << 30, n)).cuda()
         z = torch.zeros(n, dtype=torch.int64, device="cuda")
         row = {"n": n, "nnz": nnz, "bytes": byts, "lanes": {}}
-        for lanes in (1, 4, 16, 64):
-            g = B.System.from_system(sysm, "jacobi", m=2, spmv_lanes=lanes)
+        for lanes in (1, 2, 4, 16, 64):
+            g = B.System.from_system(sysm, "jacobi", spmv_lanes=lanes)
             ms = med_ms(g, lambda: g.spmv(v, z))
             row["lanes"][str(lanes)] = {"ms": ms, "gb_s": byts / ms / 1e6, "frac": byts / ms / 1e6 / HBM_PEAK_GBS}
+            # a whole Jacobi-preconditioned GMRES(30) solve with this mapping in the
+            # cycle kernel and the residual (the second of two; same bits for all)
+            for _ in range(2):
+                x, st = g.solve()
+            gs = g.stats()
+            row["lanes"][str(lanes)].update(solve_ms=gs["time_solve_ms"], refinements=gs["refinements"],
+                                            relres=gs["relres_orig"], x_sha256=hashlib.sha256(x.tobytes()).hexdigest())
             if wl == "random27_1m" and lanes == 1:
                 res["spmv"] = dict(row["lanes"]["1"], bytes=byts, workload=f"random27 n={n} nnz={nnz}")
                 dms = med_ms(g, lambda: g.dot(v, v))  # Q30 words: no product overflows
@@ -535,6 +544,7 @@ def kernel_rates(torch, B, W) -> dict:
             g.close()
         best = min(row["lanes"], key=lambda k: row["lanes"][k]["ms"])
         row["fastest"] = int(best)
+        row["same_x_every_mapping"] = len({r["x_sha256"] for r in row["lanes"].values()}) == 1
         res["spmv_mappings"][wl] = row
         progress(f"spmv mappings {wl}: " + ", ".join(f"{k}: {r['gb_s']:.0f} GB/s" for k, r in row["lanes"].items())
             + f"; auto {row['auto']}, measured {row['measured']}")

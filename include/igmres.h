@@ -60,6 +60,10 @@ enum { IGM_PRE_NONE = 0, IGM_PRE_JACOBI = 1, IGM_PRE_ILU0 = 2 };
  * Table VI) and a diagonal-only variant of the ILU construction. */
 enum { IGM_PRESET_PAPER_NOPREC = 0, IGM_PRESET_PAPER_ILU = 1, IGM_PRESET_JACOBI = 2 };
 
+/* Row-to-lane mappings of the integer SpMV (igm_policy.spmv_lanes); 4, 16 and
+ * 64 (lanes per row) are mappings too. */
+enum { IGM_SPMV_MEASURE = -1, IGM_SPMV_AUTO = 0, IGM_SPMV_SELL = 1, IGM_SPMV_MERGE = 2 };
+
 /* Overflow event code (igm_stats.first_ovf, igm_cycle_trace.first_ovf):
  *   (step j << 24) | (stage << 16) | sub
  * stages follow the steps of Fig. 2 and Sec. VI: 1 = integer SpMV w = A v_j,
@@ -136,14 +140,19 @@ typedef struct {
    * the first refinement and one more term in each later one. */
   int32_t s_rule;
   /* Launch tuning of the single-system solver's integer SpMV and FP64
-   * residual (the bits do not depend on it): lanes per row. 1 = one thread per
-   * row over the SELL-64 layout (rows of similar length); 4, 16 or 64 = that
-   * many lanes of a wavefront per row over the CSR layout (rows of very
-   * different or large lengths; 64 = a wavefront per row); 0 = automatic from
-   * the row lengths: 1 unless SELL-64 would more than double the entries
-   * loaded, then 16; -1 = measured: at setup each of 1, 4, 16, 64 runs the standalone
-   * SpMV a few times and the fastest is kept. With 4, 16, 64 or -1 the system
-   * also holds the integer matrices in CSR order (8 bytes per entry and term). */
+   * residual (the bits do not depend on it), IGM_SPMV_* or lanes per row:
+   * IGM_SPMV_SELL (1) = one thread per row over the SELL-64 layout (rows of
+   * similar length); 4, 16 or 64 = that many lanes of a wavefront per row over
+   * the CSR layout (64 = a wavefront per row); IGM_SPMV_MERGE (2) = each
+   * workgroup's chunk of rows split evenly by entries over its threads, rows
+   * cut anywhere (heavy-tailed row lengths; chunks of 1024 rows must hold
+   * fewer than 2^30 entries); IGM_SPMV_AUTO (0) = from the row lengths: SELL
+   * unless SELL-64 would more than double the entries loaded, then MERGE;
+   * IGM_SPMV_MEASURE (-1) = at setup each mapping runs the standalone SpMV a
+   * few times and the fastest is kept. The FP64 residual runs one thread per
+   * row with SELL, 16 lanes per row with MERGE, else the SpMV's lanes. Every
+   * mapping but SELL also keeps the integer matrices in CSR order (8 bytes per
+   * entry and term). */
   int32_t spmv_lanes;
   int32_t reserved_[3];
 } igm_policy;

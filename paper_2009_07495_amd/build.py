@@ -7,8 +7,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libigmres.so")
-SOURCES = ["igm_setup.cpp", "igm_bsched.cpp", "igm_api.cpp", "igm_batch.cpp", "igm_serve.cpp", "igm_kernels.hip", "igm_cycle.hip",
-           "igm_batch.hip"]
+# the cycle kernels first: they take longest to compile
+SOURCES = ["igm_cycle.hip", "igm_cycle_lanes.hip", "igm_cycle_merge.hip", "igm_batch.hip", "igm_kernels.hip",
+           "igm_api.cpp", "igm_setup.cpp", "igm_bsched.cpp", "igm_batch.cpp", "igm_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -182,8 +182,16 @@ igm_status choose_launch(igm_system *s) {
   static const int kShapesIlu[][2] = {{512, 1}, {512, 2}, {512, 4}, {512, 8}, {512, 16}};
   for (const auto &bs : s->pol.precond == IGM_PRE_ILU0 ? kShapesIlu : kShapes) {
     const int B = bs[0], R = bs[1];
-    int nb = 0;
-    IGM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cycle_kernel(B, R, s->pol.precond), B, smem));
+    // co-resident workgroups of the kernel that will run (every mapping's
+    // kernel when the mapping is measured after this choice)
+    int nb = INT32_MAX;
+    const bool tune = s->pol.spmv_lanes < 0;
+    for (int32_t map : {1, 2, 4}) {
+      if (tune ? (map == IGM_SPMV_MERGE && !s->spmv_merge_ok) : map != std::min(s->spmv_lanes, 4)) continue;
+      int k = 0;
+      IGM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, cycle_kernel(B, R, s->pol.precond, map), B, smem));
+      nb = std::min(nb, k);
+    }
     const int64_t cap = std::min<int64_t>((int64_t)nb * prop.multiProcessorCount, target);
     const int64_t G = (s->n + (int64_t)B * R - 1) / ((int64_t)B * R);
     if (nb > 0 && G <= cap) {
@@ -265,7 +273,15 @@ int32_t auto_spmv_lanes(int64_t n, const int64_t *row_ptr) {
     for (int64_t i = q; i < e; ++i) w = std::max<int64_t>(w, row_ptr[i + 1] - row_ptr[i]);
     padded += w * kSlice;
   }
-  return 2 * nnz >= padded ? 1 : 16;
+  return 2 * nnz >= padded ? IGM_SPMV_SELL : IGM_SPMV_MERGE;
+}
+
+// Largest entry count of an aligned window of 1024 rows (every chunk of the
+// merge mapping lies inside one).
+int64_t max_chunk_entries(int64_t n, const int64_t *row_ptr) {
+  int64_t m = 0;
+  for (int64_t q = 0; q < n; q += 1024) m = std::max(m, row_ptr[std::min<int64_t>(n, q + 1024)] - row_ptr[q]);
+  return m;
 }
 
 igm_status tune_spmv_lanes(igm_system *s);
@@ -276,15 +292,21 @@ igm_status build(igm_system *s) {
   IGM_TRY(host_setup(s->n, s->row_ptr, s->col, s->ahat, s->bhat, s->pol, s->hs));
   HostSetup &h = s->hs;
   const bool tune = s->pol.spmv_lanes < 0;
+  const bool merge_ok = max_chunk_entries(s->n, s->row_ptr.data()) < ((int64_t)1 << 30);
   s->spmv_lanes = s->pol.spmv_lanes > 0 ? s->pol.spmv_lanes : tune ? 4 : auto_spmv_lanes(s->n, s->row_ptr.data());
+  if (s->spmv_lanes == IGM_SPMV_MERGE && !merge_ok) {
+    if (s->pol.spmv_lanes == IGM_SPMV_MERGE) return IGM_ERR_UNSUPPORTED;
+    s->spmv_lanes = 16;
+  }
+  s->spmv_merge_ok = merge_ok;
   // ILU(0): the blocked schedules of the two sweeps, sized by the LDS a
   // workgroup of the cycle kernel has left for the block's values
   BlockSchedule sf, sb;
   s->cycle_lds = cycle_smem_bytes(s->pol.m);
   s->spmv_lds_off = 0;
-  if (s->spmv_lanes > 1) {  // one int64 per thread of the largest workgroup (any lanes when measured)
+  if (s->spmv_lanes > 1) {  // sized for the largest workgroup and any mapping (measured: all are tried)
     s->spmv_lds_off = (s->cycle_lds + 255) / 256 * 256;
-    s->cycle_lds = s->spmv_lds_off + (size_t)1024 * sizeof(int64_t);
+    s->cycle_lds = s->spmv_lds_off + std::max<size_t>((size_t)1024 * sizeof(int64_t), merge_lds_bytes(1024));
   }
   s->bsf = s->bsb = BlockSweepArgs{};
   s->sweep_lanes = 0;
@@ -381,7 +403,7 @@ igm_status build(igm_system *s) {
 }
 
 igm_status launch_cycle(igm_system *s, const CycleArgs &a) {
-  const void *k = cycle_kernel(s->block, s->rows_per_thread, s->pol.precond);
+  const void *k = cycle_kernel(s->block, s->rows_per_thread, s->pol.precond, s->spmv_lanes);
   void *args[] = {(void *)&a};
   IGM_HIP(hipLaunchCooperativeKernel(k, dim3(s->grid), dim3(s->block), args, s->cycle_lds, s->stream));
   return IGM_OK;
@@ -435,7 +457,8 @@ igm_status tune_spmv_lanes(igm_system *s) {
   IGM_HIP(hipEventCreate(&ev.e1));
   float best = 0.0f;
   int32_t pick = 1;
-  for (int32_t g : {1, 4, 16, 64}) {
+  for (int32_t g : {1, 2, 4, 16, 64}) {
+    if (g == IGM_SPMV_MERGE && !s->spmv_merge_ok) continue;
     s->spmv_lanes = g;
     const CycleArgs a = make_args(s);
     IGM_HIP(launch_spmv(s->stream, a, s->hs.nterms, s->d_V, s->d_z));

@@ -40,6 +40,10 @@ template <class T>
 using hvec = std::vector<T, NoInitAlloc<T>>;
 
 constexpr int kMaxTerms = 9;       // A_0 .. A_8
+// LDS of the merge-based chunk SpMV of a workgroup of `block` threads: int32
+// row offsets (block + 1, padded to 16 bytes), then two int64 limb sums per row.
+constexpr size_t merge_rp_bytes(int block) { return ((size_t)(block + 1) * 4 + 15) / 16 * 16; }
+constexpr size_t merge_lds_bytes(int block) { return merge_rp_bytes(block) + (size_t)block * 16; }
 constexpr int kSlice = 64;         // SELL slice height = wavefront width
 constexpr int kSyncGroups = 8;     // arrival words per grid reduction (K)
 constexpr int kMaxRows = 16;       // largest rows-per-thread instantiation
@@ -254,7 +258,10 @@ struct CycleArgs {
   const double *cscale;      // eq. (eq2): the update adds gamma (x^(k)_i / s_i); null for eq. (eq1)
 };
 
-const void *cycle_kernel(int block, int R, int pre);
+// SpMV mappings of the cycle kernel: one thread per row over SELL-64, lanes
+// per row over CSR, chunks split evenly by entries over the workgroup.
+constexpr int kMapSell = 0, kMapLanes = 1, kMapMerge = 2;
+const void *cycle_kernel(int block, int R, int pre, int spmv_lanes);
 size_t cycle_smem_bytes(int m);
 
 }  // namespace igm
@@ -306,6 +313,7 @@ struct igm_system {
   // integer matrices in CSR order (spmv_lanes > 1) and the chosen lanes per row
   int64_t *d_cval[igm::kMaxTerms] = {nullptr};
   int32_t spmv_lanes = 1;
+  bool spmv_merge_ok = true;  // every 1024-row window holds fewer than 2^30 entries
   size_t spmv_lds_off = 0;
   int32_t sweep_lanes = 0;
   size_t cycle_lds = 0, sweep_lds_off = 0;

@@ -300,6 +300,19 @@ __global__ __launch_bounds__(kB) void k_spmv_lanes(CycleArgs a, int nterms, cons
   note_event(o, &a.state->first_ovf, ev_code(1, 1, 0));
 }
 
+// The standalone SpMV with each chunk of kB rows split evenly by entries over
+// the workgroup (spmv_chunk_merge); the loop over chunks is uniform.
+__global__ __launch_bounds__(kB) void k_spmv_merge(CycleArgs a, int nterms, const int64_t *__restrict__ v,
+                                                   int64_t *z) {
+  __shared__ __align__(16) char lds[merge_lds_bytes(kB)];
+  bool o = false;
+  for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < a.n; r0 += (int64_t)gridDim.x * kB) {
+    const int64_t zr = spmv_chunk_merge<kB>(a, r0, v, nterms, lds, o);
+    if (r0 + threadIdx.x < a.n) z[r0 + threadIdx.x] = zr;
+  }
+  note_event(o, &a.state->first_ovf, ev_code(1, 1, 0));
+}
+
 __global__ __launch_bounds__(kB) void k_diag_solve(CycleArgs a, const int64_t *__restrict__ z, int64_t *w) {
   bool o = false;
   for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
@@ -420,6 +433,7 @@ hipError_t launch_residual(hipStream_t st, int64_t n, const int64_t *rp, const i
                            const double *ahat, const double *b, const double *bhat, const double *x,
                            const double *cscale, double *r, double *rhat, unsigned long long *red, int lanes) {
   if (n <= 0) return hipSuccess;
+  if (lanes == IGM_SPMV_MERGE) lanes = 16;  // FP64 sums keep their order: lanes per row
   const unsigned rows_blocks = (unsigned)((n + kB / std::max(lanes, 1) - 1) / (kB / std::max(lanes, 1)));
   if (lanes == 4)
     hipLaunchKernelGGL(k_residual_lanes<4>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
@@ -506,7 +520,8 @@ hipError_t launch_start_vector(hipStream_t st, const CycleArgs &a, const double 
 
 hipError_t launch_spmv(hipStream_t st, const CycleArgs &a, int nterms, const int64_t *v, int64_t *z) {
   const unsigned g = grid_stride_blocks(a.n);
-  if (a.spmv_lanes == 4) hipLaunchKernelGGL(k_spmv_lanes<4>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  if (a.spmv_lanes == IGM_SPMV_MERGE) hipLaunchKernelGGL(k_spmv_merge, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  else if (a.spmv_lanes == 4) hipLaunchKernelGGL(k_spmv_lanes<4>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else if (a.spmv_lanes == 16) hipLaunchKernelGGL(k_spmv_lanes<16>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else if (a.spmv_lanes == 64) hipLaunchKernelGGL(k_spmv_lanes<64>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else hipLaunchKernelGGL(k_spmv, dim3(g), dim3(kB), 0, st, a, nterms, v, z);

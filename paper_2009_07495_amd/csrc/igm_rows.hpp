@@ -144,6 +144,111 @@ __device__ __forceinline__ void spmv_chunk_lanes(const A &a, int64_t row0, const
   }
 }
 
+// The SpMV of BLOCK consecutive rows row0 .. row0 + BLOCK - 1 (rows >= a.n
+// give 0) by one workgroup, its entries split evenly over the threads whatever
+// the row lengths: the merge-based partition of Merrill and Garland (SC16). The
+// chunk's BLOCK row ends and E entries form one merged sequence of BLOCK + E
+// items; thread t takes items [t p, (t + 1) p), p = ceil((BLOCK + E) / BLOCK),
+// so it walks a contiguous run of entries and crosses at most p row ends. The
+// exact partial sums of one row from different threads meet in LDS through
+// 64-bit atomic adds of the two limbs: integer addition is exact, so the row's
+// term sum, the overflow flag and z equal spmv_row's whatever the split.
+// Returns row row0 + threadIdx.x's z. LDS: merge_lds_bytes(BLOCK) at lds.
+// Called by every thread of the workgroup; chunk entries below 2^31.
+constexpr int kMergeBatch = 4;
+
+template <int BLOCK, class A>
+__device__ __forceinline__ int64_t spmv_chunk_merge(const A &a, int64_t row0, const int64_t *__restrict__ v,
+                                                    int nterms, char *lds, bool &ovf) {
+  int32_t *rp = (int32_t *)lds;  // rp[i]: first entry of row i relative to the chunk; rp[BLOCK] = E
+  unsigned long long *slo = (unsigned long long *)(lds + merge_rp_bytes(BLOCK));
+  unsigned long long *shi = slo + BLOCK;
+  const int t = (int)threadIdx.x;
+  const int64_t left = a.n - row0;
+  const int nrows = left <= 0 ? 0 : left >= BLOCK ? BLOCK : (int)left;
+  const int64_t base = nrows > 0 ? a.crp[row0] : 0;
+  const int E = nrows > 0 ? (int)(a.crp[row0 + nrows] - base) : 0;
+  if (t == 0) rp[0] = 0;
+  rp[t + 1] = t < nrows ? (int32_t)(a.crp[row0 + t + 1] - base) : E;  // padded rows: empty
+  __syncthreads();
+  // thread t's first item: i row ends and j entries before it (merge-path
+  // search: row end i precedes entry j exactly when rp[i + 1] <= j)
+  const int total = BLOCK + E;
+  const int per = (total + BLOCK - 1) / BLOCK;
+  const int d0 = min(t * per, total), d1 = min(d0 + per, total);
+  int lo = max(0, d0 - E), hi = min(d0, BLOCK);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (rp[mid + 1] <= d0 - mid - 1) lo = mid + 1;
+    else hi = mid;
+  }
+  const int i0 = lo, j0 = d0 - lo;
+  const int32_t *__restrict__ col = a.ccol + base;
+  Acc tot;
+  tot.zero();
+  for (int l = 0; l < nterms; ++l) {
+    const int64_t *__restrict__ val = a.cval[l] + base;
+    slo[t] = 0;
+    shi[t] = 0;
+    __syncthreads();
+    int i = i0, j = j0;
+    Acc acc;
+    acc.zero();
+    for (int d = d0; d < d1;) {
+      // the next batch of this thread's entries (loads issued together), then
+      // the merged walk over them and the row ends between them
+      int32_t c[kMergeBatch];
+      int64_t vv[kMergeBatch], xv[kMergeBatch];
+#pragma unroll
+      for (int u = 0; u < kMergeBatch; ++u)
+        if (j + u < E) {
+          c[u] = col[j + u];
+          vv[u] = val[j + u];
+        }
+#pragma unroll
+      for (int u = 0; u < kMergeBatch; ++u)
+        if (j + u < E) xv[u] = v[c[u]];
+      // products of the entries this batch may consume (an entry whose product
+      // is formed but which another thread consumes is in the same chunk, so
+      // the overflow flag of the SpMV is unchanged)
+      int64_t pr[kMergeBatch];
+#pragma unroll
+      for (int u = 0; u < kMergeBatch; ++u) pr[u] = (j + u < E && d + u < d1) ? mulw(vv[u], xv[u], ovf) : 0;
+      int u = 0;
+      while (d < d1 && u < kMergeBatch) {
+        if (i < BLOCK && rp[i + 1] <= j) {  // row i ends here
+          atomicAdd(slo + i, (unsigned long long)acc.lo);
+          atomicAdd(shi + i, (unsigned long long)acc.hi);
+          acc.zero();
+          ++i;
+        } else {
+          int64_t pu = pr[0];
+#pragma unroll
+          for (int q = 1; q < kMergeBatch; ++q)
+            if (q == u) pu = pr[q];
+          acc.add(pu);
+          ++j;
+          ++u;
+        }
+        ++d;
+      }
+    }
+    if (i < BLOCK) {  // the row this thread's items end inside
+      atomicAdd(slo + i, (unsigned long long)acc.lo);
+      atomicAdd(shi + i, (unsigned long long)acc.hi);
+    }
+    __syncthreads();
+    Acc rs;
+    rs.lo = (int64_t)slo[t];
+    rs.hi = (int64_t)shi[t];
+    int64_t tl = rs.value(ovf);
+    if (l > 0) tl = asr(tl, a.alpha[l]);
+    tot.add(tl);
+    __syncthreads();
+  }
+  return tot.value(ovf);
+}
+
 // Preconditioner apply (Sec. VI), forward substitution for one row: y_i = tdiv(z_i - sum_{j<i}
 // Lbar_ij y_j, Lbar_ii) (COH: y read with device-coherent loads).
 template <bool COH = false, class A>

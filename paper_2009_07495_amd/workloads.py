@@ -257,6 +257,34 @@ def skewed(n: int, mean_len: float = 8.0, shape: float = 1.5, max_len: int = 409
     return System(f"skewed_{n}_m{mean_len:g}_s{seed}", n, row_ptr, c_all[order].astype(np.int32), v_all[order], b)
 
 
+def arrow(n: int, seed: int = 7) -> System:
+    """Row 0 dense (every column), every other row its diagonal, column 0 and
+    its two neighbours: one row as long as the matrix beside rows of 4 or
+    fewer entries. Off-diagonal values N(0, 1), diagonal 1.1 times the row's
+    absolute sum."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [np.zeros(n, dtype=np.int64)], [np.arange(n, dtype=np.int64)]
+    for d in (0, -1, 1):  # column 0 (d = 0 marks it), left and right neighbours
+        r = np.arange(1, n, dtype=np.int64)
+        c = np.zeros_like(r) if d == 0 else r + d
+        keep = (c >= 0) & (c < n) & (c != r) & ~((d == -1) & (c == 0))
+        rows.append(r[keep])
+        cols.append(c[keep])
+    r_all, c_all = np.concatenate(rows), np.concatenate(cols)
+    r_all = np.concatenate([r_all, np.arange(1, n, dtype=np.int64)])  # diagonals of rows 1..n-1
+    c_all = np.concatenate([c_all, np.arange(1, n, dtype=np.int64)])
+    order = np.lexsort((c_all, r_all))
+    r_all, c_all = r_all[order], c_all[order]
+    v = rng.standard_normal(len(r_all))
+    diag = r_all == c_all
+    absum = np.bincount(r_all[~diag], weights=np.abs(v[~diag]), minlength=n)
+    v[diag] = 1.1 * absum[r_all[diag]] + 1.0
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r_all, minlength=n), out=row_ptr[1:])
+    b = rng.uniform(-1.0, 1.0, size=n)
+    return System(f"arrow_{n}_s{seed}", n, row_ptr, c_all.astype(np.int32), v, b)
+
+
 def served_requests(count: int = 20000, seed: int = 5, n_lo: int = 4096, n_hi: int = 1 << 20):
     """Request stream for the served solver, one (system, preset) at a time:
     sizes log-uniform on [n_lo, n_hi], family uniform over 2D 5-point

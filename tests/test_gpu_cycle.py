@@ -394,17 +394,20 @@ SPMV_LANE_CASES = [
     ("skewed_2500_multiterm", lambda: W.skewed(2500, mean_len=30.0, seed=13), "jacobi",
      dict(m=15, alpha_a=24, s_terms=2)),
     ("r27_9x8x6", lambda: W.random27(9, 8, 6, seed=8), "paper_ilu", dict(m=20)),
+    ("arrow_3000", lambda: W.arrow(3000), "jacobi", dict(m=20)),
+    ("arrow_2100_ilu", lambda: W.arrow(2100, seed=9), "paper_ilu", dict(m=12)),
 ]
 
 
 @pytest.mark.parametrize("name,gen,preset,kw", SPMV_LANE_CASES)
-@pytest.mark.parametrize("lanes", [1, 4, 16, 64, -1])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 16, 64, -1])
 def test_spmv_lane_mappings_bit_exact(orc, torch, name, gen, preset, kw, lanes):
     """The integer SpMV inside the cycle kernel with one thread per row over
-    SELL-64 or 4, 16, 64 lanes per row over CSR (-1: the mapping measured at
-    setup), and the FP64 residual of the refinement loop with the same
-    mapping: the cycle trace (whole basis) and a whole solve equal the
-    oracle's bit for bit, with the library's own and with 3 workgroups."""
+    SELL-64 (1), each workgroup's rows split evenly by entries (2), or 4, 16,
+    64 lanes per row over CSR (-1: the mapping measured at setup), and the
+    FP64 residual of the refinement loop with its mapping: the cycle trace
+    (whole basis) and a whole solve equal the oracle's bit for bit, with the
+    library's own and with 3 workgroups."""
     s = gen()
     o = orc.OracleSystem.from_system(s, orc.policy(preset, **kw))
     v1 = first_v1(o, s.n)
@@ -413,7 +416,7 @@ def test_spmv_lane_mappings_bit_exact(orc, torch, name, gen, preset, kw, lanes):
     for grid in (0, 3):
         g = B.System.from_system(s, preset, grid_blocks=grid, spmv_lanes=lanes, **kw)
         got = g.stats()["spmv_lanes"]
-        assert got == lanes if lanes > 0 else got in (1, 4, 16, 64)
+        assert got == lanes if lanes > 0 else got in (1, 2, 4, 16, 64)
         assert_trace_equal(g.int_cycle(v1), to, s.n)
         x, st = g.solve()
         assert st == so["status"] and np.array_equal(x, xo), (name, lanes, grid)
@@ -422,10 +425,11 @@ def test_spmv_lane_mappings_bit_exact(orc, torch, name, gen, preset, kw, lanes):
 
 def test_automatic_spmv_lanes_follow_the_row_lengths(torch):
     """The automatic mapping: one thread per row for stencils (SELL-64 pads
-    little), 16 lanes per row for heavy-tailed row lengths (SELL-64 would load
-    more than twice the entries)."""
+    little), the even split by entries for heavy-tailed row lengths (SELL-64
+    would load more than twice the entries)."""
     for gen, want in ((lambda: W.poisson2d(40, 30), 1), (lambda: W.random27(9, 8, 6, seed=8), 1),
-                      (lambda: W.skewed(3001, seed=12), 16), (lambda: W.skewed(2500, mean_len=30.0, seed=13), 16)):
+                      (lambda: W.skewed(3001, seed=12), 2), (lambda: W.skewed(2500, mean_len=30.0, seed=13), 2),
+                      (lambda: W.arrow(3000), 2)):
         g = B.System.from_system(gen(), "jacobi")
         assert g.stats()["spmv_lanes"] == want
         g.close()

@@ -23,10 +23,13 @@ SYSTEMS = [
     ("dd_weakdiag_jacobi", lambda: W.random_dd(257, 0.05, 7, dominance=0.1, nonneg_diag=False), "jacobi", {}),
     # heavy-tailed row lengths (rows up to 548 entries), two terms
     ("skewed_4099_multiterm", lambda: W.skewed(4099, seed=11), "jacobi", dict(s_terms=1)),
+    # one row as long as the matrix (every column) beside rows of 4 entries
+    ("arrow_3000", lambda: W.arrow(3000), "jacobi", {}),
 ]
-# lanes per row of the SpMV and the residual: SELL-64, then 4, 16 and 64 lanes
-# per row over CSR (every mapping must give the same bits)
-LANES = [1, 4, 16, 64]
+# row-to-lane mappings of the SpMV and the residual: SELL-64 (1), chunks split
+# evenly by entries (2), then 4, 16 and 64 lanes per row over CSR (every
+# mapping must give the same bits)
+LANES = [1, 2, 4, 16, 64]
 
 
 @pytest.fixture(scope="module")
