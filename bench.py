@@ -31,7 +31,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 # Sources the persistent cycle kernel is compiled from: a traffic figure
 # measured with hardware counters is reported only while they are unchanged.
-CYCLE_SOURCES = ("igm_cycle.hip", "igm_sweep.hpp", "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp")
+# sources of the single-system cycle kernels (every mapping) and what they include
+CYCLE_SOURCES = ("igm_cycle.hip", "igm_cycle_lanes.hip", "igm_cycle_merge.hip", "igm_cycle.hpp", "igm_bsweep.hpp",
+                 "igm_sweep.hpp", "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp",
+                 "../../include/igmres.h")
 
 
 def cycle_sources_digest() -> str:
