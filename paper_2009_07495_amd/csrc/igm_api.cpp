@@ -65,6 +65,7 @@ igm_status upload_schedule(igm_system *s, const BlockSchedule &h, BlockSweepArgs
   d.nb = h.nb;
   d.narrow = h.narrow ? 1 : 0;
   d.max_levels = h.max_levels;
+  d.max_width = h.max_width;
   int32_t *prow = nullptr, *plen = nullptr, *ecode = nullptr, *lvbase = nullptr, *lvoff = nullptr, *wbase = nullptr;
   int64_t *levent = nullptr, *eval = nullptr, *pdiag = nullptr;
   uint64_t *pmag = nullptr;
@@ -84,6 +85,7 @@ igm_status upload_schedule(igm_system *s, const BlockSchedule &h, BlockSweepArgs
   IGM_TRY(upload(s, lvoff, h.lvoff));
   IGM_TRY(upload(s, wbase, h.wbase));
   IGM_TRY(upload(s, wrec, h.wrec));
+  d.pad_slot = h.pad_slot;
   d.prow = prow; d.plen = plen; d.ecode = ecode; d.eval = eval; d.evalf = evalf; d.pdiag = pdiag;
   d.lvbase = lvbase; d.lvoff = lvoff; d.levent = levent; d.wbase = wbase; d.wrec = wrec;
   d.pmag = pmag; d.pshift = pshift;

@@ -59,6 +59,7 @@ void block_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> &ptr, 
   hvec<int32_t> lv(n), sorted(n);  // local level of each position; sorted index inside its block
   std::vector<int32_t> nl(nb);
   std::vector<int64_t> eslots(nb);  // entry slots of each block (levels padded to their longest row)
+  std::vector<int32_t> widest(nb);  // rows of each block's widest level
   for_blocks(nb, [&](int32_t q) {
     const int64_t p0 = (int64_t)q * S, p1 = std::min<int64_t>(n, p0 + S);
     int32_t top = 0;
@@ -81,11 +82,16 @@ void block_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> &ptr, 
       width[lv[p]] = std::max<int64_t>(width[lv[p]], ptr[r + 1] - ptr[r]);
     }
     int64_t slots = 0;
-    for (int32_t l = 0; l < top; ++l) slots += width[l] * fill[l + 1];
+    int32_t wmax = 0;
+    for (int32_t l = 0; l < top; ++l) {
+      slots += width[l] * fill[l + 1];
+      wmax = std::max(wmax, fill[l + 1]);  // rows of level l
+    }
     for (int32_t l = 0; l < top; ++l) fill[l + 1] += fill[l];
     for (int64_t p = p0; p < p1; ++p) sorted[p] = fill[lv[p]]++;
     nl[q] = top;
     eslots[q] = slots;
+    widest[q] = wmax;
   });
   o.lvbase.assign(nb + 1, 0);
   std::vector<int64_t> ebase(nb + 1, 0);
@@ -93,16 +99,21 @@ void block_schedule(int64_t n, bool lower, int32_t S, const hvec<int64_t> &ptr, 
     o.lvbase[q + 1] = o.lvbase[q] + nl[q] + 1;
     ebase[q + 1] = ebase[q] + eslots[q];
     o.max_levels = std::max(o.max_levels, nl[q]);
+    o.max_width = std::max(o.max_width, widest[q]);
   }
-  const int64_t nslots = ebase[nb];
+  const int64_t nslots = ebase[nb];  // one more slot follows: the padding slot (code 0, value 0)
   o.prow.resize(n);
   o.plen.resize(n);
   o.pdiag.resize(n);
   o.pmag.resize(n);
   o.pshift.resize(n);
-  o.ecode.resize(nslots);
-  o.eval.resize(nslots);
-  o.evalf.resize(nslots);
+  o.ecode.resize(nslots + 1);
+  o.eval.resize(nslots + 1);
+  o.evalf.resize(nslots + 1);
+  o.ecode[nslots] = 0;
+  o.eval[nslots] = 0;
+  o.evalf[nslots] = 0.0;
+  o.pad_slot = nslots;
   o.lvoff.resize(o.lvbase[nb]);
   o.levent.resize(o.lvbase[nb]);
   std::vector<std::vector<WaitRec>> recs(nb);

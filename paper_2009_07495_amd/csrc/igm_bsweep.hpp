@@ -322,4 +322,258 @@ __device__ __forceinline__ void block_sweep(const BlockSweepArgs &b, const TX *s
   }
 }
 
+// One row of the integer sweep held by a compute lane: stage 1 (loaded three
+// levels ahead, addressed by the position alone; lanes and entries without a
+// row or entry load the padding slot, so every compute lane issues the same
+// loads) and stage 2 (loaded one level ahead: the right-hand side and the
+// values of the entries from other blocks, whose waits the helper has taken by
+// then; lanes and entries without one load a dummy word).
+template <int PRE>
+struct IntRow {
+  bool act;  // the lane has a row
+  int lp;    // position inside the block (act)
+  int32_t row;
+  int32_t len;
+  int64_t dg;
+  uint64_t mag;
+  int32_t sh;
+  int64_t rhs;
+  int32_t c[PRE];
+  int64_t v[PRE];
+  int64_t x[PRE];
+};
+
+// One integer sweep by the whole grid with a helper wavefront (dst =
+// tdiv(src - strict part, diagonal), the same schedule and the same bits as
+// block_sweep). Wavefront 0 of the workgroup is the helper: it takes the waits
+// on other blocks two levels ahead, stores each finished level's values to
+// global memory from LDS and publishes the block's progress (one add per
+// level, after its stores of that level have completed). Wavefronts 1 .. W
+// compute, G lanes per row, W as few as the widest level needs (the rest
+// idle): they read the block's own values from LDS and everything else from
+// registers loaded ahead, and issue no global store and no wait, so the loads
+// in flight for the next levels are never drained by a step of this one.
+// Per level L: the helper publishes level L - 2, stores level L - 1 and takes
+// the waits of level L + 2; the compute lanes compute L and load stage 2 of
+// L + 1 and stage 1 of L + 3; one workgroup barrier. The three rows in flight
+// rotate through fixed registers (the loop is unrolled by three). A level
+// wider than the row ring (kRowRing) is stored by the compute lanes themselves
+// (waited before the barrier); a level wider than one pass takes more passes.
+// `lds` holds sweep_lds_bytes(S, max_levels) bytes. Every thread of every
+// workgroup calls it.
+template <int BLOCK, int G>
+__device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const int64_t *src, int64_t *dst, char *lds,
+                                                bool &ovf, bool &to) {
+  static_assert(BLOCK % 64 == 0 && BLOCK >= 128 && G >= 1 && G <= 16 && (G & (G - 1)) == 0, "lanes per row");
+  constexpr int PRE = G >= 16 ? 1 : 16 / G;  // entries per lane held in registers
+  using Row = IntRow<PRE>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const bool helper = wave == 0;
+  // compute wavefronts: enough for the widest level in one pass, at most all but the helper
+  const int nw = min(BLOCK / 64 - 1, max(1, (b.max_width * G + 63) / 64));
+  const bool computing = wave >= 1 && wave <= nw;
+  const int rpp = nw * 64 / G;  // rows per pass
+  const int ct = computing ? tid - 64 : 0;
+  const int rs = ct / G, gl = ct % G;
+  const int klv = b.max_levels + 1;
+  int64_t *vals = (int64_t *)lds;
+  int64_t *levent = (int64_t *)(lds + 8 * (size_t)b.S);
+  int32_t *lvoff = (int32_t *)(levent + klv);
+  WaitRec *recs = (WaitRec *)((char *)lvoff + (4 * (size_t)klv + 15) / 16 * 16);
+  unsigned *seen = (unsigned *)(recs + kRecWindow);
+  int32_t *ring = (int32_t *)(seen + kSeenSlots + 4);  // rows of the last two levels: [L & 1][i]
+  const int64_t pad = b.pad_slot;
+
+  for (int q = blockIdx.x; q < b.nb; q += gridDim.x) {
+    const int64_t q0 = (int64_t)q * b.S;
+    const int lb = b.lvbase[q];
+    const int nl = b.lvbase[q + 1] - lb - 1;
+    unsigned *prog = b.prog + (int64_t)q * kLevStride;
+    int wr = b.wbase[q], win_lo = wr, win_hi = wr;  // the helper's next wait record and its window
+    const int we = b.wbase[q + 1];
+    for (int i = tid; i <= nl; i += BLOCK) {
+      lvoff[i] = b.lvoff[lb + i];
+      levent[i] = b.levent[lb + i];
+    }
+    for (int i = tid; i < kSeenSlots; i += BLOCK) seen[i] = 0;
+
+    // stage 1 of pass `pass` of level L (L clamped to the block's last level)
+    auto stage1 = [&](int L, int pass, Row &r) {
+      L = L < nl ? L : nl - 1;
+      const int p0 = lvoff[L], cnt = lvoff[L + 1] - p0;
+      const int i = pass * rpp + rs;
+      r.act = i < cnt;
+      r.lp = r.act ? p0 + i : p0;
+      const int64_t lev0 = levent[L];
+      const int width = (int)((levent[L + 1] - lev0) / cnt);
+      const int64_t pos = q0 + r.lp;
+      r.row = b.prow[pos];
+      r.len = b.plen[pos];
+      r.dg = b.pdiag[pos];
+      r.mag = b.pmag[pos];
+      r.sh = b.pshift[pos];
+#pragma unroll
+      for (int j = 0; j < PRE; ++j) {
+        const int k = gl + j * G;
+        const int64_t e = (r.act && k < width) ? lev0 + i + (int64_t)k * cnt : pad;
+        r.c[j] = b.ecode[e];
+        r.v[j] = b.eval[e];
+      }
+    };
+    // stage 2: the right-hand side and the other blocks' values (their waits are taken)
+    auto stage2 = [&](Row &r) {
+      r.rhs = ld_coh(src + r.row);
+#pragma unroll
+      for (int j = 0; j < PRE; ++j) {
+        const int k = gl + j * G;
+        const bool cross = k < r.len && r.c[j] < 0;
+        r.x[j] = ld_coh(dst + (cross ? -(int64_t)r.c[j] - 1 : (int64_t)r.row));
+      }
+    };
+    // the row's value (the group's lane 0 holds it); L = the row's level
+    auto compute = [&](const Row &r, int L) {
+      Acc acc;
+      acc.zero();
+#pragma unroll
+      for (int j = 0; j < PRE; ++j) {
+        const int k = gl + j * G;
+        const int32_t c = r.c[j];
+        const int64_t xl = vals[c >= 0 ? c : 0];
+        const int64_t xv = c >= 0 ? xl : r.x[j];
+        if (r.act && k < r.len) acc.sub(b.narrow ? mul_w32(xv, (int32_t)r.v[j], ovf) : mulw(xv, r.v[j], ovf));
+      }
+      if (r.act) {
+        const int cnt = lvoff[L + 1] - lvoff[L];
+        const int64_t e0 = levent[L] + (r.lp - lvoff[L]);
+        for (int k = gl + PRE * G; k < r.len; k += G) {  // entries beyond the registers
+          const int64_t e = e0 + (int64_t)k * cnt;
+          const int32_t c = b.ecode[e];
+          const int64_t v = b.eval[e];
+          const int64_t xv = c >= 0 ? vals[c] : ld_coh(dst + (-(int64_t)c - 1));
+          acc.sub(mulw(xv, v, ovf));
+        }
+      }
+      if constexpr (G > 1) {
+        acc.lo = group_sum64<G>(acc.lo);
+        acc.hi = group_sum64<G>(acc.hi);
+      }
+      int64_t y = 0;
+      if (r.act && gl == 0) {
+        acc.add(r.rhs);
+        y = tdiv_magic(acc.value(ovf), r.dg, r.mag, r.sh, ovf);
+      }
+      return y;
+    };
+    // the row's value into LDS and its row into the ring (or, for a level
+    // the ring does not hold, straight to global memory)
+    auto keep = [&](const Row &r, int64_t y, int L) {
+      if (r.act && gl == 0) {
+        vals[r.lp] = y;
+        if (lvoff[L + 1] - lvoff[L] <= kRowRing) ring[(L & 1) * kRowRing + (r.lp - lvoff[L])] = r.row;
+        else st_coh(dst + r.row, y);
+      }
+    };
+    // helper: take the waits of level L (blocking)
+    auto waits = [&](int L) {
+      for (;;) {
+        if (wr + 64 > win_hi && win_hi < we) {  // refill the window from the next record on
+          const int cnt = we - wr < kRecWindow ? we - wr : kRecWindow;
+          for (int i = lane; i < cnt; i += 64) recs[i] = b.wrec[wr + i];
+          win_lo = wr;
+          win_hi = wr + cnt;
+        }
+        const int r = wr + lane;
+        WaitRec rec{0, 0, 0, 0};
+        if (r < win_hi) rec = recs[r - win_lo];
+        const bool mine = r < win_hi && rec.level == L;
+        const unsigned long long got = __ballot(mine);
+        if (mine) {
+          const unsigned target = (unsigned)rec.need;
+          const bool cached = rec.slot < kSeenSlots;
+          unsigned v = cached ? seen[rec.slot] : 0u;
+          for (int spin = 0; v < target; ++spin) {
+            v = ld_coh(b.prog + (int64_t)rec.dep * kLevStride);
+            if (v >= target) break;
+            if (spin >= kSpinLimit || to) {
+              to = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
+          }
+          if (cached) seen[rec.slot] = v;
+        }
+        const int cnt = __popcll(got);  // the records of a level are consecutive
+        wr += cnt;
+        if (cnt < 64) break;
+      }
+    };
+    // helper: level L's values from LDS to global memory (levels the ring held)
+    auto store_level = [&](int L) {
+      const int p0 = lvoff[L], cnt = lvoff[L + 1] - p0;
+      if (cnt > kRowRing) return;
+      for (int i = lane; i < cnt; i += 64) st_coh(dst + ring[(L & 1) * kRowRing + i], vals[p0 + i]);
+    };
+    auto publish = [&]() {
+      wait_vm();
+      if (lane == 0) __hip_atomic_fetch_add(prog, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+
+    // The helper and the compute wavefronts run separate loops with one
+    // workgroup barrier per level each (a barrier counts per wavefront; the
+    // branch is the same in every lane of a wavefront), so the loads the
+    // helper waits for never mix with the compute lanes' loads in flight.
+    if (helper) {
+      waits(0);
+      waits(1);
+      __syncthreads();
+      for (int L = 0; L < nl; ++L) {
+        if (L >= 2) publish();          // level L - 2: its stores were issued a level ago
+        if (L >= 1) store_level(L - 1);
+        if (L + 2 < nl) waits(L + 2);   // two levels ahead: level L + 2's stage 2 is loaded in step L + 1
+        __syncthreads();
+      }
+      if (nl >= 2) publish();
+      store_level(nl - 1);
+      publish();
+    } else {
+      __syncthreads();
+      Row R0, R1, R2;
+      if (computing) {
+        stage1(0, 0, R0);
+        stage1(1, 0, R1);
+        stage2(R0);
+        stage1(2, 0, R2);
+      }
+      // level L with A = its row (both stages loaded), B = level L + 1's
+      // (stage 1 loaded); A's registers take level L + 3's stage 1
+      auto step = [&](int L, Row &A, Row &B) {
+        if (computing) {
+          const int64_t y = compute(A, L);
+          keep(A, y, L);
+          for (int pass = 1; pass * rpp < lvoff[L + 1] - lvoff[L]; ++pass) {  // wider levels, A's registers
+            stage1(L, pass, A);
+            stage2(A);
+            const int64_t yp = compute(A, L);
+            keep(A, yp, L);
+          }
+          if (lvoff[L + 1] - lvoff[L] > kRowRing) wait_vm();  // stored by the compute lanes themselves
+          stage2(B);
+          stage1(L + 3, 0, A);
+        }
+        __syncthreads();
+      };
+      int L = 0;
+      for (; L + 3 <= nl; L += 3) {
+        step(L, R0, R1);
+        step(L + 1, R1, R2);
+        step(L + 2, R2, R0);
+      }
+      if (L < nl) step(L, R0, R1);
+      if (L + 1 < nl) step(L + 1, R1, R2);
+    }
+  }
+}
+
 }  // namespace igm

@@ -31,15 +31,12 @@ constexpr int kGivens = 64;
 // the 16 words of a cache line), other workgroups first read them
 // after that barrier, and a launch starts with caches coherent with memory.
 
-// One integer sweep of the ILU(0) preconditioner apply with G = 8 or 16 lanes
-// per row (a runtime choice: the bits do not depend on it; fewer lanes per
-// row hold more entries per lane in registers than the cycle kernel has to
-// spare, and it would spill).
+// One integer sweep of the ILU(0) preconditioner apply with G = 4, 8 or 16
+// lanes per row (a runtime choice: the bits do not depend on it).
 template <int BLOCK>
 __device__ __forceinline__ void ilu_sweep(int G, const BlockSweepArgs &b, const int64_t *src, int64_t *dst,
                                           char *lds, bool &ovf, bool &to) {
-  if (G == 16) block_sweep<BLOCK, 16, false>(b, src, dst, lds, ovf, to);
-  else block_sweep<BLOCK, 8, false>(b, src, dst, lds, ovf, to);
+  block_sweep_int<BLOCK, 4>(b, src, dst, lds, ovf, to);
 }
 
 // The integer SpMV of row `row` (chunk of BLOCK rows from row0, the one this

@@ -79,6 +79,7 @@ struct BlockSchedule {
   int32_t S = 0, nb = 0;     // rows per block, blocks
   int32_t max_slots = 0;     // most dependency blocks of one block
   int32_t max_levels = 0;    // most local levels of one block
+  int32_t max_width = 0;     // most rows of one local level
   bool narrow = false;       // every factor value fits in int32
   hvec<int32_t> prow;        // n: row of each sorted position
   hvec<int32_t> plen;        // n: entries of each sorted position's row
@@ -99,6 +100,7 @@ struct BlockSchedule {
   hvec<int64_t> levent;
   hvec<int32_t> wbase;       // nb + 1: where each block's wait records start in wrec
   hvec<WaitRec> wrec;        // per block, sorted by level
+  int64_t pad_slot = 0;      // the slot after every block's entries (ecode, eval, evalf hold pad_slot + 1)
 };
 
 // Device view of one BlockSchedule.
@@ -106,6 +108,7 @@ struct BlockSweepArgs {
   int32_t S, nb;
   int32_t narrow;      // every factor value fits in int32
   int32_t max_levels;  // most local levels of one block (sizes the LDS copy of a block's level table)
+  int32_t max_width;   // most rows of one local level (sizes the integer sweep's compute wavefronts)
   const int32_t *prow, *plen;
   const int32_t *ecode;
   const int64_t *eval;
@@ -116,8 +119,12 @@ struct BlockSweepArgs {
   const int32_t *lvbase, *lvoff, *wbase;
   const int64_t *levent;
   const WaitRec *wrec;
+  // a slot past every block's entries (code 0, value 0): the integer sweep's
+  // prefetch loads it for lanes and entries without one
+  int64_t pad_slot;
   // nb progress words kLevStride apart, zero at the start of the sweep: every
-  // wavefront of the block's workgroup adds one per finished level
+  // wavefront of the block's workgroup adds one per finished level (the FP64
+  // sweep); the helper wavefront adds one per level (the integer sweep)
   unsigned *prog;
 };
 
@@ -127,15 +134,18 @@ struct BlockSweepArgs {
 // levels), the record window, that cache and two flags.
 constexpr int kSeenSlots = 256;
 constexpr int kRecWindow = 256;
+// The integer sweep adds the rows of its last two levels (kRowRing each).
+constexpr int kRowRing = 1024;
 inline size_t sweep_lds_bytes(int64_t S, int32_t max_levels) {
   const size_t lv = (size_t)max_levels + 1;
-  return 8 * (size_t)S + 8 * lv + (4 * lv + 15) / 16 * 16 + 16 * (size_t)kRecWindow + 4 * (size_t)kSeenSlots + 16;
+  return 8 * (size_t)S + 8 * lv + (4 * lv + 15) / 16 * 16 + 16 * (size_t)kRecWindow + 4 * (size_t)kSeenSlots + 16 +
+         8 * (size_t)kRowRing;
 }
 // Rows per block and lanes per row of the blocked sweeps when the policy
 // leaves them open, and the static LDS the cycle kernel keeps besides its
 // dynamic part (reduction scratch and flags; an upper bound).
 constexpr int kSweepRowsAuto = 16384;
-constexpr int kSweepLanesAuto = 8;
+constexpr int kSweepLanesAuto = 4;
 constexpr int kCycleStaticLds = 4096;
 
 // Truncating division by an invariant nonzero divisor d through one
