@@ -499,7 +499,7 @@ def kernel_rates(torch, B, W) -> dict:
     """Standalone SpMV and Gram-Schmidt inner-product kernels (Fig. 2), timed
     with HIP events around the kernels: the SpMV with each row-to-lane mapping
     (1: one thread per row over SELL-64; 2: each workgroup's rows split evenly
-    by entries; 4, 16, 64 lanes per row over CSR) on the
+    by entries; 4, 8, 16, 32, 64 lanes per row over CSR) on the
     27-point 1M-row matrix, the 7-point 64^3 matrix and a heavy-tailed 1M-row
     matrix, with the mapping the automatic rule and the setup-time measurement
     pick; the inner product on the 27-point matrix's vector length."""
@@ -524,7 +524,7 @@ def kernel_rates(torch, B, W) -> dict:
         v = torch.from_numpy(rng.integers(-(1 << 30), 1 << 30, n)).cuda()
         z = torch.zeros(n, dtype=torch.int64, device="cuda")
         row = {"n": n, "nnz": nnz, "bytes": byts, "lanes": {}}
-        for lanes in (1, 2, 4, 16, 64):
+        for lanes in (1, 2, 4, 8, 16, 32, 64):
             g = B.System.from_system(sysm, "jacobi", spmv_lanes=lanes)
             ms = med_ms(g, lambda: g.spmv(v, z))
             row["lanes"][str(lanes)] = {"ms": ms, "gb_s": byts / ms / 1e6, "frac": byts / ms / 1e6 / HBM_PEAK_GBS}

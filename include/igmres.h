@@ -142,14 +142,14 @@ typedef struct {
   /* Launch tuning of the single-system solver's integer SpMV and FP64
    * residual (the bits do not depend on it), IGM_SPMV_* or lanes per row:
    * IGM_SPMV_SELL (1) = one thread per row over the SELL-64 layout (rows of
-   * similar length); 4, 16 or 64 = that many lanes of a wavefront per row over
-   * the CSR layout (64 = a wavefront per row); IGM_SPMV_MERGE (2) = each
+   * similar length); 4, 8, 16, 32 or 64 = that many lanes of a wavefront per
+   * row over the CSR layout (64 = a wavefront per row); IGM_SPMV_MERGE (2) = each
    * workgroup's chunk of rows split evenly by entries over its threads, rows
    * cut anywhere (heavy-tailed row lengths; chunks of 1024 rows must hold
    * fewer than 2^30 entries); IGM_SPMV_AUTO (0) = from the row lengths: SELL
    * unless SELL-64 would more than double the entries loaded, then MERGE;
-   * IGM_SPMV_MEASURE (-1) = at setup each mapping runs the standalone SpMV a
-   * few times and the fastest is kept. The FP64 residual runs one thread per
+   * IGM_SPMV_MEASURE (-1) = at setup each mapping (SELL, MERGE, 4 to 64
+   * lanes) runs the standalone SpMV a few times and the fastest is kept. The FP64 residual runs one thread per
    * row with SELL, 16 lanes per row with MERGE, else the SpMV's lanes. Every
    * mapping but SELL also keeps the integer matrices in CSR order (8 bytes per
    * entry and term). */

@@ -459,7 +459,7 @@ igm_status tune_spmv_lanes(igm_system *s) {
   IGM_HIP(hipEventCreate(&ev.e1));
   float best = 0.0f;
   int32_t pick = 1;
-  for (int32_t g : {1, 2, 4, 16, 64}) {
+  for (int32_t g : {1, 2, 4, 8, 16, 32, 64}) {
     if (g == IGM_SPMV_MERGE && !s->spmv_merge_ok) continue;
     s->spmv_lanes = g;
     const CycleArgs a = make_args(s);

@@ -56,7 +56,7 @@ __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long
 }
 
 // eq. (b): r = b - A x (scaled) and rhat = bhat - Ahat x (original).
-// eq. (b) with G lanes per row (G = 4, 16, 64): the lanes of a group form the
+// eq. (b) with G lanes per row (G = 4, 8, 16, 32, 64): the lanes of a group form the
 // products of G consecutive entries at once, then every lane of the group adds
 // them one after another in entry order, so r and rhat round exactly as the
 // sums in CSR order of residual_row.
@@ -438,6 +438,12 @@ hipError_t launch_residual(hipStream_t st, int64_t n, const int64_t *rp, const i
   if (lanes == 4)
     hipLaunchKernelGGL(k_residual_lanes<4>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
                        cscale, r, rhat, red);
+  else if (lanes == 8)
+    hipLaunchKernelGGL(k_residual_lanes<8>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
+                       cscale, r, rhat, red);
+  else if (lanes == 32)
+    hipLaunchKernelGGL(k_residual_lanes<32>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
+                       cscale, r, rhat, red);
   else if (lanes == 16)
     hipLaunchKernelGGL(k_residual_lanes<16>, dim3(rows_blocks), dim3(kB), 0, st, n, rp, col, a, ahat, b, bhat, x,
                        cscale, r, rhat, red);
@@ -522,7 +528,9 @@ hipError_t launch_spmv(hipStream_t st, const CycleArgs &a, int nterms, const int
   const unsigned g = grid_stride_blocks(a.n);
   if (a.spmv_lanes == IGM_SPMV_MERGE) hipLaunchKernelGGL(k_spmv_merge, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else if (a.spmv_lanes == 4) hipLaunchKernelGGL(k_spmv_lanes<4>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  else if (a.spmv_lanes == 8) hipLaunchKernelGGL(k_spmv_lanes<8>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else if (a.spmv_lanes == 16) hipLaunchKernelGGL(k_spmv_lanes<16>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  else if (a.spmv_lanes == 32) hipLaunchKernelGGL(k_spmv_lanes<32>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else if (a.spmv_lanes == 64) hipLaunchKernelGGL(k_spmv_lanes<64>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else hipLaunchKernelGGL(k_spmv, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   return hipGetLastError();

@@ -79,7 +79,7 @@ __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64
   return tot.value(ovf);
 }
 
-// The same SpMV row by g lanes (g = 4, 16 or 64, the same in every lane:
+// The same SpMV row by g lanes (g = 4, 8, 16, 32 or 64, the same in every lane:
 // aligned groups of consecutive lanes of one wavefront) over the CSR layout of
 // the integer matrices (crp, ccol, cval): lane l of the group takes entries l,
 // l + g, ...; the exact partial sums are combined over the group, so every

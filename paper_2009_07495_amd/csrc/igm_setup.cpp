@@ -78,8 +78,8 @@ igm_status check_policy(const igm_policy &p) {
   if (p.sweep_rows < 0 || p.sweep_rows % 64 != 0 || p.sweep_rows > (1 << 20)) return IGM_ERR_ARG;
   if (p.sweep_lanes != 0 && p.sweep_lanes != 4 && p.sweep_lanes != 8 && p.sweep_lanes != 16) return IGM_ERR_ARG;
   if (p.s_rule < 0 || p.s_rule > 1) return IGM_ERR_ARG;
-  if (p.spmv_lanes != -1 && p.spmv_lanes != 0 && p.spmv_lanes != 1 && p.spmv_lanes != 2 && p.spmv_lanes != 4 && p.spmv_lanes != 16 && p.spmv_lanes != 64)
-    return IGM_ERR_ARG;
+  if (p.spmv_lanes < -1 || p.spmv_lanes > 64 || (p.spmv_lanes > 2 && (p.spmv_lanes & (p.spmv_lanes - 1)) != 0))
+    return IGM_ERR_ARG;  // -1, 0, 1, 2, or 4, 8, 16, 32, 64 lanes per row
   return IGM_OK;
 }
 

@@ -63,7 +63,9 @@ def test_create_system_rejects_bad_input_before_touching_the_device():
     val = np.ones(3)
     st, h = binding.igm_create_system(2, rp, col, val, np.ones(2), binding.make_policy("paper_noprec"))
     assert st == binding.ERR_ARG and not h.value
-    bad = binding.make_policy("paper_noprec", df=70)
-    st, h = binding.igm_create_system(2, np.array([0, 1, 2]), np.array([0, 1], dtype=np.int32), val[:2],
-                                      np.ones(2), bad)
-    assert st == binding.ERR_ARG
+    for kw in (dict(df=70), dict(spmv_lanes=3), dict(spmv_lanes=128), dict(spmv_lanes=-2), dict(sweep_lanes=2),
+               dict(sweep_rows=100)):
+        bad = binding.make_policy("paper_noprec", **kw)
+        st, h = binding.igm_create_system(2, np.array([0, 1, 2]), np.array([0, 1], dtype=np.int32), val[:2],
+                                          np.ones(2), bad)
+        assert st == binding.ERR_ARG, kw

@@ -400,7 +400,7 @@ SPMV_LANE_CASES = [
 
 
 @pytest.mark.parametrize("name,gen,preset,kw", SPMV_LANE_CASES)
-@pytest.mark.parametrize("lanes", [1, 2, 4, 16, 64, -1])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64, -1])
 def test_spmv_lane_mappings_bit_exact(orc, torch, name, gen, preset, kw, lanes):
     """The integer SpMV inside the cycle kernel with one thread per row over
     SELL-64 (1), each workgroup's rows split evenly by entries (2), or 4, 16,
@@ -416,7 +416,7 @@ def test_spmv_lane_mappings_bit_exact(orc, torch, name, gen, preset, kw, lanes):
     for grid in (0, 3):
         g = B.System.from_system(s, preset, grid_blocks=grid, spmv_lanes=lanes, **kw)
         got = g.stats()["spmv_lanes"]
-        assert got == lanes if lanes > 0 else got in (1, 2, 4, 16, 64)
+        assert got == lanes if lanes > 0 else got in (1, 2, 4, 8, 16, 32, 64)
         assert_trace_equal(g.int_cycle(v1), to, s.n)
         x, st = g.solve()
         assert st == so["status"] and np.array_equal(x, xo), (name, lanes, grid)

@@ -29,7 +29,7 @@ SYSTEMS = [
 # row-to-lane mappings of the SpMV and the residual: SELL-64 (1), chunks split
 # evenly by entries (2), then 4, 16 and 64 lanes per row over CSR (every
 # mapping must give the same bits)
-LANES = [1, 2, 4, 16, 64]
+LANES = [1, 2, 4, 8, 16, 32, 64]
 
 
 @pytest.fixture(scope="module")
