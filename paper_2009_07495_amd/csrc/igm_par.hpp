@@ -28,10 +28,12 @@ struct SetupRegion {
 };
 
 // f(chunk, lo, hi) over [0, n) in nt contiguous chunks (serially when nt <= 1
-// or n is small). Chunk c covers rows before those of chunk c + 1.
+// or n is below `serial_below` items). Chunk c covers rows before those of
+// chunk c + 1. Callers whose items are large (slices of many rows) pass a
+// smaller threshold.
 template <class F>
-void par_ranges(int nt, int64_t n, F &&f) {
-  if (nt <= 1 || n < 32768) {
+void par_ranges(int nt, int64_t n, F &&f, int64_t serial_below = 32768) {
+  if (nt <= 1 || n < serial_below) {
     f(0, (int64_t)0, n);
     return;
   }

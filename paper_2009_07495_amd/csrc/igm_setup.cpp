@@ -165,7 +165,8 @@ static igm_status split_terms(int nt, const igm_policy &p, HostSetup &h) {
   std::atomic<bool> bad{false};
   // the remainders are needed only for terms beyond A_0
   hvec<double> rem(p.s_terms > 0 ? nnz : 0);
-  h.abar.assign(1, hvec<int64_t>(nnz));
+  h.abar.clear();
+  h.abar.emplace_back(nnz);  // not assign(1, ...): that copies a whole array on one thread
   h.alpha[0] = 0;
   par_ranges(nt, nnz, [&](int, int64_t lo, int64_t hi) {
     bool b = false;
@@ -381,8 +382,8 @@ static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const
 // rows its strict lower part reads (rows in increasing order); backward levels
 // likewise on the strict upper part in decreasing order.
 static void level_sets(int64_t n, HostSetup &h) {
-  std::vector<int32_t> lev(n);
-  auto group = [&](hvec<int32_t> &ptr, hvec<int32_t> &rows, int32_t nlev) {
+  // rows grouped by level, rows increasing inside a level
+  auto group = [n](const std::vector<int32_t> &lev, int32_t nlev, hvec<int32_t> &ptr, hvec<int32_t> &rows) {
     ptr.assign(nlev + 1, 0);
     for (int64_t i = 0; i < n; ++i) ptr[lev[i] + 1]++;
     for (int32_t k = 0; k < nlev; ++k) ptr[k + 1] += ptr[k];
@@ -390,22 +391,37 @@ static void level_sets(int64_t n, HostSetup &h) {
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
     for (int64_t i = 0; i < n; ++i) rows[fill[lev[i]]++] = (int32_t)i;
   };
-  int32_t nlev = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    int32_t l = 0;
-    for (int64_t e = h.lptr[i]; e < h.lptr[i + 1]; ++e) l = std::max(l, lev[h.lcol[e]] + 1);
-    lev[i] = l;
-    nlev = std::max(nlev, l + 1);
+  // the two scans are independent: the backward one runs on a second thread
+  auto forward = [&] {
+    std::vector<int32_t> lev(n);
+    int32_t nlev = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      int32_t l = 0;
+      for (int64_t e = h.lptr[i]; e < h.lptr[i + 1]; ++e) l = std::max(l, lev[h.lcol[e]] + 1);
+      lev[i] = l;
+      nlev = std::max(nlev, l + 1);
+    }
+    group(lev, nlev, h.flev_ptr, h.flev_rows);
+  };
+  auto backward = [&] {
+    std::vector<int32_t> lev(n);
+    int32_t nlev = 0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+      int32_t l = 0;
+      for (int64_t e = h.uptr[i]; e < h.uptr[i + 1]; ++e) l = std::max(l, lev[h.ucol[e]] + 1);
+      lev[i] = l;
+      nlev = std::max(nlev, l + 1);
+    }
+    group(lev, nlev, h.blev_ptr, h.blev_rows);
+  };
+  if (setup_thread_count() > 1 && n >= 32768) {
+    std::thread tb(backward);
+    forward();
+    tb.join();
+  } else {
+    forward();
+    backward();
   }
-  group(h.flev_ptr, h.flev_rows, nlev);
-  nlev = 0;
-  for (int64_t i = n - 1; i >= 0; --i) {
-    int32_t l = 0;
-    for (int64_t e = h.uptr[i]; e < h.uptr[i + 1]; ++e) l = std::max(l, lev[h.ucol[e]] + 1);
-    lev[i] = l;
-    nlev = std::max(nlev, l + 1);
-  }
-  group(h.blev_ptr, h.blev_rows, nlev);
 }
 
 // SELL-64: rows in slices of 64, each slice stored column-major with the width
@@ -428,11 +444,12 @@ static void build_sell(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<in
   for (int l = 0; l < h.nterms; ++l) h.sell_val[l].resize(tot);
   par_ranges(nt, ns, [&](int, int64_t s0, int64_t s1) {
     for (int64_t s = s0; s < s1; ++s) {
-      for (int lane = 0; lane < kSlice; ++lane) {
-        int64_t i = s * kSlice + lane;
-        for (int64_t k = 0; k < h.sell_w[s]; ++k) {
-          int64_t pos = h.sell_off[s] + k * kSlice + lane;
-          int64_t e = (i < n) ? rp[i] + k : -1;
+      // written in layout order (entry k of the 64 rows, then k + 1)
+      for (int64_t k = 0; k < h.sell_w[s]; ++k) {
+        for (int lane = 0; lane < kSlice; ++lane) {
+          const int64_t i = s * kSlice + lane;
+          const int64_t pos = h.sell_off[s] + k * kSlice + lane;
+          const int64_t e = (i < n) ? rp[i] + k : -1;
           if (i < n && e < rp[i + 1]) {
             h.sell_col[pos] = col[e];
             for (int l = 0; l < h.nterms; ++l) h.sell_val[l][pos] = h.abar[l][e];
@@ -443,7 +460,7 @@ static void build_sell(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<in
         }
       }
     }
-  });
+  }, 64);  // a slice is 64 rows
 }
 
 igm_status host_setup(int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
