@@ -421,7 +421,17 @@ typedef struct {
                                the application); 0 = 8, < 0 = none */
   int64_t pool_bytes;       /* device memory for resident requests; 0 = 16 GiB */
   int64_t stage_bytes;      /* pinned host memory for prepared requests and results; 0 = 4 GiB */
-  int32_t reserved_[6];
+  /* 0: the host makes a request's structure (validation, diagonal positions,
+   * factor patterns and level sets, SELL-64 offsets and columns) and the
+   * request's team computes the values on the device before solving it
+   * (scaling of eqs. (eq1)/(eq3), the integer matrix of eq. (A), the FP64
+   * ILU(0) of Sec. VI-A level by level, the factor casts, the SELL-64 values;
+   * the same operations in the same order as the host, so the same bits),
+   * wherever that applies (one matrix term, no Gauss-Seidel splitting,
+   * ILU(0) factors that fit in the request's basis array), else on the host;
+   * 1: the whole setup on the host. */
+  int32_t host_setup;
+  int32_t reserved_[5];
 } igm_server_config;
 
 /* Start a server on the current device. Errors: IGM_ERR_ARG, IGM_ERR_OOM,

@@ -448,7 +448,8 @@ class Batch:
 class ServerConfig(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("block", C.c_int32), ("rows_per_thread", C.c_int32),
                 ("max_slots", C.c_int32), ("setup_threads", C.c_int32), ("reserve_cus", C.c_int32),
-                ("pool_bytes", C.c_int64), ("stage_bytes", C.c_int64), ("reserved_", C.c_int32 * 6)]
+                ("pool_bytes", C.c_int64), ("stage_bytes", C.c_int64), ("host_setup", C.c_int32),
+                ("reserved_", C.c_int32 * 5)]
 
 
 class ServerStats(C.Structure):
@@ -468,9 +469,9 @@ class Server:
     they arrive (continuous batching). Owned; closing drains it."""
 
     def __init__(self, block=0, rows_per_thread=0, max_slots=0, setup_threads=0, pool_bytes=0, reserve_cus=0,
-                 stage_bytes=0):
+                 stage_bytes=0, host_setup=False):
         cfg = ServerConfig(C.sizeof(ServerConfig), block, rows_per_thread, max_slots, setup_threads, reserve_cus,
-                           int(pool_bytes), int(stage_bytes))
+                           int(pool_bytes), int(stage_bytes), 1 if host_setup else 0)
         h = C.c_void_p()
         _check(lib().igm_server_create(C.byref(cfg), C.byref(h)), "igm_server_create")
         self.h = h

@@ -36,30 +36,22 @@ void walk_region(const HostSystem &hs, bool own_x, F &&f) {
   const HostSetup &h = hs.h;
   const size_t n = (size_t)hs.n, nz = (size_t)hs.nnz;
   const size_t ldv = (size_t)((hs.n + 15) / 16 * 16);
-  // data: inputs and setup products, x, exchange words
+  const size_t sell = h.sell_off.empty() ? 0 : (size_t)h.sell_off.back();
+  const bool pre = hs.pol.precond != IGM_PRE_NONE, ilu = hs.pol.precond == IGM_PRE_ILU0;
+  // inputs and structure (always made by the host), x, exchange words
   f("row_ptr", sizeof(int64_t) * (n + 1));
   f("col", sizeof(int32_t) * nz);
-  f("a", sizeof(double) * nz);
   f("ahat", sizeof(double) * nz);
-  f("b", sizeof(double) * n);
   f("bhat", sizeof(double) * n);
   f("sell_off", sizeof(int64_t) * h.sell_off.size());
   f("sell_w", sizeof(int32_t) * h.sell_w.size());
   f("sell_col", sizeof(int32_t) * h.sell_col.size());
-  for (int l = 0; l < hs.nterms; ++l) f("sell_val", sizeof(int64_t) * h.sell_val[l].size());
-  if (hs.pol.precond != IGM_PRE_NONE) {
-    f("ldiag", sizeof(int64_t) * n);
-    f("udiag", sizeof(int64_t) * n);
-  }
-  if (hs.pol.precond == IGM_PRE_ILU0) {
+  if (hs.device_setup) f("diag_pos", sizeof(int64_t) * n);
+  if (ilu) {
     f("lptr", sizeof(int64_t) * h.lptr.size());
     f("uptr", sizeof(int64_t) * h.uptr.size());
     f("lcol", sizeof(int32_t) * h.lcol.size());
     f("ucol", sizeof(int32_t) * h.ucol.size());
-    f("lval", sizeof(int64_t) * h.lval.size());
-    f("uval", sizeof(int64_t) * h.uval.size());
-    f("lvalf", sizeof(double) * hs.lvalf.size());
-    f("uvalf", sizeof(double) * hs.uvalf.size());
     f("flev_ptr", sizeof(int32_t) * h.flev_ptr.size());
     f("flev_rows", sizeof(int32_t) * h.flev_rows.size());
     f("blev_ptr", sizeof(int32_t) * h.blev_ptr.size());
@@ -67,8 +59,22 @@ void walk_region(const HostSystem &hs, bool own_x, F &&f) {
   }
   if (own_x) f("x", sizeof(double) * n);
   f("words", sizeof(unsigned long long) * (size_t)kTeamSlots * kTeamWords);
+  // values of the setup (made by the host, or by the kernel with device setup)
+  f("a", sizeof(double) * nz);
+  f("b", sizeof(double) * n);
+  for (int l = 0; l < hs.nterms; ++l) f("sell_val", sizeof(int64_t) * sell);
+  if (pre) {
+    f("ldiag", sizeof(int64_t) * n);
+    f("udiag", sizeof(int64_t) * n);
+  }
+  if (ilu) {
+    f("lval", sizeof(int64_t) * (size_t)h.lptr[n]);
+    f("uval", sizeof(int64_t) * (size_t)h.uptr[n]);
+    f("lvalf", sizeof(double) * (size_t)h.lptr[n]);
+    f("uvalf", sizeof(double) * (size_t)h.uptr[n]);
+  }
   // work arrays (written before they are read)
-  if (hs.pol.precond == IGM_PRE_ILU0) {
+  if (ilu) {
     f("zbuf", sizeof(int64_t) * n);
     f("wbuf", sizeof(int64_t) * n);
     f("fbuf", sizeof(double) * n);
@@ -76,6 +82,9 @@ void walk_region(const HostSystem &hs, bool own_x, F &&f) {
   }
   f("V", sizeof(int64_t) * (size_t)(hs.pol.m + 1) * ldv);
 }
+
+// The first array of the setup's values (not part of a device setup's image).
+bool is_value_array(const char *name) { return std::string(name) == "a"; }
 
 bool is_work_array(const char *name) {
   const std::string nm(name);
@@ -92,6 +101,7 @@ const void *array_source(const HostSystem &hs, const char *name, int &term) {
   if (nm == "ahat") return hs.ahat.data();
   if (nm == "b") return h.b.data();
   if (nm == "bhat") return hs.bhat.data();
+  if (nm == "diag_pos") return h.diag_pos.data();
   if (nm == "sell_off") return h.sell_off.data();
   if (nm == "sell_w") return h.sell_w.data();
   if (nm == "sell_col") return h.sell_col.data();
@@ -116,7 +126,7 @@ const void *array_source(const HostSystem &hs, const char *name, int &term) {
 }  // namespace
 
 igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
-                          const double *b, const igm_policy &pol, HostSystem &out) {
+                          const double *b, const igm_policy &pol, HostSystem &out, bool allow_device_setup) {
   if (pol.struct_size != (int32_t)sizeof(igm_policy)) return IGM_ERR_ARG;
   igm_status st = check_policy(pol);
   if (st != IGM_OK) return st;
@@ -131,6 +141,15 @@ igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col,
   par_assign(out.col, col, out.nnz);
   par_assign(out.ahat, val, out.nnz);
   par_assign(out.bhat, b, n);
+  // device setup: the ILU(0) factors are built in the basis array, which must hold them
+  const int64_t ldv = (n + 15) / 16 * 16;
+  out.device_setup = allow_device_setup && pol.s_terms == 0 && !pol.gauss_seidel &&
+                     (pol.precond != IGM_PRE_ILU0 || out.nnz <= (int64_t)(pol.m + 1) * ldv);
+  if (out.device_setup) {
+    st = host_structure(n, out.row_ptr, out.col, pol, out.h);
+    out.nterms = 1;
+    return st;
+  }
   st = host_setup(n, out.row_ptr, out.col, out.ahat, out.bhat, pol, out.h);
   if (st != IGM_OK) return st;
   out.nterms = std::min(pol.s_terms + 1, out.h.nterms);
@@ -163,6 +182,8 @@ void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
   S.gtol = p.gtol;
   S.tol = p.tol;
   for (int l = 0; l < kMaxTerms; ++l) S.alpha[l] = h.alpha[l];
+  S.device_setup = hs.device_setup ? 1 : 0;
+  S.alpha_a = p.alpha_a;
   if (p.precond == IGM_PRE_ILU0) {
     S.nflev = h.flev_ptr.empty() ? 0 : (int32_t)h.flev_ptr.size() - 1;
     S.nblev = h.blev_ptr.empty() ? 0 : (int32_t)h.blev_ptr.size() - 1;
@@ -180,6 +201,7 @@ void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
     else if (nm == "ahat") S.ahat = (const double *)d;
     else if (nm == "b") S.b = (const double *)d;
     else if (nm == "bhat") S.bhat = (const double *)d;
+    else if (nm == "diag_pos") S.diag_pos = (const int64_t *)d;
     else if (nm == "sell_off") S.sell_off = (const int64_t *)d;
     else if (nm == "sell_w") S.sell_w = (const int32_t *)d;
     else if (nm == "sell_col") S.sell_col = (const int32_t *)d;
@@ -212,7 +234,7 @@ size_t image_bytes(const HostSystem &hs) {
   size_t total = 0;
   bool work = false;
   walk_region(hs, true, [&](const char *name, size_t bytes) {
-    work = work || is_work_array(name);
+    work = work || is_work_array(name) || (hs.device_setup && is_value_array(name));
     if (!work) total += align_up(bytes);
   });
   return total;
@@ -223,7 +245,7 @@ void build_image(const HostSystem &hs, char *img, const double *x0) {
   int term = 0;
   bool work = false;
   walk_region(hs, true, [&](const char *name, size_t bytes) {
-    work = work || is_work_array(name);
+    work = work || is_work_array(name) || (hs.device_setup && is_value_array(name));
     if (work) return;
     char *d = img + off;
     const size_t span = align_up(bytes);

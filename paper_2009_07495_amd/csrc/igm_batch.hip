@@ -18,6 +18,7 @@
 // system depend neither on its team size, the launch shape, nor the other
 // systems of the batch: they equal those of the single-system solver.
 #include "igm_batch.hpp"
+#include "igm_dsetup.hpp"
 #include "igm_rows.hpp"
 #include "igm_sweep.hpp"
 #include "igm_team.hpp"
@@ -248,6 +249,10 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
     t_prev = t_;                         \
   }
 
+    // served requests with a device setup: the values of the setup first
+    const igm_status setup_status =
+        (SERVED && S.device_setup) ? device_setup<BLOCK>(tm, tsh, S, g0, TB) : IGM_OK;
+
     // ILU level counters start from zero for every solve; the exchanges of
     // the norms below order these stores before any member's first sweep
     if (pre == IGM_PRE_ILU0 && S.team > 1) {
@@ -277,6 +282,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
     double ro = 0.0, rs = 0.0;
     for (int kref = 0;; ++kref) {
       if (tsh.abort) break;
+      if (setup_status != IGM_OK) { status = setup_status; break; }
       // integer matrix terms of this refinement (k = kref + 1): Abar_0 and s(k) corrections, eq. (AA)
       const int nterms_k = S.s_rule ? (S.nterms < kref + 1 ? S.nterms : kref + 1) : S.nterms;
       // ---- eq. (b): r = b - A x and rhat = bhat - Ahat x, rows in CSR order

@@ -41,6 +41,12 @@ struct BatchSys {
   const int64_t *lval, *uval;
   const double *lvalf, *uvalf;   // the same values in FP64 (start step)
   const int32_t *flev_ptr, *flev_rows, *blev_ptr, *blev_rows;
+  // device setup (device_setup = 1): the kernel computes a, b, sell_val[0],
+  // ldiag, udiag, lval, uval, lvalf, uvalf from ahat, bhat and the structure
+  // (diag_pos: each row's diagonal entry) before the solve
+  int32_t device_setup;
+  int32_t alpha_a;
+  const int64_t *diag_pos;
   int64_t *V;                    // (m+1) x ldv basis
   int64_t *zbuf, *wbuf;          // ILU: SpMV output and preconditioned vector
   double *fbuf;                  // ILU: FP64 substitution of the start step
@@ -102,14 +108,20 @@ struct HostSystem {
   HostSetup h;
   int nterms = 1;
   hvec<double> lvalf, uvalf;  // FP64 copies of the integer factors (start step)
+  // the values of the setup (scaling, integer matrix, factors) are computed
+  // by the solving kernel from the inputs; the host made the structure only
+  bool device_setup = false;
 };
 
 // Largest m of the batched kernel (H lives in LDS).
 constexpr int kMaxBatchM = 64;
 
 // Validates (as igm_create_system) and runs the host setup of one system.
+// With allow_device_setup the host makes only the structure when the kernel
+// can compute the values (one matrix term, no Gauss-Seidel splitting, ILU(0)
+// factors that fit in the basis array during the setup).
 igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
-                          const double *b, const igm_policy &pol, HostSystem &out);
+                          const double *b, const igm_policy &pol, HostSystem &out, bool allow_device_setup = false);
 // Device bytes of one system's region (inputs, setup products, basis, work
 // vectors, exchange words; the solution vector only if own_x).
 size_t system_bytes(const HostSystem &hs, bool own_x);

@@ -194,6 +194,13 @@ igm_status host_setup(int64_t n, const hvec<int64_t> &row_ptr, const hvec<int32_
                       const hvec<double> &ahat, const hvec<double> &bhat, const igm_policy &pol,
                       HostSetup &out);
 igm_status check_policy(const igm_policy &p);
+// The structural part of host_setup only, for a setup whose values are
+// computed on the device: diagonal positions (-1 where a row has none; the
+// device reports that, after the errors the host setup finds first), the
+// factor patterns and level sets, the SELL-64 offsets, widths and columns. One matrix term, no
+// Gauss-Seidel splitting, one-sided scaling (else IGM_ERR_UNSUPPORTED).
+igm_status host_structure(int64_t n, const hvec<int64_t> &row_ptr, const hvec<int32_t> &col, const igm_policy &pol,
+                          HostSetup &out);
 // Overflow-driven shift retry (igm_policy.shift_retry): adjusts the shift that
 // the stage of overflow event `code` names; false if none can change.
 bool adjust_shifts(igm_policy &p, int64_t code);

@@ -126,6 +126,7 @@ struct igm_server {
   int device = 0;
   hipStream_t kstream = nullptr;
   int block = 0, rows = 0, grid = 0, max_slots = 0;
+  bool host_setup = false;  // config: every request's whole setup on the host
   char *d_pool = nullptr;
   Pool pool, stage;
   unsigned long long *d_arrive = nullptr;  // per slot, monotonic
@@ -190,7 +191,8 @@ void setup_worker(igm_server *sv) {
     }
     TraceRange trace_setup("igm request setup");
     HostSystem hs;
-    igm_status st = prepare_system(r->n, r->rp.data(), r->col.data(), r->val.data(), r->b.data(), r->pol, hs);
+    igm_status st =
+        prepare_system(r->n, r->rp.data(), r->col.data(), r->val.data(), r->b.data(), r->pol, hs, !sv->host_setup);
     hvec<int64_t>().swap(r->rp);
     hvec<int32_t>().swap(r->col);
     hvec<double>().swap(r->val);
@@ -238,6 +240,7 @@ void publish(igm_server *sv, Request *r) {
   BatchSys S = r->rec;
   S.row_ptr = rebase(S.row_ptr, base);
   S.col = rebase(S.col, base);
+  S.diag_pos = rebase(S.diag_pos, base);
   S.a = rebase(S.a, base);
   S.ahat = rebase(S.ahat, base);
   S.b = rebase(S.b, base);
@@ -457,13 +460,14 @@ igm_status igm_server_create(const igm_server_config *cfg, igm_server **out) {
   if (c.reserve_cus == 0) c.reserve_cus = 8;
   if (c.reserve_cus < 0) c.reserve_cus = 0;
   if (c.max_slots < 1 || c.max_slots > 65536 || c.setup_threads < 1 || c.setup_threads > 64 || c.pool_bytes < 0 ||
-      c.stage_bytes < 0)
+      c.stage_bytes < 0 || c.host_setup < 0 || c.host_setup > 1)
     return IGM_ERR_ARG;
   igm_server *sv = new (std::nothrow) igm_server();
   if (!sv) return IGM_ERR_OOM;
   sv->block = c.block;
   sv->rows = c.rows_per_thread;
   sv->max_slots = c.max_slots;
+  sv->host_setup = c.host_setup != 0;
   igm_status st = IGM_OK;
   hipDeviceProp_t prop;
   int nb = 0, wall_khz = 0;

@@ -313,20 +313,11 @@ static igm_status gs_split_fp(int nt, int64_t n, const hvec<int64_t> &rp, const 
 
 // eqs. (dl), (dl2), (l1), (u1): Lbar = trunc(L |D|^1/2), Ubar = trunc(sgn(D)
 // |D|^1/2 U) with U unit upper (stored entries divided by the pivot).
-static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
-                               const hvec<double> &piv, bool offdiag, bool upper, HostSetup &h) {
-  h.ldiag.resize(n);
-  h.udiag.resize(n);
-  hvec<double> sq(n);
-  std::atomic<bool> zero{false};
-  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
-    for (int64_t i = lo; i < hi; ++i) {
-      if (piv[i] == 0.0 || !isfinite(piv[i])) { zero = true; return; }
-      sq[i] = sqrt(fabs(piv[i]));
-    }
-  });
-  if (zero) return IGM_ERR_ZERO_PIVOT;
-  // row offsets of the strict triangles
+// Patterns of the strict triangles of the integer factors (lptr, lcol, uptr,
+// ucol; entries in CSR order): below the diagonal when offdiag, above it too
+// when upper.
+static void factor_pattern(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col, bool offdiag,
+                           bool upper, HostSetup &h) {
   h.lptr.assign(n + 1, 0);
   h.uptr.assign(n + 1, 0);
   if (offdiag) {
@@ -347,8 +338,34 @@ static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const
     }
   }
   h.lcol.resize(h.lptr[n]);
-  h.lval.resize(h.lptr[n]);
   h.ucol.resize(h.uptr[n]);
+  if (!offdiag) return;
+  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      int64_t pl = h.lptr[i], pu = h.uptr[i];
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        if (col[e] < i) h.lcol[pl++] = col[e];
+        else if (upper && col[e] > i) h.ucol[pu++] = col[e];
+      }
+    }
+  });
+}
+
+static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
+                               const hvec<double> &piv, bool offdiag, bool upper, HostSetup &h) {
+  h.ldiag.resize(n);
+  h.udiag.resize(n);
+  hvec<double> sq(n);
+  std::atomic<bool> zero{false};
+  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      if (piv[i] == 0.0 || !isfinite(piv[i])) { zero = true; return; }
+      sq[i] = sqrt(fabs(piv[i]));
+    }
+  });
+  if (zero) return IGM_ERR_ZERO_PIVOT;
+  factor_pattern(nt, n, rp, col, offdiag, upper, h);
+  h.lval.resize(h.lptr[n]);
   h.uval.resize(h.uptr[n]);
   FirstError fe(nt);
   par_ranges(nt, n, [&](int c, int64_t lo, int64_t hi) {
@@ -364,10 +381,8 @@ static igm_status cast_factors(int nt, int64_t n, const hvec<int64_t> &rp, const
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
           int32_t j = col[e];
           if (j < i) {
-            h.lcol[pl] = j;
             h.lval[pl++] = cast_i64(h.lu[e] * sq[j], bad);
           } else if (upper && j > i) {
-            h.ucol[pu] = j;
             h.uval[pu++] = cast_i64(su * (h.lu[e] / piv[i]), bad);
           }
         }
@@ -427,7 +442,7 @@ static void level_sets(int64_t n, HostSetup &h) {
 // SELL-64: rows in slices of 64, each slice stored column-major with the width
 // of its longest row; padding entries have value 0 and point at the row itself.
 static void build_sell(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col,
-                       HostSetup &h) {
+                       HostSetup &h, bool values = true) {
   int64_t ns = (n + kSlice - 1) / kSlice;
   h.nslices = ns;
   h.sell_off.assign(ns + 1, 0);
@@ -440,8 +455,8 @@ static void build_sell(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<in
   }
   int64_t tot = h.sell_off[ns];
   h.sell_col.resize(tot);
-  h.sell_val.assign(h.nterms, hvec<int64_t>());
-  for (int l = 0; l < h.nterms; ++l) h.sell_val[l].resize(tot);
+  h.sell_val.assign(values ? h.nterms : 0, hvec<int64_t>());
+  for (int l = 0; l < (int)h.sell_val.size(); ++l) h.sell_val[l].resize(tot);
   par_ranges(nt, ns, [&](int, int64_t s0, int64_t s1) {
     for (int64_t s = s0; s < s1; ++s) {
       // written in layout order (entry k of the 64 rows, then k + 1)
@@ -452,10 +467,10 @@ static void build_sell(int nt, int64_t n, const hvec<int64_t> &rp, const hvec<in
           const int64_t e = (i < n) ? rp[i] + k : -1;
           if (i < n && e < rp[i + 1]) {
             h.sell_col[pos] = col[e];
-            for (int l = 0; l < h.nterms; ++l) h.sell_val[l][pos] = h.abar[l][e];
+            for (int l = 0; l < (int)h.sell_val.size(); ++l) h.sell_val[l][pos] = h.abar[l][e];
           } else {
             h.sell_col[pos] = (int32_t)std::min<int64_t>(i, n - 1);
-            for (int l = 0; l < h.nterms; ++l) h.sell_val[l][pos] = 0;
+            for (int l = 0; l < (int)h.sell_val.size(); ++l) h.sell_val[l][pos] = 0;
           }
         }
       }
@@ -495,6 +510,28 @@ igm_status host_setup(int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &c
     level_sets(n, h);
   }
   build_sell(nt, n, rp, col, h);
+  return IGM_OK;
+}
+
+igm_status host_structure(int64_t n, const hvec<int64_t> &rp, const hvec<int32_t> &col, const igm_policy &pol,
+                          HostSetup &h) {
+  SetupRegion region;
+  const int nt = setup_thread_count();
+  h = HostSetup();
+  if (pol.s_terms != 0 || pol.gauss_seidel || pol.two_sided) return IGM_ERR_UNSUPPORTED;
+  h.nterms = 1;
+  h.alpha[0] = 0;
+  h.diag_pos.assign(n, -1);
+  par_ranges(nt, n, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i)
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+        if (col[e] == i) h.diag_pos[i] = e;
+  });
+  if (pol.precond != IGM_PRE_NONE) {  // a missing diagonal (-1) is reported by the device, in the host's order
+    factor_pattern(nt, n, rp, col, pol.precond == IGM_PRE_ILU0, true, h);
+    if (pol.precond == IGM_PRE_ILU0) level_sets(n, h);
+  }
+  build_sell(nt, n, rp, col, h, false);
   return IGM_OK;
 }
 

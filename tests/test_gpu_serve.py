@@ -191,3 +191,64 @@ def test_requests_after_quiet_spells(orc, torch):
     stats = sv.stats()
     assert stats["submitted"] == stats["completed"] == len(reqs)
     sv.close(30000)
+
+
+def test_device_setup_equals_host_setup(orc, torch):
+    """A served request's setup values computed by its team on the device
+    (scaling, integer matrix, FP64 ILU(0), factor casts, SELL-64 values) give
+    the same solve bit for bit as the whole setup on the host, for every
+    preset; requests the device setup does not take (several matrix terms,
+    the Gauss-Seidel splitting) run with the host setup on either server."""
+    reqs = mix() + [(W.convdiff3d(9, 8, 7, seed=77), "jacobi", dict(alpha_a=24, s_terms=2)),
+                    (W.random27(8, 7, 6, seed=78), "paper_ilu", dict(gauss_seidel=1))]
+    reqs = [(r[0], r[1], r[2] if len(r) > 2 else {}) for r in reqs]
+    out = []
+    for host in (False, True):
+        sv = B.Server(host_setup=host)
+        try:
+            tickets = [sv.submit(s, p, m=30, **kw) for s, p, kw in reqs]
+            out.append([sv.wait(t, 120000) for t in tickets])
+        finally:
+            sv.close(30000)
+    for (s, p, kw), (xd, sd), (xh, sh) in zip(reqs, out[0], out[1]):
+        assert sd["status"] == sh["status"] == B.OK, s.name
+        assert sd["refinements"] == sh["refinements"] and sd["iterations"] == sh["iterations"]
+        assert np.array_equal(xd, xh), s.name
+        check(xd, sd, oracle(orc, s, p, m=30, **kw))
+
+
+def test_device_setup_errors_match_host_order(orc, torch):
+    """Setup failures found on the device come back with the status the host
+    setup (and the oracle) reports first: an all-zero row, a row without its
+    diagonal under a preconditioner, a structurally zero ILU(0) pivot, and a
+    matrix with both an all-zero row and a missing diagonal (the zero row is
+    reported first, as the host's order of steps has it)."""
+    base = W.random_dd(12, 0.3, 16)
+    cases = []
+    val = base.val.copy()
+    val[base.row_ptr[4]:base.row_ptr[5]] = 0.0
+    cases.append((W.System("zero row", base.n, base.row_ptr, base.col, val, base.b), "jacobi"))
+    # row 3 without its diagonal entry
+    keep = np.ones(len(base.col), dtype=bool)
+    rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    keep[(rows == 3) & (base.col == 3)] = False
+    rp = np.zeros(base.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows[keep], minlength=base.n), out=rp[1:])
+    nodiag = W.System("no diagonal", base.n, rp, base.col[keep], base.val[keep], base.b)
+    cases.append((nodiag, "paper_ilu"))
+    cases.append((W.from_dense(np.array([[0.0, 1.0], [1.0, 1.0]]), np.ones(2)), "paper_ilu"))
+    val = nodiag.val.copy()
+    val[nodiag.row_ptr[7]:nodiag.row_ptr[8]] = 0.0  # and an all-zero row 7
+    cases.append((W.System("zero row and no diagonal", nodiag.n, nodiag.row_ptr, nodiag.col, val, nodiag.b),
+                  "jacobi"))
+    for host in (False, True):
+        sv = B.Server(host_setup=host)
+        try:
+            tickets = [sv.submit(s, p, m=10) for s, p in cases]
+            for (s, p), t in zip(cases, tickets):
+                _, st = sv.wait(t, 60000)
+                with pytest.raises(orc.OracleError) as eo:
+                    orc.OracleSystem.from_system(s, orc.policy(p, m=10))
+                assert st["status"] == eo.value.status, (s.name, host, st["status"], eo.value.status)
+        finally:
+            sv.close(30000)
