@@ -328,4 +328,6 @@ WORKLOADS = {
     "poisson2d_64": (lambda: poisson2d(64), "paper_noprec", 30),
     "convdiff3d_64": (lambda: convdiff3d(64, seed=2), "jacobi", 50),
     "random27_1m": (lambda: random27(128, 128, 64, seed=3), "paper_ilu", 30),
+    # heavy-tailed row lengths (the SpMV row-to-lane mappings' benchmark matrix)
+    "skewed_1m": (lambda: skewed(1 << 20, seed=6), "jacobi", 30),
 }

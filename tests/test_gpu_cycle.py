@@ -341,6 +341,26 @@ def test_full_size_workload_matches_recorded_oracle_run(torch, name):
     assert hashlib.sha256(x.tobytes()).hexdigest() == gold["x_sha256"]
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 16])
+def test_full_size_skewed_solve_every_mapping(torch, lanes):
+    """The 1M-row heavy-tailed matrix (the SpMV mappings' benchmark matrix)
+    solved at full size with one thread per row over SELL-64, the merge split
+    and 16 lanes per row: each matches the oracle's recorded whole solve
+    (refinements, residual history, solution hash)."""
+    gold = _golden().get("skewed_1m")
+    if gold is None:
+        pytest.skip("no recorded oracle run")
+    gen, preset, m = W.WORKLOADS["skewed_1m"]
+    g = B.System.from_system(gen(), preset, m=m, spmv_lanes=lanes)
+    x, st = g.solve()
+    gs = g.stats()
+    assert st == B.OK and gs["relres_orig"] <= 1e-10 and gs["spmv_lanes"] == lanes
+    assert gs["refinements"] == gold["refinements"] and gs["iterations"] == gold["iterations"]
+    assert [float(v) for v in g.history()["relres_orig"]] == gold["hist_relres_orig"]
+    assert hashlib.sha256(x.tobytes()).hexdigest() == gold["x_sha256"]
+    g.close()
+
+
 ILU_SWEEP_CASES = [
     ("r27_11x9x8", lambda: W.random27(11, 9, 8, seed=31), dict(m=12)),
     ("dd_301_ragged", lambda: W.random_dd(301, 0.04, 32), dict(m=10)),

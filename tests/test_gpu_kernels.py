@@ -220,3 +220,21 @@ def test_dot_norm_many_workgroups(orc, torch, n, preset):
             n_g, ev = g.norm(wd)
             assert n_g == n_o and (ev != B.NO_EVENT) == novf, (n, preset, n_g, n_o, ev, novf)
     g.close()
+
+
+def test_spmv_full_size_every_mapping(orc, torch):
+    """The standalone integer SpMV at full size (the 1M-row heavy-tailed
+    matrix of the mapping benchmark, 7.7M entries, rows of 1 to 4,093
+    entries) with every row-to-lane mapping equals the oracle's product bit
+    for bit, with the same overflow event (none)."""
+    s = W.skewed(1 << 20, seed=6)
+    o = orc.OracleSystem.from_system(s, orc.policy("jacobi"))
+    v = np.random.default_rng(2).integers(-(1 << 30), 1 << 30, s.n)
+    zo, ev_o = o.spmv(v)
+    vd = dev(torch, v)
+    for lanes in LANES:
+        g = B.System.from_system(s, "jacobi", spmv_lanes=lanes)
+        zd = torch.zeros(s.n, dtype=torch.int64, device="cuda")
+        ev_g = g.spmv(vd, zd)
+        assert ev_g == ev_o and np.array_equal(zd.cpu().numpy(), zo), lanes
+        g.close()
