@@ -98,7 +98,7 @@ typedef struct {
   int32_t grid_blocks;  /* launch tuning: workgroups of the cycle kernel; 0 = automatic */
   int32_t phase_clock;  /* 1 = record where int-GMRES calls spend their time (igm_stats.phase_us); costs a few % */
   /* Overflow-driven shift retries allowed per solve, 0..64 (0 = none, the
-   * paper's setting; the single-system solver only). The paper reports that an
+   * paper's setting; every solver). The paper reports that an
    * auto-tuning of the operand shift was tried for the solver without
    * preconditioner (Sec. VII-D) but gives no rule; the rule here: when an
    * int-GMRES call overflows, the stage of its first event (see the event
@@ -110,14 +110,16 @@ typedef struct {
    * repeated from the same v1. Overflow in the SpMV, the preconditioner apply
    * or the rotation of g, or with the shift at its limit, ends the solve with
    * IGM_ERR_OVERFLOW as without retries. Adjusted shifts stay in the system's
-   * policy (igm_get_policy) for later solves. */
+   * policy (igm_get_policy) for later solves; in the batched and served
+   * solvers they last for the rest of that system's solve (each solve starts
+   * from the policy's shifts). */
   int32_t shift_retry;
   /* 0: scaling of eq. (eq1) (rows by Dhat, the paper's setting); 1: eq. (eq2)
    * with D1 = D2 = Dhat^(1/2) (the paper leaves D1, D2 open; this choice keeps
    * a symmetric matrix symmetric): A = D1^-1 Ahat D2^-1, b = D1^-1 bhat,
    * computed as a_ij = ahat_ij / (s_i s_j), s = sqrt(dhat); the scaled
    * residual of Fig. 1 is D1^-1 (bhat - Ahat xhat) and each correction
-   * returns through D2^-1. Single-system solver only. */
+   * returns through D2^-1. Every solver supports it. */
   int32_t two_sided;
   /* With precond = IGM_PRE_ILU0 only: 1 = build the factors from the
    * Gauss-Seidel splitting M = D + L_A instead of ILU(0) (the paper reports a
@@ -379,7 +381,7 @@ igm_status igm_batch_solve_device(igm_batch *bt, double *x_dev);
 igm_status igm_batch_solve(igm_batch *bt, double *x);
 
 /* Result of system i in the last solve: status, refinements, iterations,
- * first_ovf, relres_orig, relres_scaled, time_solve_ms (device wall time from
+ * first_ovf, shift_retries, relres_orig, relres_scaled, time_solve_ms (device wall time from
  * the start to the end of the system's solve), n, nnz, nterms, grid_blocks
  * (its team size), block_threads, rows_per_thread. */
 igm_status igm_batch_get_result(const igm_batch *bt, int32_t i, igm_stats *out);
@@ -457,7 +459,7 @@ igm_status igm_server_submit(igm_server *sv, int64_t n, const int64_t *row_ptr, 
  * n doubles, may be NULL) receives the solution, *stats (may be NULL) its
  * statistics, and the request is forgotten (a ticket is collected once).
  * Statistics of a served request: status, refinements, iterations,
- * first_ovf, relres_orig/scaled, n, nnz, grid_blocks (team size);
+ * first_ovf, shift_retries, relres_orig/scaled, n, nnz, grid_blocks (team size);
  * time_solve_ms = submission to result (latency), time_setup_ms = submission
  * to prepared, time_cycle_ms = admission to result, time_kernel_ms = device
  * time of the solve. IGM_ERR_ARG for an unknown ticket. */

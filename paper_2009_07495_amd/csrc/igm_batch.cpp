@@ -62,6 +62,7 @@ void walk_region(const HostSystem &hs, bool own_x, F &&f) {
   // values of the setup (made by the host, or by the kernel with device setup)
   f("a", sizeof(double) * nz);
   f("b", sizeof(double) * n);
+  if (hs.pol.two_sided) f("cscale", sizeof(double) * n);
   for (int l = 0; l < hs.nterms; ++l) f("sell_val", sizeof(int64_t) * sell);
   if (pre) {
     f("ldiag", sizeof(int64_t) * n);
@@ -101,6 +102,7 @@ const void *array_source(const HostSystem &hs, const char *name, int &term) {
   if (nm == "ahat") return hs.ahat.data();
   if (nm == "b") return h.b.data();
   if (nm == "bhat") return hs.bhat.data();
+  if (nm == "cscale") return h.cscale.data();
   if (nm == "diag_pos") return h.diag_pos.data();
   if (nm == "sell_off") return h.sell_off.data();
   if (nm == "sell_w") return h.sell_w.data();
@@ -131,7 +133,6 @@ igm_status prepare_system(int64_t n, const int64_t *row_ptr, const int32_t *col,
   igm_status st = check_policy(pol);
   if (st != IGM_OK) return st;
   if (pol.m > kMaxBatchM) return IGM_ERR_UNSUPPORTED;
-  if (pol.shift_retry != 0 || pol.two_sided != 0) return IGM_ERR_UNSUPPORTED;  // single-system solver only
   st = validate_csr(n, row_ptr, col, val, b);
   if (st != IGM_OK) return st;
   out.n = n;
@@ -181,6 +182,7 @@ void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
   S.b_cs_num = p.b_cs_num; S.b_cs_den = p.b_cs_den;
   S.gtol = p.gtol;
   S.tol = p.tol;
+  S.shift_retry = p.shift_retry;
   for (int l = 0; l < kMaxTerms; ++l) S.alpha[l] = h.alpha[l];
   S.device_setup = hs.device_setup ? 1 : 0;
   S.alpha_a = p.alpha_a;
@@ -201,6 +203,7 @@ void record_for(const HostSystem &hs, bool own_x, char *base, BatchSys &S) {
     else if (nm == "ahat") S.ahat = (const double *)d;
     else if (nm == "b") S.b = (const double *)d;
     else if (nm == "bhat") S.bhat = (const double *)d;
+    else if (nm == "cscale") S.cscale = (const double *)d;
     else if (nm == "diag_pos") S.diag_pos = (const int64_t *)d;
     else if (nm == "sell_off") S.sell_off = (const int64_t *)d;
     else if (nm == "sell_w") S.sell_w = (const int32_t *)d;
@@ -656,6 +659,7 @@ igm_status igm_batch_get_result(const igm_batch *bt, int32_t i, igm_stats *out) 
   out->refinements = r.refinements;
   out->iterations = r.iterations;
   out->first_ovf = r.first_ovf;
+  out->shift_retries = r.shift_retries;
   out->relres_orig = r.relres_orig;
   out->relres_scaled = r.relres_scaled;
   out->time_solve_ms = r.t_end >= r.t_begin ? (double)(r.t_end - r.t_begin) * bt->wall_us_per_tick / 1000.0 : 0.0;

@@ -113,6 +113,17 @@ __device__ __forceinline__ double team_norm1(Team &tm, TeamShared &sh, const dou
 // overflow events travel through the max-reductions as 2^53 - code (0 = none)
 constexpr int64_t kEvBias = (int64_t)1 << 53;
 
+// A team's working shifts: the policy's, adjusted by overflow retries
+// (adjust_shift_fields). Kept wavefront-uniform so they stay in scalar registers.
+struct CallShifts {
+  int32_t b_dot, b_axpy, b_norm, b_div_num, b_div_den, b_rot, b_tmp, b_cs_num, b_cs_den;
+  __device__ void uniform() {
+    int32_t *f[] = {&b_dot, &b_axpy, &b_norm, &b_div_num, &b_div_den, &b_rot, &b_tmp, &b_cs_num, &b_cs_den};
+#pragma unroll
+    for (int32_t *p : f) *p = __builtin_amdgcn_readfirstlane(*p);
+  }
+};
+
 }  // namespace
 
 // minimum wavefronts per SIMD the compiler must allow, which bounds the
@@ -277,10 +288,17 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       team_norm2<BLOCK, R>(tm, tsh, xa, xb, nb, nbh, mua, mub);
     }
 
-    int status = IGM_NOT_CONVERGED, refinements = 0, iterations = 0, jstar_last = -1;
+    int status = IGM_NOT_CONVERGED, refinements = 0, iterations = 0, jstar_last = -1, retries = 0;
+    CallShifts sf{S.b_dot, S.b_axpy, S.b_norm, S.b_div_num, S.b_div_den, S.b_rot, S.b_tmp, S.b_cs_num, S.b_cs_den};
+    sf.uniform();
+    // an int-GMRES call that overflows and can adjust a shift is repeated: the
+    // refinement starts again from the same x, so the residual step rebuilds
+    // the same v1 bit for bit
+    bool again = false;
     int64_t first_ovf = kNoEvent;
     double ro = 0.0, rs = 0.0;
-    for (int kref = 0;; ++kref) {
+    for (int kref = 0;; kref += again ? 0 : 1) {
+      again = false;
       if (tsh.abort) break;
       if (setup_status != IGM_OK) { status = setup_status; break; }
       // integer matrix terms of this refinement (k = kref + 1): Abar_0 and s(k) corrections, eq. (AA)
@@ -292,8 +310,11 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
         const int64_t row = g0 + k * TB;
         r[k] = 0.0;
         rh[k] = 0.0;
-        if (row < n)
+        if (row < n) {
           residual_row(S.row_ptr[row], S.row_ptr[row + 1], S.col, S.a, S.ahat, x, S.b[row], S.bhat[row], r[k], rh[k]);
+          // eq. (eq2): x holds xhat and the scaled residual is D1^-1 (bhat - Ahat xhat)
+          if (S.cscale) r[k] = rh[k] / S.cscale[row];
+        }
       }
       double nr, nrh, gamma, mu_rh;
       team_norm2<BLOCK, R>(tm, tsh, r, rh, nr, nrh, gamma, mu_rh);
@@ -401,9 +422,9 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       }
       team_barrier(tm, tsh);  // v1 visible to the team
 
-      const int sh_dot = df - S.b_dot;
+      const int sh_dot = df - sf.b_dot;
       auto fin_dot = [&](int64_t Sv, bool &o) { return asr(Sv, sh_dot); };
-      auto fin_norm = [&](int64_t Sv, bool &o) { return shl(isqrt64(Sv), S.b_norm, o); };
+      auto fin_norm = [&](int64_t Sv, bool &o) { return shl(isqrt64(Sv), sf.b_norm, o); };
       auto record = [&](int64_t code) { atomicMin(&sh_ovf, (long long)code); };
 
       int64_t w[R];
@@ -411,14 +432,14 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       bool lucky = false;
       // earlier rotation i (1-based) on (carry, col[i]); thread kGivensThread only
       auto rotate = [&](int j, int i) {
-        const int64_t x0 = asr(carry, S.b_rot), x1 = asr(col[i], S.b_rot);
+        const int64_t x0 = asr(carry, sf.b_rot), x1 = asr(col[i], sf.b_rot);
         const int64_t c = sc[i - 1], s = ss[i - 1];
         bool o = false;
         const int64_t ms = subc(0, s, o);
         const int64_t top = addc(mulw(x0, c, o), mulw(x1, s, o), o);
         const int64_t bot = addc(mulw(x0, ms, o), mulw(x1, c, o), o);
-        col[i - 1] = asr(top, df - S.b_rot);
-        carry = asr(bot, df - S.b_rot);
+        col[i - 1] = asr(top, df - sf.b_rot);
+        carry = asr(bot, df - sf.b_rot);
         if (o) record(ev_code(j, 6, i));
       };
       // radius, new rotation, rotation of g and H update for column j on (carry, hn); thread kGivensThread only
@@ -426,20 +447,20 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
         col[j - 1] = carry;
         col[j] = hn;
         bool o = false;  // rotation radius t_mp
-        const int64_t p0 = asr(col[j - 1], S.b_tmp), p1 = asr(col[j], S.b_tmp);
+        const int64_t p0 = asr(col[j - 1], sf.b_tmp), p1 = asr(col[j], sf.b_tmp);
         const int64_t ssq = addc(sqrc(p0, o), sqrc(p1, o), o);
-        const int64_t tmp = shl(isqrt64(ssq), S.b_tmp, o);
+        const int64_t tmp = shl(isqrt64(ssq), sf.b_tmp, o);
         if (o) record(ev_code(j, 7, 0));
-        const int64_t den2 = asr(tmp, S.b_cs_den);  // new rotation c_j, s_j
+        const int64_t den2 = asr(tmp, sf.b_cs_den);  // new rotation c_j, s_j
         int stop = 0;
         if (den2 == 0) {  // new rotation: zero denominator
           sh_jstar = j - 1;
           stop = 1;
         } else {
           bool oc = false;
-          const int e2 = df - S.b_cs_num - S.b_cs_den;
-          const int64_t cj = normalize_elem(col[j - 1], den2, S.b_cs_num, e2, oc);
-          const int64_t sj = normalize_elem(col[j], den2, S.b_cs_num, e2, oc);
+          const int e2 = df - sf.b_cs_num - sf.b_cs_den;
+          const int64_t cj = normalize_elem(col[j - 1], den2, sf.b_cs_num, e2, oc);
+          const int64_t sj = normalize_elem(col[j], den2, sf.b_cs_num, e2, oc);
           if (oc) record(ev_code(j, 8, 0));
           sc[j - 1] = cj;
           ss[j - 1] = sj;
@@ -547,7 +568,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           bool o = false;
 #pragma unroll
           for (int k = 0; k < R; ++k)  // inner product: only w is shifted
-            if (k < nk) acc.add(mulw(asr(w[k], S.b_dot), vv[k], o));
+            if (k < nk) acc.add(mulw(asr(w[k], sf.b_dot), vv[k], o));
           if (o) record(ev_code(j, 3, 2 * (i - 1)));
           int64_t vnext[R];
           if (i < j) {
@@ -570,11 +591,11 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
             if (i == 1) carry = h;
           }
           // update of w: only h is shifted
-          const int64_t hs = asr(h, S.b_axpy);
+          const int64_t hs = asr(h, sf.b_axpy);
           bool ou = false;
 #pragma unroll
           for (int k = 0; k < R; ++k)
-            if (k < nk) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - S.b_axpy), ou);
+            if (k < nk) w[k] = subc(w[k], asr(mulw(hs, vv[k], ou), df - sf.b_axpy), ou);
           if (ou) record(ev_code(j, 3, 2 * (i - 1) + 1));
           if (i < j) {
 #pragma unroll
@@ -589,7 +610,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
           bool o = false;
 #pragma unroll
           for (int k = 0; k < R; ++k)
-            if (k < nk) acc.add(sqrc(asr(w[k], S.b_norm), o));
+            if (k < nk) acc.add(sqrc(asr(w[k], sf.b_norm), o));
           if (o) record(ev_code(j, 4, 0));
           bool os = false;
           hn = team_sum<BLOCK>(tm, acc, tsh, fin_norm, [&] {
@@ -599,16 +620,16 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
         }
         IGM_TICK(3)
         // ---- normalisation v_{j+1} = w / h_{j+1,j}
-        const int64_t den = asr(hn, S.b_div_den);
+        const int64_t den = asr(hn, sf.b_div_den);
         lucky = den == 0;
         if (!lucky) {
           int64_t *__restrict__ vn = S.V + (size_t)j * ldv;
-          const int e = df - S.b_div_num - S.b_div_den;
+          const int e = df - sf.b_div_num - sf.b_div_den;
           bool ov = false;
 #pragma unroll
           for (int k = 0; k < R; ++k) {
             const int64_t row = g0 + k * TB;
-            if (row < n) vn[row] = normalize_elem(w[k], den, S.b_div_num, e, ov);
+            if (row < n) vn[row] = normalize_elem(w[k], den, sf.b_div_num, e, ov);
           }
           if (ov) record(ev_code(j, 5, 0));
         }
@@ -629,6 +650,14 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
         if (tid == 0 && sh_ovf != (long long)kNoEvent) e1[0] = (unsigned long long)(kEvBias - (int64_t)sh_ovf);
         team_reduce<BLOCK, 1, true>(tm, tsh, e1);
         ev = e1[0] ? kEvBias - (int64_t)e1[0] : kNoEvent;
+      }
+      if (tsh.abort) break;
+      // every thread of every member takes the same decision from the same event
+      if (ev != kNoEvent && retries < S.shift_retry && adjust_shift_fields(sf, df, ev)) {
+        retries += 1;
+        sf.uniform();
+        again = true;
+        continue;
       }
       const int js = sh_jstar;
       refinements += 1;
@@ -654,7 +683,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
         if (row < n) {
           double acc = 0.0;
           for (int i = 0; i < js; ++i) acc = acc + sy[i] * ldexp((double)S.V[(size_t)i * ldv + row], -df);
-          x[row] = x[row] + gamma * acc;
+          x[row] = x[row] + gamma * (S.cscale ? acc / S.cscale[row] : acc);
         }
       }
       team_barrier(tm, tsh);  // x visible to the team
@@ -678,6 +707,7 @@ __global__ __launch_bounds__(BLOCK, batch_waves<BLOCK>()) void k_batch(BatchArgs
       res.iterations = iterations;
       res.jstar = jstar_last;
       res.first_ovf = first_ovf;
+      res.shift_retries = retries;
       res.relres_orig = ro;
       res.relres_scaled = rs;
       res.t_begin = t_begin;

@@ -47,6 +47,13 @@ struct BatchSys {
   int32_t device_setup;
   int32_t alpha_a;
   const int64_t *diag_pos;
+  // eq. (eq2) (two-sided scaling): s_i = sqrt(dhat_i), null for eq. (eq1);
+  // the scaled residual is rhat_i / s_i and the update adds gamma x^(k)_i / s_i
+  const double *cscale;
+  // int-GMRES calls that overflow are repeated from the same v1 with adjusted
+  // shifts, at most shift_retry times per solve (igm_policy.shift_retry)
+  int32_t shift_retry;
+  int32_t pad_;
   int64_t *V;                    // (m+1) x ldv basis
   int64_t *zbuf, *wbuf;          // ILU: SpMV output and preconditioned vector
   double *fbuf;                  // ILU: FP64 substitution of the start step
@@ -69,6 +76,8 @@ struct BatchSys {
 struct BatchResult {
   int32_t status, refinements, iterations, jstar;
   int64_t first_ovf;
+  int32_t shift_retries;  // calls repeated with adjusted shifts
+  int32_t pad_;
   double relres_orig, relres_scaled;
   uint64_t t_begin, t_end;  // device wall clock (start and end of the solve)
   // wall-clock ticks of the first member's thread 0 per phase: 0 SpMV +

@@ -6,6 +6,8 @@
 // would report:
 //   1. eq. (eq3) / (eq1): dhat_i = max_j |ahat_ij| 2^-alpha_a; a = ahat / dhat_i,
 //      b = bhat / dhat_i (IGM_ERR_SINGULAR_ROW, IGM_ERR_RANGE: the first row);
+//      two-sided, eq. (eq2): s_i = sqrt(dhat_i) for every row first, then
+//      a_ij = ahat_ij / (s_i s_j), b_i = bhat_i / s_i;
 //   2. eq. (A) with one term: Abar = trunc(A), written straight into the
 //      SELL-64 layout (IGM_ERR_RANGE);
 //   3. Sec. VI-A: the FP64 ILU(0) of A in place (rows of one level of the
@@ -77,11 +79,23 @@ __device__ igm_status device_setup(Team &tm, TeamShared &tsh, const BatchSys &S,
     if (mu == 0.0) { fail(1, i, IGM_ERR_SINGULAR_ROW); continue; }
     const double d = ldexp(mu, -S.alpha_a);
     if (d == 0.0 || !isfinite(d)) { fail(1, i, IGM_ERR_RANGE); continue; }
+    if (S.cscale) {
+      const_cast<double *>(S.cscale)[i] = sqrt(d);
+      continue;
+    }
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) a[e] = S.ahat[e] / d;
     b[i] = S.bhat[i] / d;
   }
   if ((st = team_err()) != IGM_OK) return st;
   team_barrier(tm, tsh);
+  if (S.cscale) {  // every s_j is in place
+    const double *__restrict__ cs = S.cscale;
+    for (int64_t i = g0; i < n; i += TB) {
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) a[e] = S.ahat[e] / (cs[i] * cs[col[e]]);
+      b[i] = S.bhat[i] / cs[i];
+    }
+    team_barrier(tm, tsh);
+  }
 
   // 2. the integer matrix in the SELL-64 layout: thread t of the team takes
   // lane t % 64 of slices t / 64, t / 64 + TB / 64, ...

@@ -198,12 +198,46 @@ igm_status check_policy(const igm_policy &p);
 // computed on the device: diagonal positions (-1 where a row has none; the
 // device reports that, after the errors the host setup finds first), the
 // factor patterns and level sets, the SELL-64 offsets, widths and columns. One matrix term, no
-// Gauss-Seidel splitting, one-sided scaling (else IGM_ERR_UNSUPPORTED).
+// Gauss-Seidel splitting (else IGM_ERR_UNSUPPORTED).
 igm_status host_structure(int64_t n, const hvec<int64_t> &row_ptr, const hvec<int32_t> &col, const igm_policy &pol,
                           HostSetup &out);
 // Overflow-driven shift retry (igm_policy.shift_retry): adjusts the shift that
-// the stage of overflow event `code` names; false if none can change.
-bool adjust_shifts(igm_policy &p, int64_t code);
+// the stage of overflow event `code` names, in any record with the shift
+// fields of igm_policy (the policy on the host, a team's working copy on the
+// device); false if none can change. A right shift taken before a product
+// grows by 4, at most to df (more bits dropped, a smaller product); a
+// division's exponents shrink by 4, the numerator's first (a smaller
+// quotient). Event codes: stage in bits 16-23, sub-stage in bits 0-15.
+template <class P>
+__host__ __device__ inline bool adjust_shift_fields(P &p, int32_t df, int64_t code) {
+  // each case names its field directly (no pointer chosen at run time, so a
+  // device copy of the fields stays in registers)
+  auto raise = [df](int32_t &b) {
+    if (b >= df) return false;
+    b = b + 4 < df ? b + 4 : df;
+    return true;
+  };
+  auto lower = [](int32_t &num, int32_t &den) {
+    if (num > 0) {
+      num = num > 4 ? num - 4 : 0;
+      return true;
+    }
+    if (den <= 0) return false;
+    den = den > 4 ? den - 4 : 0;
+    return true;
+  };
+  if (code == INT64_MAX) return false;
+  switch ((int)((code >> 16) & 0xFF)) {
+    case 3: return (code & 1) == 0 ? raise(p.b_dot) : raise(p.b_axpy);  // inner product (even sub) / update
+    case 4: return raise(p.b_norm);                                      // norm of w
+    case 5: return lower(p.b_div_num, p.b_div_den);                      // normalisation
+    case 6: return raise(p.b_rot);                                       // earlier rotations
+    case 7: return raise(p.b_tmp);                                       // rotation radius
+    case 8: return lower(p.b_cs_num, p.b_cs_den);                        // new rotation
+    default: return false;                                               // SpMV, preconditioner, rotation of g
+  }
+}
+inline bool adjust_shifts(igm_policy &p, int64_t code) { return adjust_shift_fields(p, p.df, code); }
 // Rows of the largest level set of the ILU sweeps (0 without ILU).
 int32_t max_level_rows(const HostSetup &h);
 // Threads per workgroup that take part in the counter-driven ILU sweeps of a

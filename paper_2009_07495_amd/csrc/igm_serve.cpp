@@ -245,6 +245,7 @@ void publish(igm_server *sv, Request *r) {
   S.ahat = rebase(S.ahat, base);
   S.b = rebase(S.b, base);
   S.bhat = rebase(S.bhat, base);
+  S.cscale = rebase(S.cscale, base);
   S.sell_off = rebase(S.sell_off, base);
   S.sell_w = rebase(S.sell_w, base);
   S.sell_col = rebase(S.sell_col, base);
@@ -420,6 +421,7 @@ void fill_stats(const igm_server *sv, const Request *r, igm_stats *out) {
   out->refinements = r->res.refinements;
   out->iterations = r->res.iterations;
   out->first_ovf = r->res.first_ovf;
+  out->shift_retries = r->res.shift_retries;
   out->relres_orig = r->res.relres_orig;
   out->relres_scaled = r->res.relres_scaled;
   out->time_solve_ms = ms_between(r->t_submit, r->t_done);

@@ -83,33 +83,6 @@ igm_status check_policy(const igm_policy &p) {
   return IGM_OK;
 }
 
-bool adjust_shifts(igm_policy &p, int64_t code) {
-  if (code == INT64_MAX) return false;
-  const int stage = (int)((code >> 16) & 0xFF);
-  // a right shift applied before a product: more bits dropped, smaller product
-  auto raise = [&](int32_t &b) {
-    if (b >= p.df) return false;
-    b = std::min(b + 4, p.df);
-    return true;
-  };
-  // a division's exponents (numerator first): a smaller quotient
-  auto lower = [](int32_t &num, int32_t &den) {
-    int32_t &e = num > 0 ? num : den;
-    if (e <= 0) return false;
-    e = std::max(e - 4, 0);
-    return true;
-  };
-  switch (stage) {
-    case 3: return (code & 1) == 0 ? raise(p.b_dot) : raise(p.b_axpy);  // inner product (even sub) / update
-    case 4: return raise(p.b_norm);                                      // norm of w
-    case 5: return lower(p.b_div_num, p.b_div_den);                      // normalisation
-    case 6: return raise(p.b_rot);                                       // earlier rotations
-    case 7: return raise(p.b_tmp);                                       // rotation radius
-    case 8: return lower(p.b_cs_num, p.b_cs_den);                        // new rotation
-    default: return false;                                               // SpMV, preconditioner, rotation of g
-  }
-}
-
 // C cast to int64 with a range check (|y| < 2^63).
 static inline int64_t cast_i64(double y, bool &bad) {
   if (!(y >= -9223372036854775808.0 && y < 9223372036854775808.0)) {
@@ -518,7 +491,7 @@ igm_status host_structure(int64_t n, const hvec<int64_t> &rp, const hvec<int32_t
   SetupRegion region;
   const int nt = setup_thread_count();
   h = HostSetup();
-  if (pol.s_terms != 0 || pol.gauss_seidel || pol.two_sided) return IGM_ERR_UNSUPPORTED;
+  if (pol.s_terms != 0 || pol.gauss_seidel) return IGM_ERR_UNSUPPORTED;
   h.nterms = 1;
   h.alpha[0] = 0;
   h.diag_pos.assign(n, -1);

@@ -235,10 +235,56 @@ def test_shift_retry_matches_oracle(orc, torch, retries):
     assert np.array_equal(x.cpu().numpy(), xo)
 
 
-def test_shift_retry_not_in_batches(torch):
-    with pytest.raises(B.IgmError) as e:
-        B.Batch([W.poisson2d(16)], "paper_noprec", m=10, shift_retry=4)
-    assert e.value.status == B.ERR_UNSUPPORTED
+def check_batched_result(r, x, xo, so, name):
+    for k in ("status", "refinements", "iterations", "first_ovf", "shift_retries", "relres_orig", "relres_scaled"):
+        assert r[k] == so[k], (name, k, r[k], so[k])
+    assert np.array_equal(x, xo), (name, np.abs(x - xo).max())
+
+
+def retry_systems():
+    """Systems whose calls overflow with all product shifts at 0; the retries
+    each needs differ (12 to 20), so the teams' shifts diverge; the 3000-row
+    one is shared by two workgroups at 2048 rows each."""
+    return [W.poisson2d(32), W.poisson2d(45, 37), W.poisson2d(7, 5), W.poisson2d(60, 50),
+            W.from_dense(np.array([[2.5]]), np.array([-1.5]))]
+
+
+@pytest.mark.parametrize("retries,shape", [(40, (256, 8)), (3, (256, 8)), (40, (1024, 4))])
+def test_shift_retry_batched_matches_oracle(orc, torch, retries, shape):
+    """Overflow-driven shift retries inside the batched kernel: each system's
+    team adjusts its own working shifts and repeats the call; every system
+    returns the oracle's status, retry count, event code, counts and x bit for
+    bit, when the retries repair the overflow (40) and when the limit ends
+    the solve (3)."""
+    systems = retry_systems()
+    kw = dict(ZERO_SHIFTS, shift_retry=retries, m=30)
+    refs = [orc.OracleSystem.from_system(s, orc.policy("paper_noprec", **kw)).solve() for s in systems]
+    assert all(so["shift_retries"] > 0 for _, so in refs)
+    assert retries < 12 or len({so["shift_retries"] for _, so in refs}) > 1
+    bt = B.Batch(systems, "paper_noprec", **kw)
+    assert bt.set_shape(*shape) == B.OK
+    if shape == (256, 8):
+        assert bt.result(3)["grid_blocks"] == 2
+    x, _ = bt.solve()
+    for i, (s, (xo, so)) in enumerate(zip(systems, refs)):
+        check_batched_result(bt.result(i), x[bt.offsets[i]:bt.offsets[i + 1]], xo, so, s.name)
+    bt.close()
+
+
+@pytest.mark.parametrize("retries", [40, 3])
+def test_shift_retry_served_matches_oracle(orc, torch, retries):
+    """The same retries for served requests, solved side by side."""
+    systems = retry_systems()
+    kw = dict(ZERO_SHIFTS, shift_retry=retries, m=30)
+    sv = B.Server()
+    try:
+        tickets = [sv.submit(s, "paper_noprec", **kw) for s in systems]
+        out = [sv.wait(t, 120000) for t in tickets]
+    finally:
+        sv.close(30000)
+    for s, (x, st) in zip(systems, out):
+        xo, so = orc.OracleSystem.from_system(s, orc.policy("paper_noprec", **kw)).solve()
+        check_batched_result(st, x, xo, so, s.name)
 
 
 @pytest.mark.parametrize("preset,gen", [("paper_noprec", lambda: W.poisson2d(37, 29)),
@@ -257,9 +303,37 @@ def test_two_sided_scaling_matches_oracle(orc, torch, preset, gen):
     assert np.array_equal(h["relres_orig"], so["hist_relres_orig"])
     assert np.array_equal(h["relres_scaled"], so["hist_relres_scaled"])
     assert np.array_equal(x, xo)
-    with pytest.raises(B.IgmError) as e:
-        B.Batch([s], preset, two_sided=1)
-    assert e.value.status == B.ERR_UNSUPPORTED
+
+
+TWO_SIDED = [("paper_noprec", [lambda: W.poisson2d(37, 29), lambda: W.poisson2d(70, 60)]),
+             ("jacobi", [lambda: W.convdiff3d(14, 13, 12, seed=33), lambda: W.convdiff2d(91, 77, seed=35)]),
+             ("paper_ilu", [lambda: W.random27(12, 11, 10, seed=34), lambda: W.random27(20, 20, 12, seed=36)])]
+
+
+@pytest.mark.parametrize("preset,gens", TWO_SIDED)
+def test_two_sided_scaling_batched_and_served(orc, torch, preset, gens):
+    """Eq. (eq2) in the batched kernel (the second system of each pair is
+    shared by several workgroups) and in the served solver, with the scaling
+    computed by the request's team on the device and on the host: every
+    system returns the oracle's x bit for bit."""
+    systems = [g() for g in gens]
+    refs = [orc.OracleSystem.from_system(s, orc.policy(preset, two_sided=1)).solve() for s in systems]
+    bt = B.Batch(systems, preset, two_sided=1)
+    assert bt.set_shape(256, 8) == B.OK
+    assert bt.result(1)["grid_blocks"] > 1
+    x, _ = bt.solve()
+    for i, (s, (xo, so)) in enumerate(zip(systems, refs)):
+        assert so["status"] == B.OK
+        check_batched_result(bt.result(i), x[bt.offsets[i]:bt.offsets[i + 1]], xo, so, s.name)
+    bt.close()
+    for host in (False, True):
+        sv = B.Server(host_setup=host)
+        try:
+            out = [sv.wait(t, 120000) for t in [sv.submit(s, preset, two_sided=1) for s in systems]]
+        finally:
+            sv.close(30000)
+        for s, (xs, st), (xo, so) in zip(systems, out, refs):
+            check_batched_result(st, xs, xo, so, (s.name, host))
 
 
 @pytest.mark.parametrize("gen", [lambda: W.convdiff2d(91, 77, seed=41), lambda: W.random27(20, 20, 12, seed=42),
