@@ -238,6 +238,13 @@ def single(torch, B, W, workload: str, steps: int, warmup: int, grid_blocks: int
     ph = g.stats()["phase_us"]
     out["cycle_phases_us"] = dict(zip(["spmv_precond", "mgs_local", "mgs_grid_wait", "norm", "normalize",
                                        "givens", "step_barrier", "total"], [round(v, 1) for v in ph]))
+    # the basis streamed by the local Gram-Schmidt work of that call (workgroup
+    # 0's clock): steps (steps + 1) / 2 columns of n words
+    last_steps = int([j for j in g.history()["jstar"] if j >= 0][-1])
+    mgs_bytes = 8 * sysm.n * last_steps * (last_steps + 1) / 2
+    out["mgs_local_stream"] = {"steps": last_steps, "bytes": mgs_bytes,
+                               "gb_s": mgs_bytes / (ph[1] * 1e-6) / 1e9 if ph[1] > 0 else None,
+                               "frac": mgs_bytes / (ph[1] * 1e-6) / 1e9 / HBM_PEAK_GBS if ph[1] > 0 else None}
     g.close()
     return out, sysm, preset, m
 
@@ -302,6 +309,7 @@ def main():
         "stream_copy": copy,
         "paper_context": head["paper_context"],
         "cycle_phases_us": head["cycle_phases_us"],
+        "mgs_local_stream": head["mgs_local_stream"],
     }
     if not args.no_second and args.workload != "convdiff3d_64":
         progress("single-system solver: convdiff3d_64")
@@ -495,6 +503,35 @@ def served(B, W, count: int, distinct: int, rate: float = 2000.0, plain_sample: 
             "speedup_vs_plain_loop": cap / plain_rate}
 
 
+def dot_by_length(torch, B, rng) -> dict:
+    """The inner-product kernel (k_reduce, the kernel of igm_dot and
+    igm_norm) on two distinct int64 vectors of 2^20 to 2^26 words, through
+    the allocation-free entry point (whose launch also runs a one-thread
+    clearing kernel): HIP events on the stream around 50 back-to-back calls.
+    At 2^20 words (16.8 MB) the fixed cost of a launch and of the completion
+    ticket (about 5 us) dominates; from 2^24 words on the kernel streams."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for lg in (20, 22, 24, 26):
+        n = 1 << lg
+        w = torch.from_numpy(rng.integers(-(1 << 30), 1 << 30, n)).cuda()
+        v = torch.from_numpy(rng.integers(-(1 << 30), 1 << 30, n)).cuda()
+        res = torch.zeros(2, dtype=torch.int64, device="cuda")
+        for _ in range(5):
+            assert B.igm_reduce_noalloc(0, n, w, v, 0, 30, res, stream) == B.OK
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(50):
+            B.igm_reduce_noalloc(0, n, w, v, 0, 30, res, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1000.0 / 50
+        out[str(n)] = {"us_per_call": us, "bytes": 16 * n, "gb_s": 16 * n / us / 1e3,
+                       "frac": 16 * n / us / 1e3 / HBM_PEAK_GBS}
+        del w, v, res
+    return out
+
+
 def kernel_rates(torch, B, W) -> dict:
     """Standalone SpMV and Gram-Schmidt inner-product kernels (Fig. 2), timed
     with HIP events around the kernels: the SpMV with each row-to-lane mapping
@@ -537,9 +574,12 @@ def kernel_rates(torch, B, W) -> dict:
                                             relres=gs["relres_orig"], x_sha256=hashlib.sha256(x.tobytes()).hexdigest())
             if wl == "random27_1m" and lanes == 1:
                 res["spmv"] = dict(row["lanes"]["1"], bytes=byts, workload=f"random27 n={n} nnz={nnz}")
-                dms = med_ms(g, lambda: g.dot(v, v))  # Q30 words: no product overflows
+                w2 = torch.from_numpy(rng.integers(-(1 << 30), 1 << 30, n)).cuda()
+                dms = med_ms(g, lambda: g.dot(w2, v))  # Q30 words: no product overflows
                 res["dot"] = {"ms": dms, "gb_s": 16 * n / dms / 1e6, "frac": 16 * n / dms / 1e6 / HBM_PEAK_GBS,
-                              "bytes": 16 * n, "workload": f"random27 n={n}"}
+                              "bytes": 16 * n, "workload": f"random27 n={n}, two distinct vectors"}
+                res["dot_by_length"] = dot_by_length(torch, B, rng)
+                del w2
             g.close()
         for key, lanes in (("auto", 0), ("measured", -1)):
             g = B.System.from_system(sysm, "jacobi", m=2, spmv_lanes=lanes)

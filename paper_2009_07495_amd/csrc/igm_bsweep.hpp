@@ -16,8 +16,10 @@
 // `to` is set and the rows are computed from whatever values are present, so
 // the sweep always ends.
 //
-// The waits of a level are taken by wavefront 0, one record per lane; what
-// each dependency block was last seen to have finished is cached in LDS
+// Wavefront 0 of the workgroup is a helper: it takes the waits of a level,
+// one record per lane, stores the finished levels and publishes the
+// progress; what each dependency block was last seen to have finished is
+// cached in LDS
 // (`seen`), so a requirement already met costs no memory access. The values
 // other blocks need go out with device-coherent stores and come in with
 // device-coherent loads, so no cache write-back or invalidation is needed.
@@ -62,290 +64,29 @@ __device__ __forceinline__ int64_t tdiv_magic(int64_t a, int64_t d, uint64_t m, 
   return neg ? (int64_t)(0ull - q) : (int64_t)q;
 }
 
-// The first-pass row of one level held in registers by a lane: stage 1
-// (issued two levels ahead: everything addressed by the position alone) and
-// stage 2 (one level ahead: the right-hand side and, when the waits of the
-// level are already known to be met, the values of other blocks).
-template <int PRE, class VT, class TX>
-struct SweepRow {
-  bool act;
-  int lp;       // position inside the block
-  int len;      // entries
-  int64_t e0;   // slot of entry 0; entry k at e0 + k * cnt
-  int32_t cnt;  // rows of the level
-  int32_t row;
-  int64_t dg;   // the diagonal (as a divisor: mag, sh)
-  uint64_t mag;
-  int32_t sh;
-  TX rhs;
-  bool xok;     // x holds the values of the entries from other blocks
-  int32_t c[PRE];
-  VT v[PRE];
-  TX x[PRE];
-};
-
-// One sweep by the whole grid. FP = false: integer values (TX = int64_t),
-// dst = tdiv(src - strict part, diagonal); FP = true: doubles, G must be 1.
-// `lds` holds sweep_lds_bytes(S, max_levels) bytes: the block's values, its
-// level table (entry starts, offsets), a window of its wait records, the
-// cache of what each dependency block was seen to have finished, and two
-// flags. The level table and the records are copied there when a block
-// starts, so nothing on the path from one level to the next reads global
-// memory except the values other blocks computed. Must be called by every
-// thread of every workgroup (BLOCK threads each).
-//
-// Per level L of a block: compute L from the registers; publish level L - 1
-// (this wavefront's stores of it have had a whole level to complete, so the
-// wait is short); issue stage 2 of L + 1 and stage 1 of L + 2; store L (LDS
-// and global); wavefront 0 takes the waits of L + 1 and checks from the cache
-// whether those of L + 2 are already met; one workgroup barrier. Only the
-// in-block values come from LDS on the critical path; rows of a level beyond
-// the first pass of BLOCK / G rows are loaded when computed.
-template <int BLOCK, int G, bool FP, class TX>
-__device__ __forceinline__ void block_sweep(const BlockSweepArgs &b, const TX *src, TX *dst, char *lds, bool &ovf,
-                                            bool &to) {
-  static_assert(BLOCK % 64 == 0 && G >= 1 && G <= 16 && (G & (G - 1)) == 0, "lanes per row");
-  static_assert(!FP || G == 1, "the FP64 substitution sums each row in CSR order");
-  constexpr int RPP = BLOCK / G;      // rows per pass
-  constexpr int NW = BLOCK / 64;      // wavefronts: each adds one to the progress word per level
-  constexpr int PRE = G >= 16 ? 1 : 16 / G;  // entries per lane held in registers
-  using VT = typename std::conditional<FP, double, int64_t>::type;
-  using Row = SweepRow<PRE, VT, TX>;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int rs = tid / G, gl = tid % G;
-  const int klv = b.max_levels + 1;
-  TX *vals = (TX *)lds;
-  int64_t *levent = (int64_t *)(lds + 8 * (size_t)b.S);
-  int32_t *lvoff = (int32_t *)(levent + klv);
-  WaitRec *recs = (WaitRec *)((char *)lvoff + (4 * (size_t)klv + 15) / 16 * 16);
-  unsigned *seen = (unsigned *)(recs + kRecWindow);
-  int *ready = (int *)(seen + kSeenSlots);
-
-  for (int q = blockIdx.x; q < b.nb; q += gridDim.x) {
-    const int64_t q0 = (int64_t)q * b.S;
-    const int lb = b.lvbase[q];
-    const int nl = b.lvbase[q + 1] - lb - 1;
-    unsigned *prog = b.prog + (int64_t)q * kLevStride;
-    // wavefront 0: the next wait record, and the records held in `recs`
-    int wr = b.wbase[q], win_lo = wr, win_hi = wr;
-    const int we = b.wbase[q + 1];
-    for (int i = tid; i <= nl; i += BLOCK) {
-      lvoff[i] = b.lvoff[lb + i];
-      levent[i] = b.levent[lb + i];
-    }
-
-    // stage 1 of pass `pass` of level L for this lane
-    auto stage1 = [&](int L, int pass, Row &r) {
-      const int p0 = lvoff[L], p1 = lvoff[L + 1];
-      r.cnt = p1 - p0;
-      const int i = pass * RPP + rs;
-      r.act = p0 + i < p1;
-      r.lp = p0 + i;
-      r.xok = false;
-      r.len = 0;
-      if (!r.act) return;
-      const int64_t lev0 = levent[L];
-      const int width = (int)((levent[L + 1] - lev0) / r.cnt);
-      const int64_t pos = q0 + r.lp;
-      r.row = b.prow[pos];
-      r.len = b.plen[pos];
-      r.dg = b.pdiag[pos];
-      if constexpr (!FP) {
-        r.mag = b.pmag[pos];
-        r.sh = b.pshift[pos];
-      }
-      r.e0 = lev0 + i;
-#pragma unroll
-      for (int j = 0; j < PRE; ++j) {
-        const int k = gl + j * G;
-        if (k < width) {  // slots past the row's length are padding of the level: readable
-          const int64_t e = r.e0 + (int64_t)k * r.cnt;
-          r.c[j] = b.ecode[e];
-          if constexpr (FP) r.v[j] = b.evalf[e];
-          else r.v[j] = b.eval[e];
-        }
-      }
-    };
-    // stage 2: the right-hand side, and the values of other blocks if the
-    // level's waits are met (`met`)
-    auto stage2 = [&](Row &r, bool met) {
-      if (!r.act) return;
-      r.rhs = ld_coh(src + r.row);
-      if (!met) return;
-#pragma unroll
-      for (int j = 0; j < PRE; ++j) {
-        const int k = gl + j * G;
-        if (k < r.len && r.c[j] < 0) r.x[j] = ld_coh(dst + (-(int64_t)r.c[j] - 1));
-      }
-      r.xok = true;
-    };
-    // the row's value: in-block values from LDS, others from registers or memory
-    auto compute = [&](const Row &r) {
-      Acc acc;
-      acc.zero();
-      double facc = 0.0;
-      if (r.act) {
-        // c >= 0: the value is the block's own, in LDS; otherwise xr
-        auto term = [&](int32_t c, VT v, TX xr) {
-          const TX xv = c >= 0 ? vals[c] : xr;
-          if constexpr (FP) {
-            facc = facc + v * xv;
-          } else {
-            acc.sub(b.narrow ? mul_w32(xv, (int32_t)v, ovf) : mulw(xv, v, ovf));
-          }
-        };
-#pragma unroll
-        for (int j = 0; j < PRE; ++j) {
-          const int k = gl + j * G;
-          if (k < r.len) {
-            const int32_t c = r.c[j];
-            TX xv;  // the block's own values from LDS: no wait on the prefetched registers
-            if (c >= 0) xv = vals[c];
-            else if (r.xok) xv = r.x[j];
-            else xv = ld_coh(dst + (-(int64_t)c - 1));
-            term(-1, r.v[j], xv);
-          }
-        }
-        for (int k = gl + PRE * G; k < r.len; k += G) {  // entries beyond the registers, in order
-          const int64_t e = r.e0 + (int64_t)k * r.cnt;
-          const int32_t c = b.ecode[e];
-          VT v;
-          if constexpr (FP) v = b.evalf[e];
-          else v = b.eval[e];
-          term(c, v, c >= 0 ? (TX)0 : ld_coh(dst + (-(int64_t)c - 1)));
-        }
-      }
-      if constexpr (!FP && G > 1) {
-        acc.lo = group_sum64<G>(acc.lo);
-        acc.hi = group_sum64<G>(acc.hi);
-      }
-      TX y = 0;
-      if (r.act && gl == 0) {
-        if constexpr (FP) {
-          y = (r.rhs - facc) / (double)r.dg;
-        } else {
-          acc.add(r.rhs);
-          y = tdiv_magic(acc.value(ovf), r.dg, r.mag, r.sh, ovf);
-        }
-      }
-      return y;
-    };
-    auto store = [&](const Row &r, TX y) {
-      if (r.act && gl == 0) {
-        vals[r.lp] = y;
-        st_coh(dst + r.row, y);
-      }
-    };
-    // wavefront 0: take the waits of level L (blocking); then report whether
-    // the records of level L + 1 are already met by what was seen
-    auto waits = [&](int L) {
-      if (tid >= 64) return;
-      for (;;) {
-        if (wr + 64 > win_hi && win_hi < we) {  // refill the window from the next record on
-          const int cnt = we - wr < kRecWindow ? we - wr : kRecWindow;
-          for (int i = lane; i < cnt; i += 64) recs[i] = b.wrec[wr + i];
-          win_lo = wr;
-          win_hi = wr + cnt;
-        }
-        const int r = wr + lane;
-        WaitRec rec{0, 0, 0, 0};
-        if (r < win_hi) rec = recs[r - win_lo];
-        const bool mine = r < win_hi && rec.level == L;
-        const unsigned long long got = __ballot(mine);
-        if (mine) {
-          const unsigned target = (unsigned)rec.need * NW;
-          const bool cached = rec.slot < kSeenSlots;
-          unsigned v = cached ? seen[rec.slot] : 0u;
-          for (int spin = 0; v < target; ++spin) {
-            v = ld_coh(b.prog + (int64_t)rec.dep * kLevStride);
-            if (v >= target) break;
-            if (spin >= kSpinLimit || to) {
-              to = true;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(IGM_POLL_SLEEP);
-          }
-          if (cached) seen[rec.slot] = v;
-        }
-        const int cnt = __popcll(got);  // the records of a level are consecutive
-        wr += cnt;
-        if (cnt < 64) break;
-      }
-      // level L + 1: met if every record of it is below the cached progress
-      // (records beyond the window count as not met)
-      const int r = wr + lane;
-      WaitRec rec{0, 0, 0, 0};
-      if (r < win_hi) rec = recs[r - win_lo];
-      const bool mine = r < win_hi && rec.level == L + 1;
-      const bool ok = (r >= win_hi && r < we) ? false
-                      : !mine || (rec.slot < kSeenSlots && seen[rec.slot] >= (unsigned)rec.need * NW);
-      const unsigned long long all = __ballot(mine);
-      const bool met = __all(ok) && __popcll(all) < 64;
-      if (lane == 0) ready[(L + 1) & 1] = met ? 1 : 0;
-    };
-    auto publish = [&]() {
-      wait_vm();
-      if (lane == 0) __hip_atomic_fetch_add(prog, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    };
-
-    for (int s = tid; s < kSeenSlots; s += BLOCK) seen[s] = 0;
-    __syncthreads();
-    waits(0);
-    __syncthreads();
-    Row A, B;
-    stage1(0, 0, A);
-    stage2(A, true);
-    if (nl > 1) stage1(1, 0, B);
-    for (int L = 0; L < nl; ++L) {
-      const TX y = compute(A);
-      if (L > 0) publish();
-      Row C;
-      if (L + 1 < nl) stage2(B, ready[(L + 1) & 1] != 0);
-      if (L + 2 < nl) stage1(L + 2, 0, C);
-      store(A, y);
-      // passes after the first (levels wider than BLOCK / G rows)
-      const int cnt = A.cnt;
-      for (int pass = 1; pass * RPP < cnt; ++pass) {
-        Row P;
-        stage1(L, pass, P);
-        stage2(P, true);
-        const TX yp = compute(P);
-        store(P, yp);
-      }
-      waits(L + 1);
-      __syncthreads();
-      A = B;
-      B = C;
-    }
-    publish();
-  }
-}
-
 // One row of the integer sweep held by a compute lane: stage 1 (loaded three
 // levels ahead, addressed by the position alone; lanes and entries without a
 // row or entry load the padding slot, so every compute lane issues the same
 // loads) and stage 2 (loaded one level ahead: the right-hand side and the
 // values of the entries from other blocks, whose waits the helper has taken by
 // then; lanes and entries without one load a dummy word).
-template <int PRE>
+template <int PRE, class T>
 struct IntRow {
   bool act;  // the lane has a row
   int lp;    // position inside the block (act)
   int32_t row;
   int32_t len;
   int64_t dg;
-  uint64_t mag;
+  uint64_t mag;  // integer sweep only
   int32_t sh;
-  int64_t rhs;
+  T rhs;
   int32_t c[PRE];
-  int64_t v[PRE];
-  int64_t x[PRE];
+  T v[PRE];
+  T x[PRE];
 };
 
-// One integer sweep by the whole grid with a helper wavefront (dst =
-// tdiv(src - strict part, diagonal), the same schedule and the same bits as
-// block_sweep). Wavefront 0 of the workgroup is the helper: it takes the waits
+// One sweep by the whole grid with a helper wavefront (integer: dst =
+// tdiv(src - strict part, diagonal)). Wavefront 0 of the workgroup is the helper: it takes the waits
 // on other blocks two levels ahead, stores each finished level's values to
 // global memory from LDS and publishes the block's progress (one add per
 // level, after its stores of that level have completed). Wavefronts 1 .. W
@@ -360,13 +101,16 @@ struct IntRow {
 // wider than the row ring (kRowRing) is stored by the compute lanes themselves
 // (waited before the barrier); a level wider than one pass takes more passes.
 // `lds` holds sweep_lds_bytes(S, max_levels) bytes. Every thread of every
-// workgroup calls it.
-template <int BLOCK, int G>
-__device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const int64_t *src, int64_t *dst, char *lds,
+// workgroup calls it. FP = true: the FP64 substitution of the start step on
+// the same schedule (doubles, the factor values converted to double, one lane
+// per row summing its products in CSR order, then (rhs - sum) / diagonal).
+template <int BLOCK, int G, bool FP = false, class TX = typename std::conditional<FP, double, int64_t>::type>
+__device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const TX *src, TX *dst, char *lds,
                                                 bool &ovf, bool &to) {
   static_assert(BLOCK % 64 == 0 && BLOCK >= 128 && G >= 1 && G <= 16 && (G & (G - 1)) == 0, "lanes per row");
+  static_assert(!FP || G == 1, "the FP64 substitution sums each row in CSR order");
   constexpr int PRE = G >= 16 ? 1 : 16 / G;  // entries per lane held in registers
-  using Row = IntRow<PRE>;
+  using Row = IntRow<PRE, TX>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -378,7 +122,7 @@ __device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const i
   const int ct = computing ? tid - 64 : 0;
   const int rs = ct / G, gl = ct % G;
   const int klv = b.max_levels + 1;
-  int64_t *vals = (int64_t *)lds;
+  TX *vals = (TX *)lds;
   int64_t *levent = (int64_t *)(lds + 8 * (size_t)b.S);
   int32_t *lvoff = (int32_t *)(levent + klv);
   WaitRec *recs = (WaitRec *)((char *)lvoff + (4 * (size_t)klv + 15) / 16 * 16);
@@ -412,14 +156,17 @@ __device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const i
       r.row = b.prow[pos];
       r.len = b.plen[pos];
       r.dg = b.pdiag[pos];
-      r.mag = b.pmag[pos];
-      r.sh = b.pshift[pos];
+      if constexpr (!FP) {
+        r.mag = b.pmag[pos];
+        r.sh = b.pshift[pos];
+      }
 #pragma unroll
       for (int j = 0; j < PRE; ++j) {
         const int k = gl + j * G;
         const int64_t e = (r.act && k < width) ? lev0 + i + (int64_t)k * cnt : pad;
         r.c[j] = b.ecode[e];
-        r.v[j] = b.eval[e];
+        if constexpr (FP) r.v[j] = b.evalf[e];
+        else r.v[j] = b.eval[e];
       }
     };
     // stage 2: the right-hand side and the other blocks' values (their waits are taken)
@@ -433,42 +180,63 @@ __device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const i
       }
     };
     // the row's value (the group's lane 0 holds it); L = the row's level
-    auto compute = [&](const Row &r, int L) {
-      Acc acc;
-      acc.zero();
+    auto compute = [&](const Row &r, int L) -> TX {
+      if constexpr (FP) {
+        double facc = 0.0;  // entries in CSR order: registers, then the rest
 #pragma unroll
-      for (int j = 0; j < PRE; ++j) {
-        const int k = gl + j * G;
-        const int32_t c = r.c[j];
-        const int64_t xl = vals[c >= 0 ? c : 0];
-        const int64_t xv = c >= 0 ? xl : r.x[j];
-        if (r.act && k < r.len) acc.sub(b.narrow ? mul_w32(xv, (int32_t)r.v[j], ovf) : mulw(xv, r.v[j], ovf));
-      }
-      if (r.act) {
+        for (int j = 0; j < PRE; ++j) {
+          const int32_t c = r.c[j];
+          const double xl = vals[c >= 0 ? c : 0];
+          const double xv = c >= 0 ? xl : r.x[j];
+          if (r.act && j < r.len) facc = facc + r.v[j] * xv;
+        }
+        if (!r.act) return 0.0;
         const int cnt = lvoff[L + 1] - lvoff[L];
         const int64_t e0 = levent[L] + (r.lp - lvoff[L]);
-        for (int k = gl + PRE * G; k < r.len; k += G) {  // entries beyond the registers
+        for (int k = PRE; k < r.len; ++k) {
           const int64_t e = e0 + (int64_t)k * cnt;
           const int32_t c = b.ecode[e];
-          const int64_t v = b.eval[e];
-          const int64_t xv = c >= 0 ? vals[c] : ld_coh(dst + (-(int64_t)c - 1));
-          acc.sub(mulw(xv, v, ovf));
+          const double xv = c >= 0 ? vals[c] : ld_coh(dst + (-(int64_t)c - 1));
+          facc = facc + b.evalf[e] * xv;
         }
+        return (r.rhs - facc) / (double)r.dg;
+      } else {
+        Acc acc;
+        acc.zero();
+#pragma unroll
+        for (int j = 0; j < PRE; ++j) {
+          const int k = gl + j * G;
+          const int32_t c = r.c[j];
+          const int64_t xl = vals[c >= 0 ? c : 0];
+          const int64_t xv = c >= 0 ? xl : r.x[j];
+          if (r.act && k < r.len) acc.sub(b.narrow ? mul_w32(xv, (int32_t)r.v[j], ovf) : mulw(xv, r.v[j], ovf));
+        }
+        if (r.act) {
+          const int cnt = lvoff[L + 1] - lvoff[L];
+          const int64_t e0 = levent[L] + (r.lp - lvoff[L]);
+          for (int k = gl + PRE * G; k < r.len; k += G) {  // entries beyond the registers
+            const int64_t e = e0 + (int64_t)k * cnt;
+            const int32_t c = b.ecode[e];
+            const int64_t v = b.eval[e];
+            const int64_t xv = c >= 0 ? vals[c] : ld_coh(dst + (-(int64_t)c - 1));
+            acc.sub(mulw(xv, v, ovf));
+          }
+        }
+        if constexpr (G > 1) {
+          acc.lo = group_sum64<G>(acc.lo);
+          acc.hi = group_sum64<G>(acc.hi);
+        }
+        int64_t y = 0;
+        if (r.act && gl == 0) {
+          acc.add(r.rhs);
+          y = tdiv_magic(acc.value(ovf), r.dg, r.mag, r.sh, ovf);
+        }
+        return y;
       }
-      if constexpr (G > 1) {
-        acc.lo = group_sum64<G>(acc.lo);
-        acc.hi = group_sum64<G>(acc.hi);
-      }
-      int64_t y = 0;
-      if (r.act && gl == 0) {
-        acc.add(r.rhs);
-        y = tdiv_magic(acc.value(ovf), r.dg, r.mag, r.sh, ovf);
-      }
-      return y;
     };
     // the row's value into LDS and its row into the ring (or, for a level
     // the ring does not hold, straight to global memory)
-    auto keep = [&](const Row &r, int64_t y, int L) {
+    auto keep = [&](const Row &r, TX y, int L) {
       if (r.act && gl == 0) {
         vals[r.lp] = y;
         if (lvoff[L + 1] - lvoff[L] <= kRowRing) ring[(L & 1) * kRowRing + (r.lp - lvoff[L])] = r.row;
@@ -550,12 +318,12 @@ __device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const i
       // (stage 1 loaded); A's registers take level L + 3's stage 1
       auto step = [&](int L, Row &A, Row &B) {
         if (computing) {
-          const int64_t y = compute(A, L);
+          const TX y = compute(A, L);
           keep(A, y, L);
           for (int pass = 1; pass * rpp < lvoff[L + 1] - lvoff[L]; ++pass) {  // wider levels, A's registers
             stage1(L, pass, A);
             stage2(A);
-            const int64_t yp = compute(A, L);
+            const TX yp = compute(A, L);
             keep(A, yp, L);
           }
           if (lvoff[L + 1] - lvoff[L] > kRowRing) wait_vm();  // stored by the compute lanes themselves

@@ -56,7 +56,9 @@ __device__ __forceinline__ int64_t cycle_spmv(const CycleArgs &a, int64_t row, i
     __syncthreads();
     return z;
   } else {
-    return spmv_row(a, row, vj, a.nterms, ovf);
+    // the matrix is streamed: each Arnoldi step reads it once, and its lines
+    // would only evict the basis and the gathered vector
+    return spmv_row<kRowChunk, true>(a, row, vj, a.nterms, ovf);
   }
 }
 

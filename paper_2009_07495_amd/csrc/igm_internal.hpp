@@ -122,9 +122,8 @@ struct BlockSweepArgs {
   // a slot past every block's entries (code 0, value 0): the integer sweep's
   // prefetch loads it for lanes and entries without one
   int64_t pad_slot;
-  // nb progress words kLevStride apart, zero at the start of the sweep: every
-  // wavefront of the block's workgroup adds one per finished level (the FP64
-  // sweep); the helper wavefront adds one per level (the integer sweep)
+  // nb progress words kLevStride apart, zero at the start of the sweep: the
+  // block's helper wavefront adds one per finished level
   unsigned *prog;
 };
 

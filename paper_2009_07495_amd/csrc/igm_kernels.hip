@@ -241,15 +241,16 @@ __global__ __launch_bounds__(kB) void k_scale(int64_t n, const double *__restric
 // converted to double, forward y_i = (bk_i - sum L_ij y_j) / Lbar_ii, then
 // backward u_i = (y_i - sum U_ij u_j) / Ubar_ii in place; each row sums in CSR
 // order. One launch per direction, run block by block on the schedules of
-// the integer sweeps (igm_bsweep.hpp); a block waits for the blocks it reads,
-// so the launch must be co-resident (cooperative).
-constexpr int kSweepBlock = 64;  // one wavefront per workgroup: a level of a block rarely has more rows
+// the integer sweeps with their helper wavefront (igm_bsweep.hpp); a block
+// waits for the blocks it reads, so the launch must be co-resident
+// (cooperative).
+constexpr int kSweepBlock = 256;  // the helper and up to three computing wavefronts
 
 __global__ __launch_bounds__(kSweepBlock) void k_fp_bsweep(BlockSweepArgs b, const double *src, double *dst,
                                                            CycleState *state) {
   extern __shared__ double fsm[];
   bool ovf = false, to = false;
-  block_sweep<kSweepBlock, 1, true>(b, src, dst, (char *)fsm, ovf, to);
+  block_sweep_int<kSweepBlock, 1, true>(b, src, dst, (char *)fsm, ovf, to);
   if (to) __hip_atomic_store(&state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -277,10 +278,12 @@ __global__ __launch_bounds__(kB) void k_cast_v1(int64_t n, const double *__restr
 
 // ---- standalone integer kernels ------------------------------------------
 
+// The standalone SpMV over SELL-64: one thread per row (a workgroup per 256
+// rows), 16 entries in flight per row, the matrix streamed non-temporally.
 __global__ __launch_bounds__(kB) void k_spmv(CycleArgs a, int nterms, const int64_t *__restrict__ v, int64_t *z) {
   bool o = false;
   for (int64_t row = (int64_t)blockIdx.x * kB + threadIdx.x; row < a.n; row += (int64_t)gridDim.x * kB)
-    z[row] = spmv_row(a, row, v, nterms, o);
+    z[row] = spmv_row<16, true>(a, row, v, nterms, o);
   note_event(o, &a.state->first_ovf, ev_code(1, 1, 0));
 }
 
@@ -532,7 +535,7 @@ hipError_t launch_spmv(hipStream_t st, const CycleArgs &a, int nterms, const int
   else if (a.spmv_lanes == 16) hipLaunchKernelGGL(k_spmv_lanes<16>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else if (a.spmv_lanes == 32) hipLaunchKernelGGL(k_spmv_lanes<32>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
   else if (a.spmv_lanes == 64) hipLaunchKernelGGL(k_spmv_lanes<64>, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
-  else hipLaunchKernelGGL(k_spmv, dim3(g), dim3(kB), 0, st, a, nterms, v, z);
+  else hipLaunchKernelGGL(k_spmv, dim3(blocks_for(a.n)), dim3(kB), 0, st, a, nterms, v, z);
   return hipGetLastError();
 }
 

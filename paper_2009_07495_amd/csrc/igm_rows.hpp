@@ -42,8 +42,11 @@ __device__ __forceinline__ void row_visit(int64_t lo, int64_t hi, const int32_t 
 // asr(A_l v, alpha_l), the matrices in SELL-64 layout (slice = 64 rows stored
 // column-major, so the 64 lanes of a wavefront read consecutive words). Every
 // sum is exact; `ovf` is set if a product, a term or the total leaves int64.
-// `a` is any record with the SELL fields of CycleArgs.
-template <class A>
+// `a` is any record with the SELL fields of CycleArgs. CH entries are in
+// flight per chunk; NT loads the values and column indices as streaming
+// (non-temporal) data, which leaves the caches to the gathered v: faster once
+// the matrix is far larger than the last-level cache and read once per pass.
+template <int CH = kRowChunk, bool NT = false, class A>
 __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64_t *__restrict__ v,
                                             int nterms, bool &ovf) {
   const int64_t slice = row >> 6;
@@ -55,21 +58,26 @@ __device__ __forceinline__ int64_t spmv_row(const A &a, int64_t row, const int64
     const int64_t *__restrict__ val = a.sell_val[l];
     Acc acc;
     acc.zero();
-    for (int e0 = 0; e0 < wdt; e0 += kRowChunk) {
-      int64_t vv[kRowChunk], xv[kRowChunk];
-      int32_t c[kRowChunk];
+    for (int e0 = 0; e0 < wdt; e0 += CH) {
+      int64_t vv[CH], xv[CH];
+      int32_t c[CH];
 #pragma unroll
-      for (int k = 0; k < kRowChunk; ++k)
+      for (int k = 0; k < CH; ++k)
         if (e0 + k < wdt) {
           const int64_t pos = base + (int64_t)(e0 + k) * 64;
-          vv[k] = val[pos];
-          c[k] = a.sell_col[pos];
+          if (NT) {
+            vv[k] = __builtin_nontemporal_load(val + pos);
+            c[k] = __builtin_nontemporal_load(a.sell_col + pos);
+          } else {
+            vv[k] = val[pos];
+            c[k] = a.sell_col[pos];
+          }
         }
 #pragma unroll
-      for (int k = 0; k < kRowChunk; ++k)
+      for (int k = 0; k < CH; ++k)
         if (e0 + k < wdt) xv[k] = v[c[k]];
 #pragma unroll
-      for (int k = 0; k < kRowChunk; ++k)
+      for (int k = 0; k < CH; ++k)
         if (e0 + k < wdt) acc.add(mulw(vv[k], xv[k], ovf));
     }
     int64_t t = acc.value(ovf);
