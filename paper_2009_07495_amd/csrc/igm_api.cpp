@@ -419,13 +419,22 @@ igm_status prepare_cycle(igm_system *s) {
   return IGM_OK;
 }
 
+// Lanes per row of the FP64 residual: the SpMV's mapping, except that with
+// SELL-64 (one thread per row over the CSR arrays, which the residual reads)
+// rows of 16 or more entries on average go to groups of 8 lanes, whose loads
+// of consecutive entries coalesce (1M-row 27-point matrix: 481 -> 239 us).
+// The sums keep the CSR order of each row either way.
+static int residual_lanes(const igm_system *s) {
+  return s->spmv_lanes == 1 && s->nnz >= 16 * s->n ? 8 : s->spmv_lanes;
+}
+
 // The FP64 residual step of a refinement (eq. (b), both norms, relres and
 // gamma of eq. (gammak)) for the iterate x, its scalars copied to dst (pinned
 // host memory) at the end; everything is enqueued on the system's stream.
 igm_status enqueue_residual(igm_system *s, const double *x, double *dst) {
   IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
   IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
-                          s->d_cscale, s->d_r, s->d_rhat, s->d_red, s->spmv_lanes));
+                          s->d_cscale, s->d_r, s->d_rhat, s->d_red, residual_lanes(s)));
   IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_r, s->d_red + kRedMuR, s->d_red + kRedSumR));
   IGM_HIP(launch_dnrm_sum(s->stream, s->n, s->d_rhat, s->d_red + kRedMuRhat, s->d_red + kRedSumRhat));
   IGM_HIP(launch_fin_residual(s->stream, s->d_red, s->d_scal + kScalNormB, s->d_scal));
@@ -847,7 +856,7 @@ igm_status igm_residual(igm_system *s, const double *x, double *r, double *rhat)
   if (!s || !x || !r || !rhat) return IGM_ERR_ARG;
   IGM_HIP(hipMemsetAsync(s->d_red, 0, sizeof(unsigned long long) * kRedTotal, s->stream));
   IGM_HIP(launch_residual(s->stream, s->n, s->d_row_ptr, s->d_col, s->d_a, s->d_ahat, s->d_b, s->d_bhat, x,
-                          s->d_cscale, r, rhat, s->d_red, s->spmv_lanes));
+                          s->d_cscale, r, rhat, s->d_red, residual_lanes(s)));
   IGM_HIP(hipStreamSynchronize(s->stream));
   return IGM_OK;
 }

@@ -103,7 +103,9 @@ struct IntRow {
 // `lds` holds sweep_lds_bytes(S, max_levels) bytes. Every thread of every
 // workgroup calls it. FP = true: the FP64 substitution of the start step on
 // the same schedule (doubles, the factor values converted to double, one lane
-// per row summing its products in CSR order, then (rhs - sum) / diagonal).
+// per row summing its products in CSR order, then (rhs - sum) / diagonal;
+// splitting the products over several lanes and adding them in order through
+// shuffles measured slower).
 template <int BLOCK, int G, bool FP = false, class TX = typename std::conditional<FP, double, int64_t>::type>
 __device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const TX *src, TX *dst, char *lds,
                                                 bool &ovf, bool &to) {
@@ -193,7 +195,7 @@ __device__ __forceinline__ void block_sweep_int(const BlockSweepArgs &b, const T
         if (!r.act) return 0.0;
         const int cnt = lvoff[L + 1] - lvoff[L];
         const int64_t e0 = levent[L] + (r.lp - lvoff[L]);
-        for (int k = PRE; k < r.len; ++k) {
+        for (int k = PRE; k < r.len; ++k) {  // entries beyond the registers, in order
           const int64_t e = e0 + (int64_t)k * cnt;
           const int32_t c = b.ecode[e];
           const double xv = c >= 0 ? vals[c] : ld_coh(dst + (-(int64_t)c - 1));
