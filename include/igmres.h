@@ -131,8 +131,9 @@ typedef struct {
   /* Launch tuning of the ILU(0) sweeps of the single-system solver (the bits
    * do not depend on either): rows per block of the blocked sweeps, a multiple
    * of 64 (0 = automatic: as many as the workgroup's LDS holds, at most
-   * 16384), and lanes per row of the integer sweeps, 4, 8 or 16 (0 =
-   * automatic, 4). */
+   * 16384), and lanes per row of the integer sweeps: 0, 4, 8 or 16 are
+   * accepted, and the sweeps run 4 lanes per row whatever the value (building
+   * the 8- and 16-lane sweeps into the cycle kernel as well made it spill). */
   int32_t sweep_rows;
   int32_t sweep_lanes;
   /* s(k) of eq. (AA), the correction matrices used by the int-GMRES call of

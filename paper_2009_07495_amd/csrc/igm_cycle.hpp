@@ -31,10 +31,11 @@ constexpr int kGivens = 64;
 // the 16 words of a cache line), other workgroups first read them
 // after that barrier, and a launch starts with caches coherent with memory.
 
-// One integer sweep of the ILU(0) preconditioner apply with G = 4, 8 or 16
-// lanes per row (a runtime choice: the bits do not depend on it).
+// One integer sweep of the ILU(0) preconditioner apply, 4 lanes per row
+// (the bits do not depend on the width; building 8 and 16 lanes per row into
+// the kernel as well raised its spills, so igm_policy.sweep_lanes is not used).
 template <int BLOCK>
-__device__ __forceinline__ void ilu_sweep(int G, const BlockSweepArgs &b, const int64_t *src, int64_t *dst,
+__device__ __forceinline__ void ilu_sweep(const BlockSweepArgs &b, const int64_t *src, int64_t *dst,
                                           char *lds, bool &ovf, bool &to) {
   block_sweep_int<BLOCK, 4>(b, src, dst, lds, ovf, to);
 }
@@ -208,9 +209,9 @@ __global__ __launch_bounds__(BLOCK) void k_cycle(CycleArgs a) {
       note_event(o1, first, ev_code(j, 1, 0));
       grid_barrier_coh(gs, ssh);
       char *slds = (char *)smem + a.sweep_lds_off;
-      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsf, (const int64_t *)a.zbuf, a.wbuf, slds, o2, to);
+      if (!ssh.abort) ilu_sweep<BLOCK>(a.bsf, (const int64_t *)a.zbuf, a.wbuf, slds, o2, to);
       grid_barrier_coh(gs, ssh);
-      if (!ssh.abort) ilu_sweep<BLOCK>(a.sweep_lanes, a.bsb, (const int64_t *)a.wbuf, a.wbuf, slds, o2, to);
+      if (!ssh.abort) ilu_sweep<BLOCK>(a.bsb, (const int64_t *)a.wbuf, a.wbuf, slds, o2, to);
       if (to) __hip_atomic_store(&a.state->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       grid_barrier_coh(gs, ssh);
       note_event(o2, first, ev_code(j, 2, 0));

@@ -130,10 +130,10 @@ struct BlockSweepArgs {
 // Dependency blocks per block whose progress a sweep caches in LDS, wait
 // records held in LDS at a time, and the LDS a sweep needs: the block's S
 // values, its level table (offsets and entry starts of max_levels + 1
-// levels), the record window, that cache and two flags.
+// levels), the record window, that cache, 16 spare bytes and the ring of the
+// rows of the last two levels (kRowRing each).
 constexpr int kSeenSlots = 256;
 constexpr int kRecWindow = 256;
-// The integer sweep adds the rows of its last two levels (kRowRing each).
 constexpr int kRowRing = 1024;
 inline size_t sweep_lds_bytes(int64_t S, int32_t max_levels) {
   const size_t lv = (size_t)max_levels + 1;
@@ -295,7 +295,7 @@ struct CycleArgs {
   const int32_t *ccol;
   const int64_t *cval[kMaxTerms];
   BlockSweepArgs bsf, bsb;  // ILU: blocked schedules of the forward and backward sweeps (igm_bsweep.hpp)
-  int32_t sweep_lanes;      // ILU: lanes per row in the integer sweeps (1, 2, 4, 8 or 16)
+  int32_t sweep_lanes;      // ILU: the policy's lanes per row (the sweeps run 4 whatever the value)
   int32_t sweep_lds_off;    // ILU: byte offset of the sweeps' LDS (S values, then the seen cache)
   int64_t *H, *c, *s, *g;
   CycleState *state;

@@ -446,7 +446,7 @@ ILU_SWEEP_CASES = [
 @pytest.mark.parametrize("rows,lanes", [(64, 4), (64, 8), (64, 16), (128, 8), (192, 16), (320, 4), (0, 0)])
 def test_ilu_blocked_sweeps_any_block_size(orc, torch, name, gen, kw, rows, lanes):
     """The ILU(0) preconditioner apply runs block by block (Sec. VI; blocks of
-    `rows` consecutive rows, `lanes` lanes per row): small blocks force many
+    `rows` consecutive rows; every accepted `sweep_lanes` value): small blocks force many
     blocks, waits on earlier blocks' progress across workgroups and, with
     fewer workgroups than blocks, workgroups that run several blocks in turn.
     The cycle trace (whole basis included) and a whole solve (whose FP64
