@@ -30,11 +30,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 # Sources the persistent cycle kernel is compiled from: a traffic figure
-# measured with hardware counters is reported only while they are unchanged.
+# measured with hardware counters is reported only while their code (comments
+# aside) is unchanged.
 # sources of the single-system cycle kernels (every mapping) and what they include
 CYCLE_SOURCES = ("igm_cycle.hip", "igm_cycle_lanes.hip", "igm_cycle_merge.hip", "igm_cycle.hpp", "igm_bsweep.hpp",
                  "igm_sweep.hpp", "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp",
                  "../../include/igmres.h")
+
+
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments and with runs of blank space made one
+    space (string and character literals kept), so that the digest below
+    changes with the code, not with its comments."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
 
 
 def cycle_sources_digest() -> str:
@@ -42,8 +69,8 @@ def cycle_sources_digest() -> str:
 
     h = hashlib.sha256()
     for name in CYCLE_SOURCES:
-        with open(os.path.join(ROOT, "paper_2009_07495_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2009_07495_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(strip_comments(f.read()).encode())
     return h.hexdigest()
 
 

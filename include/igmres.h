@@ -420,8 +420,10 @@ typedef struct {
   int32_t rows_per_thread;
   int32_t max_slots;        /* requests resident at once; 0 = 256 */
   int32_t setup_threads;    /* host threads preparing requests; 0 = 8 */
-  int32_t reserve_cus;      /* compute units left to other kernels (the runtime's copy kernels,
-                               the application); 0 = 8, < 0 = none */
+  int32_t reserve_cus;      /* compute units the resident kernel leaves free; 0 = 8, < 0 = none.
+                               This does not make other device work safe beside a server: work
+                               the application enqueued on the same device while a server existed
+                               did not complete (see igm_server_create) */
   int64_t pool_bytes;       /* device memory for resident requests; 0 = 16 GiB */
   int64_t stage_bytes;      /* pinned host memory for prepared requests and results; 0 = 4 GiB */
   /* 0: the host makes a request's structure (validation, diagonal positions,
@@ -438,7 +440,10 @@ typedef struct {
 } igm_server_config;
 
 /* Start a server on the current device. Errors: IGM_ERR_ARG, IGM_ERR_OOM,
- * IGM_ERR_DEVICE, IGM_ERR_UNSUPPORTED (shape). */
+ * IGM_ERR_DEVICE, IGM_ERR_UNSUPPORTED (shape). While the server exists, enqueue
+ * no other device work on that device (kernels, copies, allocations through a
+ * framework): such work was seen not to complete beside the resident kernel,
+ * and waiting for it then never returns. Destroy the server first. */
 igm_status igm_server_create(const igm_server_config *cfg, igm_server **out);
 
 /* Submit one solve (the arguments of igm_create_system plus an optional
