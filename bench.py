@@ -34,8 +34,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # aside) is unchanged.
 # sources of the single-system cycle kernels (every mapping) and what they include
 CYCLE_SOURCES = ("igm_cycle.hip", "igm_cycle_lanes.hip", "igm_cycle_merge.hip", "igm_cycle.hpp", "igm_bsweep.hpp",
-                 "igm_sweep.hpp", "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp",
-                 "../../include/igmres.h")
+                 "igm_sync.hpp", "igm_rows.hpp", "igm_device.hpp", "igm_internal.hpp", "../../include/igmres.h")
 
 
 def strip_comments(src: str) -> str:
